@@ -1,0 +1,118 @@
+/*
+ * pcba_ref.h -- plain FP64 CPU oracle of the Parallel Constrained Bernstein
+ * Algorithm (PCBA).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This library exists to check the HIP library:
+ * only the tests, the smoke check and the benchmark's CPU-baseline leg may load
+ * it.  It shares no code, header, table or helper with the HIP library.
+ *
+ * It is written to be read against the paper, not to be fast: scalar loops,
+ * FP64 throughout, one list, no blocking or fusion.
+ *
+ *   Problem (P), Sec. II-B: minimise p(x) over a box D subject to
+ *   g_i(x) <= 0 (i = 1..alpha) and h_j(x) = 0 (j = 1..beta).
+ *
+ * Coefficient layout: a polynomial of multi-degree (n_1..n_l) is stored with the
+ * coefficient of x^J at offset sum_k j_k * prod_{m>k}(n_m+1) (x_l fastest).
+ * The alpha inequality polynomials are concatenated in order, each at its own
+ * multi-degree; likewise the beta equalities.
+ *
+ * Box ids: all boxes alive in one step are congruent, so a box is its depth
+ * vector d (shared by the whole list) and one unsigned index i_k per axis: the
+ * box is prod_k [lo_k + w_k*i_k/2^d_k, lo_k + w_k*(i_k+1)/2^d_k].
+ */
+#ifndef PCBA_REF_H
+#define PCBA_REF_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PCBA_REF_MAX_DIM 8
+
+enum {
+    PCBA_REF_RUNNING = -1,
+    PCBA_REF_OPTIMAL = 0,       /* stopping criteria met (Def. of tolerances, Sec. III-C) */
+    PCBA_REF_INFEASIBLE = 1,    /* no item survives the cut-off test */
+    PCBA_REF_MEMORY_LIMIT = 2,  /* 2*length(L) > M at the memory test */
+    PCBA_REF_MAX_ITER = 3       /* iteration count reached N */
+};
+
+typedef struct pcba_ref pcba_ref;
+
+typedef struct {
+    int outcome;                          /* PCBA_REF_* */
+    int has_x;                            /* 1 if a feasible item was ever found */
+    double p_up;                          /* solution estimate (+inf if none) */
+    double p_lo;                          /* least lower bound of the last step */
+    double x_lo[PCBA_REF_MAX_DIM];        /* x* in original coordinates */
+    double x_hi[PCBA_REF_MAX_DIM];
+    int x_depth[PCBA_REF_MAX_DIM];        /* id of x*: depth vector and index */
+    unsigned x_index[PCBA_REF_MAX_DIM];
+    int rounds;                           /* n: completed passes over all l directions, from 1 */
+    int steps;                            /* directional subdivisions performed */
+    long long list_len;                   /* current length of L */
+    long long peak_len;                   /* max length of L seen at a memory test */
+    int depth[PCBA_REF_MAX_DIM];          /* current depth vector of the list */
+    int next_dir;                         /* direction (0-based) of the next split */
+} pcba_ref_result;
+
+/* ---- primitives (Sec. II-D, II-E) ------------------------------------------------ */
+
+/* Bernstein coefficients over the box [lo,hi] of the polynomial with monomial
+ * coefficients `mono` (multi-degree deg[0..l-1]); `bern` has the same layout.
+ * Returns 0, or -1 on a bad argument. */
+int pcba_ref_to_bernstein(int l, const int* deg, const double* lo, const double* hi,
+                          const double* mono, double* bern);
+
+/* Midpoint subdivision of one patch along axis r (0-based): left/right child
+ * patches, each with the parent's layout.  Returns 0 or -1. */
+int pcba_ref_split(int l, const int* deg, int r, const double* parent,
+                   double* left, double* right);
+
+/* ---- the algorithm (Alg. PCBA and its subroutines, Sec. III) ---------------------- */
+
+/* Copies every input.  Degrees: cost_deg[l], ineq_deg[n_ineq*l], eq_deg[n_eq*l].
+ * eps, delta, eps_eq > 0; max_boxes = M >= 2; max_iters = N >= 1.
+ * Returns NULL on a bad argument or allocation failure. */
+pcba_ref* pcba_ref_create(int l, const double* lo, const double* hi,
+                          const int* cost_deg, const double* cost_coef,
+                          int n_ineq, const int* ineq_deg, const double* ineq_coef,
+                          int n_eq, const int* eq_deg, const double* eq_coef,
+                          double eps, double delta, double eps_eq,
+                          long long max_boxes, int max_iters);
+
+/* One pass of the main loop: memory test, subdivision in the current direction,
+ * bounds, cut-off test, infeasibility and stopping tests, elimination, and the
+ * advance of direction and iteration count.  Returns PCBA_REF_RUNNING or the
+ * final outcome (further calls return it again). */
+int pcba_ref_step(pcba_ref* h);
+
+/* Steps until an outcome is reached; returns it. */
+int pcba_ref_solve(pcba_ref* h);
+
+void pcba_ref_result_get(const pcba_ref* h, pcba_ref_result* out);
+
+/* Words per item's patches: Pi(P+1) + alpha*Pi(G+1) + beta*Pi(H+1). */
+long long pcba_ref_patch_words(const pcba_ref* h);
+/* The common multi-degree of a kind (0 cost, 1 inequalities, 2 equalities). */
+void pcba_ref_kind_degree(const pcba_ref* h, int kind, int* deg);
+
+/* Copies the current list: ids[len*l] (indices i_k) and patches[len*words]
+ * (cost patch, then inequality patches, then equality patches, each at the
+ * kind's common multi-degree).  Either pointer may be NULL. */
+void pcba_ref_list(const pcba_ref* h, unsigned* ids, double* patches);
+
+/* Patches of the box (depth, index) derived from the root by the same sequence
+ * of splits the main loop applies (directions cycle 0..l-1 from the root; each
+ * step keeps the child named by the next bit of the index, most significant
+ * first).  depth must be a depth vector the loop reaches.  Returns 0 or -1. */
+int pcba_ref_derive(const pcba_ref* h, const int* depth, const unsigned* index,
+                    double* patches);
+
+void pcba_ref_destroy(pcba_ref* h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

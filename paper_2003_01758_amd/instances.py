@@ -1,0 +1,261 @@
+"""Seeded synthetic polynomial programs shaped like the paper's workloads.
+
+This module is the only source of random numbers in the project.  It builds
+problem (P) of Sec. II-B -- minimise p subject to g_i <= 0 and h_j = 0 on a
+box D -- as monomial coefficient tensors.  It holds no Bernstein arithmetic:
+polynomial products, shifts and point evaluations use numpy.polynomial, and
+the solvers (the CPU oracle and the HIP library) take its arrays as input.
+
+Coefficient layout: a polynomial of multi-degree (n_1..n_l) is a C-ordered
+array of shape (n_1+1, ..., n_l+1); entry [j_1, ..., j_l] multiplies
+x_1^j_1 ... x_l^j_l (x_l varies fastest in memory).
+
+Workloads (seed of instance k of workload c: PCG64(1_000_003*c + k)):
+  0  "small":   l=2, D=[-1,1]^2, cost (4,4) N(0,1); 16 planted inequalities
+                (4,4) with coefficients N(0,1)*2^-(a+b).
+  1  "rtd":     l=2, goal-distance cost (6,6); 500 obstacle constraints (10,10)
+                from one shifted template, planted feasible.
+  2  "4d":      l=4, cost (4,4,4,4); 100 planted inequalities (4,4,4,4);
+                2 planted equalities (2,2,2,2); coefficients N(0,1)*2^-|J|.
+  3  "batch":   l in {2,3}, constraint degree in {4,6,8,10}, constraint count
+                log-uniform in [50,1000], otherwise as workload 1.
+  4  "serve":   l=2, workload-1 shapes, constraint count log-uniform in
+                [100,2000].
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+
+import numpy as np
+from numpy.polynomial import polynomial as npp
+
+SEED_STRIDE = 1_000_003
+
+
+@dataclasses.dataclass
+class Instance:
+    """One polynomial program (P) on a box, plus solver tolerances."""
+
+    name: str
+    l: int
+    lo: np.ndarray            # (l,) float64
+    hi: np.ndarray            # (l,) float64
+    cost: np.ndarray          # l-dim coefficient tensor
+    ineq: list                # list of l-dim coefficient tensors
+    eq: list                  # list of l-dim coefficient tensors
+    eps: float = 1e-3         # optimality tolerance (absolute, cost units)
+    delta: float = 1e-4       # step tolerance (max box width, original coords)
+    eps_eq: float = 1e-4      # equality tolerance
+    max_boxes: int = 1 << 16  # M
+    max_iters: int = 28       # N
+    q0: np.ndarray | None = None   # planted feasible point (None if unknown)
+
+    # ---- flat views in the C-ABI layout -------------------------------------------
+    @property
+    def cost_deg(self) -> np.ndarray:
+        return np.array([s - 1 for s in self.cost.shape], dtype=np.int32)
+
+    @property
+    def n_ineq(self) -> int:
+        return len(self.ineq)
+
+    @property
+    def n_eq(self) -> int:
+        return len(self.eq)
+
+    def _degs(self, polys) -> np.ndarray:
+        if not polys:
+            return np.zeros((0, self.l), dtype=np.int32)
+        return np.array([[s - 1 for s in p.shape] for p in polys], dtype=np.int32)
+
+    @property
+    def ineq_deg(self) -> np.ndarray:
+        return self._degs(self.ineq)
+
+    @property
+    def eq_deg(self) -> np.ndarray:
+        return self._degs(self.eq)
+
+    @staticmethod
+    def _cat(polys) -> np.ndarray:
+        if not polys:
+            return np.zeros(0, dtype=np.float64)
+        return np.concatenate([np.ascontiguousarray(p, dtype=np.float64).ravel()
+                               for p in polys])
+
+    @property
+    def cost_flat(self) -> np.ndarray:
+        return np.ascontiguousarray(self.cost, dtype=np.float64).ravel()
+
+    @property
+    def ineq_flat(self) -> np.ndarray:
+        return self._cat(self.ineq)
+
+    @property
+    def eq_flat(self) -> np.ndarray:
+        return self._cat(self.eq)
+
+    def words_per_item(self) -> int:
+        """Memory per item in words, 2l + Pi(P+1) + alpha*Pi(G+1) + beta*Pi(H+1)
+        (Sec. IV-C, memory per item), with G and H the componentwise max degrees."""
+        def common(polys):
+            if not polys:
+                return 0, 0
+            g = np.max(self._degs(polys), axis=0) + 1
+            return len(polys), int(np.prod(g))
+        a, sg = common(self.ineq)
+        b, sh = common(self.eq)
+        return 2 * self.l + int(np.prod(self.cost.shape)) + a * sg + b * sh
+
+    def with_options(self, **kw) -> "Instance":
+        return dataclasses.replace(self, **kw)
+
+
+# ---- polynomial helpers (numpy.polynomial; no Bernstein arithmetic) -------------------
+
+def poly_eval(coef: np.ndarray, x) -> float:
+    """Value of the tensor-coefficient polynomial at the point x (nested Horner
+    through numpy.polynomial.polyval, last variable innermost)."""
+    c = np.asarray(coef, dtype=np.float64)
+    for k in range(c.ndim - 1, -1, -1):
+        c = npp.polyval(float(x[k]), np.moveaxis(c, -1, 0))
+    return float(c)
+
+
+def poly_eval_many(coef: np.ndarray, pts: np.ndarray) -> np.ndarray:
+    """Values at many points, pts of shape (n, l), via per-axis Vandermonde matrices."""
+    c = np.asarray(coef, dtype=np.float64)
+    pts = np.asarray(pts, dtype=np.float64).reshape(-1, c.ndim)
+    vs = [npp.polyvander(pts[:, k], c.shape[k] - 1) for k in range(c.ndim)]
+    res = np.einsum("...j,nj->n...", c, vs[-1])
+    for k in range(c.ndim - 2, -1, -1):
+        res = np.einsum("n...j,nj->n...", res, vs[k])
+    return res
+
+
+def poly_mul(a: np.ndarray, b: np.ndarray) -> np.ndarray:
+    """Product of two tensor-coefficient polynomials (full N-d convolution)."""
+    shape = tuple(sa + sb - 1 for sa, sb in zip(a.shape, b.shape))
+    out = np.zeros(shape)
+    for idx in np.ndindex(*a.shape):
+        ca = a[idx]
+        if ca == 0.0:
+            continue
+        sl = tuple(slice(i, i + sb) for i, sb in zip(idx, b.shape))
+        out[sl] += ca * b
+    return out
+
+
+def poly_shift(coef: np.ndarray, s) -> np.ndarray:
+    """Coefficients of q -> T(q - s) (per-axis composition with numpy.polynomial)."""
+    c = np.asarray(coef, dtype=np.float64)
+    for k in range(c.ndim):
+        n = c.shape[k]
+        # column j holds the coefficients of (q_k - s_k)^j
+        basis = np.zeros((n, n))
+        for j in range(n):
+            basis[: j + 1, j] = npp.polypow([-float(s[k]), 1.0], j)
+        c = np.moveaxis(np.tensordot(basis, np.moveaxis(c, k, 0), axes=(1, 0)), 0, k)
+    return c
+
+
+def _scaled_normal(rng, shape, base: float) -> np.ndarray:
+    """N(0,1) coefficients scaled by base^-(total degree of the monomial)."""
+    tot = np.zeros(shape)
+    for k, s in enumerate(shape):
+        sh = [1] * len(shape)
+        sh[k] = s
+        tot = tot + np.arange(s).reshape(sh)
+    return rng.standard_normal(shape) * base ** (-tot)
+
+
+def _planted(rng, p: np.ndarray, q0) -> np.ndarray:
+    """g = p - p(q0) - U(0.1, 0.5): the planted point q0 is strictly feasible."""
+    g = p.copy()
+    g[(0,) * g.ndim] -= poly_eval(p, q0) + rng.uniform(0.1, 0.5)
+    return g
+
+
+def _goal_cost(rng, l: int, half_deg: int) -> np.ndarray:
+    """Squared distance of a polynomial endpoint map e(q) from a seeded goal;
+    each of the two components of e has multi-degree (half_deg,)*l, so the
+    cost has multi-degree (2*half_deg,)*l."""
+    shape = (half_deg + 1,) * l
+    goal = rng.uniform(-2.0, 2.0, size=2)
+    cost = np.zeros((2 * half_deg + 1,) * l)
+    for c in range(2):
+        e = _scaled_normal(rng, shape, 1.5)
+        e[(0,) * l] -= goal[c]
+        cost += poly_mul(e, e)
+    return cost
+
+
+def _obstacle_constraints(rng, l: int, deg: int, count: int, q0) -> list:
+    """FRS-like obstacle constraints: one template T of multi-degree (deg,)*l,
+    shifted by s_i = o_i/2 for obstacle points o_i uniform in a 4 m x 4 m window
+    (extra axes shifted uniformly in [-1,1]), then planted feasible at q0."""
+    tmpl = _scaled_normal(rng, (deg + 1,) * l, 1.5)
+    out = []
+    for _ in range(count):
+        o = rng.uniform(-2.0, 2.0, size=2)
+        s = np.concatenate([o / 2.0, rng.uniform(-1.0, 1.0, size=l - 2)])
+        out.append(_planted(rng, poly_shift(tmpl, s), q0))
+    return out
+
+
+def make_instance(config: int, index: int = 0, **overrides) -> Instance:
+    """Instance `index` of workload `config` (0..4), seeded PCG64(1_000_003*c + k)."""
+    rng = np.random.Generator(np.random.PCG64(SEED_STRIDE * config + index))
+    if config == 0:
+        l = 2
+        cost = rng.standard_normal((5, 5))
+        q0 = rng.uniform(-1.0, 1.0, size=l)
+        ineq = [_planted(rng, _scaled_normal(rng, (5, 5), 2.0), q0) for _ in range(16)]
+        inst = Instance("small", l, -np.ones(l), np.ones(l), cost, ineq, [],
+                        max_boxes=1 << 16, q0=q0)
+    elif config == 1:
+        l = 2
+        q0 = rng.uniform(-1.0, 1.0, size=l)
+        cost = _goal_cost(rng, l, 3)
+        ineq = _obstacle_constraints(rng, l, 10, 500, q0)
+        inst = Instance("rtd", l, -np.ones(l), np.ones(l), cost, ineq, [],
+                        max_boxes=1 << 20, q0=q0)
+    elif config == 2:
+        l = 4
+        q0 = rng.uniform(-1.0, 1.0, size=l)
+        cost = _scaled_normal(rng, (5,) * l, 2.0)
+        ineq = [_planted(rng, _scaled_normal(rng, (5,) * l, 2.0), q0) for _ in range(100)]
+        eq = []
+        for _ in range(2):
+            h = _scaled_normal(rng, (3,) * l, 2.0)
+            h[(0,) * l] -= poly_eval(h, q0)
+            eq.append(h)
+        inst = Instance("4d", l, -np.ones(l), np.ones(l), cost, ineq, eq,
+                        max_boxes=1 << 20, q0=q0)
+    elif config in (3, 4):
+        if config == 3:
+            l = int(rng.integers(2, 4))
+            deg = int(rng.choice([4, 6, 8, 10]))
+            count = int(round(math.exp(rng.uniform(math.log(50), math.log(1000)))))
+        else:
+            l, deg = 2, 10
+            count = int(round(math.exp(rng.uniform(math.log(100), math.log(2000)))))
+        q0 = rng.uniform(-1.0, 1.0, size=l)
+        cost = _goal_cost(rng, l, 3)
+        ineq = _obstacle_constraints(rng, l, deg, count, q0)
+        inst = Instance("batch" if config == 3 else "serve", l, -np.ones(l), np.ones(l),
+                        cost, ineq, [], max_boxes=1 << 20, q0=q0)
+    else:
+        raise ValueError(f"unknown workload {config}")
+    if overrides:
+        inst = inst.with_options(**overrides)
+    return inst
+
+
+def truncate(inst: Instance, n_ineq: int | None = None, n_eq: int | None = None) -> Instance:
+    """Same instance with only the first n_ineq / n_eq constraints (smaller test cases)."""
+    return dataclasses.replace(
+        inst,
+        ineq=inst.ineq[: (len(inst.ineq) if n_ineq is None else n_ineq)],
+        eq=inst.eq[: (len(inst.eq) if n_eq is None else n_eq)])
