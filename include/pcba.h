@@ -1,0 +1,221 @@
+/*
+ * pcba.h -- C ABI of the MI355X (gfx950) implementation of the Parallel
+ * Constrained Bernstein Algorithm (PCBA): a branch-and-bound solver for
+ * polynomial programs on a box.
+ *
+ * Problem (P), Sec. II-B of the paper:
+ *     minimise p(x) over x in D = [lo_1,hi_1] x ... x [lo_l,hi_l]
+ *     subject to g_i(x) <= 0 (i = 1..alpha) and h_j(x) = 0 (j = 1..beta).
+ * Algorithm inputs (Alg. PCBA): optimality tolerance eps, step tolerance delta,
+ * equality tolerance eps_eq, the maximum number of patches M and of
+ * iterations N.  Outputs: the estimate p* and a box x* (Alg. PCBA, return step),
+ * or "infeasible".
+ *
+ * Conventions for every entry point:
+ *  - Return value: PCBA_OK (0) or a negative PCBA_E_* code.  No exception ever
+ *    crosses this boundary.  pcba_last_error() gives a message for the calling
+ *    thread's last failure.
+ *  - Pointers named *_coef / *_deg / lo / hi are HOST pointers.  Their contents
+ *    are copied during the call; the caller may free them on return.
+ *  - Polynomial layout: for multi-degree (n_1..n_l) the coefficient of x^J sits
+ *    at offset sum_k j_k * prod_{m>k}(n_m+1) (row-major, x_l fastest).  The alpha
+ *    inequality tensors are concatenated in order i = 1..alpha, each at its own
+ *    multi-degree given by ineq_deg[i*l .. i*l+l-1]; equalities likewise.
+ *  - `stream` arguments are hipStream_t values passed as void* (NULL = the
+ *    library's own stream).  The library calls the HIP runtime directly.
+ *  - A problem handle is not thread-safe; distinct handles are independent.
+ *  - Solver outcomes (infeasible, memory limit, iteration cap, time limit) are
+ *    results, not errors: they are reported in pcba_result_t.outcome.
+ */
+#ifndef PCBA_H
+#define PCBA_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PCBA_MAX_DIM 8      /* largest dimension l accepted */
+#define PCBA_MAX_DEGREE 15  /* largest degree per variable accepted */
+
+/* arithmetic of the per-step subdivision */
+enum {
+    PCBA_FP64_PLAIN = 0,  /* FP64 patches, unwidened bounds (the paper's semantics) */
+    PCBA_FP32 = 1         /* FP32 patches; every bound widened by a rigorous
+                             rounding-error bound carried per patch; FP64 root,
+                             periodic FP64 re-derivation, FP64 certification */
+};
+
+/* outcomes (pcba_result_t.outcome) */
+enum {
+    PCBA_RUNNING = -1,
+    PCBA_OPTIMAL = 0,       /* stopping criteria met (tolerance definition, Sec. III-C) */
+    PCBA_INFEASIBLE = 1,    /* every box eliminated as infeasible */
+    PCBA_MEMORY_LIMIT = 2,  /* memory test: 2*length(L) > M */
+    PCBA_MAX_ITER = 3,      /* iteration count reached N */
+    PCBA_TIMEOUT = 4        /* options.time_limit_s elapsed */
+};
+
+/* error codes (return values) */
+enum {
+    PCBA_OK = 0,
+    PCBA_E_ARG = -1,     /* NULL pointer, l outside 1..PCBA_MAX_DIM, lo >= hi,
+                            non-finite bound or coefficient, degree outside
+                            0..PCBA_MAX_DEGREE, eps/delta/eps_eq <= 0, M < 2, N < 1,
+                            unknown precision */
+    PCBA_E_NOMEM = -2,   /* device memory for the root item and its two children
+                            (or a growth step) could not be allocated */
+    PCBA_E_DEVICE = -3,  /* a HIP runtime call failed */
+    PCBA_E_STATE = -4    /* call out of order (e.g. reading a list never solved) */
+};
+
+typedef struct {
+    double eps;              /* optimality tolerance, absolute, cost units (Def. of tolerances) */
+    double delta;            /* step tolerance: max box width in the coordinates of D */
+    double eps_eq;           /* equality tolerance */
+    int64_t max_boxes;       /* M of the memory test (Alg. PCBA) */
+    int32_t max_iters;       /* N (Alg. PCBA) */
+    int32_t precision;       /* PCBA_FP64_PLAIN or PCBA_FP32 */
+    int32_t rederive_every;  /* PCBA_FP32: steps between FP64 re-derivations (0 = never) */
+    int32_t stale_filter;    /* 1: skip writing children whose cost lower bound already
+                                exceeds the previous solution estimate (results are
+                                unchanged); 0: write every child */
+    double time_limit_s;     /* 0 = none */
+} pcba_options;
+
+typedef struct {
+    int32_t outcome;            /* PCBA_OPTIMAL ... PCBA_TIMEOUT (PCBA_RUNNING if unsolved) */
+    int32_t has_x;              /* 1 if a feasible box was ever found */
+    double p_up;                /* solution estimate p* (+inf if no feasible box) */
+    double p_lo;                /* least lower bound of the last step */
+    double x_lo[PCBA_MAX_DIM];  /* x* in the coordinates of D */
+    double x_hi[PCBA_MAX_DIM];
+    int32_t x_depth[PCBA_MAX_DIM];   /* id of x*: depth per axis ... */
+    uint32_t x_index[PCBA_MAX_DIM];  /* ... and index per axis */
+    int32_t rounds;             /* n: completed passes over all directions, from 1 */
+    int32_t steps;              /* directional subdivisions performed */
+    int64_t list_len;           /* length of the list L now */
+    int64_t peak_len;           /* max length of L at a memory test */
+    int32_t depth[PCBA_MAX_DIM];/* depth vector of the boxes in L */
+    int32_t next_dir;           /* direction (0-based) of the next subdivision */
+    int32_t certified;          /* 1: FP64 re-derivation of x* certifies every g_i <= 0
+                                   and every h_j inside the eps_eq band with a rigorous
+                                   FP64 error bound */
+    double p_cert;              /* rigorous FP64 upper bound of p over x* */
+    double cert_err;            /* the FP64 error bound used for the certificate */
+    double err_max;             /* PCBA_FP32: largest per-patch error bound in the list */
+    double seconds;             /* wall time of the last solve call */
+    int64_t capacity;           /* items the device list can hold now */
+} pcba_result_t;
+
+typedef struct pcba_problem pcba_problem;
+
+/* Fills *opt with defaults: eps 1e-3, delta 1e-4, eps_eq 1e-4, M 2^20, N 28,
+ * FP64 plain, re-derivation every 8 steps, stale filter on, no time limit. */
+void pcba_default_options(pcba_options* opt);
+
+/* Builds problem (P) and its root item: every polynomial is zero-padded to the
+ * common multi-degree of its kind (the memory formula of Sec. IV-C stores each
+ * kind at one multi-degree) and converted to Bernstein form over D in FP64 on
+ * the device (InitPatches, Alg. PCBA).  opt may be NULL (defaults).
+ * On success *out owns device memory until pcba_destroy_problem. */
+int pcba_create_problem(int32_t l, const double* lo, const double* hi,
+                        const int32_t* cost_deg, const double* cost_coef,
+                        int32_t n_ineq, const int32_t* ineq_deg, const double* ineq_coef,
+                        int32_t n_eq, const int32_t* eq_deg, const double* eq_coef,
+                        const pcba_options* opt, pcba_problem** out);
+
+/* Runs Alg. PCBA to an outcome (memory test, subdivision, bounds, cut-off test,
+ * elimination, stopping tests, advance), then certifies x* in FP64.
+ * Blocks until done.  A problem already solved is left unchanged. */
+int pcba_solve(pcba_problem* prob, void* stream);
+
+/* Advances the problem by at most n_steps passes of the main loop (fewer if an
+ * outcome is reached).  Used to compare step traces; blocks until done. */
+int pcba_step(pcba_problem* prob, int32_t n_steps, void* stream);
+
+/* Solves n independent problems together: every batched step subdivides,
+ * bounds and compacts the lists of all unfinished problems in one launch per
+ * kernel.  Each result equals the result of pcba_solve on that problem alone. */
+int pcba_solve_batch(pcba_problem* const* probs, int32_t n, void* stream);
+
+/* Copies the outcome and statistics of the last solve into *out (host). */
+int pcba_result(const pcba_problem* prob, pcba_result_t* out);
+
+/* Current list: length, then ids (host, len*l uint32: index per axis) and the
+ * patches converted to FP64 (host, len*words doubles; words = pcba_patch_words).
+ * Patches are the cost patch, the inequality patches, then the equality patches,
+ * each at its kind's common multi-degree.  ids or patches may be NULL. */
+int pcba_list_size(const pcba_problem* prob, int64_t* len);
+int pcba_read_list(const pcba_problem* prob, uint32_t* ids, double* patches, int64_t cap);
+/* PCBA_FP32 only: per-item, per-polynomial error bounds (host, len*(1+alpha+beta)). */
+int pcba_read_errors(const pcba_problem* prob, double* err, int64_t cap);
+int64_t pcba_patch_words(const pcba_problem* prob);
+
+/* FP64 root patches (host, words doubles) as computed on the device. */
+int pcba_read_root(const pcba_problem* prob, double* patches);
+
+/* Device bytes one list item occupies for this problem (patches, id, error terms). */
+int64_t pcba_item_bytes(const pcba_problem* prob);
+
+/* Returns the problem to its initial state (L = {root item}), recomputing the
+ * root patches on the device from the monomial coefficients it keeps resident,
+ * so a solve can be repeated with no host-to-device traffic. */
+int pcba_reset(pcba_problem* prob, void* stream);
+
+/* Per-step trace of the last solve (device ring of PCBA_MAX_TRACE records):
+ * for step s < min(steps, cap): parents subdivided k_in[s], children kept
+ * k_kept[s], and p_up[s], p_lo[s] after the cut-off test.  Any pointer may be
+ * NULL.  Returns the number of records written, or a negative error. */
+#define PCBA_MAX_TRACE 512
+int pcba_read_trace(const pcba_problem* prob, int32_t* k_in, int32_t* k_kept, double* p_up,
+                    double* p_lo, int32_t cap);
+
+/* Releases every resource of the problem.  NULL is accepted. */
+void pcba_destroy_problem(pcba_problem* prob);
+
+/* ---- continuous batching (serving) ------------------------------------------------
+ * An engine advances a changing set of resident problems together.  Problems
+ * are admitted while the sum of their device footprints stays within the
+ * budget; each pcba_engine_run call performs up to n_steps batched steps over
+ * every admitted, unfinished problem; finished problems are certified and
+ * handed back by pcba_engine_poll, freeing their share of the budget. */
+typedef struct pcba_engine pcba_engine;
+
+/* budget_bytes <= 0 means unlimited.  Each admitted problem is charged the
+ * footprint of max(its capacity, reserve_boxes) list items (pcba_footprint_bytes);
+ * a list that must grow beyond its charge waits, paused, until the budget has
+ * room, except the oldest admitted problem, which always grows (so the engine
+ * always makes progress). */
+int pcba_engine_create(int64_t budget_bytes, int64_t reserve_boxes, void* stream,
+                       pcba_engine** out);
+/* Admits prob (returns 1 in *admitted) if its charge fits the remaining budget
+ * (or the engine is empty), else leaves it with the caller (0 in *admitted). */
+int pcba_engine_submit(pcba_engine* eng, pcba_problem* prob, int32_t* admitted);
+/* Runs up to n_steps batched steps; *n_active = unfinished admitted problems. */
+int pcba_engine_run(pcba_engine* eng, int32_t n_steps, int32_t* n_active);
+/* Moves up to cap finished problems into done[]; *n_done = how many. */
+int pcba_engine_poll(pcba_engine* eng, pcba_problem** done, int32_t cap, int32_t* n_done);
+int64_t pcba_engine_used_bytes(const pcba_engine* eng);
+void pcba_engine_destroy(pcba_engine* eng);
+
+/* ---- kernel timing (HIP events around every launch of the step kernels) ----------
+ * Kernel ids: 0 subdivide+bound FP64, 1 subdivide+bound FP32, 2 FP32 re-derivation,
+ * 3 cut-off+compaction, 4 plan/memory test.  Off by default; timing adds one
+ * event pair per launch. */
+#define PCBA_NUM_KERNELS 5
+void pcba_profile_enable(int32_t on);
+void pcba_profile_reset(void);
+/* total milliseconds and launch counts per kernel id (arrays of PCBA_NUM_KERNELS) */
+void pcba_profile_read(double* ms, int64_t* launches);
+
+/* Footprint estimate used for admission: bytes of a list of `boxes` items. */
+int64_t pcba_footprint_bytes(const pcba_problem* prob, int64_t boxes);
+
+const char* pcba_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,127 @@
+// pcba_internal.h -- device data model shared by the kernels and the host
+// runtime of the PCBA library (not part of the public C ABI).
+//
+// List storage (per problem): two item buffers used in turn.  In a step the
+// parents are the K items named by `live` in buffer `cur`; the children of
+// parent j go to slots 2j (left) and 2j+1 (right) of buffer cur^1, the order
+// the subdivision of Alg. Subdivision produces when each item is replaced by
+// its two halves.  The cut-off test then writes the slots of the surviving
+// children, in order, into `live`: elimination is a stream compaction of slot
+// indices, and no patch is moved.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pcba {
+
+constexpr int KINDS = 3;      // 0 cost p, 1 inequalities g_i, 2 equalities h_j
+constexpr int MAXL = 8;       // PCBA_MAX_DIM
+constexpr int MAXM = 16;      // longest fibre: degree 15 + 1
+constexpr int SUB_THREADS = 256;
+constexpr int CUT_THREADS = 1024;
+constexpr int MAX_BATCH = 2048;   // problems per launch
+
+// per-child feasibility flags (OR-ed by every tile of the child)
+enum : uint32_t {
+    F_INFEAS = 1u,   // some g_i has min B > 0, or some h_j has min B > 0 or max B < 0
+    F_NOTFEAS = 2u   // some g_i has max B > 0, or some h_j leaves the eps_eq band
+};
+
+enum : int32_t {
+    ST_RUNNING = -1,
+    ST_OPTIMAL = 0,
+    ST_INFEASIBLE = 1,
+    ST_MEMLIMIT = 2,
+    ST_MAXITER = 3,
+    ST_TIMEOUT = 4,
+    ST_GROW = 16     // paused: the next step needs more list capacity
+};
+
+// Device-resident solver state of one problem (written by the cut kernel).
+struct InstState {
+    int32_t status;
+    int32_t K;          // live parents
+    int32_t r;          // direction of the next split (0-based)
+    int32_t n;          // iteration count, starts at 1
+    int32_t steps;
+    int32_t cur;        // buffer holding the parents
+    int32_t has_x;
+    int32_t cert_ok;
+    double p_up, p_lo;
+    int32_t depth[MAXL];
+    uint32_t x_index[MAXL];
+    int32_t x_depth[MAXL];
+    int64_t peak;
+    double p_cert, cert_err;
+    double err_max;
+};
+
+constexpr int MAX_TRACE = 512;   // PCBA_MAX_TRACE
+
+// One record per step, written by the cut kernel.
+struct TraceRec {
+    int32_t k_in, k_kept;
+    double p_up, p_lo;
+};
+
+// Read-only description of one problem for a launch.
+struct DevInst {
+    int32_t l, n_polys, T, fp32;
+    int32_t dims[KINDS][MAXL];     // fibre length (degree + 1) per axis and kind
+    int32_t S[KINDS];              // coefficients per patch of each kind
+    int32_t count[KINDS];          // 1, alpha, beta
+    int32_t tile_polys[KINDS];     // patches per tile
+    int32_t tile_start[KINDS + 1]; // first tile of each kind; tile_start[KINDS] = T
+    int64_t off[KINDS];            // element offset of each kind inside an item
+    int64_t stride;                // elements per item slot
+    int32_t M;                     // memory-test bound
+    int32_t cap;                   // slots per buffer
+    int32_t N;                     // iteration cap
+    int32_t stale;                 // stale-estimate write filter on
+    int32_t rederive;              // FP32: re-derive from the FP64 root every this many steps
+    int32_t pad0;
+    double eps, delta, eps_eq;
+    double width0[MAXL];           // hi - lo of D
+    void* buf[2];                  // item buffers (double or float), cap * stride each
+    uint32_t* ids[2];              // cap * l box indices
+    float* err[2];                 // FP32 mode: cap * n_polys error bounds
+    int32_t* live;                 // cap/2 parent slots
+    double* minP;                  // child records, cap each
+    double* maxP;
+    uint32_t* flags;
+    const double* root;            // FP64 root patches (item layout, W doubles)
+    const double* root_err;        // FP64 error bound of each root patch
+    double* cert;                  // certification scratch: n_polys * 3 doubles
+    TraceRec* trace;               // MAX_TRACE step records
+    InstState* st;
+};
+
+// ordered integer keys: key(a) < key(b) iff a < b (non-NaN), so min/max of
+// floating values can use integer atomics
+__device__ __forceinline__ unsigned long long fkey(double x)
+{
+    unsigned long long b = (unsigned long long)__double_as_longlong(x);
+    return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
+}
+__device__ __forceinline__ double funkey(unsigned long long k)
+{
+    unsigned long long b = (k >> 63) ? (k & 0x7fffffffffffffffull) : ~k;
+    return __longlong_as_double((long long)b);
+}
+__device__ __forceinline__ unsigned int fkey(float x)
+{
+    unsigned int b = __float_as_uint(x);
+    return (b >> 31) ? ~b : (b | 0x80000000u);
+}
+__device__ __forceinline__ float funkey(unsigned int k)
+{
+    unsigned int b = (k >> 31) ? (k & 0x7fffffffu) : ~k;
+    return __uint_as_float(b);
+}
+
+template <typename T> struct KeyOf;
+template <> struct KeyOf<double> { typedef unsigned long long type; };
+template <> struct KeyOf<float> { typedef unsigned int type; };
+
+}  // namespace pcba

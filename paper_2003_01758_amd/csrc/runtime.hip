@@ -1,0 +1,1009 @@
+// runtime.hip -- host runtime behind include/pcba.h: problem creation (root
+// conversion on the device), the batched step engine (plan, subdivide+bound,
+// cut-off+compaction, growth of the device list), certification and read-out.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/pcba.h"
+#include "kernels.h"
+
+using namespace pcba;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string& msg)
+{
+    g_last_error = msg;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                    \
+    do {                                                                                 \
+        hipError_t e_ = (expr);                                                          \
+        if (e_ != hipSuccess)                                                            \
+            return fail(PCBA_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+constexpr int GRID_MAX = 2048;
+constexpr int STEPS_PER_SYNC = 8;
+constexpr int TILE_ELEMS = 2816;   // target coefficients per tile (per LDS region)
+constexpr int MAX_PATCH = 3584;    // largest patch (coefficients): LDS stays within 64 KB
+constexpr int CAP0 = 64;           // initial list capacity (items per buffer)
+
+double now_s()
+{
+    using namespace std::chrono;
+    return duration<double>(steady_clock::now().time_since_epoch()).count();
+}
+
+double binom(int n, int k)
+{
+    if (k < 0 || k > n) return 0.0;
+    double c = 1.0;
+    for (int i = 1; i <= k; ++i) c = c * (double)(n - k + i) / (double)i;
+    return c;
+}
+
+// kernel timing: event pairs recorded around every launch while enabled
+struct Profile {
+    bool on = false;
+    double ms[PCBA_NUM_KERNELS] = {};
+    int64_t launches[PCBA_NUM_KERNELS] = {};
+    std::vector<hipEvent_t> ev;      // pool: 2 events per record
+    std::vector<int> kid;            // kernel id of each pending record
+    size_t used = 0;
+};
+Profile g_prof;
+
+hipError_t prof_begin(hipStream_t s)
+{
+    if (!g_prof.on) return hipSuccess;
+    if (2 * (g_prof.used + 1) > g_prof.ev.size()) {
+        for (int q = 0; q < 2; ++q) {
+            hipEvent_t e;
+            hipError_t r = hipEventCreate(&e);
+            if (r != hipSuccess) return r;
+            g_prof.ev.push_back(e);
+        }
+    }
+    return hipEventRecord(g_prof.ev[2 * g_prof.used], s);
+}
+hipError_t prof_end(int kernel, hipStream_t s)
+{
+    if (!g_prof.on) return hipSuccess;
+    hipError_t r = hipEventRecord(g_prof.ev[2 * g_prof.used + 1], s);
+    if ((size_t)g_prof.kid.size() <= g_prof.used) g_prof.kid.resize(g_prof.used + 1);
+    g_prof.kid[g_prof.used] = kernel;
+    g_prof.used += 1;
+    return r;
+}
+// after the stream is synchronised: fold the pending records into the totals
+void prof_collect()
+{
+    for (size_t i = 0; i < g_prof.used; ++i) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, g_prof.ev[2 * i], g_prof.ev[2 * i + 1]) == hipSuccess) {
+            g_prof.ms[g_prof.kid[i]] += ms;
+            g_prof.launches[g_prof.kid[i]] += 1;
+        }
+    }
+    g_prof.used = 0;
+}
+
+}  // namespace
+
+struct pcba_problem {
+    int l = 0;
+    double lo[MAXL] = {}, hi[MAXL] = {};
+    int deg[KINDS][MAXL] = {};
+    int S[KINDS] = {};
+    int count[KINDS] = {};
+    int64_t off[KINDS] = {};
+    int64_t W = 0;
+    int n_polys = 0;
+    pcba_options opt{};
+    bool fp32 = false;
+    size_t elem = 8;
+    int tile_polys[KINDS] = {};
+    int tile_start[KINDS + 1] = {};
+    int T = 0;
+    int64_t stride = 0;
+    int maxm = 1;
+    int max_S = 1;
+    int64_t M_eff = 0;
+
+    // device
+    double* d_root = nullptr;
+    double* d_root_err = nullptr;
+    double* d_cert = nullptr;
+    void* d_buf[2] = {nullptr, nullptr};
+    uint32_t* d_ids[2] = {nullptr, nullptr};
+    float* d_err[2] = {nullptr, nullptr};
+    int32_t* d_live = nullptr;
+    double* d_minP = nullptr;
+    double* d_maxP = nullptr;
+    uint32_t* d_flags = nullptr;
+    InstState* d_st = nullptr;
+    TraceRec* d_trace = nullptr;
+    double* d_mono = nullptr;     // monomials in item layout (kept for pcba_reset)
+    double* d_mats = nullptr;     // pre-map and conversion matrices
+    int* d_matoff = nullptr;
+    int64_t cap = 0;
+
+    InstState h_st{};
+    bool certified_done = false;
+    double seconds = 0.0;
+    double t_start = 0.0;
+    int64_t footprint = 0;   // bytes charged by an engine
+    int host_steps = 0;      // steps known on the host (for re-derivation planning)
+};
+
+struct pcba_engine {
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    int64_t budget = 0, used = 0;
+    int64_t reserve = 0;      // list items charged to every admitted problem at least
+    std::vector<pcba_problem*> active;
+    std::vector<pcba_problem*> done;
+    DevInst* d_insts = nullptr;
+    int d_insts_cap = 0;
+    long long* d_plan = nullptr;
+    int plan_cap = 0;
+    InstState* d_states = nullptr;
+    InstState* h_states = nullptr;
+    int states_cap = 0;
+    bool dirty = true;
+};
+
+// ------------------------------------------------------------------ helpers
+
+static DevInst make_dev(const pcba_problem* P)
+{
+    DevInst I;
+    memset(&I, 0, sizeof(I));
+    I.l = P->l;
+    I.n_polys = P->n_polys;
+    I.T = P->T;
+    I.fp32 = P->fp32 ? 1 : 0;
+    for (int t = 0; t < KINDS; ++t) {
+        for (int k = 0; k < MAXL; ++k) I.dims[t][k] = (k < P->l) ? P->deg[t][k] + 1 : 1;
+        I.S[t] = P->S[t];
+        I.count[t] = P->count[t];
+        I.tile_polys[t] = P->tile_polys[t];
+        I.tile_start[t] = P->tile_start[t];
+        I.off[t] = P->off[t];
+    }
+    I.tile_start[KINDS] = P->tile_start[KINDS];
+    I.stride = P->stride;
+    I.M = (int32_t)std::min<int64_t>(P->M_eff, INT32_MAX);
+    I.cap = (int32_t)P->cap;
+    I.N = P->opt.max_iters;
+    I.stale = P->opt.stale_filter ? 1 : 0;
+    I.rederive = P->fp32 ? P->opt.rederive_every : 0;
+    I.eps = P->opt.eps;
+    I.delta = P->opt.delta;
+    I.eps_eq = P->opt.eps_eq;
+    for (int k = 0; k < MAXL; ++k) I.width0[k] = (k < P->l) ? P->hi[k] - P->lo[k] : 0.0;
+    for (int b = 0; b < 2; ++b) {
+        I.buf[b] = P->d_buf[b];
+        I.ids[b] = P->d_ids[b];
+        I.err[b] = P->d_err[b];
+    }
+    I.live = P->d_live;
+    I.minP = P->d_minP;
+    I.maxP = P->d_maxP;
+    I.flags = P->d_flags;
+    I.root = P->d_root;
+    I.root_err = P->d_root_err;
+    I.cert = P->d_cert;
+    I.trace = P->d_trace;
+    I.st = P->d_st;
+    return I;
+}
+
+static int64_t item_bytes(const pcba_problem* P)
+{
+    return P->stride * (int64_t)P->elem + (int64_t)P->l * 4 + (P->fp32 ? P->n_polys * 4 : 0) + 4 + 8 + 8 + 4;
+}
+
+static void free_list(pcba_problem* P)
+{
+    for (int b = 0; b < 2; ++b) {
+        if (P->d_buf[b]) (void)hipFree(P->d_buf[b]);
+        if (P->d_ids[b]) (void)hipFree(P->d_ids[b]);
+        if (P->d_err[b]) (void)hipFree(P->d_err[b]);
+        P->d_buf[b] = nullptr;
+        P->d_ids[b] = nullptr;
+        P->d_err[b] = nullptr;
+    }
+    if (P->d_live) (void)hipFree(P->d_live);
+    if (P->d_minP) (void)hipFree(P->d_minP);
+    if (P->d_maxP) (void)hipFree(P->d_maxP);
+    if (P->d_flags) (void)hipFree(P->d_flags);
+    P->d_live = nullptr;
+    P->d_minP = P->d_maxP = nullptr;
+    P->d_flags = nullptr;
+}
+
+// (Re)allocates the list for `ncap` slots per buffer, keeping the current
+// parents: the slots [0, old cap) of the parent buffer, their ids and error
+// terms, and the live list are copied; the flags are cleared.
+static int alloc_list(pcba_problem* P, int64_t ncap, hipStream_t s)
+{
+    void* nb[2] = {nullptr, nullptr};
+    uint32_t* ni[2] = {nullptr, nullptr};
+    float* ne[2] = {nullptr, nullptr};
+    int32_t* nlive = nullptr;
+    double *nmin = nullptr, *nmax = nullptr;
+    uint32_t* nfl = nullptr;
+    auto cleanup = [&]() {
+        for (int b = 0; b < 2; ++b) {
+            if (nb[b]) (void)hipFree(nb[b]);
+            if (ni[b]) (void)hipFree(ni[b]);
+            if (ne[b]) (void)hipFree(ne[b]);
+        }
+        if (nlive) (void)hipFree(nlive);
+        if (nmin) (void)hipFree(nmin);
+        if (nmax) (void)hipFree(nmax);
+        if (nfl) (void)hipFree(nfl);
+    };
+    bool ok = true;
+    for (int b = 0; b < 2 && ok; ++b) {
+        ok = hipMalloc(&nb[b], (size_t)ncap * P->stride * P->elem) == hipSuccess &&
+             hipMalloc((void**)&ni[b], (size_t)ncap * P->l * sizeof(uint32_t)) == hipSuccess;
+        if (ok && P->fp32)
+            ok = hipMalloc((void**)&ne[b], (size_t)ncap * P->n_polys * sizeof(float)) == hipSuccess;
+    }
+    ok = ok && hipMalloc((void**)&nlive, (size_t)ncap * sizeof(int32_t)) == hipSuccess &&
+         hipMalloc((void**)&nmin, (size_t)ncap * sizeof(double)) == hipSuccess &&
+         hipMalloc((void**)&nmax, (size_t)ncap * sizeof(double)) == hipSuccess &&
+         hipMalloc((void**)&nfl, (size_t)ncap * sizeof(uint32_t)) == hipSuccess;
+    if (!ok) {
+        (void)hipGetLastError();
+        cleanup();
+        return fail(PCBA_E_NOMEM, "device list allocation failed");
+    }
+    hipError_t e = hipMemsetAsync(nfl, 0, (size_t)ncap * sizeof(uint32_t), s);
+    if (e == hipSuccess && P->cap > 0) {
+        const int cur = P->h_st.cur;
+        const int64_t used = std::min<int64_t>(P->cap, ncap);
+        e = hipMemcpyAsync(nb[cur], P->d_buf[cur], (size_t)used * P->stride * P->elem,
+                           hipMemcpyDeviceToDevice, s);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(ni[cur], P->d_ids[cur], (size_t)used * P->l * sizeof(uint32_t),
+                               hipMemcpyDeviceToDevice, s);
+        if (e == hipSuccess && P->fp32)
+            e = hipMemcpyAsync(ne[cur], P->d_err[cur], (size_t)used * P->n_polys * sizeof(float),
+                               hipMemcpyDeviceToDevice, s);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(nlive, P->d_live, (size_t)used * sizeof(int32_t),
+                               hipMemcpyDeviceToDevice, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+    }
+    if (e != hipSuccess) {
+        cleanup();
+        return fail(PCBA_E_DEVICE, std::string("list growth: ") + hipGetErrorString(e));
+    }
+    free_list(P);
+    for (int b = 0; b < 2; ++b) {
+        P->d_buf[b] = nb[b];
+        P->d_ids[b] = ni[b];
+        P->d_err[b] = ne[b];
+    }
+    P->d_live = nlive;
+    P->d_minP = nmin;
+    P->d_maxP = nmax;
+    P->d_flags = nfl;
+    P->cap = ncap;
+    return PCBA_OK;
+}
+
+// Initial state: L = {root item}; root patches recomputed from the resident
+// monomials (InitPatches), n = 1, r = 1 (0-based 0), p_up = +inf.
+static int init_state(pcba_problem* P, hipStream_t s)
+{
+    InstState st0;
+    memset(&st0, 0, sizeof(st0));
+    st0.status = ST_RUNNING;
+    st0.K = 1;
+    st0.n = 1;
+    st0.p_up = INFINITY;
+    st0.p_lo = INFINITY;
+    st0.peak = 0;
+    st0.p_cert = INFINITY;
+    P->h_st = st0;
+    P->certified_done = false;
+    P->seconds = 0.0;
+    P->host_steps = 0;
+    static const int32_t zero = 0;
+    HIP_TRY(hipMemcpyAsync(P->d_st, &st0, sizeof(st0), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(P->d_live, &zero, sizeof(zero), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemsetAsync(P->d_ids[0], 0, (size_t)P->l * sizeof(uint32_t), s));
+    HIP_TRY(hipMemsetAsync(P->d_flags, 0, (size_t)P->cap * sizeof(uint32_t), s));
+    DevInst I = make_dev(P);
+    HIP_TRY(launch_root(I, P->d_mono, P->d_mats, P->d_matoff, P->d_root, P->d_root_err, P->W,
+                        P->max_S, s));
+    HIP_TRY(hipStreamSynchronize(s));  // st0 lives on this stack frame
+    return PCBA_OK;
+}
+
+// ------------------------------------------------------------------ C ABI
+
+extern "C" {
+
+const char* pcba_last_error(void) { return g_last_error.c_str(); }
+
+void pcba_default_options(pcba_options* o)
+{
+    if (!o) return;
+    memset(o, 0, sizeof(*o));
+    o->eps = 1e-3;
+    o->delta = 1e-4;
+    o->eps_eq = 1e-4;
+    o->max_boxes = 1 << 20;
+    o->max_iters = 28;
+    o->precision = PCBA_FP64_PLAIN;
+    o->rederive_every = 8;
+    o->stale_filter = 1;
+    o->time_limit_s = 0.0;
+}
+
+int pcba_create_problem(int32_t l, const double* lo, const double* hi, const int32_t* cost_deg,
+                        const double* cost_coef, int32_t n_ineq, const int32_t* ineq_deg,
+                        const double* ineq_coef, int32_t n_eq, const int32_t* eq_deg,
+                        const double* eq_coef, const pcba_options* opt, pcba_problem** out)
+{
+    if (!out) return fail(PCBA_E_ARG, "out is NULL");
+    *out = nullptr;
+    if (l < 1 || l > PCBA_MAX_DIM) return fail(PCBA_E_ARG, "l outside 1..PCBA_MAX_DIM");
+    if (!lo || !hi || !cost_deg || !cost_coef) return fail(PCBA_E_ARG, "NULL box or cost");
+    if (n_ineq < 0 || n_eq < 0) return fail(PCBA_E_ARG, "negative constraint count");
+    if (n_ineq > 0 && (!ineq_deg || !ineq_coef)) return fail(PCBA_E_ARG, "NULL inequality arrays");
+    if (n_eq > 0 && (!eq_deg || !eq_coef)) return fail(PCBA_E_ARG, "NULL equality arrays");
+    pcba_options o;
+    pcba_default_options(&o);
+    if (opt) o = *opt;
+    if (!(o.eps > 0) || !(o.delta > 0) || !(o.eps_eq > 0) || !std::isfinite(o.eps) ||
+        !std::isfinite(o.eps_eq))
+        return fail(PCBA_E_ARG, "eps, delta and eps_eq must be positive");
+    if (o.max_boxes < 2) return fail(PCBA_E_ARG, "max_boxes (M) must be >= 2");
+    if (o.max_iters < 1) return fail(PCBA_E_ARG, "max_iters (N) must be >= 1");
+    if (o.precision != PCBA_FP64_PLAIN && o.precision != PCBA_FP32)
+        return fail(PCBA_E_ARG, "unknown precision");
+    if (o.rederive_every < 0) return fail(PCBA_E_ARG, "rederive_every must be >= 0");
+    for (int k = 0; k < l; ++k)
+        if (!std::isfinite(lo[k]) || !std::isfinite(hi[k]) || !(hi[k] > lo[k]))
+            return fail(PCBA_E_ARG, "box bounds must be finite with lo < hi");
+
+    pcba_problem* P = new pcba_problem();
+    P->l = l;
+    for (int k = 0; k < l; ++k) { P->lo[k] = lo[k]; P->hi[k] = hi[k]; }
+    P->opt = o;
+    P->fp32 = o.precision == PCBA_FP32;
+    P->elem = P->fp32 ? 4 : 8;
+    P->count[0] = 1;
+    P->count[1] = n_ineq;
+    P->count[2] = n_eq;
+    const int32_t* degs[KINDS] = {cost_deg, ineq_deg, eq_deg};
+    const double* coefs[KINDS] = {cost_coef, ineq_coef, eq_coef};
+    for (int t = 0; t < KINDS; ++t) {
+        for (int i = 0; i < P->count[t]; ++i)
+            for (int k = 0; k < l; ++k) {
+                const int d = degs[t][i * l + k];
+                if (d < 0 || d > PCBA_MAX_DEGREE) {
+                    delete P;
+                    return fail(PCBA_E_ARG, "degree outside 0..PCBA_MAX_DEGREE");
+                }
+                P->deg[t][k] = std::max(P->deg[t][k], d);
+            }
+        int64_t S = 1;
+        for (int k = 0; k < l; ++k) S *= P->deg[t][k] + 1;
+        if (S > MAX_PATCH) {
+            delete P;
+            return fail(PCBA_E_ARG, "a patch exceeds 3584 coefficients");
+        }
+        P->S[t] = P->count[t] ? (int)S : 0;
+        for (int k = 0; k < l; ++k) P->maxm = std::max(P->maxm, P->deg[t][k] + 1);
+    }
+    P->off[0] = 0;
+    P->off[1] = P->S[0];
+    P->off[2] = P->off[1] + (int64_t)P->count[1] * P->S[1];
+    P->W = P->off[2] + (int64_t)P->count[2] * P->S[2];
+    P->n_polys = 1 + n_ineq + n_eq;
+    P->max_S = std::max(P->S[0], std::max(P->S[1], P->S[2]));
+    const int64_t align = P->fp32 ? 64 : 32;  // 256-byte item slots
+    P->stride = (P->W + align - 1) / align * align;
+    // tiles: the cost alone, then runs of constraint patches of ~TILE_ELEMS coefficients
+    P->tile_polys[0] = 1;
+    P->tile_start[0] = 0;
+    int T = 1;
+    for (int t = 1; t < KINDS; ++t) {
+        P->tile_start[t] = T;
+        if (P->count[t] == 0) { P->tile_polys[t] = 1; continue; }
+        P->tile_polys[t] = std::max(1, std::min(P->count[t], TILE_ELEMS / std::max(1, P->S[t])));
+        T += (P->count[t] + P->tile_polys[t] - 1) / P->tile_polys[t];
+    }
+    P->tile_start[KINDS] = T;
+    P->T = T;
+
+    // monomials, zero-padded to each kind's common multi-degree, in item layout
+    std::vector<double> mono(P->W, 0.0);
+    for (int t = 0; t < KINDS; ++t) {
+        int64_t in_off = 0;
+        for (int i = 0; i < P->count[t]; ++i) {
+            const int32_t* d = degs[t] + i * l;
+            int64_t sd = 1;
+            for (int k = 0; k < l; ++k) sd *= d[k] + 1;
+            for (int64_t q = 0; q < sd; ++q) {
+                const double v = coefs[t][in_off + q];
+                if (!std::isfinite(v)) {
+                    delete P;
+                    return fail(PCBA_E_ARG, "non-finite coefficient");
+                }
+                int64_t rem = q, o2 = 0, mul = 1;
+                for (int k = l - 1; k >= 0; --k) {
+                    const int64_t jk = rem % (d[k] + 1);
+                    rem /= d[k] + 1;
+                    o2 += jk * mul;
+                    mul *= P->deg[t][k] + 1;
+                }
+                mono[P->off[t] + (int64_t)i * P->S[t] + o2] = v;
+            }
+            in_off += sd;
+        }
+    }
+    // per kind and axis: pre-map matrix A (x = lo + w t) and conversion matrix U
+    std::vector<double> mats;
+    std::vector<int> matoff(KINDS * MAXL, 0);
+    for (int t = 0; t < KINDS; ++t)
+        for (int r = 0; r < l; ++r) {
+            const int n = P->deg[t][r], m = n + 1;
+            const double w = hi[r] - lo[r];
+            matoff[t * MAXL + r] = (int)mats.size();
+            std::vector<double> A(m * m, 0.0), U(m * m, 0.0);
+            for (int i = 0; i <= n; ++i) {
+                double wi = 1.0;
+                for (int q = 0; q < i; ++q) wi *= w;
+                for (int j = i; j <= n; ++j) {
+                    double lp = 1.0;
+                    for (int q = 0; q < j - i; ++q) lp *= lo[r];
+                    A[i * m + j] = wi * binom(j, i) * lp;
+                }
+            }
+            for (int k = 0; k <= n; ++k)
+                for (int i = 0; i <= k; ++i) U[k * m + i] = binom(k, i) / binom(n, i);
+            mats.insert(mats.end(), A.begin(), A.end());
+            mats.insert(mats.end(), U.begin(), U.end());
+        }
+
+    // memory-test bound: M, and no more than the device can hold for two buffers
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) {
+        delete P;
+        return fail(PCBA_E_DEVICE, "hipMemGetInfo failed (no device?)");
+    }
+    const int64_t per_item = 2 * item_bytes(P);
+    const int64_t hbm_items = (int64_t)((double)free_b * 0.85) / std::max<int64_t>(1, per_item);
+    P->M_eff = std::min<int64_t>(o.max_boxes, std::max<int64_t>(2, hbm_items));
+    if (P->M_eff < 2) {
+        delete P;
+        return fail(PCBA_E_NOMEM, "not enough device memory for the root item and two children");
+    }
+
+    hipStream_t s = nullptr;
+    bool ok = hipStreamCreateWithFlags(&s, hipStreamNonBlocking) == hipSuccess &&
+              hipMalloc((void**)&P->d_root, P->W * sizeof(double)) == hipSuccess &&
+              hipMalloc((void**)&P->d_root_err, P->n_polys * sizeof(double)) == hipSuccess &&
+              hipMalloc((void**)&P->d_cert, 3 * P->n_polys * sizeof(double)) == hipSuccess &&
+              hipMalloc((void**)&P->d_st, sizeof(InstState)) == hipSuccess &&
+              hipMalloc((void**)&P->d_trace, MAX_TRACE * sizeof(TraceRec)) == hipSuccess &&
+              hipMalloc((void**)&P->d_mono, P->W * sizeof(double)) == hipSuccess &&
+              hipMalloc((void**)&P->d_mats, std::max<size_t>(1, mats.size()) * sizeof(double)) == hipSuccess &&
+              hipMalloc((void**)&P->d_matoff, matoff.size() * sizeof(int)) == hipSuccess;
+    if (!ok) {
+        (void)hipGetLastError();
+        if (s) (void)hipStreamDestroy(s);
+        pcba_destroy_problem(P);
+        return fail(PCBA_E_NOMEM, "device allocation failed");
+    }
+    const int64_t cap0 = std::min<int64_t>(P->M_eff, CAP0);
+    int rc = alloc_list(P, std::max<int64_t>(2, cap0), s);
+    if (rc != PCBA_OK) {
+        std::string m = g_last_error;
+        (void)hipStreamDestroy(s);
+        pcba_destroy_problem(P);
+        return fail(rc, m);
+    }
+    hipError_t e = hipMemcpyAsync(P->d_mono, mono.data(), P->W * sizeof(double), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess && !mats.empty())
+        e = hipMemcpyAsync(P->d_mats, mats.data(), mats.size() * sizeof(double), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(P->d_matoff, matoff.data(), matoff.size() * sizeof(int), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e == hipSuccess) {
+        rc = init_state(P, s);
+        if (rc == PCBA_OK) e = hipStreamSynchronize(s);
+    }
+    (void)hipStreamDestroy(s);
+    if (e != hipSuccess || rc != PCBA_OK) {
+        std::string m = e != hipSuccess ? std::string(hipGetErrorString(e)) : g_last_error;
+        pcba_destroy_problem(P);
+        return fail(PCBA_E_DEVICE, std::string("root conversion: ") + m);
+    }
+    *out = P;
+    return PCBA_OK;
+}
+
+int pcba_reset(pcba_problem* P, void* stream)
+{
+    if (!P) return fail(PCBA_E_ARG, "NULL problem");
+    hipStream_t s = (hipStream_t)stream;
+    const int rc = init_state(P, s);
+    if (rc != PCBA_OK) return rc;
+    HIP_TRY(hipStreamSynchronize(s));
+    return PCBA_OK;
+}
+
+int pcba_read_trace(const pcba_problem* P, int32_t* k_in, int32_t* k_kept, double* p_up,
+                    double* p_lo, int32_t cap)
+{
+    if (!P || cap < 0) return fail(PCBA_E_ARG, "bad arguments");
+    const int n = std::min<int>(std::min<int>(P->h_st.steps, MAX_TRACE), cap);
+    if (n <= 0) return 0;
+    std::vector<TraceRec> h(n);
+    HIP_TRY(hipMemcpy(h.data(), P->d_trace, n * sizeof(TraceRec), hipMemcpyDeviceToHost));
+    for (int i = 0; i < n; ++i) {
+        if (k_in) k_in[i] = h[i].k_in;
+        if (k_kept) k_kept[i] = h[i].k_kept;
+        if (p_up) p_up[i] = h[i].p_up;
+        if (p_lo) p_lo[i] = h[i].p_lo;
+    }
+    return n;
+}
+
+void pcba_profile_enable(int32_t on) { g_prof.on = on != 0; }
+void pcba_profile_reset(void)
+{
+    for (int k = 0; k < PCBA_NUM_KERNELS; ++k) { g_prof.ms[k] = 0.0; g_prof.launches[k] = 0; }
+    g_prof.used = 0;
+}
+void pcba_profile_read(double* ms, int64_t* launches)
+{
+    for (int k = 0; k < PCBA_NUM_KERNELS; ++k) {
+        if (ms) ms[k] = g_prof.ms[k];
+        if (launches) launches[k] = g_prof.launches[k];
+    }
+}
+
+void pcba_destroy_problem(pcba_problem* P)
+{
+    if (!P) return;
+    free_list(P);
+    if (P->d_root) (void)hipFree(P->d_root);
+    if (P->d_root_err) (void)hipFree(P->d_root_err);
+    if (P->d_cert) (void)hipFree(P->d_cert);
+    if (P->d_st) (void)hipFree(P->d_st);
+    if (P->d_trace) (void)hipFree(P->d_trace);
+    if (P->d_mono) (void)hipFree(P->d_mono);
+    if (P->d_mats) (void)hipFree(P->d_mats);
+    if (P->d_matoff) (void)hipFree(P->d_matoff);
+    delete P;
+}
+
+int64_t pcba_patch_words(const pcba_problem* P) { return P ? P->W : 0; }
+int64_t pcba_item_bytes(const pcba_problem* P) { return P ? item_bytes(P) : 0; }
+
+int64_t pcba_footprint_bytes(const pcba_problem* P, int64_t boxes)
+{
+    if (!P) return 0;
+    // two buffers of `boxes` slots each, plus the root and records
+    return 2 * boxes * item_bytes(P) + P->W * 8 + P->n_polys * 32 + (int64_t)sizeof(InstState);
+}
+
+// ---------------------------------------------------------------- engine
+
+int pcba_engine_create(int64_t budget_bytes, int64_t reserve_boxes, void* stream, pcba_engine** out)
+{
+    if (!out || reserve_boxes < 0) return fail(PCBA_E_ARG, "bad engine arguments");
+    pcba_engine* E = new pcba_engine();
+    E->budget = budget_bytes > 0 ? budget_bytes : INT64_MAX;
+    E->reserve = reserve_boxes;
+    if (stream) {
+        E->stream = (hipStream_t)stream;
+    } else {
+        if (hipStreamCreateWithFlags(&E->stream, hipStreamNonBlocking) != hipSuccess) {
+            delete E;
+            return fail(PCBA_E_DEVICE, "stream creation failed");
+        }
+        E->own_stream = true;
+    }
+    *out = E;
+    return PCBA_OK;
+}
+
+void pcba_engine_destroy(pcba_engine* E)
+{
+    if (!E) return;
+    if (E->stream) (void)hipStreamSynchronize(E->stream);
+    if (E->d_insts) (void)hipFree(E->d_insts);
+    if (E->d_plan) (void)hipFree(E->d_plan);
+    if (E->d_states) (void)hipFree(E->d_states);
+    if (E->h_states) (void)hipHostFree(E->h_states);
+    if (E->own_stream) (void)hipStreamDestroy(E->stream);
+    delete E;
+}
+
+int64_t pcba_engine_used_bytes(const pcba_engine* E) { return E ? E->used : 0; }
+
+int pcba_engine_submit(pcba_engine* E, pcba_problem* P, int32_t* admitted)
+{
+    if (!E || !P || !admitted) return fail(PCBA_E_ARG, "NULL argument");
+    *admitted = 0;
+    if (E->active.size() >= (size_t)MAX_BATCH) return PCBA_OK;
+    const int64_t fp = pcba_footprint_bytes(P, std::max(P->cap, E->reserve));
+    if (!E->active.empty() && E->used + fp > E->budget) return PCBA_OK;
+    P->footprint = fp;
+    E->used += fp;
+    P->t_start = now_s();
+    P->host_steps = P->h_st.steps;
+    E->active.push_back(P);
+    E->dirty = true;
+    *admitted = 1;
+    return PCBA_OK;
+}
+
+static int engine_upload(pcba_engine* E)
+{
+    const int n = (int)E->active.size();
+    if (n > E->d_insts_cap) {
+        if (E->d_insts) (void)hipFree(E->d_insts);
+        if (E->d_plan) (void)hipFree(E->d_plan);
+        if (E->d_states) (void)hipFree(E->d_states);
+        if (E->h_states) (void)hipHostFree(E->h_states);
+        E->d_insts = nullptr;
+        E->d_plan = nullptr;
+        E->d_states = nullptr;
+        E->h_states = nullptr;
+        const int c = std::max(n, 2 * E->d_insts_cap);
+        HIP_TRY(hipMalloc((void**)&E->d_insts, c * sizeof(DevInst)));
+        HIP_TRY(hipMalloc((void**)&E->d_plan, 3 * (size_t)(c + 1) * sizeof(long long)));
+        HIP_TRY(hipMalloc((void**)&E->d_states, c * sizeof(InstState)));
+        HIP_TRY(hipHostMalloc((void**)&E->h_states, c * sizeof(InstState), hipHostMallocDefault));
+        E->d_insts_cap = c;
+    }
+    std::vector<DevInst> h(n);
+    for (int b = 0; b < n; ++b) h[b] = make_dev(E->active[b]);
+    if (n) HIP_TRY(hipMemcpyAsync(E->d_insts, h.data(), n * sizeof(DevInst), hipMemcpyHostToDevice, E->stream));
+    E->dirty = false;
+    return PCBA_OK;
+}
+
+// LDS bytes of the subdivision kernel for a problem (its largest tile)
+static size_t sub_lds(const pcba_problem* P)
+{
+    int TE = P->S[0], TP = 1;
+    for (int t = 1; t < KINDS; ++t)
+        if (P->count[t]) {
+            TE = std::max(TE, P->tile_polys[t] * P->S[t]);
+            TP = std::max(TP, P->tile_polys[t]);
+        }
+    const size_t key = P->fp32 ? 4 : 8;
+    return 2 * (size_t)TE * P->elem + 5 * (size_t)TP * key + 16;
+}
+static size_t rederive_lds(const pcba_problem* P)
+{
+    int TE = P->S[0];
+    for (int t = 1; t < KINDS; ++t)
+        if (P->count[t]) TE = std::max(TE, P->tile_polys[t] * P->S[t]);
+    return 2 * (size_t)TE * 8 + (size_t)P->l * P->maxm * P->maxm * 8 + 16;
+}
+
+static int certify(pcba_problem* P, hipStream_t s)
+{
+    DevInst I = make_dev(P);
+    HIP_TRY(launch_certify(I, P->max_S, P->maxm, s));
+    HIP_TRY(hipMemcpyAsync(&P->h_st, P->d_st, sizeof(InstState), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    P->certified_done = true;
+    return PCBA_OK;
+}
+
+// One batch of up to n_steps steps over the active problems, then a sync.
+static int engine_steps(pcba_engine* E, int n_steps)
+{
+    if (E->active.empty()) return PCBA_OK;
+    if (E->dirty) {
+        int rc = engine_upload(E);
+        if (rc != PCBA_OK) return rc;
+    }
+    const int n = (int)E->active.size();
+    bool any64 = false, any32 = false, anyrd = false;
+    int maxm64 = 1, maxm32 = 1;
+    size_t lds64 = 0, lds32 = 0, ldsrd = 0;
+    for (auto* P : E->active) {
+        if (P->fp32) {
+            any32 = true;
+            maxm32 = std::max(maxm32, P->maxm);
+            lds32 = std::max(lds32, sub_lds(P));
+            if (P->opt.rederive_every > 0) {
+                anyrd = true;
+                ldsrd = std::max(ldsrd, rederive_lds(P));
+            }
+        } else {
+            any64 = true;
+            maxm64 = std::max(maxm64, P->maxm);
+            lds64 = std::max(lds64, sub_lds(P));
+        }
+    }
+    for (int s = 0; s < n_steps; ++s) {
+        // upper bound of this step's units: K at most doubles per step, and a
+        // problem never holds more than cap/2 parents
+        int64_t ub64 = 0, ub32 = 0, ubrd = 0;
+        for (auto* P : E->active) {
+            if (P->h_st.status != ST_RUNNING) continue;
+            const int64_t k = std::min<int64_t>(P->cap / 2, (int64_t)P->h_st.K << std::min(s, 30));
+            const int64_t u = k * P->T;
+            if (!P->fp32) ub64 += u;
+            else {
+                const int st = P->host_steps + s;
+                const bool due = P->opt.rederive_every > 0 && ((st + 1) % P->opt.rederive_every) == 0;
+                if (due) ubrd += u; else ub32 += u;
+            }
+        }
+        HIP_TRY(prof_begin(E->stream));
+        HIP_TRY(launch_plan(E->d_insts, n, E->d_plan, E->stream));
+        HIP_TRY(prof_end(4, E->stream));
+        if (any64 && ub64 > 0) {
+            HIP_TRY(prof_begin(E->stream));
+            HIP_TRY(launch_sub(E->d_insts, n, E->d_plan, false, maxm64,
+                               (int)std::min<int64_t>(GRID_MAX, ub64), lds64, E->stream));
+            HIP_TRY(prof_end(0, E->stream));
+        }
+        if (any32 && ub32 > 0) {
+            HIP_TRY(prof_begin(E->stream));
+            HIP_TRY(launch_sub(E->d_insts, n, E->d_plan, true, maxm32,
+                               (int)std::min<int64_t>(GRID_MAX, ub32), lds32, E->stream));
+            HIP_TRY(prof_end(1, E->stream));
+        }
+        if (anyrd && ubrd > 0) {
+            HIP_TRY(prof_begin(E->stream));
+            HIP_TRY(launch_rederive(E->d_insts, n, E->d_plan, (int)std::min<int64_t>(GRID_MAX, ubrd),
+                                    ldsrd, E->stream));
+            HIP_TRY(prof_end(2, E->stream));
+        }
+        HIP_TRY(prof_begin(E->stream));
+        HIP_TRY(launch_cut(E->d_insts, n, E->stream));
+        HIP_TRY(prof_end(3, E->stream));
+    }
+    HIP_TRY(launch_gather(E->d_insts, n, E->d_states, E->stream));
+    HIP_TRY(hipMemcpyAsync(E->h_states, E->d_states, n * sizeof(InstState), hipMemcpyDeviceToHost,
+                           E->stream));
+    HIP_TRY(hipStreamSynchronize(E->stream));
+    prof_collect();
+
+    // growth, time limits, finished problems
+    const double t = now_s();
+    std::vector<pcba_problem*> still;
+    for (int b = 0; b < n; ++b) {
+        pcba_problem* P = E->active[b];
+        P->h_st = E->h_states[b];
+        P->host_steps = P->h_st.steps;
+        if (P->h_st.status == ST_GROW) {
+            const int64_t want = std::min<int64_t>(P->M_eff, std::max<int64_t>(2 * P->cap, 4 * (int64_t)P->h_st.K));
+            const int64_t extra = pcba_footprint_bytes(P, std::max(want, E->reserve)) - P->footprint;
+            if (b > 0 && extra > 0 && E->used + extra > E->budget) {
+                still.push_back(P);   // stays paused until the budget has room
+                continue;
+            }
+            int rc = alloc_list(P, want, E->stream);
+            InstState& st = P->h_st;
+            if (rc == PCBA_OK) {
+                st.status = ST_RUNNING;
+            } else {
+                // the device cannot hold the next step: the memory test fires
+                P->M_eff = P->cap;
+                st.status = ST_MEMLIMIT;
+            }
+            HIP_TRY(hipMemcpyAsync(P->d_st, &st, sizeof(st), hipMemcpyHostToDevice, E->stream));
+            HIP_TRY(hipStreamSynchronize(E->stream));
+            E->dirty = true;
+            const int64_t fp = pcba_footprint_bytes(P, std::max(P->cap, E->reserve));
+            E->used += fp - P->footprint;
+            P->footprint = fp;
+        }
+        if (P->h_st.status == ST_RUNNING && P->opt.time_limit_s > 0 &&
+            t - P->t_start > P->opt.time_limit_s) {
+            P->h_st.status = ST_TIMEOUT;
+            HIP_TRY(hipMemcpyAsync(P->d_st, &P->h_st, sizeof(InstState), hipMemcpyHostToDevice, E->stream));
+        }
+        if (P->h_st.status == ST_RUNNING) {
+            still.push_back(P);
+        } else {
+            int rc = certify(P, E->stream);
+            if (rc != PCBA_OK) return rc;
+            P->seconds = now_s() - P->t_start;
+            E->used -= P->footprint;
+            P->footprint = 0;
+            E->done.push_back(P);
+            E->dirty = true;
+        }
+    }
+    if (still.size() != E->active.size()) {
+        E->active.swap(still);
+        E->dirty = true;
+    }
+    return PCBA_OK;
+}
+
+int pcba_engine_run(pcba_engine* E, int32_t n_steps, int32_t* n_active)
+{
+    if (!E || n_steps < 0) return fail(PCBA_E_ARG, "bad engine arguments");
+    int rc = engine_steps(E, n_steps);
+    if (n_active) *n_active = (int32_t)E->active.size();
+    return rc;
+}
+
+int pcba_engine_poll(pcba_engine* E, pcba_problem** done, int32_t cap, int32_t* n_done)
+{
+    if (!E || !n_done || (cap > 0 && !done)) return fail(PCBA_E_ARG, "NULL argument");
+    int k = 0;
+    while (k < cap && !E->done.empty()) {
+        done[k++] = E->done.front();
+        E->done.erase(E->done.begin());
+    }
+    *n_done = k;
+    return PCBA_OK;
+}
+
+// ---------------------------------------------------------------- solve
+
+int pcba_solve_batch(pcba_problem* const* probs, int32_t n, void* stream)
+{
+    if (n < 0 || (n > 0 && !probs)) return fail(PCBA_E_ARG, "bad batch");
+    pcba_engine* E = nullptr;
+    int rc = pcba_engine_create(0, 0, stream, &E);
+    if (rc != PCBA_OK) return rc;
+    const double t0 = now_s();
+    for (int i = 0; i < n; ++i) {
+        if (!probs[i]) { pcba_engine_destroy(E); return fail(PCBA_E_ARG, "NULL problem in batch"); }
+        if (probs[i]->h_st.status != ST_RUNNING) continue;
+        int32_t adm = 0;
+        rc = pcba_engine_submit(E, probs[i], &adm);
+        if (rc != PCBA_OK || !adm) {
+            pcba_engine_destroy(E);
+            return rc != PCBA_OK ? rc : fail(PCBA_E_ARG, "batch larger than one engine launch");
+        }
+        probs[i]->t_start = t0;
+    }
+    while (!E->active.empty()) {
+        rc = engine_steps(E, STEPS_PER_SYNC);
+        if (rc != PCBA_OK) break;
+    }
+    pcba_engine_destroy(E);
+    return rc;
+}
+
+int pcba_solve(pcba_problem* P, void* stream)
+{
+    if (!P) return fail(PCBA_E_ARG, "NULL problem");
+    pcba_problem* arr[1] = {P};
+    return pcba_solve_batch(arr, 1, stream);
+}
+
+int pcba_step(pcba_problem* P, int32_t n_steps, void* stream)
+{
+    if (!P || n_steps < 0) return fail(PCBA_E_ARG, "bad arguments");
+    if (P->h_st.status != ST_RUNNING) return PCBA_OK;
+    pcba_engine* E = nullptr;
+    int rc = pcba_engine_create(0, 0, stream, &E);
+    if (rc != PCBA_OK) return rc;
+    int32_t adm = 0;
+    rc = pcba_engine_submit(E, P, &adm);
+    const int target = P->h_st.steps + n_steps;
+    while (rc == PCBA_OK && !E->active.empty() && P->h_st.steps < target) {
+        rc = engine_steps(E, std::min(STEPS_PER_SYNC, target - P->h_st.steps));
+    }
+    if (!E->active.empty()) { E->used = 0; E->active.clear(); }
+    pcba_engine_destroy(E);
+    return rc;
+}
+
+int pcba_result(const pcba_problem* P, pcba_result_t* out)
+{
+    if (!P || !out) return fail(PCBA_E_ARG, "NULL argument");
+    memset(out, 0, sizeof(*out));
+    const InstState& st = P->h_st;
+    out->outcome = (st.status == ST_GROW) ? PCBA_RUNNING : st.status;
+    out->has_x = st.has_x;
+    out->p_up = st.p_up;
+    out->p_lo = st.p_lo;
+    for (int k = 0; k < P->l; ++k) {
+        out->depth[k] = st.depth[k];
+        if (st.has_x) {
+            const double w = P->hi[k] - P->lo[k];
+            out->x_depth[k] = st.x_depth[k];
+            out->x_index[k] = st.x_index[k];
+            out->x_lo[k] = P->lo[k] + w * ldexp((double)st.x_index[k], -st.x_depth[k]);
+            out->x_hi[k] = P->lo[k] + w * ldexp((double)st.x_index[k] + 1.0, -st.x_depth[k]);
+        }
+    }
+    out->rounds = st.n;
+    out->steps = st.steps;
+    out->list_len = st.K;
+    out->peak_len = st.peak;
+    out->next_dir = st.r;
+    out->certified = P->certified_done ? st.cert_ok : 0;
+    out->p_cert = P->certified_done ? st.p_cert : INFINITY;
+    out->cert_err = st.cert_err;
+    out->err_max = st.err_max;
+    out->seconds = P->seconds;
+    out->capacity = P->cap;
+    return PCBA_OK;
+}
+
+int pcba_list_size(const pcba_problem* P, int64_t* len)
+{
+    if (!P || !len) return fail(PCBA_E_ARG, "NULL argument");
+    *len = P->h_st.K;
+    return PCBA_OK;
+}
+
+static int read_list_impl(const pcba_problem* P, uint32_t* ids, double* patches, double* err,
+                          int64_t cap)
+{
+    const int K = P->h_st.K;
+    if (cap < K) return fail(PCBA_E_ARG, "capacity smaller than the list");
+    if (K == 0) return PCBA_OK;
+    hipStream_t s = nullptr;
+    HIP_TRY(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+    double* d_out = nullptr;
+    uint32_t* d_ids = nullptr;
+    double* d_err = nullptr;
+    hipError_t e = hipMalloc((void**)&d_out, (size_t)K * P->W * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc((void**)&d_ids, (size_t)K * P->l * sizeof(uint32_t));
+    if (e == hipSuccess && P->fp32) e = hipMalloc((void**)&d_err, (size_t)K * P->n_polys * sizeof(double));
+    if (e == hipSuccess) e = launch_pack(make_dev(P), K, d_out, d_ids, d_err, P->W, s);
+    if (e == hipSuccess && patches)
+        e = hipMemcpyAsync(patches, d_out, (size_t)K * P->W * sizeof(double), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess && ids)
+        e = hipMemcpyAsync(ids, d_ids, (size_t)K * P->l * sizeof(uint32_t), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess && err && P->fp32)
+        e = hipMemcpyAsync(err, d_err, (size_t)K * P->n_polys * sizeof(double), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (d_out) (void)hipFree(d_out);
+    if (d_ids) (void)hipFree(d_ids);
+    if (d_err) (void)hipFree(d_err);
+    (void)hipStreamDestroy(s);
+    if (e != hipSuccess) return fail(PCBA_E_DEVICE, std::string("read list: ") + hipGetErrorString(e));
+    return PCBA_OK;
+}
+
+int pcba_read_list(const pcba_problem* P, uint32_t* ids, double* patches, int64_t cap)
+{
+    if (!P) return fail(PCBA_E_ARG, "NULL problem");
+    return read_list_impl(P, ids, patches, nullptr, cap);
+}
+
+int pcba_read_errors(const pcba_problem* P, double* err, int64_t cap)
+{
+    if (!P || !err) return fail(PCBA_E_ARG, "NULL argument");
+    if (!P->fp32) return fail(PCBA_E_STATE, "error bounds exist only in PCBA_FP32 mode");
+    return read_list_impl(P, nullptr, nullptr, err, cap);
+}
+
+int pcba_read_root(const pcba_problem* P, double* patches)
+{
+    if (!P || !patches) return fail(PCBA_E_ARG, "NULL argument");
+    HIP_TRY(hipMemcpy(patches, P->d_root, P->W * sizeof(double), hipMemcpyDeviceToHost));
+    return PCBA_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,69 @@
+"""The C-ABI library loads on the CPU and exports every entry point that
+include/pcba.h declares (no compute call: there may be no GPU here)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "pcba.h")
+LIB = os.path.join(ROOT, "paper_2003_01758_amd", "libpcba.so")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"\b(pcba_[a-z_0-9]+)\s*\(", text)
+    return sorted(set(names))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ("pcba_create_problem", "pcba_solve", "pcba_result", "pcba_destroy_problem",
+                     "pcba_solve_batch", "pcba_engine_submit", "pcba_engine_run",
+                     "pcba_engine_poll", "pcba_last_error"):
+        assert required in names
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(LIB)
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert missing == []
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_default_options_and_argument_validation_without_device():
+    from paper_2003_01758_amd import pcba
+    o = pcba.default_options()
+    assert o.eps == 1e-3 and o.delta == 1e-4 and o.max_iters == 28 and o.max_boxes == 1 << 20
+    # argument errors are detected before any device call
+    L = pcba.lib()
+    h = ctypes.c_void_p()
+    rc = L.pcba_create_problem(0, None, None, None, None, 0, None, None, 0, None, None, None,
+                               ctypes.byref(h))
+    assert rc == pcba.E_ARG and b"l outside" in L.pcba_last_error()
+    import numpy as np
+    lo = np.array([0.0, 1.0])
+    hi = np.array([1.0, 1.0])   # lo >= hi on axis 1
+    deg = np.array([1, 1], dtype=np.int32)
+    coef = np.ones(4)
+    rc = L.pcba_create_problem(2, lo.ctypes.data, hi.ctypes.data, deg.ctypes.data, coef.ctypes.data,
+                               0, None, None, 0, None, None, None, ctypes.byref(h))
+    assert rc == pcba.E_ARG
+    hi = np.array([1.0, 2.0])
+    coef[2] = np.nan
+    rc = L.pcba_create_problem(2, lo.ctypes.data, hi.ctypes.data, deg.ctypes.data, coef.ctypes.data,
+                               0, None, None, 0, None, None, None, ctypes.byref(h))
+    assert rc == pcba.E_ARG
+    bad = pcba.default_options(eps=0.0)
+    coef[2] = 1.0
+    rc = L.pcba_create_problem(2, lo.ctypes.data, hi.ctypes.data, deg.ctypes.data, coef.ctypes.data,
+                               0, None, None, 0, None, None, ctypes.byref(bad), ctypes.byref(h))
+    assert rc == pcba.E_ARG
+    deg16 = np.array([16, 1], dtype=np.int32)
+    rc = L.pcba_create_problem(2, lo.ctypes.data, hi.ctypes.data, deg16.ctypes.data,
+                               np.ones(34).ctypes.data, 0, None, None, 0, None, None, None,
+                               ctypes.byref(h))
+    assert rc == pcba.E_ARG
