@@ -40,11 +40,10 @@ def certified(r, pcba):
     return (r["outcome"] == pcba.OPTIMAL and r["certified"]) or r["outcome"] == pcba.INFEASIBLE
 
 
-def run_mode(pcba, insts, precision, steps, warmup):
-    probs = [pcba.Problem(i, precision=precision) for i in insts]
+def run_mode(pcba, insts, precision, steps, warmup, **opts):
+    probs = [pcba.Problem(i, precision=precision, **opts) for i in insts]
     for w in range(warmup):
-        for p in probs:
-            p.reset()
+        pcba.reset_batch(probs)
         pcba.solve_batch(probs)
         log(f"[bench] {precision} warmup {w + 1}/{warmup} done")
     pcba.profile_reset()
@@ -55,8 +54,7 @@ def run_mode(pcba, insts, precision, steps, warmup):
     elapsed = 0.0
     for s in range(steps):
         t0 = time.perf_counter()
-        for p in probs:
-            p.reset()
+        pcba.reset_batch(probs)
         res = pcba.solve_batch(probs)
         elapsed += time.perf_counter() - t0
         # algorithmic bytes of the subdivide+bound kernel: every parent read once,
@@ -113,6 +111,8 @@ def main():
     ap.add_argument("--batch", type=int, default=32)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--rederive", type=int, default=None, help="FP32 re-derivation period (steps)")
+    ap.add_argument("--stale", type=int, default=None, help="1/0: stale-estimate write filter")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: this build has no multi-GPU path (asked for {args.gpus})",
@@ -125,8 +125,13 @@ def main():
     insts = [make_instance(1, k) for k in range(args.batch)]
     log(f"[bench] {len(insts)} rtd-shaped plans, {insts[0].n_ineq} constraints, "
         f"{insts[0].words_per_item()} words per item")
-    r64 = run_mode(pcba, insts, "fp64", args.steps, args.warmup)
-    r32 = run_mode(pcba, insts, "fp32", args.steps, args.warmup)
+    opts = {}
+    if args.stale is not None:
+        opts["stale_filter"] = args.stale
+    r64 = run_mode(pcba, insts, "fp64", args.steps, args.warmup, **opts)
+    if args.rederive is not None:
+        opts["rederive_every"] = args.rederive
+    r32 = run_mode(pcba, insts, "fp32", args.steps, args.warmup, **opts)
 
     # parity of the two GPU paths on the last step (both provably within eps of f*)
     dp = max(abs(a["p_up"] - b["p_up"]) for a, b in zip(r32["results"], r64["results"])
@@ -152,6 +157,8 @@ def main():
             "workload": "rtd-shaped plans: l=2 on [-1,1]^2, goal-distance cost (6,6), "
                         "500 obstacle constraints (10,10), eps 1e-3, delta 1e-4, M 2^20, N 28",
             "batch": args.batch,
+            "rederive_every": args.rederive if args.rederive is not None else 8,
+            "stale_filter": args.stale if args.stale is not None else 0,
             "path": "fp32 patches with rigorous widening + fp64 root, re-derivation and certification"
                     if best is r32 else "fp64 plain",
         },

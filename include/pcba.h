@@ -112,7 +112,7 @@ typedef struct {
 typedef struct pcba_problem pcba_problem;
 
 /* Fills *opt with defaults: eps 1e-3, delta 1e-4, eps_eq 1e-4, M 2^20, N 28,
- * FP64 plain, re-derivation every 8 steps, stale filter on, no time limit. */
+ * FP64 plain, re-derivation every 8 steps, stale filter off, no time limit. */
 void pcba_default_options(pcba_options* opt);
 
 /* Builds problem (P) and its root item: every polynomial is zero-padded to the
@@ -163,6 +163,8 @@ int64_t pcba_item_bytes(const pcba_problem* prob);
  * root patches on the device from the monomial coefficients it keeps resident,
  * so a solve can be repeated with no host-to-device traffic. */
 int pcba_reset(pcba_problem* prob, void* stream);
+/* pcba_reset for n problems with one launch per kernel. */
+int pcba_reset_batch(pcba_problem* const* probs, int32_t n, void* stream);
 
 /* Per-step trace of the last solve (device ring of PCBA_MAX_TRACE records):
  * for step s < min(steps, cap): parents subdivided k_in[s], children kept

@@ -71,6 +71,7 @@ __device__ int block_min_i(int v, int* sh)
 //   class 0: FP64 problems (k_sub<double>)
 //   class 1: FP32 problems splitting their FP32 parents (k_sub<float>)
 //   class 2: FP32 problems whose step re-derives the children from the root
+//   class 3: the transform rows of those problems (k_tmat, one thread per row)
 // plan[c*(n+1) + b] = first unit of problem b in class c; plan[c*(n+1) + n] = total.
 __device__ __forceinline__ int unit_class(const DevInst& I, const InstState* st)
 {
@@ -80,14 +81,15 @@ __device__ __forceinline__ int unit_class(const DevInst& I, const InstState* st)
 }
 
 __global__ __launch_bounds__(1024) void k_plan(const DevInst* __restrict__ insts, int n,
-                                               long long* __restrict__ plan)
+                                               long long* __restrict__ plan,
+                                               StepInfo* __restrict__ info)
 {
-    __shared__ long long wtot[3][16];
+    __shared__ long long wtot[4][16];
     const int t = threadIdx.x, lane = t & 63, w = t >> 6, nw = blockDim.x >> 6;
-    long long carry[3] = {0, 0, 0};
+    long long carry[4] = {0, 0, 0, 0};
     for (int b0 = 0; b0 < n; b0 += blockDim.x) {
         const int b = b0 + t;
-        long long v[3] = {0, 0, 0};
+        long long v[4] = {0, 0, 0, 0};
         if (b < n) {
             const DevInst& I = insts[b];
             InstState* st = I.st;
@@ -98,10 +100,23 @@ __global__ __launch_bounds__(1024) void k_plan(const DevInst* __restrict__ insts
                 if ((int64_t)st->K > st->peak) st->peak = st->K;
                 if (2LL * st->K > (int64_t)I.M) st->status = ST_MEMLIMIT;
                 else if (2LL * st->K > (int64_t)I.cap) st->status = ST_GROW;
-                else v[unit_class(I, st)] = (long long)st->K * I.T;
+                else {
+                    const int c = unit_class(I, st);
+                    v[c] = (long long)st->K * I.T;
+                    if (c == 2) v[3] = (long long)st->K * 2 * I.rows;
+                }
             }
+            StepInfo si;
+            si.K = st->K;
+            si.cur = st->cur;
+            si.r = st->r;
+            si.steps = st->steps;
+            si.p_up = st->p_up;
+            si.stamp = step_stamp(st);
+            si.pad = 0;
+            info[b] = si;
         }
-        for (int c = 0; c < 3; ++c) {
+        for (int c = 0; c < 4; ++c) {
             long long x = v[c];
             for (int o = 1; o < 64; o <<= 1) {
                 long long y = __shfl_up(x, o, 64);
@@ -111,7 +126,7 @@ __global__ __launch_bounds__(1024) void k_plan(const DevInst* __restrict__ insts
             v[c] = x - v[c];  // exclusive within the wave
         }
         __syncthreads();
-        for (int c = 0; c < 3; ++c) {
+        for (int c = 0; c < 4; ++c) {
             long long before = carry[c];
             for (int q = 0; q < w; ++q) before += wtot[c][q];
             if (b < n) plan[c * (n + 1) + b] = before + v[c];
@@ -121,7 +136,7 @@ __global__ __launch_bounds__(1024) void k_plan(const DevInst* __restrict__ insts
         }
         __syncthreads();
     }
-    if (t < 3) plan[t * (n + 1) + n] = carry[t];
+    if (t < 4) plan[t * (n + 1) + n] = carry[t];
 }
 
 __device__ __forceinline__ int find_inst(const long long* __restrict__ pre, int n, long long u)
@@ -132,6 +147,13 @@ __device__ __forceinline__ int find_inst(const long long* __restrict__ pre, int 
         if (pre[mid] <= u) lo = mid; else hi = mid;
     }
     return lo;
+}
+// the same for a unit shared by the whole workgroup: the result is made
+// wave-uniform so that the problem's descriptor and state are read through
+// scalar loads
+__device__ __forceinline__ int find_inst_uniform(const long long* __restrict__ pre, int n, long long u)
+{
+    return __builtin_amdgcn_readfirstlane(find_inst(pre, n, u));
 }
 
 // geometry of a fibre along axis r inside a patch of dims[0..l-1]
@@ -175,90 +197,132 @@ __device__ __forceinline__ float round_up_f(double x)
 
 // ------------------------------------------------------------------ k_root
 
-// One workgroup per polynomial.  mats holds, per kind and axis, the pre-map
-// matrix A (x = lo + w t substituted) followed by the conversion matrix U,
-// each m x m row-major; matoff[kind*MAXL + r] is the offset of that pair.
-__global__ __launch_bounds__(256) void k_root(DevInst I, const double* __restrict__ mono,
-                                             const double* __restrict__ mats,
-                                             const int* __restrict__ matoff,
-                                             double* __restrict__ root,
-                                             double* __restrict__ root_err)
+__device__ __forceinline__ int find_block(const int* __restrict__ pre, int n, int u)
+{
+    int lo = 0, hi = n;  // pre[lo] <= u < pre[hi]
+    while (hi - lo > 1) {
+        int mid = (lo + hi) >> 1;
+        if (pre[mid] <= u) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ void poly_kind(const DevInst& I, int poly, int& kind, int& idx)
+{
+    kind = 0;
+    idx = poly;
+    if (idx >= I.count[0]) {
+        idx -= I.count[0];
+        kind = 1;
+        if (idx >= I.count[1]) { idx -= I.count[1]; kind = 2; }
+    }
+}
+
+// InitPatches: one workgroup per (problem, polynomial), blocks of problem b
+// are [pre[b], pre[b+1]).  Per axis r, the pre-map matrix A (x = lo + w t
+// substituted) then the conversion matrix U are applied; every output
+// coefficient is one thread's sum over i in increasing order.  A second pass
+// runs the same chain on |coefficients| with |matrices|; its largest value
+// times gamma bounds the FP64 rounding error.  The root item is written into
+// slot 0 of buffer 0 in the working precision, with its error bound in FP32 mode.
+__global__ __launch_bounds__(256) void k_root(const DevInst* __restrict__ insts, int n,
+                                             const int* __restrict__ pre)
 {
     extern __shared__ double sh[];
-    __shared__ double red[4];
-    const int poly = blockIdx.x;
-    int kind = 0, idx = poly;
-    if (idx >= I.count[0]) { idx -= I.count[0]; kind = 1; if (idx >= I.count[1]) { idx -= I.count[1]; kind = 2; } }
+    __shared__ double red[2][4];
+    const int bi = find_block(pre, n, blockIdx.x);
+    const DevInst& I = insts[bi];
+    const int poly = blockIdx.x - pre[bi];
+    int kind, idx;
+    poly_kind(I, poly, kind, idx);
     const int S = I.S[kind];
     const int64_t off = I.off[kind] + (int64_t)idx * S;
-    double* x = sh;       // current values
-    double* y = sh + S;   // scratch
+    double* x = sh;
+    double* y = sh + S;
     int q_total = 2;
-    double amax = 0.0;
-    // pass 0: the conversion itself; pass 1: the same chain on |coefficients|
-    // with |matrices|, whose largest entry bounds the rounding error
+    double amax = 0.0, vmax = 0.0;
     for (int absp = 0; absp < 2; ++absp) {
-        for (int e = threadIdx.x; e < S; e += blockDim.x) x[e] = absp ? fabs(mono[off + e]) : mono[off + e];
+        for (int e = threadIdx.x; e < S; e += blockDim.x)
+            x[e] = absp ? fabs(I.mono[off + e]) : I.mono[off + e];
         __syncthreads();
         for (int r = 0; r < I.l; ++r) {
             FibreGeom g = fibre_geom(I.dims[kind], I.l, r, S);
-            const double* A = mats + matoff[kind * MAXL + r];
+            const double* A = I.mats + I.matoff[kind * MAXL + r];
             const double* U = A + g.m * g.m;
             if (absp) q_total += 2 * (g.m + 4);
             for (int pass = 0; pass < 2; ++pass) {
                 const double* Mx = pass ? U : A;
-                double* src = pass ? y : x;
+                const double* src = pass ? y : x;
                 double* dst = pass ? x : y;
-                for (int f = threadIdx.x; f < g.F; f += blockDim.x) {
-                    const int base = fibre_base(g, f);
-                    for (int k = 0; k < g.m; ++k) {
-                        double acc = 0.0;
-                        for (int i = 0; i < g.m; ++i) {
-                            const double mk = absp ? fabs(Mx[k * g.m + i]) : Mx[k * g.m + i];
-                            acc += mk * src[base + i * g.stride];
-                        }
-                        dst[base + k * g.stride] = acc;
+                for (int o = threadIdx.x; o < S; o += blockDim.x) {
+                    const int k = (o / g.stride) % g.m;
+                    const int base = o - k * g.stride;
+                    double acc = 0.0;
+                    for (int i = 0; i < g.m; ++i) {
+                        const double mk = absp ? fabs(Mx[k * g.m + i]) : Mx[k * g.m + i];
+                        acc += mk * src[base + i * g.stride];
                     }
+                    dst[o] = acc;
                 }
                 __syncthreads();
             }
         }
         for (int e = threadIdx.x; e < S; e += blockDim.x) {
-            if (absp) amax = fmax(amax, x[e]);
-            else root[off + e] = x[e];
+            if (absp) {
+                amax = fmax(amax, x[e]);
+            } else {
+                I.root[off + e] = x[e];
+                vmax = fmax(vmax, fabs(x[e]));
+                if (I.fp32) ((float*)I.buf[0])[off + e] = (float)x[e];
+                else ((double*)I.buf[0])[off + e] = x[e];
+            }
         }
         __syncthreads();
     }
-    for (int o = 32; o > 0; o >>= 1) amax = fmax(amax, __shfl_xor(amax, o, 64));
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = amax;
+    for (int o = 32; o > 0; o >>= 1) {
+        amax = fmax(amax, __shfl_xor(amax, o, 64));
+        vmax = fmax(vmax, __shfl_xor(vmax, o, 64));
+    }
+    if ((threadIdx.x & 63) == 0) { red[0][threadIdx.x >> 6] = amax; red[1][threadIdx.x >> 6] = vmax; }
     __syncthreads();
     if (threadIdx.x == 0) {
-        double m = 0.0;
-        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) m = fmax(m, red[w]);
-        root_err[poly] = gamma64(q_total) * m * 1.01;
+        double m = 0.0, v = 0.0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) { m = fmax(m, red[0][w]); v = fmax(v, red[1][w]); }
+        const double e64 = gamma64(q_total) * m * 1.01;
+        I.root_err[poly] = e64;
+        // FP32: the FP64 bound plus rounding to FP32 (u = 2^-23 relative) plus underflow
+        if (I.fp32) I.err[0][poly] = round_up_f(e64 + v * 0x1p-23 + 0x1p-126);
     }
 }
 
-// Root item into slot 0 of buffer 0 (FP32 mode: rounded, with its error bound).
-template <typename T>
-__global__ void k_root_item(DevInst I, int64_t W)
+// Initial solver state of every problem: L = {root item}, n = 1, r = first
+// direction, p_up = p_lo = +inf.
+__global__ void k_reset(const DevInst* __restrict__ insts, int n)
 {
-    T* dst = (T*)I.buf[0];
-    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < W;
-         e += (int64_t)gridDim.x * blockDim.x)
-        dst[e] = (T)I.root[e];
-    if (I.fp32 && blockIdx.x == 0) {
-        // e0 = FP64 conversion bound + rounding to FP32 (half an ulp, taken as u = 2^-23 rel.)
-        for (int p = threadIdx.x; p < I.n_polys; p += blockDim.x) {
-            int kind = 0, idx = p;
-            if (idx >= I.count[0]) { idx -= I.count[0]; kind = 1; if (idx >= I.count[1]) { idx -= I.count[1]; kind = 2; } }
-            const int S = I.S[kind];
-            const double* P = I.root + I.off[kind] + (int64_t)idx * S;
-            double amax = 0.0;
-            for (int e = 0; e < S; ++e) amax = fmax(amax, fabs(P[e]));
-            I.err[0][p] = round_up_f(I.root_err[p] + amax * 0x1p-23 + 0x1p-126);
-        }
-    }
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= n) return;
+    const DevInst& I = insts[b];
+    InstState* st = I.st;
+    st->status = ST_RUNNING;
+    st->K = 1;
+    st->r = 0;
+    st->n = 1;
+    st->steps = 0;
+    st->cur = 0;
+    st->has_x = 0;
+    st->cert_ok = 0;
+    st->p_up = INFINITY;
+    st->p_lo = INFINITY;
+    for (int k = 0; k < MAXL; ++k) { st->depth[k] = 0; st->x_index[k] = 0; st->x_depth[k] = 0; }
+    st->peak = 0;
+    st->p_cert = INFINITY;
+    st->cert_err = 0.0;
+    st->err_max = 0.0;
+    st->epoch = st->epoch + 1u;
+    I.live[0] = 0;
+    for (int k = 0; k < I.l; ++k) I.ids[0][k] = 0;
+    I.flags[0] = 0;
+    I.flags[1] = 0;
 }
 
 // ------------------------------------------------------------------ k_sub
@@ -301,16 +365,39 @@ __device__ __forceinline__ void split_fibre(T* __restrict__ a, T* __restrict__ b
     }
 }
 
-// Splits np consecutive patches of one kind (parent tile at `src`) along axis
-// r inside LDS, and reduces per-patch min/max of both children and the
-// parent's max |coefficient|.  All threads of the block call it.
-template <typename T, int MM>
-__device__ void split_tile_lds(const T* __restrict__ src, int np, int S, const FibreGeom& g,
-                               SubLds<T> L)
+// Barrier for LDS data only: waits for this wave's LDS operations, not for its
+// global stores, which stay in flight across the barrier.
+__device__ __forceinline__ void lds_barrier()
+{
+    asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+
+// Stages a tile of np patches (TE = np*S coefficients at `src`) into LDS and
+// resets the per-patch keys.  Callers follow with lds_barrier().
+// global -> LDS copy with LB independent loads in flight per thread
+template <typename T, int LB = 12>
+__device__ __forceinline__ void copy_to_lds(T* __restrict__ dst, const T* __restrict__ src, int n)
+{
+    for (int e0 = threadIdx.x; e0 < n; e0 += LB * blockDim.x) {
+        T v[LB];
+#pragma unroll
+        for (int q = 0; q < LB; ++q) {
+            const int e = e0 + q * blockDim.x;
+            if (e < n) v[q] = src[e];
+        }
+#pragma unroll
+        for (int q = 0; q < LB; ++q) {
+            const int e = e0 + q * blockDim.x;
+            if (e < n) dst[e] = v[q];
+        }
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ void tile_load(const T* __restrict__ src, int np, int TE, SubLds<T> L)
 {
     typedef typename KeyOf<T>::type K;
-    const int TE = np * S;
-    for (int e = threadIdx.x; e < TE; e += blockDim.x) L.a[e] = src[e];
+    copy_to_lds<T>(L.a, src, TE);
     for (int p = threadIdx.x; p < np; p += blockDim.x) {
         L.key[5 * p + 0] = ~(K)0;  // min left
         L.key[5 * p + 1] = 0;      // max left
@@ -318,7 +405,14 @@ __device__ void split_tile_lds(const T* __restrict__ src, int np, int S, const F
         L.key[5 * p + 3] = 0;      // max right
         L.key[5 * p + 4] = 0;      // max |parent|
     }
-    __syncthreads();
+}
+
+// Splits the staged tile along the fibres of geometry g: left child in place
+// in L.a, right child in L.b, per-patch min/max of both children and max
+// |parent| folded into the keys.  Callers follow with lds_barrier().
+template <typename T, int MM>
+__device__ __forceinline__ void tile_split(int np, int S, const FibreGeom& g, SubLds<T> L)
+{
     const int TF = np * g.F;
     for (int f = threadIdx.x; f < TF; f += blockDim.x) {
         const int p = f / g.F;
@@ -340,7 +434,21 @@ __device__ void split_tile_lds(const T* __restrict__ src, int np, int S, const F
         atomicMax(&L.key[5 * p + 3], fkey(mxR));
         atomicMax(&L.key[5 * p + 4], fkey(amax));
     }
-    __syncthreads();
+}
+
+// Unit v of a problem with K parents and T tiles: the K cost tiles first (so
+// that the cost bounds of most children are recorded before their constraint
+// tiles start), then the constraint tiles parent by parent.
+__device__ __forceinline__ void unit_of(long long v, int K, int T, int& j, int& t)
+{
+    if (v < K) {
+        j = (int)v;
+        t = 0;
+    } else {
+        const long long w = v - K;
+        j = (int)(w / (T - 1));
+        t = 1 + (int)(w - (long long)j * (T - 1));
+    }
 }
 
 // widened bound of one patch of a child: lo/hi in double
@@ -356,191 +464,279 @@ __device__ __forceinline__ void child_bounds(T mn, T mx, double e, double& lo, d
     }
 }
 
-template <typename T, int MM>
+// Where one unit of k_sub / k_rederive lives (all fields wave-uniform).
+struct SubCtx {
+    int bi, j, t, kind, p0, np, S, TE, pslot, cur, r;
+    int64_t toff;
+    double pprev;
+    uint32_t stamp;
+};
+
+// Resolves unit u: the problem (hint only moves forward, since a block's
+// units increase), the parent and tile, and the child flags seen so far.
+__device__ __forceinline__ void resolve_unit(const DevInst* __restrict__ insts, int n,
+                                             const long long* __restrict__ pre,
+                                             const StepInfo* __restrict__ info, long long u,
+                                             int& hint, SubCtx& c)
+{
+    if (pre[hint + 1] <= u) {
+        int lo = hint + 1, hi = n;  // pre[lo] <= u < pre[hi]
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (pre[mid] <= u) lo = mid; else hi = mid;
+        }
+        hint = lo;
+    }
+    hint = __builtin_amdgcn_readfirstlane(hint);
+    const DevInst& I = insts[hint];
+    const StepInfo si = info[hint];
+    c.bi = hint;
+    unit_of(u - pre[hint], si.K, I.T, c.j, c.t);
+    c.cur = si.cur;
+    c.r = si.r;
+    c.pprev = si.p_up;
+    c.stamp = si.stamp;
+    c.pslot = __builtin_amdgcn_readfirstlane(I.live[c.j]);
+    c.kind = (c.t < I.tile_start[1]) ? 0 : ((c.t < I.tile_start[2]) ? 1 : 2);
+    c.p0 = (c.t - I.tile_start[c.kind]) * I.tile_polys[c.kind];
+    c.np = min(I.tile_polys[c.kind], I.count[c.kind] - c.p0);
+    c.S = I.S[c.kind];
+    c.TE = c.np * c.S;
+    c.toff = I.off[c.kind] + (int64_t)c.p0 * c.S;
+}
+
+// Thread 0 only: flags already OR-ed into the unit's children by other tiles.
+// The value is a hint (other tiles may set more flags later); it reaches the
+// other threads through LDS, so every wave of the block takes the same branch.
+__device__ __forceinline__ void load_hint(const DevInst& I, const SubCtx& c, uint32_t& fl, uint32_t& fr)
+{
+    fl = fr = 0;
+    if (threadIdx.x == 0 && c.kind != 0) {
+        fl = __hip_atomic_load(&I.flags[2 * c.j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        fr = __hip_atomic_load(&I.flags[2 * c.j + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+// Issues the global loads of a unit's parent tile into registers.
+template <typename T, int LB>
+__device__ __forceinline__ void issue_tile(const DevInst& I, const SubCtx& c, T (&v)[LB])
+{
+    const T* src = (const T*)I.buf[c.cur] + (int64_t)c.pslot * I.stride + c.toff;
+#pragma unroll
+    for (int q = 0; q < LB; ++q) {
+        const int e = threadIdx.x + q * SUB_THREADS;
+        if (e < c.TE) v[q] = src[e];
+    }
+}
+
+// k_sub: one unit = (parent, tile) per workgroup, software-pipelined: the next
+// unit's tile is in flight in registers while the current one is split in LDS.
+template <typename T, int MM, int LB>
 __global__ __launch_bounds__(SUB_THREADS) void k_sub(const DevInst* __restrict__ insts, int n_inst,
-                                                    const long long* __restrict__ plan)
+                                                    const long long* __restrict__ plan,
+                                                    const StepInfo* __restrict__ info)
 {
     typedef typename KeyOf<T>::type K;
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ uint32_t s_flag[2];
     __shared__ int s_dead[2];
-    __shared__ double s_cost[4];
 
-    // units of this launch: every running problem of this class contributes K * T
     const bool fp32 = sizeof(T) == 4;
     const long long* pre = plan + (fp32 ? 1 : 0) * (n_inst + 1);
     const long long total = pre[n_inst];
+    long long u = blockIdx.x;
+    if (u >= total) return;
+    int hint = 0;
+    SubCtx c, nc;
+    T v[LB];
+    uint32_t hfl, hfr;   // thread 0: flag hints of the current unit's children
+    resolve_unit(insts, n_inst, pre, info, u, hint, c);
+    issue_tile<T, LB>(insts[c.bi], c, v);
+    load_hint(insts[c.bi], c, hfl, hfr);
 
-    for (long long u = blockIdx.x; u < total; u += gridDim.x) {
-        const int bi = find_inst(pre, n_inst, u);
-        const DevInst& I = insts[bi];
-        const InstState* st = I.st;
-        const long long local = u - pre[bi];
-        const int j = (int)(local / I.T);
-        const int t = (int)(local - (long long)j * I.T);
-        const int cur = st->cur, r = st->r, l = I.l;
-        const double pprev = st->p_up;
-        const int pslot = I.live[j];
-        const T* parent = (const T*)I.buf[cur] + (int64_t)pslot * I.stride;
+    for (;;) {
+        const DevInst& I = insts[c.bi];
+        const int j = c.j, l = I.l, kind = c.kind, np = c.np, S = c.S, TE = c.TE;
+        const int cur = c.cur, r = c.r, pslot = c.pslot;
+        const int64_t toff = c.toff;
         T* childL = (T*)I.buf[cur ^ 1] + (int64_t)(2 * j) * I.stride;
         T* childR = childL + I.stride;
-        const int kind = (t < I.tile_start[1]) ? 0 : ((t < I.tile_start[2]) ? 1 : 2);
-        const int p0 = (t - I.tile_start[kind]) * I.tile_polys[kind];
-        const int np = min(I.tile_polys[kind], I.count[kind] - p0);
-        const int S = I.S[kind];
 
-        // LDS carve-up: a | b | keys
-        int TEmax = 0;
-        {
-            // the host sizes LDS for the largest tile over the launch; recompute
-            // this unit's layout from its own tile (cost tile may be larger)
-            TEmax = max(np * S, I.S[0]);
-        }
         SubLds<T> L;
         L.a = (T*)smem;
-        L.b = L.a + TEmax;
-        L.key = (K*)(L.b + TEmax);
-
-        if (threadIdx.x < 2) s_flag[threadIdx.x] = 0;
-        if (threadIdx.x == 0) { s_dead[0] = 0; s_dead[1] = 0; }
-
-        // ---- stale-estimate filter: cost lower bounds of both children ----
-        const bool need_cost = (kind == 0) || (I.stale && pprev < INFINITY);
-        double minPL = 0, minPR = 0;
-        if (need_cost) {
-            FibreGeom gc = fibre_geom(I.dims[0], l, r, I.S[0]);
-            split_tile_lds<T, MM>(parent + I.off[0], 1, I.S[0], gc, L);
-            if (threadIdx.x == 0) {
-                double e = 0.0;
-                if (fp32) {
-                    const float ep = I.err[cur][(int64_t)pslot * I.n_polys];
-                    e = (double)round_up_f((double)ep + gamma32(gc.m) * (double)funkey(L.key[4]) +
-                                           (double)gc.m * 0x1p-126);
-                    if (kind == 0) {
-                        I.err[cur ^ 1][(int64_t)(2 * j) * I.n_polys] = (float)e;
-                        I.err[cur ^ 1][(int64_t)(2 * j + 1) * I.n_polys] = (float)e;
+        L.b = L.a + TE;
+        L.key = (K*)(L.b + TE);
+        // children already condemned by other tiles (infeasible), or, with the
+        // stale filter, whose cost bound exceeds the previous solution estimate
+        if (threadIdx.x == 0) {
+            int dl = (hfl & F_INFEAS) != 0, dr = (hfr & F_INFEAS) != 0;
+            if (kind != 0 && I.stale && c.pprev < INFINITY) {
+                for (int q = 0; q < 2; ++q) {
+                    const int ch = 2 * j + q;
+                    if (__hip_atomic_load(&I.stamp[ch], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == c.stamp &&
+                        __hip_atomic_load(&I.minP[ch], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) > c.pprev) {
+                        if (q) dr = 1; else dl = 1;
                     }
                 }
-                double lo, hi;
-                child_bounds<T>(funkey(L.key[0]), funkey(L.key[1]), e, lo, hi);
-                s_cost[0] = lo; s_cost[1] = hi;
-                child_bounds<T>(funkey(L.key[2]), funkey(L.key[3]), e, lo, hi);
-                s_cost[2] = lo; s_cost[3] = hi;
-                s_dead[0] = s_cost[0] > pprev;
-                s_dead[1] = s_cost[2] > pprev;
+            }
+            s_dead[0] = dl;
+            s_dead[1] = dr;
+            s_flag[0] = 0;
+            s_flag[1] = 0;
+        }
+        // current tile: registers -> LDS
+#pragma unroll
+        for (int q = 0; q < LB; ++q) {
+            const int e = threadIdx.x + q * SUB_THREADS;
+            if (e < TE) L.a[e] = v[q];
+        }
+        for (int p = threadIdx.x; p < np; p += blockDim.x) {
+            L.key[5 * p + 0] = ~(K)0;
+            L.key[5 * p + 1] = 0;
+            L.key[5 * p + 2] = ~(K)0;
+            L.key[5 * p + 3] = 0;
+            L.key[5 * p + 4] = 0;
+        }
+        const double pprev = c.pprev;
+        const uint32_t stamp = c.stamp;
+        // next unit: resolve it and put its tile in flight
+        const long long un = u + gridDim.x;
+        const bool more = un < total;
+        if (more) {
+            resolve_unit(insts, n_inst, pre, info, un, hint, nc);
+            issue_tile<T, LB>(insts[nc.bi], nc, v);
+            load_hint(insts[nc.bi], nc, hfl, hfr);
+        }
+        lds_barrier();
+        // block-uniform: every wave reads the same LDS words after the barrier
+        const bool deadL = s_dead[0] != 0, deadR = s_dead[1] != 0;
+        if (!(deadL && deadR)) {
+            FibreGeom g = fibre_geom(I.dims[kind], l, r, S);
+            tile_split<T, MM>(np, S, g, L);
+            lds_barrier();
+
+            // per-patch bounds (widened in FP32 mode) -> records or flags of both children
+            uint32_t fL = 0, fR = 0;
+            for (int p = threadIdx.x; p < np; p += blockDim.x) {
+                const int poly = (kind == 0) ? 0 : I.count[0] + (kind == 2 ? I.count[1] : 0) + c.p0 + p;
+                double e = 0.0;
+                if (fp32) {
+                    const float ep = I.err[cur][(int64_t)pslot * I.n_polys + poly];
+                    e = (double)round_up_f((double)ep + gamma32(g.m) * (double)funkey(L.key[5 * p + 4]) +
+                                           (double)g.m * 0x1p-126);
+                    I.err[cur ^ 1][(int64_t)(2 * j) * I.n_polys + poly] = (float)e;
+                    I.err[cur ^ 1][(int64_t)(2 * j + 1) * I.n_polys + poly] = (float)e;
+                }
+                double lo[2], hi[2];
+                for (int ch = 0; ch < 2; ++ch)
+                    child_bounds<T>(funkey(L.key[5 * p + 2 * ch]), funkey(L.key[5 * p + 2 * ch + 1]), e,
+                                    lo[ch], hi[ch]);
                 if (kind == 0) {
-                    I.minP[2 * j] = s_cost[0];
-                    I.maxP[2 * j] = s_cost[1];
-                    I.minP[2 * j + 1] = s_cost[2];
-                    I.maxP[2 * j + 1] = s_cost[3];
-                    // child ids: index along r doubles, plus 1 for the right half
+                    // cost records, child ids, then the stamp that publishes the records
+                    I.minP[2 * j] = lo[0];
+                    I.maxP[2 * j] = hi[0];
+                    I.minP[2 * j + 1] = lo[1];
+                    I.maxP[2 * j + 1] = hi[1];
                     const uint32_t* pid = I.ids[cur] + (int64_t)pslot * l;
                     uint32_t* cid = I.ids[cur ^ 1] + (int64_t)(2 * j) * l;
                     for (int k = 0; k < l; ++k) {
-                        const uint32_t v = pid[k];
-                        cid[k] = (k == r) ? 2u * v : v;
-                        cid[l + k] = (k == r) ? 2u * v + 1u : v;
+                        const uint32_t vv = pid[k];
+                        cid[k] = (k == r) ? 2u * vv : vv;
+                        cid[l + k] = (k == r) ? 2u * vv + 1u : vv;
+                    }
+                    if (I.stale) {
+                        __hip_atomic_store(&I.stamp[2 * j], stamp, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                        __hip_atomic_store(&I.stamp[2 * j + 1], stamp, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                    }
+                    s_dead[0] = I.stale && lo[0] > pprev;
+                    s_dead[1] = I.stale && lo[1] > pprev;
+                } else {
+                    for (int ch = 0; ch < 2; ++ch) {
+                        uint32_t f = 0;
+                        if (kind == 1) {
+                            if (lo[ch] > 0.0) f |= F_INFEAS;
+                            if (!(hi[ch] <= 0.0)) f |= F_NOTFEAS;
+                        } else {
+                            if (lo[ch] > 0.0 || hi[ch] < 0.0) f |= F_INFEAS;
+                            if (!(-I.eps_eq <= lo[ch] && lo[ch] <= 0.0 && 0.0 <= hi[ch] && hi[ch] <= I.eps_eq))
+                                f |= F_NOTFEAS;
+                        }
+                        if (ch == 0) fL |= f; else fR |= f;
                     }
                 }
             }
-            __syncthreads();
-            minPL = s_cost[0];
-            minPR = s_cost[2];
-            (void)minPL; (void)minPR;
-            if (kind == 0) {
-                // write the cost children unless already known suboptimal
-                const int TE = I.S[0];
-                const bool wl = !s_dead[0], wr = !s_dead[1];
-                for (int e = threadIdx.x; e < TE; e += blockDim.x) {
-                    if (wl) childL[I.off[0] + e] = L.a[e];
-                    if (wr) childR[I.off[0] + e] = L.b[e];
+            if (fL) atomicOr(&s_flag[0], fL);
+            if (fR) atomicOr(&s_flag[1], fR);
+            lds_barrier();
+            if (threadIdx.x == 0) {
+                if (s_flag[0]) atomicOr(&I.flags[2 * j], s_flag[0]);
+                if (s_flag[1]) atomicOr(&I.flags[2 * j + 1], s_flag[1]);
+            }
+            // children patches (skipped when the child is already known dead)
+            const bool wl = !deadL && !s_dead[0] && !(s_flag[0] & F_INFEAS);
+            const bool wr = !deadR && !s_dead[1] && !(s_flag[1] & F_INFEAS);
+            constexpr int SB = 8;
+            for (int e0 = threadIdx.x; e0 < TE; e0 += SB * SUB_THREADS) {
+                T va[SB], vb[SB];
+#pragma unroll
+                for (int q = 0; q < SB; ++q) {
+                    const int e = e0 + q * SUB_THREADS;
+                    if (e < TE) { va[q] = L.a[e]; vb[q] = L.b[e]; }
                 }
-                __syncthreads();
-                continue;
-            }
-        }
-        // skip children another tile already found infeasible
-        if (threadIdx.x == 0) {
-            const uint32_t fl = __atomic_load_n(&I.flags[2 * j], __ATOMIC_RELAXED);
-            const uint32_t fr = __atomic_load_n(&I.flags[2 * j + 1], __ATOMIC_RELAXED);
-            if (fl & F_INFEAS) s_dead[0] = 1;
-            if (fr & F_INFEAS) s_dead[1] = 1;
-        }
-        __syncthreads();
-        const bool deadL = s_dead[0], deadR = s_dead[1];
-        __syncthreads();
-        if (deadL && deadR) continue;
-
-        // ---- the tile of constraint patches ----
-        FibreGeom g = fibre_geom(I.dims[kind], l, r, S);
-        const int64_t toff = I.off[kind] + (int64_t)p0 * S;
-        split_tile_lds<T, MM>(parent + toff, np, S, g, L);
-
-        // per-patch bounds -> feasibility flags of both children
-        uint32_t fL = 0, fR = 0;
-        for (int p = threadIdx.x; p < np; p += blockDim.x) {
-            const int poly = I.count[0] + (kind == 2 ? I.count[1] : 0) + p0 + p;
-            double e = 0.0;
-            if (fp32) {
-                const float ep = I.err[cur][(int64_t)pslot * I.n_polys + poly];
-                e = (double)round_up_f((double)ep + gamma32(g.m) * (double)funkey(L.key[5 * p + 4]) +
-                                       (double)g.m * 0x1p-126);
-                I.err[cur ^ 1][(int64_t)(2 * j) * I.n_polys + poly] = (float)e;
-                I.err[cur ^ 1][(int64_t)(2 * j + 1) * I.n_polys + poly] = (float)e;
-            }
-            for (int c = 0; c < 2; ++c) {
-                double lo, hi;
-                child_bounds<T>(funkey(L.key[5 * p + 2 * c]), funkey(L.key[5 * p + 2 * c + 1]), e, lo, hi);
-                uint32_t f = 0;
-                if (kind == 1) {
-                    if (lo > 0.0) f |= F_INFEAS;
-                    if (!(hi <= 0.0)) f |= F_NOTFEAS;
-                } else {
-                    if (lo > 0.0 || hi < 0.0) f |= F_INFEAS;
-                    if (!(-I.eps_eq <= lo && lo <= 0.0 && 0.0 <= hi && hi <= I.eps_eq)) f |= F_NOTFEAS;
+#pragma unroll
+                for (int q = 0; q < SB; ++q) {
+                    const int e = e0 + q * SUB_THREADS;
+                    if (e < TE) {
+                        if (wl) childL[toff + e] = va[q];
+                        if (wr) childR[toff + e] = vb[q];
+                    }
                 }
-                if (c == 0) fL |= f; else fR |= f;
             }
+            lds_barrier();
+        } else {
+            lds_barrier();   // s_dead is read above before the next unit rewrites it
         }
-        if (fL) atomicOr(&s_flag[0], fL);
-        if (fR) atomicOr(&s_flag[1], fR);
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            if (s_flag[0]) atomicOr(&I.flags[2 * j], s_flag[0]);
-            if (s_flag[1]) atomicOr(&I.flags[2 * j + 1], s_flag[1]);
-        }
-        // children patches (skipped when the child is already known dead)
-        const bool wl = !deadL && !(s_flag[0] & F_INFEAS);
-        const bool wr = !deadR && !(s_flag[1] & F_INFEAS);
-        const int TE = np * S;
-        for (int e = threadIdx.x; e < TE; e += blockDim.x) {
-            if (wl) childL[toff + e] = L.a[e];
-            if (wr) childR[toff + e] = L.b[e];
-        }
-        __syncthreads();
+        if (!more) break;
+        c = nc;
+        u = un;
     }
 }
 
 // ------------------------------------------------------------------ k_rederive
 
-// Bernstein sub-interval transform on [a,b] inside [0,1] for degree n:
-// T[k][j] = sum_s b^{n-k}_s(a) b^k_{j-s}(b) (the polar form of b^n_j at
-// (a,..,a, b,..,b)), rows non-negative and summing to one.
-__device__ double bern_basis(int n, int i, double t)
+// Bernstein sub-interval transform on [a,b] inside [0,1] for degree n = m-1:
+// T[k][j] = sum_s b^{n-k}_s(a) b^k_{j-s}(b), the polar form of the basis
+// polynomial b^n_j at (a,..,a, b,..,b) (n-k copies of a, k of b); rows are
+// non-negative and sum to one.  The basis values come from the recurrence
+// b^q_s(t) = (1-t) b^{q-1}_s(t) + t b^{q-1}_{s-1}(t) (all terms non-negative,
+// so each table entry carries a relative error below gamma_{2q}); with the
+// products and the sum, |T~ - T| <= gamma_{5m} T entrywise.
+// tab holds 2*m*m doubles of scratch; all threads call it.
+__device__ void build_tmat(double* __restrict__ tm, double* __restrict__ tab, int m, double a, double b)
 {
-    double c = 1.0;
-    for (int q = 1; q <= i; ++q) c = c * (double)(n - i + q) / (double)q;
-    double v = c;
-    for (int q = 0; q < i; ++q) v *= t;
-    for (int q = 0; q < n - i; ++q) v *= (1.0 - t);
-    return v;
-}
-__device__ double tmat_entry(int n, int k, int j, double a, double b)
-{
-    double s = 0.0;
-    const int s0 = max(0, j - k), s1 = min(n - k, j);
-    for (int q = s0; q <= s1; ++q) s += bern_basis(n - k, q, a) * bern_basis(k, j - q, b);
-    return s;
+    const int n = m - 1;
+    double* Ba = tab;
+    double* Bb = tab + m * m;
+    if (threadIdx.x < 2) {
+        double* B = threadIdx.x ? Bb : Ba;
+        const double t = threadIdx.x ? b : a;
+        B[0] = 1.0;
+        for (int q = 1; q <= n; ++q) {
+            B[q * m + q] = t * B[(q - 1) * m + (q - 1)];
+            for (int s = q - 1; s >= 1; --s)
+                B[q * m + s] = (1.0 - t) * B[(q - 1) * m + s] + t * B[(q - 1) * m + (s - 1)];
+            B[q * m + 0] = (1.0 - t) * B[(q - 1) * m + 0];
+        }
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < m * m; e += blockDim.x) {
+        const int k = e / m, j = e - k * m;
+        const int s0 = max(0, j - k), s1 = min(n - k, j);
+        double acc = 0.0;
+        for (int q = s0; q <= s1; ++q) acc += Ba[(n - k) * m + q] * Bb[k * m + (j - q)];
+        tm[e] = acc;
+    }
+    __syncthreads();
 }
 
 // Applies tmat (one m x m matrix per axis) to a patch in LDS (FP64), axis by
@@ -568,11 +764,76 @@ __device__ void apply_tmats(double* x, double* y, const double* tm, const int* t
     }
 }
 
-// FP32 re-derivation step: children of every live parent derived from the
-// FP64 root by box id, rounded to FP32 with a fresh error bound, then bounded
-// and flagged exactly like k_sub.
+// Sub-interval transforms of every child of every parent whose step re-derives
+// from the root: one thread per matrix row.  Row k of the transform for [a,b]
+// and degree n is T[k][j] = sum_s b^{n-k}_s(a) b^k_{j-s}(b); both basis rows come
+// from the recurrence b^q_s(t) = (1-t) b^{q-1}_s(t) + t b^{q-1}_{s-1}(t), whose
+// terms are all non-negative (relative error below gamma_{2q} per value), so
+// |T~ - T| <= gamma_{5m} T entrywise.
+__global__ __launch_bounds__(256) void k_tmat(const DevInst* __restrict__ insts, int n_inst,
+                                             const long long* __restrict__ plan)
+{
+    const long long* pre = plan + 3 * (n_inst + 1);
+    const long long total = pre[n_inst];
+    for (long long u = blockIdx.x * (long long)blockDim.x + threadIdx.x; u < total;
+         u += (long long)gridDim.x * blockDim.x) {
+        const int bi = find_inst(pre, n_inst, u);
+        const DevInst& I = insts[bi];
+        const InstState* st = I.st;
+        const long long v = u - pre[bi];
+        const int j = (int)(v / (2 * I.rows));
+        int rem = (int)(v - (long long)j * 2 * I.rows);
+        const int c = rem / I.rows;
+        rem -= c * I.rows;
+        // locate (kind, axis, row) of this thread
+        int kind = 0, k = 0, off = I.tmk[0];
+        for (;;) {
+            if (I.count[kind] == 0) { ++kind; k = 0; off = I.tmk[min(kind, KINDS - 1)]; continue; }
+            const int m = I.dims[kind][k];
+            if (rem < m) break;
+            rem -= m;
+            off += m * m;
+            if (++k == I.l) { ++kind; k = 0; off = I.tmk[min(kind, KINDS - 1)]; }
+        }
+        const int m = I.dims[kind][k], n = m - 1, row = rem;
+        const int r = st->r, cur = st->cur;
+        const uint32_t pid = I.ids[cur][(int64_t)I.live[j] * I.l + k];
+        const int d = st->depth[k] + (k == r ? 1 : 0);
+        const uint32_t idx = (k == r) ? 2u * pid + (uint32_t)c : pid;
+        const double a = ldexp((double)idx, -d), b = ldexp((double)idx + 1.0, -d);
+        double Ba[MAXM], Bb[MAXM];
+#pragma unroll
+        for (int q = 0; q < MAXM; ++q) { Ba[q] = (q == 0) ? 1.0 : 0.0; Bb[q] = Ba[q]; }
+#pragma unroll
+        for (int q = 1; q < MAXM; ++q) {
+#pragma unroll
+            for (int s2 = MAXM - 1; s2 >= 1; --s2) {
+                if (s2 <= q && q <= n - row) Ba[s2] = (1.0 - a) * Ba[s2] + a * Ba[s2 - 1];
+                if (s2 <= q && q <= row) Bb[s2] = (1.0 - b) * Bb[s2] + b * Bb[s2 - 1];
+            }
+            if (q <= n - row) Ba[0] = (1.0 - a) * Ba[0];
+            if (q <= row) Bb[0] = (1.0 - b) * Bb[0];
+        }
+        double* out = I.tmat + ((int64_t)j * 2 + c) * I.tmw + off + row * m;
+#pragma unroll
+        for (int jj = 0; jj < MAXM; ++jj) {
+            if (jj > n) break;
+            double acc = 0.0;
+#pragma unroll
+            for (int s2 = 0; s2 < MAXM; ++s2)
+                if (s2 <= n - row && jj - s2 >= 0 && jj - s2 <= row) acc += Ba[s2] * Bb[(jj - s2) & (MAXM - 1)];
+            out[jj] = acc;
+        }
+    }
+}
+
+// FP32 re-derivation step: the children of every live parent derived from the
+// FP64 root by box id (the transforms of k_tmat applied axis by axis in FP64),
+// rounded to FP32 with a fresh error bound, then bounded and flagged like
+// k_sub.  Units and their order are those of k_sub.
 __global__ __launch_bounds__(SUB_THREADS) void k_rederive(const DevInst* __restrict__ insts, int n_inst,
-                                                         const long long* __restrict__ plan)
+                                                         const long long* __restrict__ plan,
+                                                         const StepInfo* __restrict__ info)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ uint32_t s_flag[2];
@@ -580,51 +841,47 @@ __global__ __launch_bounds__(SUB_THREADS) void k_rederive(const DevInst* __restr
     const long long* pre = plan + 2 * (n_inst + 1);
     const long long total = pre[n_inst];
     for (long long u = blockIdx.x; u < total; u += gridDim.x) {
-        const int bi = find_inst(pre, n_inst, u);
+        const int bi = find_inst_uniform(pre, n_inst, u);
         const DevInst& I = insts[bi];
-        const InstState* st = I.st;
-        const long long local = u - pre[bi];
-        const int j = (int)(local / I.T);
-        const int t = (int)(local - (long long)j * I.T);
-        const int cur = st->cur, r = st->r, l = I.l;
-        const int pslot = I.live[j];
-        const uint32_t* pid = I.ids[cur] + (int64_t)pslot * l;
+        const StepInfo si = info[bi];
+        int j, t;
+        unit_of(u - pre[bi], si.K, I.T, j, t);
+        const int cur = si.cur, r = si.r, l = I.l;
+        const int pslot = __builtin_amdgcn_readfirstlane(I.live[j]);
         const int kind = (t < I.tile_start[1]) ? 0 : ((t < I.tile_start[2]) ? 1 : 2);
         const int p0 = (t - I.tile_start[kind]) * I.tile_polys[kind];
         const int np = min(I.tile_polys[kind], I.count[kind] - p0);
         const int S = I.S[kind];
-        const int TE = np * S;
-        const int64_t toff = I.off[kind] + (int64_t)p0 * S;
-
-        // LDS: x | y (TE doubles each) | tmats (l * m^2 doubles)
+        // the tile is processed in chunks of at most MAX_TILE64 coefficients
+        const int cp = max(1, MAX_TILE64 / S);
+        int tmsz = 0;
+        for (int k = 0; k < l; ++k) tmsz += I.dims[kind][k] * I.dims[kind][k];
         double* x = (double*)smem;
-        double* y = x + TE;
-        double* tm = y + TE;
+        double* y = x + min(np, cp) * S;
+        double* tm = y + min(np, cp) * S;
+        if (threadIdx.x < 2) s_flag[threadIdx.x] = 0;
         if (threadIdx.x == 0) {
             int o = 0;
             for (int k = 0; k < l; ++k) { s_tmoff[k] = o; o += I.dims[kind][k] * I.dims[kind][k]; }
         }
-        if (threadIdx.x < 2) s_flag[threadIdx.x] = 0;
-        __syncthreads();
-        for (int c = 0; c < 2; ++c) {
-            // child box: depth after this step, index with the new bit along r
-            for (int k = 0; k < l; ++k) {
-                const int m = I.dims[kind][k];
-                const int d = st->depth[k] + (k == r ? 1 : 0);
-                const uint32_t idx = (k == r) ? 2u * pid[k] + (uint32_t)c : pid[k];
-                const double a = ldexp((double)idx, -d), bb = ldexp((double)idx + 1.0, -d);
-                for (int e = threadIdx.x; e < m * m; e += blockDim.x)
-                    tm[s_tmoff[k] + e] = tmat_entry(m - 1, e / m, e % m, a, bb);
-            }
-            for (int e = threadIdx.x; e < TE; e += blockDim.x) x[e] = I.root[toff + e];
+        double g64 = 0.0;
+        for (int k = 0; k < l; ++k) g64 += gamma64(6 * I.dims[kind][k] + 6);
+        for (int cc = 0; cc < 2 * ((np + cp - 1) / cp); ++cc) {
+            const int c = cc & 1;
+            const int q0 = (cc >> 1) * cp;
+            const int nq = min(cp, np - q0);
+            const int TE = nq * S;
+            const int64_t toff = I.off[kind] + (int64_t)(p0 + q0) * S;
+            const double* tsrc = I.tmat + ((int64_t)j * 2 + c) * I.tmw + I.tmk[kind];
+            copy_to_lds<double>(tm, tsrc, tmsz);
+            copy_to_lds<double>(x, I.root + toff, TE);
             __syncthreads();
-            apply_tmats(x, y, tm, s_tmoff, I.dims[kind], l, S, np);
-            // per patch: FP64 bound, round to FP32, min/max of the FP32 values
+            apply_tmats(x, y, tm, s_tmoff, I.dims[kind], l, S, nq);
             float* child = (float*)I.buf[cur ^ 1] + (int64_t)(2 * j + c) * I.stride;
             uint32_t fl = 0;
             const int wv = threadIdx.x >> 6;
-            for (int p = wv; p < np; p += blockDim.x >> 6) {
-                const int poly = (kind == 0 ? 0 : I.count[0] + (kind == 2 ? I.count[1] : 0) + p0 + p);
+            for (int p = wv; p < nq; p += blockDim.x >> 6) {
+                const int poly = (kind == 0 ? 0 : I.count[0] + (kind == 2 ? I.count[1] : 0) + p0 + q0 + p);
                 const double* rp = I.root + toff + (int64_t)p * S;
                 float mn = INFINITY, mx = -INFINITY;
                 double rmax = 0.0;
@@ -641,8 +898,8 @@ __global__ __launch_bounds__(SUB_THREADS) void k_rederive(const DevInst* __restr
                     rmax = fmax(rmax, __shfl_xor(rmax, o, 64));
                 }
                 if ((threadIdx.x & 63) == 0) {
-                    double g64 = 0.0;
-                    for (int k = 0; k < l; ++k) g64 += gamma64(4 * I.dims[kind][k] + 6);
+                    // root bound (rows of T sum to one) + transform rounding on
+                    // |T||root| <= max|root| + rounding to FP32 + underflow
                     const double amax = fmax(fabs((double)mn), fabs((double)mx));
                     const double e = (double)round_up_f(I.root_err[poly] + g64 * rmax * 1.01 +
                                                         amax * 0x1p-23 + 0x1p-126);
@@ -657,7 +914,8 @@ __global__ __launch_bounds__(SUB_THREADS) void k_rederive(const DevInst* __restr
                         if (!(hi <= 0.0)) fl |= F_NOTFEAS;
                     } else {
                         if (lo > 0.0 || hi < 0.0) fl |= F_INFEAS;
-                        if (!(-I.eps_eq <= lo && lo <= 0.0 && 0.0 <= hi && hi <= I.eps_eq)) fl |= F_NOTFEAS;
+                        if (!(-I.eps_eq <= lo && lo <= 0.0 && 0.0 <= hi && hi <= I.eps_eq))
+                            fl |= F_NOTFEAS;
                     }
                 }
             }
@@ -668,6 +926,7 @@ __global__ __launch_bounds__(SUB_THREADS) void k_rederive(const DevInst* __restr
             if (s_flag[0]) atomicOr(&I.flags[2 * j], s_flag[0]);
             if (s_flag[1]) atomicOr(&I.flags[2 * j + 1], s_flag[1]);
             if (kind == 0) {
+                const uint32_t* pid = I.ids[cur] + (int64_t)pslot * l;
                 uint32_t* cid = I.ids[cur ^ 1] + (int64_t)(2 * j) * l;
                 for (int k = 0; k < l; ++k) {
                     const uint32_t v = pid[k];
@@ -793,41 +1052,42 @@ __global__ __launch_bounds__(CUT_THREADS) void k_cut(const DevInst* __restrict__
 
 // ------------------------------------------------------------------ certification
 
-// One workgroup per polynomial: FP64 patch of x* from the root with the
-// sub-interval transforms, its min / max and a rigorous error bound
-// (|T~ - T| <= gamma_{3m+5} T entrywise, one more gamma_m per product,
-// plus the root's own bound; all values taken as |T| |x| sums).
-__global__ __launch_bounds__(256) void k_certify(DevInst I)
+// One workgroup per (problem, polynomial): FP64 patch of x* from the root with
+// the sub-interval transforms, its min / max and a rigorous error bound: the
+// root's own bound (rows of T sum to one) plus, per axis, gamma_{6m+6} times the
+// |T| |x| chain (transform entries within gamma_{5m} relative, one product more).
+__global__ __launch_bounds__(256) void k_certify(const DevInst* __restrict__ insts, int n,
+                                                const int* __restrict__ pre)
 {
     extern __shared__ double shc[];
+    __shared__ int tmoff[MAXL];
+    __shared__ double red[3 * 4];
+    const int bi = find_block(pre, n, blockIdx.x);
+    const DevInst& I = insts[bi];
     const InstState* st = I.st;
     if (!st->has_x) return;
-    const int poly = blockIdx.x;
-    int kind = 0, idx = poly;
-    if (idx >= I.count[0]) { idx -= I.count[0]; kind = 1; if (idx >= I.count[1]) { idx -= I.count[1]; kind = 2; } }
+    const int poly = blockIdx.x - pre[bi];
+    int kind, idx;
+    poly_kind(I, poly, kind, idx);
     const int S = I.S[kind], l = I.l;
+    int mm = 1;
+    for (int k = 0; k < l; ++k) mm = max(mm, I.dims[kind][k]);
     double* x = shc;
     double* y = x + S;
     double* tm = y + S;
-    __shared__ int tmoff[MAXL];
-    __shared__ double red[3 * 4];
+    double* tab = tm + l * mm * mm;
     if (threadIdx.x == 0) {
         int o = 0;
         for (int k = 0; k < l; ++k) { tmoff[k] = o; o += I.dims[kind][k] * I.dims[kind][k]; }
     }
     __syncthreads();
-    for (int k = 0; k < l; ++k) {
-        const int m = I.dims[kind][k];
-        const double a = ldexp((double)st->x_index[k], -st->x_depth[k]);
-        const double b = ldexp((double)st->x_index[k] + 1.0, -st->x_depth[k]);
-        for (int e = threadIdx.x; e < m * m; e += blockDim.x)
-            tm[tmoff[k] + e] = tmat_entry(m - 1, e / m, e % m, a, b);
-    }
+    for (int k = 0; k < l; ++k)
+        build_tmat(tm + tmoff[k], tab, I.dims[kind][k], ldexp((double)st->x_index[k], -st->x_depth[k]),
+                   ldexp((double)st->x_index[k] + 1.0, -st->x_depth[k]));
     const double* rp = I.root + I.off[kind] + (int64_t)idx * S;
     double gsum = 0.0;
-    for (int r = 0; r < l; ++r) gsum += gamma64(4 * I.dims[kind][r] + 6);
+    for (int r = 0; r < l; ++r) gsum += gamma64(6 * I.dims[kind][r] + 6);
     double mn = INFINITY, mx = -INFINITY, am = 0.0;
-    // pass 0: the patch of x*; pass 1: |T| applied to |root|, which bounds the error
     for (int absp = 0; absp < 2; ++absp) {
         for (int e = threadIdx.x; e < S; e += blockDim.x) x[e] = absp ? fabs(rp[e]) : rp[e];
         __syncthreads();
@@ -852,34 +1112,48 @@ __global__ __launch_bounds__(256) void k_certify(DevInst I)
             mx = fmax(mx, red[3 * q + 1]);
             am = fmax(am, red[3 * q + 2]);
         }
-        // e <= root bound (rows of T sum to one) + sum over axes of gamma * |T||x|
-        const double e = I.root_err[poly] + gsum * am * 1.01;
         I.cert[3 * poly + 0] = mn;
         I.cert[3 * poly + 1] = mx;
-        I.cert[3 * poly + 2] = e;
+        I.cert[3 * poly + 2] = I.root_err[poly] + gsum * am * 1.01;
     }
 }
 
-__global__ void k_certify_final(DevInst I)
+// One workgroup per problem: every g_i certified <= 0, every h_j inside the
+// band, p_cert = max B_p + e rounded up.
+__global__ __launch_bounds__(256) void k_certify_final(const DevInst* __restrict__ insts, int n)
 {
+    __shared__ int s_bad;
+    __shared__ double s_e[4];
+    const DevInst& I = insts[blockIdx.x];
     InstState* st = I.st;
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    if (!st->has_x) { st->cert_ok = 0; st->p_cert = INFINITY; st->cert_err = 0.0; return; }
-    int ok = 1;
+    if (!st->has_x) {
+        if (threadIdx.x == 0) { st->cert_ok = 0; st->p_cert = INFINITY; st->cert_err = 0.0; }
+        return;
+    }
+    if (threadIdx.x == 0) s_bad = 0;
+    __syncthreads();
+    int bad = 0;
     double emax = 0.0;
-    for (int p = 0; p < I.n_polys; ++p) {
+    for (int p = threadIdx.x; p < I.n_polys; p += blockDim.x) {
         const double mn = I.cert[3 * p], mx = I.cert[3 * p + 1], e = I.cert[3 * p + 2];
         emax = fmax(emax, e);
         if (p < I.count[0]) continue;
         if (p < I.count[0] + I.count[1]) {
-            if (!(mx + e <= 0.0)) ok = 0;
-        } else {
-            if (!(-I.eps_eq <= mn - e && mn + e <= 0.0 && 0.0 <= mx - e && mx + e <= I.eps_eq)) ok = 0;
+            if (!(mx + e <= 0.0)) bad = 1;
+        } else if (!(-I.eps_eq <= mn - e && mn + e <= 0.0 && 0.0 <= mx - e && mx + e <= I.eps_eq)) {
+            bad = 1;
         }
     }
-    st->cert_ok = ok;
-    st->p_cert = nextafter(I.cert[1] + I.cert[2], INFINITY);
-    st->cert_err = emax;
+    if (bad) atomicOr(&s_bad, 1);
+    for (int o = 32; o > 0; o >>= 1) emax = fmax(emax, __shfl_xor(emax, o, 64));
+    if ((threadIdx.x & 63) == 0) s_e[threadIdx.x >> 6] = emax;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < (int)(blockDim.x >> 6); ++w) emax = fmax(emax, s_e[w]);
+        st->cert_ok = s_bad ? 0 : 1;
+        st->p_cert = nextafter(I.cert[1] + I.cert[2], INFINITY);
+        st->cert_err = emax;
+    }
 }
 
 // ------------------------------------------------------------------ list read-out
@@ -909,53 +1183,53 @@ __global__ void k_gather(const DevInst* __restrict__ insts, int n, InstState* __
 
 // ------------------------------------------------------------------ host launchers
 
-hipError_t launch_root(const DevInst& I, const double* mono, const double* mats, const int* matoff,
-                       double* root, double* root_err, int64_t W, int max_S, hipStream_t s)
+hipError_t launch_reset_root(const DevInst* d_insts, int n, const int* d_pre, int total_polys,
+                             int max_S, hipStream_t s)
 {
-    const size_t lds = 2 * (size_t)max_S * sizeof(double);
-    hipLaunchKernelGGL(k_root, dim3(I.n_polys), dim3(256), lds, s, I, mono, mats, matoff, root,
-                       root_err);
+    hipLaunchKernelGGL(k_reset, dim3((n + 63) / 64), dim3(64), 0, s, d_insts, n);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const int blocks = (int)std::min<int64_t>(1024, (W + 255) / 256);
-    if (I.fp32)
-        hipLaunchKernelGGL(k_root_item<float>, dim3(blocks), dim3(256), 0, s, I, W);
-    else
-        hipLaunchKernelGGL(k_root_item<double>, dim3(blocks), dim3(256), 0, s, I, W);
+    hipLaunchKernelGGL(k_root, dim3(total_polys), dim3(256), 2 * (size_t)max_S * sizeof(double), s,
+                       d_insts, n, d_pre);
     return hipGetLastError();
 }
 
-hipError_t launch_plan(const DevInst* d_insts, int n, long long* plan, hipStream_t s)
+hipError_t launch_plan(const DevInst* d_insts, int n, long long* plan, StepInfo* info, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_plan, dim3(1), dim3(1024), 0, s, d_insts, n, plan);
+    hipLaunchKernelGGL(k_plan, dim3(1), dim3(1024), 0, s, d_insts, n, plan, info);
     return hipGetLastError();
 }
 
 template <typename T, int MM>
-static hipError_t launch_sub_t(const DevInst* d_insts, int n, const long long* plan, int grid,
-                               size_t lds, hipStream_t s)
+static hipError_t launch_sub_t(const DevInst* d_insts, int n, const long long* plan,
+                               const StepInfo* info, int grid, size_t lds, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_sub<T, MM>), dim3(grid), dim3(SUB_THREADS), lds, s, d_insts, n, plan);
+    // registers per thread for a tile in flight: the largest tile / 256 lanes
+    constexpr int LB = (sizeof(T) == 8 ? MAX_TILE64 : MAX_TILE32) / SUB_THREADS;
+    hipLaunchKernelGGL((k_sub<T, MM, LB>), dim3(grid), dim3(SUB_THREADS), lds, s, d_insts, n, plan, info);
     return hipGetLastError();
 }
 
-hipError_t launch_sub(const DevInst* d_insts, int n, const long long* plan, bool fp32, int maxm,
-                      int grid, size_t lds, hipStream_t s)
+hipError_t launch_sub(const DevInst* d_insts, int n, const long long* plan, const StepInfo* info,
+                      bool fp32, int maxm, int grid, size_t lds, hipStream_t s)
 {
     if (grid <= 0) return hipSuccess;
     if (fp32) {
-        if (maxm <= 8) return launch_sub_t<float, 8>(d_insts, n, plan, grid, lds, s);
-        return launch_sub_t<float, 16>(d_insts, n, plan, grid, lds, s);
+        if (maxm <= 8) return launch_sub_t<float, 8>(d_insts, n, plan, info, grid, lds, s);
+        return launch_sub_t<float, 16>(d_insts, n, plan, info, grid, lds, s);
     }
-    if (maxm <= 8) return launch_sub_t<double, 8>(d_insts, n, plan, grid, lds, s);
-    return launch_sub_t<double, 16>(d_insts, n, plan, grid, lds, s);
+    if (maxm <= 8) return launch_sub_t<double, 8>(d_insts, n, plan, info, grid, lds, s);
+    return launch_sub_t<double, 16>(d_insts, n, plan, info, grid, lds, s);
 }
 
-hipError_t launch_rederive(const DevInst* d_insts, int n, const long long* plan, int grid,
-                           size_t lds, hipStream_t s)
+hipError_t launch_rederive(const DevInst* d_insts, int n, const long long* plan, const StepInfo* info,
+                           int grid, int tgrid, size_t lds, hipStream_t s)
 {
     if (grid <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_rederive, dim3(grid), dim3(SUB_THREADS), lds, s, d_insts, n, plan);
+    hipLaunchKernelGGL(k_tmat, dim3(tgrid), dim3(256), 0, s, d_insts, n, plan);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_rederive, dim3(grid), dim3(SUB_THREADS), lds, s, d_insts, n, plan, info);
     return hipGetLastError();
 }
 
@@ -971,13 +1245,14 @@ hipError_t launch_gather(const DevInst* d_insts, int n, InstState* out, hipStrea
     return hipGetLastError();
 }
 
-hipError_t launch_certify(const DevInst& I, int max_S, int max_m, hipStream_t s)
+hipError_t launch_certify(const DevInst* d_insts, int n, const int* d_pre, int total_polys,
+                          int max_S, int tm_words, hipStream_t s)
 {
-    const size_t lds = (2 * (size_t)max_S + (size_t)MAXL * max_m * max_m) * sizeof(double);
-    hipLaunchKernelGGL(k_certify, dim3(I.n_polys), dim3(256), lds, s, I);
+    const size_t lds = (2 * (size_t)max_S + (size_t)tm_words) * sizeof(double);
+    hipLaunchKernelGGL(k_certify, dim3(total_polys), dim3(256), lds, s, d_insts, n, d_pre);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_certify_final, dim3(1), dim3(64), 0, s, I);
+    hipLaunchKernelGGL(k_certify_final, dim3(n), dim3(256), 0, s, d_insts, n);
     return hipGetLastError();
 }
 

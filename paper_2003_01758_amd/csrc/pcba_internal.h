@@ -21,6 +21,8 @@ constexpr int MAXM = 16;      // longest fibre: degree 15 + 1
 constexpr int SUB_THREADS = 256;
 constexpr int CUT_THREADS = 1024;
 constexpr int MAX_BATCH = 2048;   // problems per launch
+constexpr int MAX_TILE64 = 3584;  // largest tile (coefficients) of an FP64 unit: 14 per lane
+constexpr int MAX_TILE32 = 7168;  // largest tile of an FP32 unit: 28 per lane
 
 // per-child feasibility flags (OR-ed by every tile of the child)
 enum : uint32_t {
@@ -55,9 +57,27 @@ struct InstState {
     int64_t peak;
     double p_cert, cert_err;
     double err_max;
+    uint32_t epoch;     // incremented by every reset: makes record stamps unique per solve
+    uint32_t pad1;
 };
 
+// What the step kernels need of a problem's state, published by the plan
+// kernel at the start of every step and read-only until the cut kernel.
+struct StepInfo {
+    int32_t K, cur, r, steps;
+    double p_up;
+    uint32_t stamp;
+    int32_t pad;
+};
+
+// stamp of the child records written in the current step of a problem
+__host__ __device__ inline uint32_t step_stamp(const InstState* st)
+{
+    return st->epoch * 65536u + (uint32_t)st->steps + 1u;
+}
+
 constexpr int MAX_TRACE = 512;   // PCBA_MAX_TRACE
+constexpr int MAX_STEPS = 60000; // steps per solve must stay below 65536 (record stamps)
 
 // One record per step, written by the cut kernel.
 struct TraceRec {
@@ -90,10 +110,18 @@ struct DevInst {
     double* minP;                  // child records, cap each
     double* maxP;
     uint32_t* flags;
-    const double* root;            // FP64 root patches (item layout, W doubles)
-    const double* root_err;        // FP64 error bound of each root patch
+    uint32_t* stamp;               // cap: step stamp of minP/maxP, set after they are written
+    double* tmat;                  // FP32 re-derivation: cap/2 parents x 2 children x tmw doubles
+    int32_t tmw;                   // transform words per child: sum over kinds and axes of m^2
+    int32_t tmk[KINDS];            // offset of each kind's transforms inside a child's block
+    int32_t rows;                  // transform rows per child: sum over kinds and axes of m
+    double* root;                  // FP64 root patches (item layout, W doubles)
+    double* root_err;              // FP64 error bound of each root patch
     double* cert;                  // certification scratch: n_polys * 3 doubles
     TraceRec* trace;               // MAX_TRACE step records
+    const double* mono;            // monomials, zero-padded, item layout (W doubles)
+    const double* mats;            // per kind and axis: pre-map A then conversion U (m x m each)
+    const int* matoff;             // KINDS * MAXL offsets into mats
     InstState* st;
 };
 

@@ -34,7 +34,7 @@ int fail(int code, const std::string& msg)
 
 constexpr int GRID_MAX = 2048;
 constexpr int STEPS_PER_SYNC = 8;
-constexpr int TILE_ELEMS = 2816;   // target coefficients per tile (per LDS region)
+constexpr int TILE_ELEMS = 2816;   // target coefficients per FP64 tile (per LDS region)
 constexpr int MAX_PATCH = 3584;    // largest patch (coefficients): LDS stays within 64 KB
 constexpr int CAP0 = 64;           // initial list capacity (items per buffer)
 
@@ -131,6 +131,9 @@ struct pcba_problem {
     double* d_minP = nullptr;
     double* d_maxP = nullptr;
     uint32_t* d_flags = nullptr;
+    uint32_t* d_stamp = nullptr;
+    double* d_tmat = nullptr;
+    int tmw = 0, rows = 0, tmk[KINDS] = {};
     InstState* d_st = nullptr;
     TraceRec* d_trace = nullptr;
     double* d_mono = nullptr;     // monomials in item layout (kept for pcba_reset)
@@ -156,9 +159,10 @@ struct pcba_engine {
     DevInst* d_insts = nullptr;
     int d_insts_cap = 0;
     long long* d_plan = nullptr;
-    int plan_cap = 0;
+    StepInfo* d_info = nullptr;
     InstState* d_states = nullptr;
     InstState* h_states = nullptr;
+    DevInst* h_insts = nullptr;    // pinned staging of the descriptors (outlives the async copy)
     int states_cap = 0;
     bool dirty = true;
 };
@@ -201,10 +205,18 @@ static DevInst make_dev(const pcba_problem* P)
     I.minP = P->d_minP;
     I.maxP = P->d_maxP;
     I.flags = P->d_flags;
+    I.stamp = P->d_stamp;
+    I.tmat = P->d_tmat;
+    I.tmw = P->tmw;
+    I.rows = P->rows;
+    for (int t = 0; t < KINDS; ++t) I.tmk[t] = P->tmk[t];
     I.root = P->d_root;
     I.root_err = P->d_root_err;
     I.cert = P->d_cert;
     I.trace = P->d_trace;
+    I.mono = P->d_mono;
+    I.mats = P->d_mats;
+    I.matoff = P->d_matoff;
     I.st = P->d_st;
     return I;
 }
@@ -228,9 +240,13 @@ static void free_list(pcba_problem* P)
     if (P->d_minP) (void)hipFree(P->d_minP);
     if (P->d_maxP) (void)hipFree(P->d_maxP);
     if (P->d_flags) (void)hipFree(P->d_flags);
+    if (P->d_stamp) (void)hipFree(P->d_stamp);
+    if (P->d_tmat) (void)hipFree(P->d_tmat);
     P->d_live = nullptr;
     P->d_minP = P->d_maxP = nullptr;
     P->d_flags = nullptr;
+    P->d_stamp = nullptr;
+    P->d_tmat = nullptr;
 }
 
 // (Re)allocates the list for `ncap` slots per buffer, keeping the current
@@ -244,7 +260,12 @@ static int alloc_list(pcba_problem* P, int64_t ncap, hipStream_t s)
     int32_t* nlive = nullptr;
     double *nmin = nullptr, *nmax = nullptr;
     uint32_t* nfl = nullptr;
+    uint32_t* nst = nullptr;
+    double* ntm = nullptr;
+    const bool need_tm = P->fp32 && P->opt.rederive_every > 0;
     auto cleanup = [&]() {
+        if (nst) (void)hipFree(nst);
+        if (ntm) (void)hipFree(ntm);
         for (int b = 0; b < 2; ++b) {
             if (nb[b]) (void)hipFree(nb[b]);
             if (ni[b]) (void)hipFree(ni[b]);
@@ -265,13 +286,17 @@ static int alloc_list(pcba_problem* P, int64_t ncap, hipStream_t s)
     ok = ok && hipMalloc((void**)&nlive, (size_t)ncap * sizeof(int32_t)) == hipSuccess &&
          hipMalloc((void**)&nmin, (size_t)ncap * sizeof(double)) == hipSuccess &&
          hipMalloc((void**)&nmax, (size_t)ncap * sizeof(double)) == hipSuccess &&
-         hipMalloc((void**)&nfl, (size_t)ncap * sizeof(uint32_t)) == hipSuccess;
+         hipMalloc((void**)&nfl, (size_t)ncap * sizeof(uint32_t)) == hipSuccess &&
+         hipMalloc((void**)&nst, (size_t)ncap * sizeof(uint32_t)) == hipSuccess;
+    if (ok && need_tm)
+        ok = hipMalloc((void**)&ntm, (size_t)(ncap / 2 + 1) * 2 * P->tmw * sizeof(double)) == hipSuccess;
     if (!ok) {
         (void)hipGetLastError();
         cleanup();
         return fail(PCBA_E_NOMEM, "device list allocation failed");
     }
     hipError_t e = hipMemsetAsync(nfl, 0, (size_t)ncap * sizeof(uint32_t), s);
+    if (e == hipSuccess) e = hipMemsetAsync(nst, 0, (size_t)ncap * sizeof(uint32_t), s);
     if (e == hipSuccess && P->cap > 0) {
         const int cur = P->h_st.cur;
         const int64_t used = std::min<int64_t>(P->cap, ncap);
@@ -302,36 +327,100 @@ static int alloc_list(pcba_problem* P, int64_t ncap, hipStream_t s)
     P->d_minP = nmin;
     P->d_maxP = nmax;
     P->d_flags = nfl;
+    P->d_stamp = nst;
+    P->d_tmat = ntm;
     P->cap = ncap;
     return PCBA_OK;
 }
 
-// Initial state: L = {root item}; root patches recomputed from the resident
-// monomials (InitPatches), n = 1, r = 1 (0-based 0), p_up = +inf.
-static int init_state(pcba_problem* P, hipStream_t s)
+// Per-thread device scratch for small per-call arrays (problem descriptors,
+// prefix sums): distinct threads never share it.
+struct Scratch {
+    void* p = nullptr;    // device
+    void* hp = nullptr;   // pinned host staging of the same size
+    size_t cap = 0;
+    ~Scratch()
+    {
+        if (p) (void)hipFree(p);
+        if (hp) (void)hipHostFree(hp);
+    }
+    hipError_t ensure(size_t bytes)
+    {
+        if (bytes <= cap) return hipSuccess;
+        if (p) (void)hipFree(p);
+        if (hp) (void)hipHostFree(hp);
+        p = hp = nullptr;
+        cap = 0;
+        hipError_t e = hipMalloc(&p, bytes);
+        if (e == hipSuccess) e = hipHostMalloc(&hp, bytes, hipHostMallocDefault);
+        if (e == hipSuccess) cap = bytes;
+        return e;
+    }
+};
+thread_local Scratch t_scratch;
+
+static size_t tm_words(const pcba_problem* P)
 {
-    InstState st0;
-    memset(&st0, 0, sizeof(st0));
-    st0.status = ST_RUNNING;
-    st0.K = 1;
-    st0.n = 1;
-    st0.p_up = INFINITY;
-    st0.p_lo = INFINITY;
-    st0.peak = 0;
-    st0.p_cert = INFINITY;
-    P->h_st = st0;
-    P->certified_done = false;
-    P->seconds = 0.0;
-    P->host_steps = 0;
-    static const int32_t zero = 0;
-    HIP_TRY(hipMemcpyAsync(P->d_st, &st0, sizeof(st0), hipMemcpyHostToDevice, s));
-    HIP_TRY(hipMemcpyAsync(P->d_live, &zero, sizeof(zero), hipMemcpyHostToDevice, s));
-    HIP_TRY(hipMemsetAsync(P->d_ids[0], 0, (size_t)P->l * sizeof(uint32_t), s));
-    HIP_TRY(hipMemsetAsync(P->d_flags, 0, (size_t)P->cap * sizeof(uint32_t), s));
-    DevInst I = make_dev(P);
-    HIP_TRY(launch_root(I, P->d_mono, P->d_mats, P->d_matoff, P->d_root, P->d_root_err, P->W,
-                        P->max_S, s));
-    HIP_TRY(hipStreamSynchronize(s));  // st0 lives on this stack frame
+    return (size_t)(P->l + 2) * P->maxm * P->maxm;
+}
+
+// Uploads the descriptors of probs and the prefix sum of their polynomial
+// counts into `sc`; returns the total polynomial count in *total.
+static int upload_descs(pcba_problem* const* probs, int n, Scratch& sc, hipStream_t s,
+                        DevInst** d_insts, int** d_pre, int* total, int* max_S, int* tmw)
+{
+    std::vector<DevInst> h(n);
+    std::vector<int> pre(n + 1, 0);
+    *max_S = 1;
+    *tmw = 1;
+    for (int b = 0; b < n; ++b) {
+        h[b] = make_dev(probs[b]);
+        pre[b + 1] = pre[b] + probs[b]->n_polys;
+        *max_S = std::max(*max_S, probs[b]->max_S);
+        *tmw = std::max(*tmw, (int)tm_words(probs[b]));
+    }
+    const size_t bytes_i = n * sizeof(DevInst);
+    const size_t off_pre = (bytes_i + 255) / 256 * 256;
+    const size_t total_b = off_pre + (n + 1) * sizeof(int);
+    // the staging buffer may still feed an earlier copy on this stream
+    HIP_TRY(hipStreamSynchronize(s));
+    HIP_TRY(sc.ensure(total_b));
+    memcpy(sc.hp, h.data(), bytes_i);
+    memcpy((char*)sc.hp + off_pre, pre.data(), (n + 1) * sizeof(int));
+    HIP_TRY(hipMemcpyAsync(sc.p, sc.hp, total_b, hipMemcpyHostToDevice, s));
+    *d_insts = (DevInst*)sc.p;
+    *d_pre = (int*)((char*)sc.p + off_pre);
+    *total = pre[n];
+    return PCBA_OK;
+}
+
+// Initial state of every problem: L = {root item}, root patches recomputed on
+// the device from the resident monomials (InitPatches), n = 1, p_up = +inf.
+static int reset_batch(pcba_problem* const* probs, int n, hipStream_t s)
+{
+    if (n <= 0) return PCBA_OK;
+    DevInst* d_insts = nullptr;
+    int* d_pre = nullptr;
+    int total = 0, max_S = 1, tmw = 1;
+    int rc = upload_descs(probs, n, t_scratch, s, &d_insts, &d_pre, &total, &max_S, &tmw);
+    if (rc != PCBA_OK) return rc;
+    HIP_TRY(launch_reset_root(d_insts, n, d_pre, total, max_S, s));
+    HIP_TRY(hipStreamSynchronize(s));   // the host descriptors above are pageable
+    for (int b = 0; b < n; ++b) {
+        pcba_problem* P = probs[b];
+        InstState st0;
+        memset(&st0, 0, sizeof(st0));
+        st0.status = ST_RUNNING;
+        st0.K = 1;
+        st0.n = 1;
+        st0.p_up = INFINITY;
+        st0.p_lo = INFINITY;
+        st0.p_cert = INFINITY;
+        P->h_st = st0;
+        P->certified_done = false;
+        P->seconds = 0.0;
+        P->host_steps = 0;
+    }
     return PCBA_OK;
 }
 
@@ -352,7 +441,7 @@ void pcba_default_options(pcba_options* o)
     o->max_iters = 28;
     o->precision = PCBA_FP64_PLAIN;
     o->rederive_every = 8;
-    o->stale_filter = 1;
+    o->stale_filter = 0;
     o->time_limit_s = 0.0;
 }
 
@@ -376,6 +465,7 @@ int pcba_create_problem(int32_t l, const double* lo, const double* hi, const int
         return fail(PCBA_E_ARG, "eps, delta and eps_eq must be positive");
     if (o.max_boxes < 2) return fail(PCBA_E_ARG, "max_boxes (M) must be >= 2");
     if (o.max_iters < 1) return fail(PCBA_E_ARG, "max_iters (N) must be >= 1");
+    if ((int64_t)o.max_iters * l >= MAX_STEPS) return fail(PCBA_E_ARG, "max_iters * l must stay below 60000");
     if (o.precision != PCBA_FP64_PLAIN && o.precision != PCBA_FP32)
         return fail(PCBA_E_ARG, "unknown precision");
     if (o.rederive_every < 0) return fail(PCBA_E_ARG, "rederive_every must be >= 0");
@@ -428,11 +518,22 @@ int pcba_create_problem(int32_t l, const double* lo, const double* hi, const int
     for (int t = 1; t < KINDS; ++t) {
         P->tile_start[t] = T;
         if (P->count[t] == 0) { P->tile_polys[t] = 1; continue; }
-        P->tile_polys[t] = std::max(1, std::min(P->count[t], TILE_ELEMS / std::max(1, P->S[t])));
+        // FP32 tiles hold twice the coefficients: the same bytes per unit
+        const int target = P->fp32 ? 2 * TILE_ELEMS : TILE_ELEMS;
+        P->tile_polys[t] = std::max(1, std::min(P->count[t], target / std::max(1, P->S[t])));
         T += (P->count[t] + P->tile_polys[t] - 1) / P->tile_polys[t];
     }
     P->tile_start[KINDS] = T;
     P->T = T;
+    // sub-interval transforms per child (FP32 re-derivation): m^2 words and m rows per kind and axis
+    for (int t = 0; t < KINDS; ++t) {
+        P->tmk[t] = P->tmw;
+        if (P->count[t] == 0) continue;
+        for (int k = 0; k < l; ++k) {
+            P->tmw += (P->deg[t][k] + 1) * (P->deg[t][k] + 1);
+            P->rows += P->deg[t][k] + 1;
+        }
+    }
 
     // monomials, zero-padded to each kind's common multi-degree, in item layout
     std::vector<double> mono(P->W, 0.0);
@@ -528,10 +629,7 @@ int pcba_create_problem(int32_t l, const double* lo, const double* hi, const int
     if (e == hipSuccess)
         e = hipMemcpyAsync(P->d_matoff, matoff.data(), matoff.size() * sizeof(int), hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
-    if (e == hipSuccess) {
-        rc = init_state(P, s);
-        if (rc == PCBA_OK) e = hipStreamSynchronize(s);
-    }
+    if (e == hipSuccess) rc = reset_batch(&P, 1, s);
     (void)hipStreamDestroy(s);
     if (e != hipSuccess || rc != PCBA_OK) {
         std::string m = e != hipSuccess ? std::string(hipGetErrorString(e)) : g_last_error;
@@ -545,11 +643,15 @@ int pcba_create_problem(int32_t l, const double* lo, const double* hi, const int
 int pcba_reset(pcba_problem* P, void* stream)
 {
     if (!P) return fail(PCBA_E_ARG, "NULL problem");
-    hipStream_t s = (hipStream_t)stream;
-    const int rc = init_state(P, s);
-    if (rc != PCBA_OK) return rc;
-    HIP_TRY(hipStreamSynchronize(s));
-    return PCBA_OK;
+    return reset_batch(&P, 1, (hipStream_t)stream);
+}
+
+int pcba_reset_batch(pcba_problem* const* probs, int32_t n, void* stream)
+{
+    if (n < 0 || (n > 0 && !probs)) return fail(PCBA_E_ARG, "bad batch");
+    for (int b = 0; b < n; ++b)
+        if (!probs[b]) return fail(PCBA_E_ARG, "NULL problem in batch");
+    return reset_batch(probs, n, (hipStream_t)stream);
 }
 
 int pcba_read_trace(const pcba_problem* P, int32_t* k_in, int32_t* k_kept, double* p_up,
@@ -635,8 +737,10 @@ void pcba_engine_destroy(pcba_engine* E)
     if (E->stream) (void)hipStreamSynchronize(E->stream);
     if (E->d_insts) (void)hipFree(E->d_insts);
     if (E->d_plan) (void)hipFree(E->d_plan);
+    if (E->d_info) (void)hipFree(E->d_info);
     if (E->d_states) (void)hipFree(E->d_states);
     if (E->h_states) (void)hipHostFree(E->h_states);
+    if (E->h_insts) (void)hipHostFree(E->h_insts);
     if (E->own_stream) (void)hipStreamDestroy(E->stream);
     delete E;
 }
@@ -666,22 +770,29 @@ static int engine_upload(pcba_engine* E)
     if (n > E->d_insts_cap) {
         if (E->d_insts) (void)hipFree(E->d_insts);
         if (E->d_plan) (void)hipFree(E->d_plan);
+        if (E->d_info) (void)hipFree(E->d_info);
         if (E->d_states) (void)hipFree(E->d_states);
         if (E->h_states) (void)hipHostFree(E->h_states);
+        if (E->h_insts) (void)hipHostFree(E->h_insts);
+        E->h_insts = nullptr;
+        E->d_info = nullptr;
         E->d_insts = nullptr;
         E->d_plan = nullptr;
         E->d_states = nullptr;
         E->h_states = nullptr;
         const int c = std::max(n, 2 * E->d_insts_cap);
         HIP_TRY(hipMalloc((void**)&E->d_insts, c * sizeof(DevInst)));
-        HIP_TRY(hipMalloc((void**)&E->d_plan, 3 * (size_t)(c + 1) * sizeof(long long)));
+        HIP_TRY(hipMalloc((void**)&E->d_plan, 4 * (size_t)(c + 1) * sizeof(long long)));
+        HIP_TRY(hipMalloc((void**)&E->d_info, (size_t)c * sizeof(StepInfo)));
         HIP_TRY(hipMalloc((void**)&E->d_states, c * sizeof(InstState)));
         HIP_TRY(hipHostMalloc((void**)&E->h_states, c * sizeof(InstState), hipHostMallocDefault));
+        HIP_TRY(hipHostMalloc((void**)&E->h_insts, c * sizeof(DevInst), hipHostMallocDefault));
         E->d_insts_cap = c;
     }
-    std::vector<DevInst> h(n);
-    for (int b = 0; b < n; ++b) h[b] = make_dev(E->active[b]);
-    if (n) HIP_TRY(hipMemcpyAsync(E->d_insts, h.data(), n * sizeof(DevInst), hipMemcpyHostToDevice, E->stream));
+    // every earlier use of the staging buffer has completed: the engine
+    // synchronises its stream at the end of each batch of steps
+    for (int b = 0; b < n; ++b) E->h_insts[b] = make_dev(E->active[b]);
+    if (n) HIP_TRY(hipMemcpyAsync(E->d_insts, E->h_insts, n * sizeof(DevInst), hipMemcpyHostToDevice, E->stream));
     E->dirty = false;
     return PCBA_OK;
 }
@@ -702,17 +813,34 @@ static size_t rederive_lds(const pcba_problem* P)
 {
     int TE = P->S[0];
     for (int t = 1; t < KINDS; ++t)
-        if (P->count[t]) TE = std::max(TE, P->tile_polys[t] * P->S[t]);
-    return 2 * (size_t)TE * 8 + (size_t)P->l * P->maxm * P->maxm * 8 + 16;
+        if (P->count[t]) {
+            const int cp = std::max(1, MAX_TILE64 / P->S[t]);
+            TE = std::max(TE, std::min(P->tile_polys[t], cp) * P->S[t]);
+        }
+    return (2 * (size_t)TE + (size_t)P->l * P->maxm * P->maxm) * 8 + 16;
 }
 
-static int certify(pcba_problem* P, hipStream_t s)
+// FP64 certification of every finished problem in one launch, then their states.
+static int certify_batch(pcba_engine* E, std::vector<pcba_problem*>& fin)
 {
-    DevInst I = make_dev(P);
-    HIP_TRY(launch_certify(I, P->max_S, P->maxm, s));
-    HIP_TRY(hipMemcpyAsync(&P->h_st, P->d_st, sizeof(InstState), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
-    P->certified_done = true;
+    const int n = (int)fin.size();
+    if (n == 0) return PCBA_OK;
+    DevInst* d_insts = nullptr;
+    int* d_pre = nullptr;
+    int total = 0, max_S = 1, tmw = 1;
+    int rc = upload_descs(fin.data(), n, t_scratch, E->stream, &d_insts, &d_pre, &total, &max_S, &tmw);
+    if (rc != PCBA_OK) return rc;
+    HIP_TRY(launch_certify(d_insts, n, d_pre, total, max_S, tmw, E->stream));
+    HIP_TRY(launch_gather(d_insts, n, E->d_states, E->stream));
+    HIP_TRY(hipMemcpyAsync(E->h_states, E->d_states, n * sizeof(InstState), hipMemcpyDeviceToHost,
+                           E->stream));
+    HIP_TRY(hipStreamSynchronize(E->stream));
+    const double t = now_s();
+    for (int b = 0; b < n; ++b) {
+        fin[b]->h_st = E->h_states[b];
+        fin[b]->certified_done = true;
+        fin[b]->seconds = t - fin[b]->t_start;
+    }
     return PCBA_OK;
 }
 
@@ -746,7 +874,7 @@ static int engine_steps(pcba_engine* E, int n_steps)
     for (int s = 0; s < n_steps; ++s) {
         // upper bound of this step's units: K at most doubles per step, and a
         // problem never holds more than cap/2 parents
-        int64_t ub64 = 0, ub32 = 0, ubrd = 0;
+        int64_t ub64 = 0, ub32 = 0, ubrd = 0, ubrows = 0;
         for (auto* P : E->active) {
             if (P->h_st.status != ST_RUNNING) continue;
             const int64_t k = std::min<int64_t>(P->cap / 2, (int64_t)P->h_st.K << std::min(s, 30));
@@ -755,28 +883,28 @@ static int engine_steps(pcba_engine* E, int n_steps)
             else {
                 const int st = P->host_steps + s;
                 const bool due = P->opt.rederive_every > 0 && ((st + 1) % P->opt.rederive_every) == 0;
-                if (due) ubrd += u; else ub32 += u;
+                if (due) { ubrd += u; ubrows += k * 2 * P->rows; } else ub32 += u;
             }
         }
         HIP_TRY(prof_begin(E->stream));
-        HIP_TRY(launch_plan(E->d_insts, n, E->d_plan, E->stream));
+        HIP_TRY(launch_plan(E->d_insts, n, E->d_plan, E->d_info, E->stream));
         HIP_TRY(prof_end(4, E->stream));
         if (any64 && ub64 > 0) {
             HIP_TRY(prof_begin(E->stream));
-            HIP_TRY(launch_sub(E->d_insts, n, E->d_plan, false, maxm64,
+            HIP_TRY(launch_sub(E->d_insts, n, E->d_plan, E->d_info, false, maxm64,
                                (int)std::min<int64_t>(GRID_MAX, ub64), lds64, E->stream));
             HIP_TRY(prof_end(0, E->stream));
         }
         if (any32 && ub32 > 0) {
             HIP_TRY(prof_begin(E->stream));
-            HIP_TRY(launch_sub(E->d_insts, n, E->d_plan, true, maxm32,
+            HIP_TRY(launch_sub(E->d_insts, n, E->d_plan, E->d_info, true, maxm32,
                                (int)std::min<int64_t>(GRID_MAX, ub32), lds32, E->stream));
             HIP_TRY(prof_end(1, E->stream));
         }
         if (anyrd && ubrd > 0) {
             HIP_TRY(prof_begin(E->stream));
-            HIP_TRY(launch_rederive(E->d_insts, n, E->d_plan, (int)std::min<int64_t>(GRID_MAX, ubrd),
-                                    ldsrd, E->stream));
+            HIP_TRY(launch_rederive(E->d_insts, n, E->d_plan, E->d_info, (int)std::min<int64_t>(GRID_MAX, ubrd),
+                                    (int)std::min<int64_t>(4096, (ubrows + 255) / 256), ldsrd, E->stream));
             HIP_TRY(prof_end(2, E->stream));
         }
         HIP_TRY(prof_begin(E->stream));
@@ -791,7 +919,7 @@ static int engine_steps(pcba_engine* E, int n_steps)
 
     // growth, time limits, finished problems
     const double t = now_s();
-    std::vector<pcba_problem*> still;
+    std::vector<pcba_problem*> still, fin;
     for (int b = 0; b < n; ++b) {
         pcba_problem* P = E->active[b];
         P->h_st = E->h_states[b];
@@ -827,14 +955,18 @@ static int engine_steps(pcba_engine* E, int n_steps)
         if (P->h_st.status == ST_RUNNING) {
             still.push_back(P);
         } else {
-            int rc = certify(P, E->stream);
-            if (rc != PCBA_OK) return rc;
-            P->seconds = now_s() - P->t_start;
+            fin.push_back(P);
+        }
+    }
+    if (!fin.empty()) {
+        int rc = certify_batch(E, fin);
+        if (rc != PCBA_OK) return rc;
+        for (auto* P : fin) {
             E->used -= P->footprint;
             P->footprint = 0;
             E->done.push_back(P);
-            E->dirty = true;
         }
+        E->dirty = true;
     }
     if (still.size() != E->active.size()) {
         E->active.swap(still);

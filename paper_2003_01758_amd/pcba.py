@@ -103,6 +103,8 @@ def lib():
         L.pcba_engine_used_bytes.restype = i64
         L.pcba_engine_destroy.argtypes = [vp]
         L.pcba_engine_destroy.restype = None
+        L.pcba_reset_batch.argtypes = [C.POINTER(vp), i32, vp]
+        L.pcba_reset_batch.restype = C.c_int
         L.pcba_reset.argtypes = [vp, vp]
         L.pcba_reset.restype = C.c_int
         L.pcba_read_trace.argtypes = [vp, vp, vp, vp, vp, i32]
@@ -265,6 +267,11 @@ def profile_read() -> dict:
     n = np.zeros(len(KERNELS), dtype=np.int64)
     lib().pcba_profile_read(ms.ctypes.data, n.ctypes.data)
     return {k: (float(ms[i]), int(n[i])) for i, k in enumerate(KERNELS)}
+
+
+def reset_batch(problems, stream=None):
+    arr = (C.c_void_p * len(problems))(*[p.h for p in problems])
+    _check(lib().pcba_reset_batch(arr, len(problems), _stream_ptr(stream)))
 
 
 def solve_batch(problems, stream=None):
