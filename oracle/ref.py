@@ -32,12 +32,20 @@ _lib = None
 
 
 def lib():
+    """The oracle library built from oracle/pcba_ref.c (rebuilt if stale)."""
     global _lib
     if _lib is None:
         path = _build.LIB
         src = os.path.join(os.path.dirname(path), "pcba_ref.c")
         if not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(src):
             _build.build()
+        _lib = load(path)
+    return _lib
+
+
+def load(path):
+    """Loads an oracle build at `path` (the tests also load mutated builds)."""
+    if True:
         L = C.CDLL(path)
         dp = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
         ip = np.ctypeslib.ndpointer(dtype=np.int32, flags="C_CONTIGUOUS")
@@ -66,16 +74,15 @@ def lib():
         L.pcba_ref_derive.restype = C.c_int
         L.pcba_ref_destroy.argtypes = [C.c_void_p]
         L.pcba_ref_destroy.restype = None
-        _lib = L
-    return _lib
+    return L
 
 
-def to_bernstein(mono: np.ndarray, lo, hi) -> np.ndarray:
+def to_bernstein(mono: np.ndarray, lo, hi, L=None) -> np.ndarray:
     """Bernstein coefficients of a monomial tensor over the box [lo, hi]."""
     mono = np.ascontiguousarray(mono, dtype=np.float64)
     deg = np.array([s - 1 for s in mono.shape], dtype=np.int32)
     out = np.empty_like(mono)
-    rc = lib().pcba_ref_to_bernstein(mono.ndim, deg, np.ascontiguousarray(lo, dtype=np.float64),
+    rc = (L or lib()).pcba_ref_to_bernstein(mono.ndim, deg, np.ascontiguousarray(lo, dtype=np.float64),
                                      np.ascontiguousarray(hi, dtype=np.float64), mono.ravel(),
                                      out.reshape(-1))
     if rc != 0:
@@ -83,13 +90,13 @@ def to_bernstein(mono: np.ndarray, lo, hi) -> np.ndarray:
     return out
 
 
-def split(patch: np.ndarray, r: int):
+def split(patch: np.ndarray, r: int, L=None):
     """Left and right child patches of a midpoint split along axis r."""
     patch = np.ascontiguousarray(patch, dtype=np.float64)
     deg = np.array([s - 1 for s in patch.shape], dtype=np.int32)
     left = np.empty_like(patch)
     right = np.empty_like(patch)
-    rc = lib().pcba_ref_split(patch.ndim, deg, r, patch.reshape(-1), left.reshape(-1),
+    rc = (L or lib()).pcba_ref_split(patch.ndim, deg, r, patch.reshape(-1), left.reshape(-1),
                               right.reshape(-1))
     if rc != 0:
         raise ValueError("pcba_ref_split rejected its arguments")
@@ -105,8 +112,9 @@ class RefSolver:
     object (l, lo, hi, cost_deg, cost_flat, ineq_deg, ineq_flat, eq_deg, eq_flat,
     eps, delta, eps_eq, max_boxes, max_iters)."""
 
-    def __init__(self, inst, **override):
-        L = lib()
+    def __init__(self, inst, L=None, **override):
+        L = L or lib()
+        self.L = L
         g = lambda k: override.get(k, getattr(inst, k))
         self.l = int(inst.l)
         self._keep = [np.ascontiguousarray(inst.ineq_deg, dtype=np.int32).ravel(),
@@ -128,20 +136,20 @@ class RefSolver:
 
     def close(self):
         if getattr(self, "h", None):
-            lib().pcba_ref_destroy(self.h)
+            self.L.pcba_ref_destroy(self.h)
             self.h = None
 
     __del__ = close
 
     def step(self) -> int:
-        return lib().pcba_ref_step(self.h)
+        return self.L.pcba_ref_step(self.h)
 
     def solve(self) -> int:
-        return lib().pcba_ref_solve(self.h)
+        return self.L.pcba_ref_solve(self.h)
 
     def result(self) -> dict:
         r = RefResult()
-        lib().pcba_ref_result_get(self.h, C.byref(r))
+        self.L.pcba_ref_result_get(self.h, C.byref(r))
         l = self.l
         return dict(outcome=r.outcome, has_x=bool(r.has_x), p_up=r.p_up, p_lo=r.p_lo,
                     x_lo=np.array(r.x_lo[:l]), x_hi=np.array(r.x_hi[:l]),
@@ -151,19 +159,19 @@ class RefSolver:
 
     def kind_degree(self, kind: int) -> np.ndarray:
         d = np.zeros(self.l, dtype=np.int32)
-        lib().pcba_ref_kind_degree(self.h, kind, d)
+        self.L.pcba_ref_kind_degree(self.h, kind, d)
         return d
 
     def list(self):
         n = self.result()["list_len"]
         ids = np.empty((n, self.l), dtype=np.uint32)
         pat = np.empty((n, self.words), dtype=np.float64)
-        lib().pcba_ref_list(self.h, ids.ctypes.data, pat.ctypes.data)
+        self.L.pcba_ref_list(self.h, ids.ctypes.data, pat.ctypes.data)
         return ids, pat
 
     def derive(self, depth, index) -> np.ndarray:
         out = np.empty(self.words, dtype=np.float64)
-        rc = lib().pcba_ref_derive(self.h, np.ascontiguousarray(depth, dtype=np.int32),
+        rc = self.L.pcba_ref_derive(self.h, np.ascontiguousarray(depth, dtype=np.int32),
                                    np.ascontiguousarray(index, dtype=np.uint32), out)
         if rc != 0:
             raise ValueError("pcba_ref_derive rejected the box id")

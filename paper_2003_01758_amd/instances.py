@@ -191,17 +191,45 @@ def _goal_cost(rng, l: int, half_deg: int) -> np.ndarray:
     return cost
 
 
+def _shift_basis(svals, n):
+    """For each shift s: the (n x n) matrix whose column j holds the coefficients
+    of (q - s)^j (repeated multiplication by the linear factor q - s)."""
+    svals = np.asarray(svals, dtype=np.float64)
+    out = np.zeros((len(svals), n, n))
+    col = np.zeros((len(svals), n))
+    col[:, 0] = 1.0
+    out[:, :, 0] = col
+    for j in range(1, n):
+        nxt = np.zeros_like(col)
+        nxt[:, 1:] = col[:, :-1]          # times q
+        nxt -= svals[:, None] * col       # times -s
+        col = nxt
+        out[:, :, j] = col
+    return out
+
+
 def _obstacle_constraints(rng, l: int, deg: int, count: int, q0) -> list:
     """FRS-like obstacle constraints: one template T of multi-degree (deg,)*l,
     shifted by s_i = o_i/2 for obstacle points o_i uniform in a 4 m x 4 m window
-    (extra axes shifted uniformly in [-1,1]), then planted feasible at q0."""
+    (extra axes shifted uniformly in [-1,1]), then planted feasible at q0:
+    g_i(q) = T(q - s_i) - T(q0 - s_i) - U(0.1, 0.5)."""
     tmpl = _scaled_normal(rng, (deg + 1,) * l, 1.5)
-    out = []
-    for _ in range(count):
+    shifts = np.empty((count, l))
+    margins = np.empty(count)
+    for i in range(count):   # the draws stay in the order of one constraint at a time
         o = rng.uniform(-2.0, 2.0, size=2)
-        s = np.concatenate([o / 2.0, rng.uniform(-1.0, 1.0, size=l - 2)])
-        out.append(_planted(rng, poly_shift(tmpl, s), q0))
-    return out
+        shifts[i] = np.concatenate([o / 2.0, rng.uniform(-1.0, 1.0, size=l - 2)])
+        margins[i] = rng.uniform(0.1, 0.5)
+    m = deg + 1
+    coef = np.broadcast_to(tmpl, (count,) + tmpl.shape).copy()
+    for k in range(l):
+        B = _shift_basis(shifts[:, k], m)                     # (count, m, m)
+        moved = np.moveaxis(coef, k + 1, 1)                   # (count, m, ...)
+        moved = np.einsum("cab,cb...->ca...", B, moved)
+        coef = np.moveaxis(moved, 1, k + 1)
+    at_q0 = poly_eval_many(tmpl, np.asarray(q0)[None, :] - shifts)
+    coef[(slice(None),) + (0,) * l] -= at_q0 + margins
+    return [np.ascontiguousarray(c) for c in coef]
 
 
 def make_instance(config: int, index: int = 0, **overrides) -> Instance:
