@@ -40,6 +40,33 @@ def certified(r, pcba):
     return (r["outcome"] == pcba.OPTIMAL and r["certified"]) or r["outcome"] == pcba.INFEASIBLE
 
 
+def patch_words(inst):
+    """Coefficients per patch of each kind (each kind at its common multi-degree)."""
+    def size(degs):
+        return int(np.prod(np.max(np.atleast_2d(degs), axis=0) + 1)) if len(degs) else 0
+    return int(np.prod(np.array(inst.cost.shape))), size(inst.ineq_deg), size(inst.eq_deg)
+
+
+def algorithmic_bytes(p, inst, precision):
+    """Bytes the subdivide+bound kernel must move over the last solve: every
+    parent's carried patches read once and every kept child's carried patches
+    written once (plus, in FP32, one error term per such patch).  Steps that
+    ran in the FP32 re-derivation kernel instead are left out."""
+    s0, s1, s2 = patch_words(inst)
+    el = 4 if precision == "fp32" else 8
+    tr, pt = p.trace(), p.trace_patches()
+    total = 0.0
+    for q in range(len(tr["k_in"])):
+        if precision == "fp32" and p.options.rederive_every > 0 and (q + 1) % p.options.rederive_every == 0:
+            continue
+        items = float(tr["k_in"][q] + tr["k_kept"][q])
+        ineq = float(pt["a_in"][q] + pt["a_kept"][q])
+        total += items * (s0 + inst.n_eq * s2) * el + ineq * s1 * el
+        if precision == "fp32":
+            total += (items * (1 + inst.n_eq) + ineq) * 4
+    return total
+
+
 def run_mode(pcba, insts, precision, steps, warmup, **opts):
     probs = [pcba.Problem(i, precision=precision, **opts) for i in insts]
     for w in range(warmup):
@@ -57,16 +84,8 @@ def run_mode(pcba, insts, precision, steps, warmup, **opts):
         pcba.reset_batch(probs)
         res = pcba.solve_batch(probs)
         elapsed += time.perf_counter() - t0
-        # algorithmic bytes of the subdivide+bound kernel: every parent read once,
-        # every kept child written once (patches, plus the per-patch error term in FP32)
-        for p, r in zip(probs, res):
-            tr = p.trace()
-            item = p.words * (4 if precision == "fp32" else 8) + (4 * p.n_polys if precision == "fp32" else 0)
-            for q in range(len(tr["k_in"])):
-                if precision == "fp32" and p.options.rederive_every > 0 and \
-                        (q + 1) % p.options.rederive_every == 0:
-                    continue  # this step ran in the re-derivation kernel
-                bytes_sub += float(tr["k_in"][q] + tr["k_kept"][q]) * item
+        for p, i in zip(probs, insts):
+            bytes_sub += algorithmic_bytes(p, i, precision)
         lat += [r["seconds"] for r in res]
         cert += sum(1 for r in res if certified(r, pcba))
         results = res
@@ -113,6 +132,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--rederive", type=int, default=None, help="FP32 re-derivation period (steps)")
     ap.add_argument("--stale", type=int, default=None, help="1/0: stale-estimate write filter")
+    ap.add_argument("--retire", type=int, default=1,
+                    help="1/0: drop inequalities certified satisfied on a box from its descendants")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: this build has no multi-GPU path (asked for {args.gpus})",
@@ -125,7 +146,7 @@ def main():
     insts = [make_instance(1, k) for k in range(args.batch)]
     log(f"[bench] {len(insts)} rtd-shaped plans, {insts[0].n_ineq} constraints, "
         f"{insts[0].words_per_item()} words per item")
-    opts = {}
+    opts = {"retire_satisfied": args.retire}
     if args.stale is not None:
         opts["stale_filter"] = args.stale
     r64 = run_mode(pcba, insts, "fp64", args.steps, args.warmup, **opts)
@@ -159,6 +180,7 @@ def main():
             "batch": args.batch,
             "rederive_every": args.rederive if args.rederive is not None else 8,
             "stale_filter": args.stale if args.stale is not None else 0,
+            "retire_satisfied": args.retire,
             "path": "fp32 patches with rigorous widening + fp64 root, re-derivation and certification"
                     if best is r32 else "fp64 plain",
         },

@@ -81,6 +81,14 @@ typedef struct {
     int32_t stale_filter;    /* 1: skip writing children whose cost lower bound already
                                 exceeds the previous solution estimate (results are
                                 unchanged); 0: write every child */
+    int32_t retire_satisfied;/* 1 (default): an inequality whose patch on a box has
+                                max B <= 0 is satisfied on the whole box (Thm. of
+                                enclosure), and, since subdivision forms convex
+                                combinations, on every sub-box; the box's descendants
+                                stop carrying that patch.  Feasibility and the lists
+                                are unchanged: in FP64 plain mode the results are
+                                identical to 0, in FP32 mode they remain rigorous.
+                                0: every box carries every patch, as in Alg. PCBA */
     double time_limit_s;     /* 0 = none */
 } pcba_options;
 
@@ -146,7 +154,9 @@ int pcba_result(const pcba_problem* prob, pcba_result_t* out);
 /* Current list: length, then ids (host, len*l uint32: index per axis) and the
  * patches converted to FP64 (host, len*words doubles; words = pcba_patch_words).
  * Patches are the cost patch, the inequality patches, then the equality patches,
- * each at its kind's common multi-degree.  ids or patches may be NULL. */
+ * each at its kind's common multi-degree.  With retire_satisfied, an inequality
+ * the box no longer carries (certified satisfied on it or on an ancestor) reads
+ * back as NaN.  ids or patches may be NULL. */
 int pcba_list_size(const pcba_problem* prob, int64_t* len);
 int pcba_read_list(const pcba_problem* prob, uint32_t* ids, double* patches, int64_t cap);
 /* PCBA_FP32 only: per-item, per-polynomial error bounds (host, len*(1+alpha+beta)). */
@@ -173,6 +183,15 @@ int pcba_reset_batch(pcba_problem* const* probs, int32_t n, void* stream);
 #define PCBA_MAX_TRACE 512
 int pcba_read_trace(const pcba_problem* prob, int32_t* k_in, int32_t* k_kept, double* p_up,
                     double* p_lo, int32_t cap);
+/* The same steps: inequality patches carried by the k_in parents (a_in[s]) and
+ * by the k_kept kept children (a_kept[s]); without retire_satisfied these are
+ * k_in[s] and k_kept[s] times the number of inequalities. */
+int pcba_read_trace_patches(const pcba_problem* prob, int64_t* a_in, int64_t* a_kept, int32_t cap);
+
+/* List buffers come from a device arena that keeps freed memory for reuse
+ * (a growing list or a new problem takes it again without a device
+ * allocation).  This returns the arena's fully free chunks to the device. */
+void pcba_release_cached_memory(void);
 
 /* Releases every resource of the problem.  NULL is accepted. */
 void pcba_destroy_problem(pcba_problem* prob);

@@ -80,6 +80,15 @@ __device__ __forceinline__ int unit_class(const DevInst& I, const InstState* st)
     return due ? 2 : 1;
 }
 
+// Units of one step of a problem: every parent has one cost tile and its
+// equality tiles; its inequality tiles are all of them, or in retiring mode as
+// many as the inequalities it still carries need (their sum is st->u1).
+__device__ __forceinline__ long long step_units(const DevInst& I, const InstState* st)
+{
+    const int T1 = I.tile_start[2] - I.tile_start[1];
+    return I.retire ? (long long)st->K * (I.T - T1) + st->u1 : (long long)st->K * I.T;
+}
+
 __global__ __launch_bounds__(1024) void k_plan(const DevInst* __restrict__ insts, int n,
                                                long long* __restrict__ plan,
                                                StepInfo* __restrict__ info)
@@ -102,7 +111,7 @@ __global__ __launch_bounds__(1024) void k_plan(const DevInst* __restrict__ insts
                 else if (2LL * st->K > (int64_t)I.cap) st->status = ST_GROW;
                 else {
                     const int c = unit_class(I, st);
-                    v[c] = (long long)st->K * I.T;
+                    v[c] = step_units(I, st);
                     if (c == 2) v[3] = (long long)st->K * 2 * I.rows;
                 }
             }
@@ -290,6 +299,8 @@ __global__ __launch_bounds__(256) void k_root(const DevInst* __restrict__ insts,
         for (int w = 0; w < (int)(blockDim.x >> 6); ++w) { m = fmax(m, red[0][w]); v = fmax(v, red[1][w]); }
         const double e64 = gamma64(q_total) * m * 1.01;
         I.root_err[poly] = e64;
+        // the root carries every inequality
+        if (I.retire && kind == 1) I.act[0][idx] = idx;
         // FP32: the FP64 bound plus rounding to FP32 (u = 2^-23 relative) plus underflow
         if (I.fp32) I.err[0][poly] = round_up_f(e64 + v * 0x1p-23 + 0x1p-126);
     }
@@ -319,6 +330,16 @@ __global__ void k_reset(const DevInst* __restrict__ insts, int n)
     st->cert_err = 0.0;
     st->err_max = 0.0;
     st->epoch = st->epoch + 1u;
+    const int T1 = I.tile_start[2] - I.tile_start[1];
+    st->u1 = T1;
+    st->a_live = I.count[1];
+    if (I.retire) {
+        I.na[0][0] = I.count[1];
+        I.na[1][0] = 0;
+        I.na[1][1] = 0;
+        I.upre[0] = 0;
+        I.upre[1] = T1;
+    }
     I.live[0] = 0;
     for (int k = 0; k < I.l; ++k) I.ids[0][k] = 0;
     I.flags[0] = 0;
@@ -333,6 +354,8 @@ struct SubLds {
     T* a;        // parent tile, overwritten by the left child
     T* b;        // right child
     typename KeyOf<T>::type* key;  // per patch: minL, maxL, minR, maxR, maxabs(parent)
+    int* id;     // retiring mode, inequality tile: per patch its inequality index ...
+    int* need;   // ... and which children still carry it (bit 0 left, bit 1 right)
 };
 
 // One fibre of fixed length M: de Casteljau with parameter 1/2 in registers.
@@ -436,19 +459,56 @@ __device__ __forceinline__ void tile_split(int np, int S, const FibreGeom& g, Su
     }
 }
 
-// Unit v of a problem with K parents and T tiles: the K cost tiles first (so
-// that the cost bounds of most children are recorded before their constraint
-// tiles start), then the constraint tiles parent by parent.
-__device__ __forceinline__ void unit_of(long long v, int K, int T, int& j, int& t)
+__device__ __forceinline__ long long uniform64(long long x)
 {
+    const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)(x & 0xffffffffll));
+    const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)((unsigned long long)x >> 32));
+    return (long long)(((unsigned long long)hi << 32) | lo);
+}
+
+// Unit v of a problem with K parents: the K cost tiles first (so that the cost
+// bounds of most children are recorded before their constraint tiles start),
+// then the equality tiles parent by parent, then the inequality tiles parent by
+// parent.  In retiring mode parent j owns inequality units [upre[j], upre[j+1]).
+// t is the tile index in item terms: an inequality tile t covers positions
+// (t - tile_start[1]) * tile_polys[1] ... of the parent's carried list.
+__device__ __forceinline__ void unit_of(const DevInst& I, long long v, int K, int& j, int& t)
+{
+    const int T1 = I.tile_start[2] - I.tile_start[1];
+    const int T2 = I.T - I.tile_start[2];
     if (v < K) {
         j = (int)v;
         t = 0;
-    } else {
-        const long long w = v - K;
-        j = (int)(w / (T - 1));
-        t = 1 + (int)(w - (long long)j * (T - 1));
+        return;
     }
+    v -= K;
+    if (v < (long long)K * T2) {
+        j = (int)(v / T2);
+        t = I.tile_start[2] + (int)(v - (long long)j * T2);
+        return;
+    }
+    v -= (long long)K * T2;
+    if (!I.retire) {
+        j = (int)(v / T1);
+        t = I.tile_start[1] + (int)(v - (long long)j * T1);
+        return;
+    }
+    // v is uniform over the workgroup, so are the probes (kept in scalar registers)
+    int lo = 0, hi = K;  // upre[lo] <= v < upre[hi]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (uniform64(I.upre[mid]) <= v) lo = mid; else hi = mid;
+    }
+    j = lo;
+    t = I.tile_start[1] + (int)(v - uniform64(I.upre[lo]));
+}
+
+// Patch index of element e of a tile of patches of S coefficients: e / S,
+// exact for e + S < 2^22 (the float quotient of e + 1/2 stays within 1/(2S)
+// of its integer part plus one half).
+__device__ __forceinline__ int patch_of(int e, float invS)
+{
+    return (int)(((float)e + 0.5f) * invS);
 }
 
 // widened bound of one patch of a child: lo/hi in double
@@ -464,10 +524,14 @@ __device__ __forceinline__ void child_bounds(T mn, T mx, double e, double& lo, d
     }
 }
 
-// Where one unit of k_sub / k_rederive lives (all fields wave-uniform).
+// Where one unit of k_sub / k_rederive lives (all fields wave-uniform).  With
+// gath set (retiring mode, inequality tile) the tile's patches are not
+// contiguous: patch q of the tile is inequality act[q] at toff + act[q] * S.
 struct SubCtx {
-    int bi, j, t, kind, p0, np, S, TE, pslot, cur, r;
+    int bi, j, t, kind, p0, np, S, TE, pslot, cur, r, gath;
     int64_t toff;
+    const int32_t* act;
+    float invS;
     double pprev;
     uint32_t stamp;
 };
@@ -491,7 +555,9 @@ __device__ __forceinline__ void resolve_unit(const DevInst* __restrict__ insts, 
     const DevInst& I = insts[hint];
     const StepInfo si = info[hint];
     c.bi = hint;
-    unit_of(u - pre[hint], si.K, I.T, c.j, c.t);
+    unit_of(I, u - pre[hint], si.K, c.j, c.t);
+    c.j = __builtin_amdgcn_readfirstlane(c.j);
+    c.t = __builtin_amdgcn_readfirstlane(c.t);
     c.cur = si.cur;
     c.r = si.r;
     c.pprev = si.p_up;
@@ -499,10 +565,20 @@ __device__ __forceinline__ void resolve_unit(const DevInst* __restrict__ insts, 
     c.pslot = __builtin_amdgcn_readfirstlane(I.live[c.j]);
     c.kind = (c.t < I.tile_start[1]) ? 0 : ((c.t < I.tile_start[2]) ? 1 : 2);
     c.p0 = (c.t - I.tile_start[c.kind]) * I.tile_polys[c.kind];
-    c.np = min(I.tile_polys[c.kind], I.count[c.kind] - c.p0);
     c.S = I.S[c.kind];
+    c.invS = 1.0f / (float)c.S;
+    c.gath = I.retire && c.kind == 1;
+    if (c.gath) {
+        const int na = __builtin_amdgcn_readfirstlane(I.na[c.cur][c.pslot]);
+        c.np = min(I.tile_polys[1], na - c.p0);
+        c.act = I.act[c.cur] + (int64_t)c.pslot * I.count[1] + c.p0;
+        c.toff = I.off[1];
+    } else {
+        c.np = min(I.tile_polys[c.kind], I.count[c.kind] - c.p0);
+        c.act = nullptr;
+        c.toff = I.off[c.kind] + (int64_t)c.p0 * c.S;
+    }
     c.TE = c.np * c.S;
-    c.toff = I.off[c.kind] + (int64_t)c.p0 * c.S;
 }
 
 // Thread 0 only: flags already OR-ed into the unit's children by other tiles.
@@ -522,6 +598,17 @@ template <typename T, int LB>
 __device__ __forceinline__ void issue_tile(const DevInst& I, const SubCtx& c, T (&v)[LB])
 {
     const T* src = (const T*)I.buf[c.cur] + (int64_t)c.pslot * I.stride + c.toff;
+    if (c.gath) {
+#pragma unroll
+        for (int q = 0; q < LB; ++q) {
+            const int e = threadIdx.x + q * SUB_THREADS;
+            if (e < c.TE) {
+                const int p = patch_of(e, c.invS);
+                v[q] = src[(unsigned)(c.act[p] * c.S + (e - p * c.S))];
+            }
+        }
+        return;
+    }
 #pragma unroll
     for (int q = 0; q < LB; ++q) {
         const int e = threadIdx.x + q * SUB_THREADS;
@@ -562,10 +649,14 @@ __global__ __launch_bounds__(SUB_THREADS) void k_sub(const DevInst* __restrict__
         T* childL = (T*)I.buf[cur ^ 1] + (int64_t)(2 * j) * I.stride;
         T* childR = childL + I.stride;
 
+        const int gath = c.gath;
+        const float invS = c.invS;
         SubLds<T> L;
         L.a = (T*)smem;
         L.b = L.a + TE;
         L.key = (K*)(L.b + TE);
+        L.id = (int*)(L.key + 5 * np);
+        L.need = L.id + np;
         // children already condemned by other tiles (infeasible), or, with the
         // stale filter, whose cost bound exceeds the previous solution estimate
         if (threadIdx.x == 0) {
@@ -596,6 +687,7 @@ __global__ __launch_bounds__(SUB_THREADS) void k_sub(const DevInst* __restrict__
             L.key[5 * p + 2] = ~(K)0;
             L.key[5 * p + 3] = 0;
             L.key[5 * p + 4] = 0;
+            if (gath) L.id[p] = c.act[p];
         }
         const double pprev = c.pprev;
         const uint32_t stamp = c.stamp;
@@ -618,7 +710,7 @@ __global__ __launch_bounds__(SUB_THREADS) void k_sub(const DevInst* __restrict__
             // per-patch bounds (widened in FP32 mode) -> records or flags of both children
             uint32_t fL = 0, fR = 0;
             for (int p = threadIdx.x; p < np; p += blockDim.x) {
-                const int poly = (kind == 0) ? 0 : I.count[0] + (kind == 2 ? I.count[1] : 0) + c.p0 + p;
+                const int poly = (kind == 0) ? 0 : I.count[0] + (kind == 2 ? I.count[1] + c.p0 + p : (gath ? L.id[p] : c.p0 + p));
                 double e = 0.0;
                 if (fp32) {
                     const float ep = I.err[cur][(int64_t)pslot * I.n_polys + poly];
@@ -663,6 +755,9 @@ __global__ __launch_bounds__(SUB_THREADS) void k_sub(const DevInst* __restrict__
                         }
                         if (ch == 0) fL |= f; else fR |= f;
                     }
+                    // an inequality certified satisfied on a child (max B <= 0)
+                    // stays satisfied on all its sub-boxes: the child drops it
+                    if (gath) L.need[p] = (hi[0] <= 0.0 ? 0 : 1) | (hi[1] <= 0.0 ? 0 : 2);
                 }
             }
             if (fL) atomicOr(&s_flag[0], fL);
@@ -676,19 +771,64 @@ __global__ __launch_bounds__(SUB_THREADS) void k_sub(const DevInst* __restrict__
             const bool wl = !deadL && !s_dead[0] && !(s_flag[0] & F_INFEAS);
             const bool wr = !deadR && !s_dead[1] && !(s_flag[1] & F_INFEAS);
             constexpr int SB = 8;
-            for (int e0 = threadIdx.x; e0 < TE; e0 += SB * SUB_THREADS) {
-                T va[SB], vb[SB];
+            if (!gath) {
+                for (int e0 = threadIdx.x; e0 < TE; e0 += SB * SUB_THREADS) {
+                    T va[SB], vb[SB];
 #pragma unroll
-                for (int q = 0; q < SB; ++q) {
-                    const int e = e0 + q * SUB_THREADS;
-                    if (e < TE) { va[q] = L.a[e]; vb[q] = L.b[e]; }
+                    for (int q = 0; q < SB; ++q) {
+                        const int e = e0 + q * SUB_THREADS;
+                        if (e < TE) { va[q] = L.a[e]; vb[q] = L.b[e]; }
+                    }
+#pragma unroll
+                    for (int q = 0; q < SB; ++q) {
+                        const int e = e0 + q * SUB_THREADS;
+                        if (e < TE) {
+                            if (wl) childL[toff + e] = va[q];
+                            if (wr) childR[toff + e] = vb[q];
+                        }
+                    }
                 }
-#pragma unroll
-                for (int q = 0; q < SB; ++q) {
-                    const int e = e0 + q * SUB_THREADS;
-                    if (e < TE) {
-                        if (wl) childL[toff + e] = va[q];
-                        if (wr) childR[toff + e] = vb[q];
+            } else {
+                // each carried patch back to its own offset, for the children that keep it
+                T* cL = childL + toff;
+                T* cR = childR + toff;
+#pragma unroll 2
+                for (int e = threadIdx.x; e < TE; e += SUB_THREADS) {
+                    const int p = patch_of(e, invS);
+                    const int nd = L.need[p];
+                    const unsigned o = (unsigned)(L.id[p] * S + (e - p * S));
+                    if (wl && (nd & 1)) cL[o] = L.a[e];
+                    if (wr && (nd & 2)) cR[o] = L.b[e];
+                }
+                // append the kept inequalities to each live child's carried list:
+                // one reservation per child and tile, ranks by wave ballot
+                if (threadIdx.x < 64) {
+                    const int lane = threadIdx.x;
+                    int cnt[2] = {0, 0};
+                    for (int q0 = 0; q0 < np; q0 += 64) {
+                        const int nd = (q0 + lane < np) ? L.need[q0 + lane] : 0;
+                        cnt[0] += __popcll(__ballot(nd & 1));
+                        cnt[1] += __popcll(__ballot(nd & 2));
+                    }
+                    int base[2] = {0, 0};
+                    const bool w2[2] = {wl, wr};
+                    if (lane == 0)
+                        for (int ch = 0; ch < 2; ++ch)
+                            if (w2[ch] && cnt[ch]) base[ch] = atomicAdd(&I.na[cur ^ 1][2 * j + ch], cnt[ch]);
+                    base[0] = __shfl(base[0], 0, 64);
+                    base[1] = __shfl(base[1], 0, 64);
+                    const unsigned long long below = (1ull << lane) - 1ull;
+                    for (int q0 = 0; q0 < np; q0 += 64) {
+                        const int p = q0 + lane;
+                        const int nd = (p < np) ? L.need[p] : 0;
+                        const int id = (p < np) ? L.id[p] : 0;
+                        for (int ch = 0; ch < 2; ++ch) {
+                            const unsigned long long bal = __ballot((nd >> ch) & 1);
+                            if (w2[ch] && ((nd >> ch) & 1))
+                                I.act[cur ^ 1][(int64_t)(2 * j + ch) * I.count[1] + base[ch] +
+                                               __popcll(bal & below)] = id;
+                            base[ch] += __popcll(bal);
+                        }
                     }
                 }
             }
@@ -845,12 +985,16 @@ __global__ __launch_bounds__(SUB_THREADS) void k_rederive(const DevInst* __restr
         const DevInst& I = insts[bi];
         const StepInfo si = info[bi];
         int j, t;
-        unit_of(u - pre[bi], si.K, I.T, j, t);
+        unit_of(I, u - pre[bi], si.K, j, t);
         const int cur = si.cur, r = si.r, l = I.l;
         const int pslot = __builtin_amdgcn_readfirstlane(I.live[j]);
         const int kind = (t < I.tile_start[1]) ? 0 : ((t < I.tile_start[2]) ? 1 : 2);
         const int p0 = (t - I.tile_start[kind]) * I.tile_polys[kind];
-        const int np = min(I.tile_polys[kind], I.count[kind] - p0);
+        // retiring mode: an inequality tile covers positions p0.. of the parent's carried list
+        const bool gath = I.retire && kind == 1;
+        const int32_t* pact = gath ? I.act[cur] + (int64_t)pslot * I.count[1] : nullptr;
+        const int navail = gath ? __builtin_amdgcn_readfirstlane(I.na[cur][pslot]) : I.count[kind];
+        const int np = min(I.tile_polys[kind], navail - p0);
         const int S = I.S[kind];
         // the tile is processed in chunks of at most MAX_TILE64 coefficients
         const int cp = max(1, MAX_TILE64 / S);
@@ -871,23 +1015,31 @@ __global__ __launch_bounds__(SUB_THREADS) void k_rederive(const DevInst* __restr
             const int q0 = (cc >> 1) * cp;
             const int nq = min(cp, np - q0);
             const int TE = nq * S;
-            const int64_t toff = I.off[kind] + (int64_t)(p0 + q0) * S;
+            const int64_t toff = I.off[kind] + (gath ? 0 : (int64_t)(p0 + q0) * S);
             const double* tsrc = I.tmat + ((int64_t)j * 2 + c) * I.tmw + I.tmk[kind];
             copy_to_lds<double>(tm, tsrc, tmsz);
-            copy_to_lds<double>(x, I.root + toff, TE);
+            if (!gath) {
+                copy_to_lds<double>(x, I.root + toff, TE);
+            } else {
+                for (int e = threadIdx.x; e < TE; e += blockDim.x) {
+                    const int p = e / S;
+                    x[e] = I.root[toff + (int64_t)pact[p0 + q0 + p] * S + (e - p * S)];
+                }
+            }
             __syncthreads();
             apply_tmats(x, y, tm, s_tmoff, I.dims[kind], l, S, nq);
             float* child = (float*)I.buf[cur ^ 1] + (int64_t)(2 * j + c) * I.stride;
             uint32_t fl = 0;
             const int wv = threadIdx.x >> 6;
             for (int p = wv; p < nq; p += blockDim.x >> 6) {
-                const int poly = (kind == 0 ? 0 : I.count[0] + (kind == 2 ? I.count[1] : 0) + p0 + q0 + p);
-                const double* rp = I.root + toff + (int64_t)p * S;
+                const int id = gath ? pact[p0 + q0 + p] : p0 + q0 + p;
+                const int poly = (kind == 0 ? 0 : I.count[0] + (kind == 2 ? I.count[1] : 0) + id);
+                const int64_t po = toff + (int64_t)(gath ? id : p) * S;   // the patch inside an item
+                const double* rp = I.root + po;
                 float mn = INFINITY, mx = -INFINITY;
                 double rmax = 0.0;
                 for (int e = threadIdx.x & 63; e < S; e += 64) {
                     const float v = (float)x[p * S + e];
-                    child[toff + (int64_t)p * S + e] = v;
                     mn = fminf(mn, v);
                     mx = fmaxf(mx, v);
                     rmax = fmax(rmax, fabs(rp[e]));
@@ -897,15 +1049,23 @@ __global__ __launch_bounds__(SUB_THREADS) void k_rederive(const DevInst* __restr
                     mx = fmaxf(mx, __shfl_xor(mx, o, 64));
                     rmax = fmax(rmax, __shfl_xor(rmax, o, 64));
                 }
+                // root bound (rows of T sum to one) + transform rounding on
+                // |T||root| <= max|root| + rounding to FP32 + underflow
+                const double amax = fmax(fabs((double)mn), fabs((double)mx));
+                const double e = (double)round_up_f(I.root_err[poly] + g64 * rmax * 1.01 +
+                                                    amax * 0x1p-23 + 0x1p-126);
+                double lo, hi;
+                child_bounds<float>(mn, mx, e, lo, hi);
+                // retiring mode: an inequality certified satisfied is not carried
+                const bool keep = !(gath && hi <= 0.0);
+                if (keep)
+                    for (int q = threadIdx.x & 63; q < S; q += 64) child[po + q] = (float)x[p * S + q];
                 if ((threadIdx.x & 63) == 0) {
-                    // root bound (rows of T sum to one) + transform rounding on
-                    // |T||root| <= max|root| + rounding to FP32 + underflow
-                    const double amax = fmax(fabs((double)mn), fabs((double)mx));
-                    const double e = (double)round_up_f(I.root_err[poly] + g64 * rmax * 1.01 +
-                                                        amax * 0x1p-23 + 0x1p-126);
                     I.err[cur ^ 1][(int64_t)(2 * j + c) * I.n_polys + poly] = (float)e;
-                    double lo, hi;
-                    child_bounds<float>(mn, mx, e, lo, hi);
+                    if (gath && keep) {
+                        const int pos = atomicAdd(&I.na[cur ^ 1][2 * j + c], 1);
+                        I.act[cur ^ 1][(int64_t)(2 * j + c) * I.count[1] + pos] = id;
+                    }
                     if (kind == 0) {
                         I.minP[2 * j + c] = lo;
                         I.maxP[2 * j + c] = hi;
@@ -946,10 +1106,13 @@ __global__ __launch_bounds__(CUT_THREADS) void k_cut(const DevInst* __restrict__
     __shared__ double shd[CUT_THREADS / 64];
     __shared__ int shi[CUT_THREADS / 64];
     __shared__ int wsum[CUT_THREADS / 64 + 1];
+    __shared__ long long wun[CUT_THREADS / 64 + 1];
+    __shared__ long long wact[CUT_THREADS / 64];
     const DevInst& I = insts[blockIdx.x];
     InstState* st = I.st;
     if (st->status != ST_RUNNING) return;
-    const int K = st->K, C = 2 * K, r = st->r;
+    const int K = st->K, C = 2 * K, r = st->r, cur = st->cur;
+    const int TP1 = I.tile_polys[1];
     const double pprev = st->p_up;
     const bool fin = pprev < INFINITY;
     const int tid = threadIdx.x;
@@ -974,9 +1137,11 @@ __global__ __launch_bounds__(CUT_THREADS) void k_cut(const DevInst* __restrict__
     }
     const double p_up = update ? m : pprev;
 
-    // least lower bound, keep mask, order-preserving compaction into live[]
+    // least lower bound, keep mask, order-preserving compaction into live[];
+    // in retiring mode also the prefix of the kept children's inequality units
     double plo = INFINITY;
     int base = 0;
+    long long ubase = 0, asum = 0;
     const int lane = tid & 63, w = tid >> 6, nw = blockDim.x >> 6;
     for (int c0 = 0; c0 < C; c0 += blockDim.x) {
         const int c = c0 + tid;
@@ -989,25 +1154,64 @@ __global__ __launch_bounds__(CUT_THREADS) void k_cut(const DevInst* __restrict__
                 keep = mnp <= p_up;
             }
         }
+        long long ti = 0;
+        if (keep && I.retire) {
+            const int a = I.na[cur ^ 1][c];
+            ti = (a + TP1 - 1) / TP1;
+            asum += a;
+        }
+        long long ui = ti;   // inclusive scan of the unit counts within the wave
+        for (int o = 1; o < 64; o <<= 1) {
+            const long long y = __shfl_up(ui, o, 64);
+            if (lane >= o) ui += y;
+        }
         const unsigned long long bal = __ballot(keep);
         const int before = __popcll(bal & ((1ull << lane) - 1ull));
         if (lane == 0) wsum[w] = __popcll(bal);
+        if (lane == 63) wun[w] = ui;
         __syncthreads();
         if (tid == 0) {
             int acc = 0;
-            for (int q = 0; q < nw; ++q) { const int v = wsum[q]; wsum[q] = acc; acc += v; }
+            long long uacc = 0;
+            for (int q = 0; q < nw; ++q) {
+                const int v = wsum[q];
+                wsum[q] = acc;
+                acc += v;
+                const long long uv = wun[q];
+                wun[q] = uacc;
+                uacc += uv;
+            }
             wsum[nw] = acc;
+            wun[nw] = uacc;
         }
         __syncthreads();
-        if (keep) I.live[base + wsum[w] + before] = c;
+        if (keep) {
+            I.live[base + wsum[w] + before] = c;
+            if (I.retire) I.upre[base + wsum[w] + before] = ubase + wun[w] + ui - ti;
+        }
         base += wsum[nw];
+        ubase += wun[nw];
         __syncthreads();
     }
     plo = block_min(plo, shd);
     const int Kn = base;
+    // inequality patches carried by the kept children
+    if (I.retire) {
+        for (int o = 32; o > 0; o >>= 1) asum += __shfl_xor(asum, o, 64);
+        if (lane == 0) wact[w] = asum;
+        __syncthreads();
+        asum = 0;
+        for (int q = 0; q < nw; ++q) asum += wact[q];
+    } else {
+        asum = (long long)Kn * I.count[1];
+    }
 
-    // clear the flags of the next step's children
-    for (int c = tid; c < 2 * Kn && c < I.cap; c += blockDim.x) I.flags[c] = 0;
+    // clear the flags of the next step's children, and in retiring mode their
+    // carried counts (they go to the buffer of this step's parents)
+    for (int c = tid; c < 2 * Kn && c < I.cap; c += blockDim.x) {
+        I.flags[c] = 0;
+        if (I.retire) I.na[cur][c] = 0;
+    }
 
     if (tid == 0) {
         if (st->steps < MAX_TRACE) {
@@ -1016,7 +1220,14 @@ __global__ __launch_bounds__(CUT_THREADS) void k_cut(const DevInst* __restrict__
             tr.k_kept = Kn;
             tr.p_up = p_up;
             tr.p_lo = plo;
+            tr.a_in = st->a_live;
+            tr.a_kept = asum;
             I.trace[st->steps] = tr;
+        }
+        st->a_live = asum;
+        if (I.retire) {
+            I.upre[Kn] = ubase;
+            st->u1 = ubase;
         }
         st->depth[r] += 1;
         st->steps += 1;
@@ -1167,7 +1378,25 @@ __global__ void k_pack(DevInst I, double* __restrict__ out, uint32_t* __restrict
     if (j >= st->K) return;
     const int slot = I.live[j];
     const T* src = (const T*)I.buf[st->cur] + (int64_t)slot * I.stride;
-    for (int64_t e = threadIdx.x; e < W; e += blockDim.x) out[(int64_t)j * W + e] = (double)src[e];
+    if (!I.retire) {
+        for (int64_t e = threadIdx.x; e < W; e += blockDim.x) out[(int64_t)j * W + e] = (double)src[e];
+    } else {
+        // inequalities the box no longer carries read back as NaN: first the
+        // whole item with the inequality block as NaN, then the carried patches
+        const int64_t a0 = I.off[1], a1 = I.off[1] + (int64_t)I.count[1] * I.S[1];
+        for (int64_t e = threadIdx.x; e < W; e += blockDim.x)
+            out[(int64_t)j * W + e] = (e >= a0 && e < a1) ? __longlong_as_double(0x7ff8000000000000ll)
+                                                        : (double)src[e];
+        __syncthreads();
+        const int na = I.na[st->cur][slot];
+        const int32_t* act = I.act[st->cur] + (int64_t)slot * I.count[1];
+        const int S = I.S[1];
+        for (int64_t e = threadIdx.x; e < (int64_t)na * S; e += blockDim.x) {
+            const int q = (int)(e / S);
+            const int64_t o = a0 + (int64_t)act[q] * S + (e - (int64_t)q * S);
+            out[(int64_t)j * W + o] = (double)src[o];
+        }
+    }
     if (threadIdx.x < (unsigned)I.l)
         ids_out[(int64_t)j * I.l + threadIdx.x] = I.ids[st->cur][(int64_t)slot * I.l + threadIdx.x];
     if (I.fp32 && err_out)

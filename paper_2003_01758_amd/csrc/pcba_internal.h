@@ -59,6 +59,8 @@ struct InstState {
     double err_max;
     uint32_t epoch;     // incremented by every reset: makes record stamps unique per solve
     uint32_t pad1;
+    int64_t u1;         // retiring mode: inequality units of the next step (sum of tiles)
+    int64_t a_live;     // inequality patches carried by the live parents
 };
 
 // What the step kernels need of a problem's state, published by the plan
@@ -83,6 +85,7 @@ constexpr int MAX_STEPS = 60000; // steps per solve must stay below 65536 (recor
 struct TraceRec {
     int32_t k_in, k_kept;
     double p_up, p_lo;
+    int64_t a_in, a_kept;   // inequality patches carried by the parents / the kept children
 };
 
 // Read-only description of one problem for a launch.
@@ -100,17 +103,23 @@ struct DevInst {
     int32_t N;                     // iteration cap
     int32_t stale;                 // stale-estimate write filter on
     int32_t rederive;              // FP32: re-derive from the FP64 root every this many steps
-    int32_t pad0;
+    int32_t retire;                // retire inequalities certified satisfied on a box
     double eps, delta, eps_eq;
     double width0[MAXL];           // hi - lo of D
     void* buf[2];                  // item buffers (double or float), cap * stride each
     uint32_t* ids[2];              // cap * l box indices
     float* err[2];                 // FP32 mode: cap * n_polys error bounds
-    int32_t* live;                 // cap/2 parent slots
+    int32_t* live;                 // cap: slots of the live items, in list order
     double* minP;                  // child records, cap each
     double* maxP;
     uint32_t* flags;
     uint32_t* stamp;               // cap: step stamp of minP/maxP, set after they are written
+    // retiring mode: a box carries only the inequalities not yet certified
+    // satisfied on it.  act[b][slot*count[1] + q], q < na[b][slot], are their
+    // indices (any order); their patches keep their offsets in the slot.
+    int32_t* act[2];
+    int32_t* na[2];
+    int64_t* upre;                 // cap + 1: first inequality unit of each live item, then the total
     double* tmat;                  // FP32 re-derivation: cap/2 parents x 2 children x tmw doubles
     int32_t tmw;                   // transform words per child: sum over kinds and axes of m^2
     int32_t tmk[KINDS];            // offset of each kind's transforms inside a child's block

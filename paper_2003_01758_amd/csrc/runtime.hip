@@ -12,6 +12,7 @@
 
 #include "../../include/pcba.h"
 #include "kernels.h"
+#include "pool.h"
 
 using namespace pcba;
 
@@ -132,6 +133,10 @@ struct pcba_problem {
     double* d_maxP = nullptr;
     uint32_t* d_flags = nullptr;
     uint32_t* d_stamp = nullptr;
+    int32_t* d_act[2] = {nullptr, nullptr};   // retiring mode: carried inequalities per slot
+    int32_t* d_na[2] = {nullptr, nullptr};
+    int64_t* d_upre = nullptr;
+    bool retire = false;
     double* d_tmat = nullptr;
     int tmw = 0, rows = 0, tmk[KINDS] = {};
     InstState* d_st = nullptr;
@@ -146,6 +151,7 @@ struct pcba_problem {
     double seconds = 0.0;
     double t_start = 0.0;
     int64_t footprint = 0;   // bytes charged by an engine
+    bool list_released = false;  // finished, and its list freed for other problems
     int host_steps = 0;      // steps known on the host (for re-derivation planning)
 };
 
@@ -192,6 +198,7 @@ static DevInst make_dev(const pcba_problem* P)
     I.N = P->opt.max_iters;
     I.stale = P->opt.stale_filter ? 1 : 0;
     I.rederive = P->fp32 ? P->opt.rederive_every : 0;
+    I.retire = P->retire ? 1 : 0;
     I.eps = P->opt.eps;
     I.delta = P->opt.delta;
     I.eps_eq = P->opt.eps_eq;
@@ -200,7 +207,10 @@ static DevInst make_dev(const pcba_problem* P)
         I.buf[b] = P->d_buf[b];
         I.ids[b] = P->d_ids[b];
         I.err[b] = P->d_err[b];
+        I.act[b] = P->d_act[b];
+        I.na[b] = P->d_na[b];
     }
+    I.upre = P->d_upre;
     I.live = P->d_live;
     I.minP = P->d_minP;
     I.maxP = P->d_maxP;
@@ -223,25 +233,32 @@ static DevInst make_dev(const pcba_problem* P)
 
 static int64_t item_bytes(const pcba_problem* P)
 {
-    return P->stride * (int64_t)P->elem + (int64_t)P->l * 4 + (P->fp32 ? P->n_polys * 4 : 0) + 4 + 8 + 8 + 4;
+    return P->stride * (int64_t)P->elem + (int64_t)P->l * 4 + (P->fp32 ? P->n_polys * 4 : 0) + 4 + 8 + 8 + 4 +
+           (P->retire ? (int64_t)P->count[1] * 4 + 4 + 4 : 0);
 }
 
 static void free_list(pcba_problem* P)
 {
     for (int b = 0; b < 2; ++b) {
-        if (P->d_buf[b]) (void)hipFree(P->d_buf[b]);
-        if (P->d_ids[b]) (void)hipFree(P->d_ids[b]);
-        if (P->d_err[b]) (void)hipFree(P->d_err[b]);
+        if (P->d_buf[b]) pool_free(P->d_buf[b]);
+        if (P->d_ids[b]) pool_free(P->d_ids[b]);
+        if (P->d_err[b]) pool_free(P->d_err[b]);
+        if (P->d_act[b]) pool_free(P->d_act[b]);
+        if (P->d_na[b]) pool_free(P->d_na[b]);
         P->d_buf[b] = nullptr;
         P->d_ids[b] = nullptr;
         P->d_err[b] = nullptr;
+        P->d_act[b] = nullptr;
+        P->d_na[b] = nullptr;
     }
-    if (P->d_live) (void)hipFree(P->d_live);
-    if (P->d_minP) (void)hipFree(P->d_minP);
-    if (P->d_maxP) (void)hipFree(P->d_maxP);
-    if (P->d_flags) (void)hipFree(P->d_flags);
-    if (P->d_stamp) (void)hipFree(P->d_stamp);
-    if (P->d_tmat) (void)hipFree(P->d_tmat);
+    if (P->d_upre) pool_free(P->d_upre);
+    P->d_upre = nullptr;
+    if (P->d_live) pool_free(P->d_live);
+    if (P->d_minP) pool_free(P->d_minP);
+    if (P->d_maxP) pool_free(P->d_maxP);
+    if (P->d_flags) pool_free(P->d_flags);
+    if (P->d_stamp) pool_free(P->d_stamp);
+    if (P->d_tmat) pool_free(P->d_tmat);
     P->d_live = nullptr;
     P->d_minP = P->d_maxP = nullptr;
     P->d_flags = nullptr;
@@ -262,34 +279,45 @@ static int alloc_list(pcba_problem* P, int64_t ncap, hipStream_t s)
     uint32_t* nfl = nullptr;
     uint32_t* nst = nullptr;
     double* ntm = nullptr;
+    int32_t* nact[2] = {nullptr, nullptr};
+    int32_t* nna[2] = {nullptr, nullptr};
+    int64_t* nup = nullptr;
     const bool need_tm = P->fp32 && P->opt.rederive_every > 0;
+    const int64_t n_up = ncap + 1;   // kept children (up to ncap) plus the end
     auto cleanup = [&]() {
-        if (nst) (void)hipFree(nst);
-        if (ntm) (void)hipFree(ntm);
+        if (nst) pool_free(nst);
+        if (ntm) pool_free(ntm);
+        if (nup) pool_free(nup);
         for (int b = 0; b < 2; ++b) {
-            if (nb[b]) (void)hipFree(nb[b]);
-            if (ni[b]) (void)hipFree(ni[b]);
-            if (ne[b]) (void)hipFree(ne[b]);
+            if (nb[b]) pool_free(nb[b]);
+            if (ni[b]) pool_free(ni[b]);
+            if (ne[b]) pool_free(ne[b]);
+            if (nact[b]) pool_free(nact[b]);
+            if (nna[b]) pool_free(nna[b]);
         }
-        if (nlive) (void)hipFree(nlive);
-        if (nmin) (void)hipFree(nmin);
-        if (nmax) (void)hipFree(nmax);
-        if (nfl) (void)hipFree(nfl);
+        if (nlive) pool_free(nlive);
+        if (nmin) pool_free(nmin);
+        if (nmax) pool_free(nmax);
+        if (nfl) pool_free(nfl);
     };
     bool ok = true;
     for (int b = 0; b < 2 && ok; ++b) {
-        ok = hipMalloc(&nb[b], (size_t)ncap * P->stride * P->elem) == hipSuccess &&
-             hipMalloc((void**)&ni[b], (size_t)ncap * P->l * sizeof(uint32_t)) == hipSuccess;
+        ok = pool_alloc(&nb[b], (size_t)ncap * P->stride * P->elem) == hipSuccess &&
+             pool_alloc((void**)&ni[b], (size_t)ncap * P->l * sizeof(uint32_t)) == hipSuccess;
         if (ok && P->fp32)
-            ok = hipMalloc((void**)&ne[b], (size_t)ncap * P->n_polys * sizeof(float)) == hipSuccess;
+            ok = pool_alloc((void**)&ne[b], (size_t)ncap * P->n_polys * sizeof(float)) == hipSuccess;
+        if (ok && P->retire)
+            ok = pool_alloc((void**)&nact[b], (size_t)ncap * P->count[1] * sizeof(int32_t)) == hipSuccess &&
+                 pool_alloc((void**)&nna[b], (size_t)ncap * sizeof(int32_t)) == hipSuccess;
     }
-    ok = ok && hipMalloc((void**)&nlive, (size_t)ncap * sizeof(int32_t)) == hipSuccess &&
-         hipMalloc((void**)&nmin, (size_t)ncap * sizeof(double)) == hipSuccess &&
-         hipMalloc((void**)&nmax, (size_t)ncap * sizeof(double)) == hipSuccess &&
-         hipMalloc((void**)&nfl, (size_t)ncap * sizeof(uint32_t)) == hipSuccess &&
-         hipMalloc((void**)&nst, (size_t)ncap * sizeof(uint32_t)) == hipSuccess;
+    if (ok && P->retire) ok = pool_alloc((void**)&nup, (size_t)n_up * sizeof(int64_t)) == hipSuccess;
+    ok = ok && pool_alloc((void**)&nlive, (size_t)ncap * sizeof(int32_t)) == hipSuccess &&
+         pool_alloc((void**)&nmin, (size_t)ncap * sizeof(double)) == hipSuccess &&
+         pool_alloc((void**)&nmax, (size_t)ncap * sizeof(double)) == hipSuccess &&
+         pool_alloc((void**)&nfl, (size_t)ncap * sizeof(uint32_t)) == hipSuccess &&
+         pool_alloc((void**)&nst, (size_t)ncap * sizeof(uint32_t)) == hipSuccess;
     if (ok && need_tm)
-        ok = hipMalloc((void**)&ntm, (size_t)(ncap / 2 + 1) * 2 * P->tmw * sizeof(double)) == hipSuccess;
+        ok = pool_alloc((void**)&ntm, (size_t)(ncap / 2 + 1) * 2 * P->tmw * sizeof(double)) == hipSuccess;
     if (!ok) {
         (void)hipGetLastError();
         cleanup();
@@ -297,6 +325,8 @@ static int alloc_list(pcba_problem* P, int64_t ncap, hipStream_t s)
     }
     hipError_t e = hipMemsetAsync(nfl, 0, (size_t)ncap * sizeof(uint32_t), s);
     if (e == hipSuccess) e = hipMemsetAsync(nst, 0, (size_t)ncap * sizeof(uint32_t), s);
+    for (int b = 0; b < 2 && e == hipSuccess && P->retire; ++b)
+        e = hipMemsetAsync(nna[b], 0, (size_t)ncap * sizeof(int32_t), s);
     if (e == hipSuccess && P->cap > 0) {
         const int cur = P->h_st.cur;
         const int64_t used = std::min<int64_t>(P->cap, ncap);
@@ -311,6 +341,16 @@ static int alloc_list(pcba_problem* P, int64_t ncap, hipStream_t s)
         if (e == hipSuccess)
             e = hipMemcpyAsync(nlive, P->d_live, (size_t)used * sizeof(int32_t),
                                hipMemcpyDeviceToDevice, s);
+        if (e == hipSuccess && P->retire) {
+            e = hipMemcpyAsync(nact[cur], P->d_act[cur], (size_t)used * P->count[1] * sizeof(int32_t),
+                               hipMemcpyDeviceToDevice, s);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(nna[cur], P->d_na[cur], (size_t)used * sizeof(int32_t),
+                                   hipMemcpyDeviceToDevice, s);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(nup, P->d_upre, (size_t)std::min<int64_t>(n_up, P->cap + 1) * sizeof(int64_t),
+                                   hipMemcpyDeviceToDevice, s);
+        }
         if (e == hipSuccess) e = hipStreamSynchronize(s);
     }
     if (e != hipSuccess) {
@@ -322,7 +362,10 @@ static int alloc_list(pcba_problem* P, int64_t ncap, hipStream_t s)
         P->d_buf[b] = nb[b];
         P->d_ids[b] = ni[b];
         P->d_err[b] = ne[b];
+        P->d_act[b] = nact[b];
+        P->d_na[b] = nna[b];
     }
+    P->d_upre = nup;
     P->d_live = nlive;
     P->d_minP = nmin;
     P->d_maxP = nmax;
@@ -399,6 +442,13 @@ static int upload_descs(pcba_problem* const* probs, int n, Scratch& sc, hipStrea
 static int reset_batch(pcba_problem* const* probs, int n, hipStream_t s)
 {
     if (n <= 0) return PCBA_OK;
+    for (int b = 0; b < n; ++b) {
+        pcba_problem* P = probs[b];
+        if (!P->list_released) continue;
+        int rc = alloc_list(P, std::max<int64_t>(2, std::min<int64_t>(P->M_eff, CAP0)), s);
+        if (rc != PCBA_OK) return rc;
+        P->list_released = false;
+    }
     DevInst* d_insts = nullptr;
     int* d_pre = nullptr;
     int total = 0, max_S = 1, tmw = 1;
@@ -442,6 +492,7 @@ void pcba_default_options(pcba_options* o)
     o->precision = PCBA_FP64_PLAIN;
     o->rederive_every = 8;
     o->stale_filter = 0;
+    o->retire_satisfied = 1;
     o->time_limit_s = 0.0;
 }
 
@@ -469,6 +520,8 @@ int pcba_create_problem(int32_t l, const double* lo, const double* hi, const int
     if (o.precision != PCBA_FP64_PLAIN && o.precision != PCBA_FP32)
         return fail(PCBA_E_ARG, "unknown precision");
     if (o.rederive_every < 0) return fail(PCBA_E_ARG, "rederive_every must be >= 0");
+    if (o.retire_satisfied != 0 && o.retire_satisfied != 1)
+        return fail(PCBA_E_ARG, "retire_satisfied must be 0 or 1");
     for (int k = 0; k < l; ++k)
         if (!std::isfinite(lo[k]) || !std::isfinite(hi[k]) || !(hi[k] > lo[k]))
             return fail(PCBA_E_ARG, "box bounds must be finite with lo < hi");
@@ -478,6 +531,7 @@ int pcba_create_problem(int32_t l, const double* lo, const double* hi, const int
     for (int k = 0; k < l; ++k) { P->lo[k] = lo[k]; P->hi[k] = hi[k]; }
     P->opt = o;
     P->fp32 = o.precision == PCBA_FP32;
+    P->retire = o.retire_satisfied == 1 && n_ineq > 0;
     P->elem = P->fp32 ? 4 : 8;
     P->count[0] = 1;
     P->count[1] = n_ineq;
@@ -592,7 +646,8 @@ int pcba_create_problem(int32_t l, const double* lo, const double* hi, const int
         return fail(PCBA_E_DEVICE, "hipMemGetInfo failed (no device?)");
     }
     const int64_t per_item = 2 * item_bytes(P);
-    const int64_t hbm_items = (int64_t)((double)free_b * 0.85) / std::max<int64_t>(1, per_item);
+    const double avail = (double)free_b + (double)pool_cached_bytes();   // cached blocks are reusable
+    const int64_t hbm_items = (int64_t)(avail * 0.85) / std::max<int64_t>(1, per_item);
     P->M_eff = std::min<int64_t>(o.max_boxes, std::max<int64_t>(2, hbm_items));
     if (P->M_eff < 2) {
         delete P;
@@ -670,6 +725,22 @@ int pcba_read_trace(const pcba_problem* P, int32_t* k_in, int32_t* k_kept, doubl
     }
     return n;
 }
+
+int pcba_read_trace_patches(const pcba_problem* P, int64_t* a_in, int64_t* a_kept, int32_t cap)
+{
+    if (!P || cap < 0) return fail(PCBA_E_ARG, "bad arguments");
+    const int n = std::min<int>(std::min<int>(P->h_st.steps, MAX_TRACE), cap);
+    if (n <= 0) return 0;
+    std::vector<TraceRec> h(n);
+    HIP_TRY(hipMemcpy(h.data(), P->d_trace, n * sizeof(TraceRec), hipMemcpyDeviceToHost));
+    for (int i = 0; i < n; ++i) {
+        if (a_in) a_in[i] = h[i].a_in;
+        if (a_kept) a_kept[i] = h[i].a_kept;
+    }
+    return n;
+}
+
+void pcba_release_cached_memory(void) { pool_trim(); }
 
 void pcba_profile_enable(int32_t on) { g_prof.on = on != 0; }
 void pcba_profile_reset(void)
@@ -807,7 +878,8 @@ static size_t sub_lds(const pcba_problem* P)
             TP = std::max(TP, P->tile_polys[t]);
         }
     const size_t key = P->fp32 ? 4 : 8;
-    return 2 * (size_t)TE * P->elem + 5 * (size_t)TP * key + 16;
+    // keys, and in retiring mode the index and the keep bits of every patch
+    return 2 * (size_t)TE * P->elem + 5 * (size_t)TP * key + (P->retire ? 8 * (size_t)TP : 0) + 16;
 }
 static size_t rederive_lds(const pcba_problem* P)
 {
@@ -842,6 +914,22 @@ static int certify_batch(pcba_engine* E, std::vector<pcba_problem*>& fin)
         fin[b]->seconds = t - fin[b]->t_start;
     }
     return PCBA_OK;
+}
+
+// Frees the lists of the finished problems the engine still holds (their
+// results stay readable; pcba_reset allocates a list again).  Returns the count.
+static int release_done_lists(pcba_engine* E)
+{
+    int k = 0;
+    (void)hipStreamSynchronize(E->stream);
+    for (auto* P : E->done) {
+        if (P->list_released || P->cap == 0) continue;
+        free_list(P);
+        P->cap = 0;
+        P->list_released = true;
+        k += 1;
+    }
+    return k;
 }
 
 // One batch of up to n_steps steps over the active problems, then a sync.
@@ -920,25 +1008,46 @@ static int engine_steps(pcba_engine* E, int n_steps)
     // growth, time limits, finished problems
     const double t = now_s();
     std::vector<pcba_problem*> still, fin;
+    // some problem will step again, or finish, without growing
+    bool progress = false;
+    for (int b = 0; b < n; ++b)
+        if (E->h_states[b].status != ST_GROW) progress = true;
     for (int b = 0; b < n; ++b) {
         pcba_problem* P = E->active[b];
         P->h_st = E->h_states[b];
         P->host_steps = P->h_st.steps;
         if (P->h_st.status == ST_GROW) {
-            const int64_t want = std::min<int64_t>(P->M_eff, std::max<int64_t>(2 * P->cap, 4 * (int64_t)P->h_st.K));
+            // room for this step's children with a quarter to spare, and at least
+            // half again the current capacity (bounded by M)
+            const int64_t need = 2 * (int64_t)P->h_st.K;
+            const int64_t want = std::min<int64_t>(P->M_eff, std::max<int64_t>(need + need / 4, P->cap + P->cap / 2));
             const int64_t extra = pcba_footprint_bytes(P, std::max(want, E->reserve)) - P->footprint;
             if (b > 0 && extra > 0 && E->used + extra > E->budget) {
                 still.push_back(P);   // stays paused until the budget has room
                 continue;
             }
-            int rc = alloc_list(P, want, E->stream);
+            // try only what can fit: the new list comes on top of the old one
+            // for the copy; finished problems give their lists back first
+            const int64_t nbytes = pcba_footprint_bytes(P, want);
+            int rc = PCBA_E_NOMEM;
+            if ((int64_t)pool_available_bytes() < nbytes) release_done_lists(E);
+            if ((int64_t)pool_available_bytes() >= nbytes) {
+                rc = alloc_list(P, want, E->stream);
+                if (rc != PCBA_OK && release_done_lists(E) > 0) rc = alloc_list(P, want, E->stream);
+            }
             InstState& st = P->h_st;
             if (rc == PCBA_OK) {
                 st.status = ST_RUNNING;
+            } else if (progress) {
+                // the device is full: wait, paused, until other problems finish
+                still.push_back(P);
+                continue;
             } else {
-                // the device cannot hold the next step: the memory test fires
+                // nothing else can free memory: the memory test fires, and the
+                // list this problem releases lets the others continue
                 P->M_eff = P->cap;
                 st.status = ST_MEMLIMIT;
+                progress = true;
             }
             HIP_TRY(hipMemcpyAsync(P->d_st, &st, sizeof(st), hipMemcpyHostToDevice, E->stream));
             HIP_TRY(hipStreamSynchronize(E->stream));
@@ -946,6 +1055,7 @@ static int engine_steps(pcba_engine* E, int n_steps)
             const int64_t fp = pcba_footprint_bytes(P, std::max(P->cap, E->reserve));
             E->used += fp - P->footprint;
             P->footprint = fp;
+            if (st.status == ST_RUNNING) progress = true;
         }
         if (P->h_st.status == ST_RUNNING && P->opt.time_limit_s > 0 &&
             t - P->t_start > P->opt.time_limit_s) {
@@ -1015,6 +1125,12 @@ int pcba_solve_batch(pcba_problem* const* probs, int32_t n, void* stream)
         }
         probs[i]->t_start = t0;
     }
+    // lists then grow within 85% of the HBM still free: a problem whose growth
+    // does not fit waits for others to finish instead of failing, so a result
+    // does not depend on what else is in the batch (the oldest always grows)
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) == hipSuccess)
+        E->budget = E->used + (int64_t)(0.85 * ((double)free_b + (double)pool_cached_bytes()));
     while (!E->active.empty()) {
         rc = engine_steps(E, STEPS_PER_SYNC);
         if (rc != PCBA_OK) break;
@@ -1092,6 +1208,7 @@ static int read_list_impl(const pcba_problem* P, uint32_t* ids, double* patches,
                           int64_t cap)
 {
     const int K = P->h_st.K;
+    if (P->list_released) return fail(PCBA_E_STATE, "the list was released to make room for other problems");
     if (cap < K) return fail(PCBA_E_ARG, "capacity smaller than the list");
     if (K == 0) return PCBA_OK;
     hipStream_t s = nullptr;

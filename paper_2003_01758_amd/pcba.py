@@ -28,7 +28,7 @@ class Options(C.Structure):
     _fields_ = [("eps", C.c_double), ("delta", C.c_double), ("eps_eq", C.c_double),
                 ("max_boxes", C.c_int64), ("max_iters", C.c_int32), ("precision", C.c_int32),
                 ("rederive_every", C.c_int32), ("stale_filter", C.c_int32),
-                ("time_limit_s", C.c_double)]
+                ("retire_satisfied", C.c_int32), ("time_limit_s", C.c_double)]
 
 
 class Result(C.Structure):
@@ -109,6 +109,10 @@ def lib():
         L.pcba_reset.restype = C.c_int
         L.pcba_read_trace.argtypes = [vp, vp, vp, vp, vp, i32]
         L.pcba_read_trace.restype = C.c_int
+        L.pcba_read_trace_patches.argtypes = [vp, vp, vp, i32]
+        L.pcba_read_trace_patches.restype = C.c_int
+        L.pcba_release_cached_memory.argtypes = []
+        L.pcba_release_cached_memory.restype = None
         L.pcba_profile_enable.argtypes = [i32]
         L.pcba_profile_enable.restype = None
         L.pcba_profile_reset.argtypes = []
@@ -153,7 +157,7 @@ class Problem:
     """Problem (P) on the device.  `inst` is an instances.Instance-like object;
     keyword options override its tolerances (eps, delta, eps_eq, max_boxes,
     max_iters) and set precision ('fp64'|'fp32'), rederive_every, stale_filter,
-    time_limit_s."""
+    retire_satisfied, time_limit_s."""
 
     def __init__(self, inst, **kw):
         L = lib()
@@ -241,6 +245,17 @@ class Problem:
             _check(n)
         return dict(k_in=k_in[:n], k_kept=k_kept[:n], p_up=p_up[:n], p_lo=p_lo[:n])
 
+    def trace_patches(self):
+        """Per-step inequality patches carried by the parents (a_in) and by the
+        kept children (a_kept) in the last solve."""
+        cap = MAX_TRACE
+        a_in = np.zeros(cap, dtype=np.int64)
+        a_kept = np.zeros(cap, dtype=np.int64)
+        n = lib().pcba_read_trace_patches(self.h, a_in.ctypes.data, a_kept.ctypes.data, cap)
+        if n < 0:
+            _check(n)
+        return dict(a_in=a_in[:n], a_kept=a_kept[:n])
+
     def root(self) -> np.ndarray:
         out = np.empty(self.words, dtype=np.float64)
         _check(lib().pcba_read_root(self.h, out.ctypes.data))
@@ -251,6 +266,11 @@ class Problem:
 
     def footprint(self, boxes: int) -> int:
         return int(lib().pcba_footprint_bytes(self.h, int(boxes)))
+
+
+def release_cached_memory():
+    """Returns the fully free chunks of the library's device arena."""
+    lib().pcba_release_cached_memory()
 
 
 def profile_enable(on: bool = True):

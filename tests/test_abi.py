@@ -38,6 +38,9 @@ def test_default_options_and_argument_validation_without_device():
     from paper_2003_01758_amd import pcba
     o = pcba.default_options()
     assert o.eps == 1e-3 and o.delta == 1e-4 and o.max_iters == 28 and o.max_boxes == 1 << 20
+    # the C side fills every field: a layout mismatch would misplace these
+    assert o.rederive_every == 8 and o.stale_filter == 0 and o.retire_satisfied == 1
+    assert o.time_limit_s == 0.0 and ctypes.sizeof(o) == 64
     # argument errors are detected before any device call
     L = pcba.lib()
     h = ctypes.c_void_p()
@@ -62,6 +65,10 @@ def test_default_options_and_argument_validation_without_device():
     rc = L.pcba_create_problem(2, lo.ctypes.data, hi.ctypes.data, deg.ctypes.data, coef.ctypes.data,
                                0, None, None, 0, None, None, ctypes.byref(bad), ctypes.byref(h))
     assert rc == pcba.E_ARG
+    bad = pcba.default_options(retire_satisfied=2)
+    rc = L.pcba_create_problem(2, lo.ctypes.data, hi.ctypes.data, deg.ctypes.data, coef.ctypes.data,
+                               0, None, None, 0, None, None, ctypes.byref(bad), ctypes.byref(h))
+    assert rc == pcba.E_ARG and b"retire_satisfied" in L.pcba_last_error()
     deg16 = np.array([16, 1], dtype=np.int32)
     rc = L.pcba_create_problem(2, lo.ctypes.data, hi.ctypes.data, deg16.ctypes.data,
                                np.ones(34).ctypes.data, 0, None, None, 0, None, None, None,
