@@ -108,7 +108,8 @@ __global__ __launch_bounds__(1024) void k_plan(const DevInst* __restrict__ insts
                 // holds pauses the problem until the host grows the list
                 if ((int64_t)st->K > st->peak) st->peak = st->K;
                 if (2LL * st->K > (int64_t)I.M) st->status = ST_MEMLIMIT;
-                else if (2LL * st->K > (int64_t)I.cap) st->status = ST_GROW;
+                else if (2LL * st->K > (int64_t)I.cap || (I.retire && 2 * st->a_live > I.hcap))
+                    st->status = ST_GROW;
                 else {
                     const int c = unit_class(I, st);
                     v[c] = step_units(I, st);
@@ -276,14 +277,19 @@ __global__ __launch_bounds__(256) void k_root(const DevInst* __restrict__ insts,
                 __syncthreads();
             }
         }
+        // the root item: slot 0 of buffer 0, or in retiring mode for an
+        // inequality its heap patch idx
+        const bool inheap = I.retire && kind == 1;
+        void* dbase = inheap ? I.heap[0] : I.buf[0];
+        const int64_t doff = inheap ? (int64_t)idx * S : I.soff[kind] + (int64_t)idx * S;
         for (int e = threadIdx.x; e < S; e += blockDim.x) {
             if (absp) {
                 amax = fmax(amax, x[e]);
             } else {
                 I.root[off + e] = x[e];
                 vmax = fmax(vmax, fabs(x[e]));
-                if (I.fp32) ((float*)I.buf[0])[off + e] = (float)x[e];
-                else ((double*)I.buf[0])[off + e] = x[e];
+                if (I.fp32) ((float*)dbase)[doff + e] = (float)x[e];
+                else ((double*)dbase)[doff + e] = x[e];
             }
         }
         __syncthreads();
@@ -300,7 +306,7 @@ __global__ __launch_bounds__(256) void k_root(const DevInst* __restrict__ insts,
         const double e64 = gamma64(q_total) * m * 1.01;
         I.root_err[poly] = e64;
         // the root carries every inequality
-        if (I.retire && kind == 1) I.act[0][idx] = idx;
+        if (I.retire && kind == 1) I.act[0][idx] = make_int2(idx, idx);
         // FP32: the FP64 bound plus rounding to FP32 (u = 2^-23 relative) plus underflow
         if (I.fp32) I.err[0][poly] = round_up_f(e64 + v * 0x1p-23 + 0x1p-126);
     }
@@ -333,6 +339,8 @@ __global__ void k_reset(const DevInst* __restrict__ insts, int n)
     const int T1 = I.tile_start[2] - I.tile_start[1];
     st->u1 = T1;
     st->a_live = I.count[1];
+    st->htop[0] = I.retire ? I.count[1] : 0;
+    st->htop[1] = 0;
     if (I.retire) {
         I.na[0][0] = I.count[1];
         I.na[1][0] = 0;
@@ -354,8 +362,9 @@ struct SubLds {
     T* a;        // parent tile, overwritten by the left child
     T* b;        // right child
     typename KeyOf<T>::type* key;  // per patch: minL, maxL, minR, maxR, maxabs(parent)
-    int* id;     // retiring mode, inequality tile: per patch its inequality index ...
-    int* need;   // ... and which children still carry it (bit 0 left, bit 1 right)
+    int* id;     // retiring mode, inequality tile: per patch its inequality index, then
+    int* need;   // which children still carry it (bit 0 left, bit 1 right), then
+    int* dst;    // its heap patch in the left child (np entries) and the right (np)
 };
 
 // One fibre of fixed length M: de Casteljau with parameter 1/2 in registers.
@@ -530,7 +539,7 @@ __device__ __forceinline__ void child_bounds(T mn, T mx, double e, double& lo, d
 struct SubCtx {
     int bi, j, t, kind, p0, np, S, TE, pslot, cur, r, gath;
     int64_t toff;
-    const int32_t* act;
+    const int2* act;
     float invS;
     double pprev;
     uint32_t stamp;
@@ -572,11 +581,11 @@ __device__ __forceinline__ void resolve_unit(const DevInst* __restrict__ insts, 
         const int na = __builtin_amdgcn_readfirstlane(I.na[c.cur][c.pslot]);
         c.np = min(I.tile_polys[1], na - c.p0);
         c.act = I.act[c.cur] + (int64_t)c.pslot * I.count[1] + c.p0;
-        c.toff = I.off[1];
+        c.toff = 0;
     } else {
         c.np = min(I.tile_polys[c.kind], I.count[c.kind] - c.p0);
         c.act = nullptr;
-        c.toff = I.off[c.kind] + (int64_t)c.p0 * c.S;
+        c.toff = I.soff[c.kind] + (int64_t)c.p0 * c.S;
     }
     c.TE = c.np * c.S;
 }
@@ -597,18 +606,19 @@ __device__ __forceinline__ void load_hint(const DevInst& I, const SubCtx& c, uin
 template <typename T, int LB>
 __device__ __forceinline__ void issue_tile(const DevInst& I, const SubCtx& c, T (&v)[LB])
 {
-    const T* src = (const T*)I.buf[c.cur] + (int64_t)c.pslot * I.stride + c.toff;
     if (c.gath) {
+        const T* hsrc = (const T*)I.heap[c.cur];
 #pragma unroll
         for (int q = 0; q < LB; ++q) {
             const int e = threadIdx.x + q * SUB_THREADS;
             if (e < c.TE) {
                 const int p = patch_of(e, c.invS);
-                v[q] = src[(unsigned)(c.act[p] * c.S + (e - p * c.S))];
+                v[q] = hsrc[(int64_t)c.act[p].y * c.S + (e - p * c.S)];
             }
         }
         return;
     }
+    const T* src = (const T*)I.buf[c.cur] + (int64_t)c.pslot * I.stride + c.toff;
 #pragma unroll
     for (int q = 0; q < LB; ++q) {
         const int e = threadIdx.x + q * SUB_THREADS;
@@ -657,6 +667,7 @@ __global__ __launch_bounds__(SUB_THREADS) void k_sub(const DevInst* __restrict__
         L.key = (K*)(L.b + TE);
         L.id = (int*)(L.key + 5 * np);
         L.need = L.id + np;
+        L.dst = L.need + np;
         // children already condemned by other tiles (infeasible), or, with the
         // stale filter, whose cost bound exceeds the previous solution estimate
         if (threadIdx.x == 0) {
@@ -687,7 +698,7 @@ __global__ __launch_bounds__(SUB_THREADS) void k_sub(const DevInst* __restrict__
             L.key[5 * p + 2] = ~(K)0;
             L.key[5 * p + 3] = 0;
             L.key[5 * p + 4] = 0;
-            if (gath) L.id[p] = c.act[p];
+            if (gath) L.id[p] = c.act[p].x;
         }
         const double pprev = c.pprev;
         const uint32_t stamp = c.stamp;
@@ -789,47 +800,60 @@ __global__ __launch_bounds__(SUB_THREADS) void k_sub(const DevInst* __restrict__
                     }
                 }
             } else {
-                // each carried patch back to its own offset, for the children that keep it
-                T* cL = childL + toff;
-                T* cR = childR + toff;
-#pragma unroll 2
-                for (int e = threadIdx.x; e < TE; e += SUB_THREADS) {
-                    const int p = patch_of(e, invS);
-                    const int nd = L.need[p];
-                    const unsigned o = (unsigned)(L.id[p] * S + (e - p * S));
-                    if (wl && (nd & 1)) cL[o] = L.a[e];
-                    if (wr && (nd & 2)) cR[o] = L.b[e];
-                }
-                // append the kept inequalities to each live child's carried list:
-                // one reservation per child and tile, ranks by wave ballot
+                // wave 0 appends the kept inequalities to each live child: one
+                // reservation per child and tile in its carried list and in the
+                // heap of buffer cur^1, ranks by wave ballot, and the heap patch
+                // of every (patch, child) into LDS for the stores below
                 if (threadIdx.x < 64) {
                     const int lane = threadIdx.x;
+                    const bool w2[2] = {wl, wr};
                     int cnt[2] = {0, 0};
                     for (int q0 = 0; q0 < np; q0 += 64) {
                         const int nd = (q0 + lane < np) ? L.need[q0 + lane] : 0;
                         cnt[0] += __popcll(__ballot(nd & 1));
                         cnt[1] += __popcll(__ballot(nd & 2));
                     }
-                    int base[2] = {0, 0};
-                    const bool w2[2] = {wl, wr};
+                    int pos[2] = {0, 0};
+                    long long hb[2] = {0, 0};
                     if (lane == 0)
                         for (int ch = 0; ch < 2; ++ch)
-                            if (w2[ch] && cnt[ch]) base[ch] = atomicAdd(&I.na[cur ^ 1][2 * j + ch], cnt[ch]);
-                    base[0] = __shfl(base[0], 0, 64);
-                    base[1] = __shfl(base[1], 0, 64);
+                            if (w2[ch] && cnt[ch]) {
+                                pos[ch] = atomicAdd(&I.na[cur ^ 1][2 * j + ch], cnt[ch]);
+                                hb[ch] = (long long)atomicAdd((unsigned long long*)&I.st->htop[cur ^ 1],
+                                                              (unsigned long long)cnt[ch]);
+                            }
+                    for (int ch = 0; ch < 2; ++ch) {
+                        pos[ch] = __shfl(pos[ch], 0, 64);
+                        hb[ch] = __shfl(hb[ch], 0, 64);
+                    }
                     const unsigned long long below = (1ull << lane) - 1ull;
                     for (int q0 = 0; q0 < np; q0 += 64) {
                         const int p = q0 + lane;
                         const int nd = (p < np) ? L.need[p] : 0;
                         const int id = (p < np) ? L.id[p] : 0;
                         for (int ch = 0; ch < 2; ++ch) {
-                            const unsigned long long bal = __ballot((nd >> ch) & 1);
-                            if (w2[ch] && ((nd >> ch) & 1))
-                                I.act[cur ^ 1][(int64_t)(2 * j + ch) * I.count[1] + base[ch] +
-                                               __popcll(bal & below)] = id;
-                            base[ch] += __popcll(bal);
+                            const bool k = w2[ch] && ((nd >> ch) & 1);
+                            const unsigned long long bal = __ballot(k);
+                            const int rank = __popcll(bal & below);
+                            if (k)
+                                I.act[cur ^ 1][(int64_t)(2 * j + ch) * I.count[1] + pos[ch] + rank] =
+                                    make_int2(id, (int)(hb[ch] + rank));
+                            if (p < np) L.dst[ch * np + p] = k ? (int)(hb[ch] + rank) : -1;
+                            pos[ch] += __popcll(bal);
+                            hb[ch] += __popcll(bal);
                         }
                     }
+                }
+                lds_barrier();
+                // each kept patch to its heap patch
+                T* hc = (T*)I.heap[cur ^ 1];
+#pragma unroll 2
+                for (int e = threadIdx.x; e < TE; e += SUB_THREADS) {
+                    const int p = patch_of(e, invS);
+                    const int dl = L.dst[p], dr = L.dst[np + p];
+                    const int r = e - p * S;
+                    if (dl >= 0) hc[(int64_t)dl * S + r] = L.a[e];
+                    if (dr >= 0) hc[(int64_t)dr * S + r] = L.b[e];
                 }
             }
             lds_barrier();
@@ -992,7 +1016,7 @@ __global__ __launch_bounds__(SUB_THREADS) void k_rederive(const DevInst* __restr
         const int p0 = (t - I.tile_start[kind]) * I.tile_polys[kind];
         // retiring mode: an inequality tile covers positions p0.. of the parent's carried list
         const bool gath = I.retire && kind == 1;
-        const int32_t* pact = gath ? I.act[cur] + (int64_t)pslot * I.count[1] : nullptr;
+        const int2* pact = gath ? I.act[cur] + (int64_t)pslot * I.count[1] : nullptr;
         const int navail = gath ? __builtin_amdgcn_readfirstlane(I.na[cur][pslot]) : I.count[kind];
         const int np = min(I.tile_polys[kind], navail - p0);
         const int S = I.S[kind];
@@ -1015,27 +1039,29 @@ __global__ __launch_bounds__(SUB_THREADS) void k_rederive(const DevInst* __restr
             const int q0 = (cc >> 1) * cp;
             const int nq = min(cp, np - q0);
             const int TE = nq * S;
-            const int64_t toff = I.off[kind] + (gath ? 0 : (int64_t)(p0 + q0) * S);
+            // the chunk's patches in the root (root layout) and in a slot
+            const int64_t roff = I.off[kind] + (gath ? 0 : (int64_t)(p0 + q0) * S);
+            const int64_t soff = I.soff[kind] + (int64_t)(p0 + q0) * S;
             const double* tsrc = I.tmat + ((int64_t)j * 2 + c) * I.tmw + I.tmk[kind];
             copy_to_lds<double>(tm, tsrc, tmsz);
             if (!gath) {
-                copy_to_lds<double>(x, I.root + toff, TE);
+                copy_to_lds<double>(x, I.root + roff, TE);
             } else {
                 for (int e = threadIdx.x; e < TE; e += blockDim.x) {
                     const int p = e / S;
-                    x[e] = I.root[toff + (int64_t)pact[p0 + q0 + p] * S + (e - p * S)];
+                    x[e] = I.root[roff + (int64_t)pact[p0 + q0 + p].x * S + (e - p * S)];
                 }
             }
             __syncthreads();
             apply_tmats(x, y, tm, s_tmoff, I.dims[kind], l, S, nq);
             float* child = (float*)I.buf[cur ^ 1] + (int64_t)(2 * j + c) * I.stride;
+            float* hc = (float*)I.heap[cur ^ 1];
             uint32_t fl = 0;
             const int wv = threadIdx.x >> 6;
             for (int p = wv; p < nq; p += blockDim.x >> 6) {
-                const int id = gath ? pact[p0 + q0 + p] : p0 + q0 + p;
+                const int id = gath ? pact[p0 + q0 + p].x : p0 + q0 + p;
                 const int poly = (kind == 0 ? 0 : I.count[0] + (kind == 2 ? I.count[1] : 0) + id);
-                const int64_t po = toff + (int64_t)(gath ? id : p) * S;   // the patch inside an item
-                const double* rp = I.root + po;
+                const double* rp = I.root + roff + (int64_t)(gath ? id : p) * S;
                 float mn = INFINITY, mx = -INFINITY;
                 double rmax = 0.0;
                 for (int e = threadIdx.x & 63; e < S; e += 64) {
@@ -1056,16 +1082,22 @@ __global__ __launch_bounds__(SUB_THREADS) void k_rederive(const DevInst* __restr
                                                     amax * 0x1p-23 + 0x1p-126);
                 double lo, hi;
                 child_bounds<float>(mn, mx, e, lo, hi);
-                // retiring mode: an inequality certified satisfied is not carried
+                // retiring mode: an inequality certified satisfied is not carried;
+                // a carried one goes to a heap patch reserved by lane 0
                 const bool keep = !(gath && hi <= 0.0);
-                if (keep)
-                    for (int q = threadIdx.x & 63; q < S; q += 64) child[po + q] = (float)x[p * S + q];
+                long long hx = 0;
+                if (gath && keep && (threadIdx.x & 63) == 0) {
+                    const int pos = atomicAdd(&I.na[cur ^ 1][2 * j + c], 1);
+                    hx = (long long)atomicAdd((unsigned long long*)&I.st->htop[cur ^ 1], 1ull);
+                    I.act[cur ^ 1][(int64_t)(2 * j + c) * I.count[1] + pos] = make_int2(id, (int)hx);
+                }
+                hx = __shfl(hx, 0, 64);
+                if (keep) {
+                    float* dp = gath ? hc + hx * S : child + soff + (int64_t)p * S;
+                    for (int q = threadIdx.x & 63; q < S; q += 64) dp[q] = (float)x[p * S + q];
+                }
                 if ((threadIdx.x & 63) == 0) {
                     I.err[cur ^ 1][(int64_t)(2 * j + c) * I.n_polys + poly] = (float)e;
-                    if (gath && keep) {
-                        const int pos = atomicAdd(&I.na[cur ^ 1][2 * j + c], 1);
-                        I.act[cur ^ 1][(int64_t)(2 * j + c) * I.count[1] + pos] = id;
-                    }
                     if (kind == 0) {
                         I.minP[2 * j + c] = lo;
                         I.maxP[2 * j + c] = hi;
@@ -1228,6 +1260,7 @@ __global__ __launch_bounds__(CUT_THREADS) void k_cut(const DevInst* __restrict__
         if (I.retire) {
             I.upre[Kn] = ubase;
             st->u1 = ubase;
+            st->htop[cur] = 0;   // this step's parents' heap takes the next children
         }
         st->depth[r] += 1;
         st->steps += 1;
@@ -1377,24 +1410,28 @@ __global__ void k_pack(DevInst I, double* __restrict__ out, uint32_t* __restrict
     const int j = blockIdx.x;
     if (j >= st->K) return;
     const int slot = I.live[j];
-    const T* src = (const T*)I.buf[st->cur] + (int64_t)slot * I.stride;
-    if (!I.retire) {
-        for (int64_t e = threadIdx.x; e < W; e += blockDim.x) out[(int64_t)j * W + e] = (double)src[e];
-    } else {
-        // inequalities the box no longer carries read back as NaN: first the
-        // whole item with the inequality block as NaN, then the carried patches
-        const int64_t a0 = I.off[1], a1 = I.off[1] + (int64_t)I.count[1] * I.S[1];
-        for (int64_t e = threadIdx.x; e < W; e += blockDim.x)
-            out[(int64_t)j * W + e] = (e >= a0 && e < a1) ? __longlong_as_double(0x7ff8000000000000ll)
-                                                        : (double)src[e];
+    const int cur = st->cur;
+    const T* src = (const T*)I.buf[cur] + (int64_t)slot * I.stride;
+    double* o = out + (int64_t)j * W;
+    // cost and equalities from the slot; the inequalities from the slot, or in
+    // retiring mode NaN except the carried ones, which come from the heap
+    const double nan = __longlong_as_double(0x7ff8000000000000ll);
+    for (int kind = 0; kind < KINDS; ++kind) {
+        const int64_t n = (int64_t)I.count[kind] * I.S[kind];
+        const bool inheap = I.retire && kind == 1;
+        for (int64_t e = threadIdx.x; e < n; e += blockDim.x)
+            o[I.off[kind] + e] = inheap ? nan : (double)src[I.soff[kind] + e];
+    }
+    if (I.retire) {
         __syncthreads();
-        const int na = I.na[st->cur][slot];
-        const int32_t* act = I.act[st->cur] + (int64_t)slot * I.count[1];
-        const int S = I.S[1];
+        const int na = I.na[cur][slot];
+        const int2* act = I.act[cur] + (int64_t)slot * I.count[1];
+        const T* h = (const T*)I.heap[cur];
+        const int64_t S = I.S[1];
         for (int64_t e = threadIdx.x; e < (int64_t)na * S; e += blockDim.x) {
-            const int q = (int)(e / S);
-            const int64_t o = a0 + (int64_t)act[q] * S + (e - (int64_t)q * S);
-            out[(int64_t)j * W + o] = (double)src[o];
+            const int64_t q = e / S;
+            const int2 a = act[q];
+            o[I.off[1] + (int64_t)a.x * S + (e - q * S)] = (double)h[(int64_t)a.y * S + (e - q * S)];
         }
     }
     if (threadIdx.x < (unsigned)I.l)

@@ -61,6 +61,7 @@ struct InstState {
     uint32_t pad1;
     int64_t u1;         // retiring mode: inequality units of the next step (sum of tiles)
     int64_t a_live;     // inequality patches carried by the live parents
+    int64_t htop[2];    // retiring mode: patches appended to each buffer's heap
 };
 
 // What the step kernels need of a problem's state, published by the plan
@@ -96,7 +97,9 @@ struct DevInst {
     int32_t count[KINDS];          // 1, alpha, beta
     int32_t tile_polys[KINDS];     // patches per tile
     int32_t tile_start[KINDS + 1]; // first tile of each kind; tile_start[KINDS] = T
-    int64_t off[KINDS];            // element offset of each kind inside an item
+    int64_t off[KINDS];            // element offset of each kind inside an item (root layout)
+    int64_t soff[KINDS];           // the same inside a list slot (retiring mode keeps the
+                                   // inequalities out of the slots, in the heaps)
     int64_t stride;                // elements per item slot
     int32_t M;                     // memory-test bound
     int32_t cap;                   // slots per buffer
@@ -116,9 +119,13 @@ struct DevInst {
     uint32_t* stamp;               // cap: step stamp of minP/maxP, set after they are written
     // retiring mode: a box carries only the inequalities not yet certified
     // satisfied on it.  act[b][slot*count[1] + q], q < na[b][slot], are their
-    // indices (any order); their patches keep their offsets in the slot.
-    int32_t* act[2];
+    // (index, heap patch) pairs, in any order; the patch itself is S[1]
+    // coefficients at heap[b] + heap_patch * S[1].  Each step appends the
+    // children's patches to the heap of buffer cur^1 (reserving with htop).
+    int2* act[2];
     int32_t* na[2];
+    void* heap[2];
+    int64_t hcap;                  // patches each heap holds
     int64_t* upre;                 // cap + 1: first inequality unit of each live item, then the total
     double* tmat;                  // FP32 re-derivation: cap/2 parents x 2 children x tmw doubles
     int32_t tmw;                   // transform words per child: sum over kinds and axes of m^2

@@ -108,6 +108,7 @@ struct pcba_problem {
     int S[KINDS] = {};
     int count[KINDS] = {};
     int64_t off[KINDS] = {};
+    int64_t soff[KINDS] = {};   // offsets inside a list slot
     int64_t W = 0;
     int n_polys = 0;
     pcba_options opt{};
@@ -133,8 +134,10 @@ struct pcba_problem {
     double* d_maxP = nullptr;
     uint32_t* d_flags = nullptr;
     uint32_t* d_stamp = nullptr;
-    int32_t* d_act[2] = {nullptr, nullptr};   // retiring mode: carried inequalities per slot
+    int2* d_act[2] = {nullptr, nullptr};   // retiring mode: carried inequalities per slot
     int32_t* d_na[2] = {nullptr, nullptr};
+    void* d_heap[2] = {nullptr, nullptr};  // retiring mode: the carried inequality patches
+    int64_t hcap = 0;                      // patches per heap
     int64_t* d_upre = nullptr;
     bool retire = false;
     double* d_tmat = nullptr;
@@ -190,6 +193,7 @@ static DevInst make_dev(const pcba_problem* P)
         I.tile_polys[t] = P->tile_polys[t];
         I.tile_start[t] = P->tile_start[t];
         I.off[t] = P->off[t];
+        I.soff[t] = P->soff[t];
     }
     I.tile_start[KINDS] = P->tile_start[KINDS];
     I.stride = P->stride;
@@ -209,7 +213,9 @@ static DevInst make_dev(const pcba_problem* P)
         I.err[b] = P->d_err[b];
         I.act[b] = P->d_act[b];
         I.na[b] = P->d_na[b];
+        I.heap[b] = P->d_heap[b];
     }
+    I.hcap = P->hcap;
     I.upre = P->d_upre;
     I.live = P->d_live;
     I.minP = P->d_minP;
@@ -234,7 +240,22 @@ static DevInst make_dev(const pcba_problem* P)
 static int64_t item_bytes(const pcba_problem* P)
 {
     return P->stride * (int64_t)P->elem + (int64_t)P->l * 4 + (P->fp32 ? P->n_polys * 4 : 0) + 4 + 8 + 8 + 4 +
-           (P->retire ? (int64_t)P->count[1] * 4 + 4 + 4 : 0);
+           (P->retire ? (int64_t)P->count[1] * 8 + 4 + 8 : 0);
+}
+
+// Device bytes of a problem with `boxes` slots per buffer and heaps of `hcap`
+// patches: two buffers of slots, two heaps, the root and records.
+static int64_t footprint_of(const pcba_problem* P, int64_t boxes, int64_t hcap)
+{
+    return 2 * boxes * item_bytes(P) + (P->retire ? 2 * hcap * P->S[1] * (int64_t)P->elem : 0) +
+           P->W * 8 + P->n_polys * 32 + (int64_t)sizeof(InstState);
+}
+
+// Heap patches of a fresh list: the root's inequalities, and room for both
+// children of the root (and a little more) before the first growth.
+static int64_t hcap0(const pcba_problem* P)
+{
+    return P->retire ? std::max<int64_t>(2, 4 * (int64_t)P->count[1]) : 0;
 }
 
 static void free_list(pcba_problem* P)
@@ -245,6 +266,8 @@ static void free_list(pcba_problem* P)
         if (P->d_err[b]) pool_free(P->d_err[b]);
         if (P->d_act[b]) pool_free(P->d_act[b]);
         if (P->d_na[b]) pool_free(P->d_na[b]);
+        if (P->d_heap[b]) pool_free(P->d_heap[b]);
+        P->d_heap[b] = nullptr;
         P->d_buf[b] = nullptr;
         P->d_ids[b] = nullptr;
         P->d_err[b] = nullptr;
@@ -266,11 +289,14 @@ static void free_list(pcba_problem* P)
     P->d_tmat = nullptr;
 }
 
-// (Re)allocates the list for `ncap` slots per buffer, keeping the current
-// parents: the slots [0, old cap) of the parent buffer, their ids and error
-// terms, and the live list are copied; the flags are cleared.
-static int alloc_list(pcba_problem* P, int64_t ncap, hipStream_t s)
+// (Re)allocates the list for `ncap` slots per buffer and, in retiring mode,
+// heaps of `nhcap` inequality patches, keeping the current parents: the slots
+// [0, old cap) of the parent buffer, their ids, error terms, carried lists and
+// heap patches, and the live list are copied; the flags are cleared.
+static int alloc_list(pcba_problem* P, int64_t ncap, int64_t nhcap, hipStream_t s)
 {
+    if (P->retire && nhcap > INT32_MAX)
+        return fail(PCBA_E_NOMEM, "an inequality heap would exceed 2^31 patches");
     void* nb[2] = {nullptr, nullptr};
     uint32_t* ni[2] = {nullptr, nullptr};
     float* ne[2] = {nullptr, nullptr};
@@ -279,8 +305,9 @@ static int alloc_list(pcba_problem* P, int64_t ncap, hipStream_t s)
     uint32_t* nfl = nullptr;
     uint32_t* nst = nullptr;
     double* ntm = nullptr;
-    int32_t* nact[2] = {nullptr, nullptr};
+    int2* nact[2] = {nullptr, nullptr};
     int32_t* nna[2] = {nullptr, nullptr};
+    void* nhp[2] = {nullptr, nullptr};
     int64_t* nup = nullptr;
     const bool need_tm = P->fp32 && P->opt.rederive_every > 0;
     const int64_t n_up = ncap + 1;   // kept children (up to ncap) plus the end
@@ -294,6 +321,7 @@ static int alloc_list(pcba_problem* P, int64_t ncap, hipStream_t s)
             if (ne[b]) pool_free(ne[b]);
             if (nact[b]) pool_free(nact[b]);
             if (nna[b]) pool_free(nna[b]);
+            if (nhp[b]) pool_free(nhp[b]);
         }
         if (nlive) pool_free(nlive);
         if (nmin) pool_free(nmin);
@@ -307,8 +335,9 @@ static int alloc_list(pcba_problem* P, int64_t ncap, hipStream_t s)
         if (ok && P->fp32)
             ok = pool_alloc((void**)&ne[b], (size_t)ncap * P->n_polys * sizeof(float)) == hipSuccess;
         if (ok && P->retire)
-            ok = pool_alloc((void**)&nact[b], (size_t)ncap * P->count[1] * sizeof(int32_t)) == hipSuccess &&
-                 pool_alloc((void**)&nna[b], (size_t)ncap * sizeof(int32_t)) == hipSuccess;
+            ok = pool_alloc((void**)&nact[b], (size_t)ncap * P->count[1] * sizeof(int2)) == hipSuccess &&
+                 pool_alloc((void**)&nna[b], (size_t)ncap * sizeof(int32_t)) == hipSuccess &&
+                 pool_alloc(&nhp[b], (size_t)nhcap * P->S[1] * P->elem) == hipSuccess;
     }
     if (ok && P->retire) ok = pool_alloc((void**)&nup, (size_t)n_up * sizeof(int64_t)) == hipSuccess;
     ok = ok && pool_alloc((void**)&nlive, (size_t)ncap * sizeof(int32_t)) == hipSuccess &&
@@ -342,8 +371,13 @@ static int alloc_list(pcba_problem* P, int64_t ncap, hipStream_t s)
             e = hipMemcpyAsync(nlive, P->d_live, (size_t)used * sizeof(int32_t),
                                hipMemcpyDeviceToDevice, s);
         if (e == hipSuccess && P->retire) {
-            e = hipMemcpyAsync(nact[cur], P->d_act[cur], (size_t)used * P->count[1] * sizeof(int32_t),
+            e = hipMemcpyAsync(nact[cur], P->d_act[cur], (size_t)used * P->count[1] * sizeof(int2),
                                hipMemcpyDeviceToDevice, s);
+            // the parents' heap patches: everything appended to that heap so far
+            const int64_t hused = std::min<int64_t>(P->h_st.htop[cur], std::min(P->hcap, nhcap));
+            if (e == hipSuccess && hused > 0)
+                e = hipMemcpyAsync(nhp[cur], P->d_heap[cur], (size_t)hused * P->S[1] * P->elem,
+                                   hipMemcpyDeviceToDevice, s);
             if (e == hipSuccess)
                 e = hipMemcpyAsync(nna[cur], P->d_na[cur], (size_t)used * sizeof(int32_t),
                                    hipMemcpyDeviceToDevice, s);
@@ -364,7 +398,9 @@ static int alloc_list(pcba_problem* P, int64_t ncap, hipStream_t s)
         P->d_err[b] = ne[b];
         P->d_act[b] = nact[b];
         P->d_na[b] = nna[b];
+        P->d_heap[b] = nhp[b];
     }
+    P->hcap = P->retire ? nhcap : 0;
     P->d_upre = nup;
     P->d_live = nlive;
     P->d_minP = nmin;
@@ -445,7 +481,7 @@ static int reset_batch(pcba_problem* const* probs, int n, hipStream_t s)
     for (int b = 0; b < n; ++b) {
         pcba_problem* P = probs[b];
         if (!P->list_released) continue;
-        int rc = alloc_list(P, std::max<int64_t>(2, std::min<int64_t>(P->M_eff, CAP0)), s);
+        int rc = alloc_list(P, std::max<int64_t>(2, std::min<int64_t>(P->M_eff, CAP0)), hcap0(P), s);
         if (rc != PCBA_OK) return rc;
         P->list_released = false;
     }
@@ -563,8 +599,18 @@ int pcba_create_problem(int32_t l, const double* lo, const double* hi, const int
     P->W = P->off[2] + (int64_t)P->count[2] * P->S[2];
     P->n_polys = 1 + n_ineq + n_eq;
     P->max_S = std::max(P->S[0], std::max(P->S[1], P->S[2]));
+    // a list slot holds the item in the same layout, except in retiring mode,
+    // where the inequalities live in the heaps and a slot is the cost, then
+    // the equalities
+    for (int t = 0; t < KINDS; ++t) P->soff[t] = P->off[t];
+    int64_t slot_words = P->W;
+    if (P->retire) {
+        P->soff[1] = P->S[0];
+        P->soff[2] = P->S[0];
+        slot_words = P->S[0] + (int64_t)P->count[2] * P->S[2];
+    }
     const int64_t align = P->fp32 ? 64 : 32;  // 256-byte item slots
-    P->stride = (P->W + align - 1) / align * align;
+    P->stride = (slot_words + align - 1) / align * align;
     // tiles: the cost alone, then runs of constraint patches of ~TILE_ELEMS coefficients
     P->tile_polys[0] = 1;
     P->tile_start[0] = 0;
@@ -671,7 +717,7 @@ int pcba_create_problem(int32_t l, const double* lo, const double* hi, const int
         return fail(PCBA_E_NOMEM, "device allocation failed");
     }
     const int64_t cap0 = std::min<int64_t>(P->M_eff, CAP0);
-    int rc = alloc_list(P, std::max<int64_t>(2, cap0), s);
+    int rc = alloc_list(P, std::max<int64_t>(2, cap0), hcap0(P), s);
     if (rc != PCBA_OK) {
         std::string m = g_last_error;
         (void)hipStreamDestroy(s);
@@ -777,8 +823,7 @@ int64_t pcba_item_bytes(const pcba_problem* P) { return P ? item_bytes(P) : 0; }
 int64_t pcba_footprint_bytes(const pcba_problem* P, int64_t boxes)
 {
     if (!P) return 0;
-    // two buffers of `boxes` slots each, plus the root and records
-    return 2 * boxes * item_bytes(P) + P->W * 8 + P->n_polys * 32 + (int64_t)sizeof(InstState);
+    return footprint_of(P, boxes, P->hcap);
 }
 
 // ---------------------------------------------------------------- engine
@@ -878,8 +923,9 @@ static size_t sub_lds(const pcba_problem* P)
             TP = std::max(TP, P->tile_polys[t]);
         }
     const size_t key = P->fp32 ? 4 : 8;
-    // keys, and in retiring mode the index and the keep bits of every patch
-    return 2 * (size_t)TE * P->elem + 5 * (size_t)TP * key + (P->retire ? 8 * (size_t)TP : 0) + 16;
+    // keys, and in retiring mode per patch its index, which children keep it,
+    // and its heap patch in each child (4 ints)
+    return 2 * (size_t)TE * P->elem + 5 * (size_t)TP * key + (P->retire ? 16 * (size_t)TP : 0) + 16;
 }
 static size_t rederive_lds(const pcba_problem* P)
 {
@@ -1018,22 +1064,28 @@ static int engine_steps(pcba_engine* E, int n_steps)
         P->host_steps = P->h_st.steps;
         if (P->h_st.status == ST_GROW) {
             // room for this step's children with a quarter to spare, and at least
-            // half again the current capacity (bounded by M)
+            // half again the current capacity (bounded by M); in retiring mode the
+            // same for the heap, whose children take at most twice the carried
+            // patches of the parents
             const int64_t need = 2 * (int64_t)P->h_st.K;
-            const int64_t want = std::min<int64_t>(P->M_eff, std::max<int64_t>(need + need / 4, P->cap + P->cap / 2));
-            const int64_t extra = pcba_footprint_bytes(P, std::max(want, E->reserve)) - P->footprint;
+            int64_t want = P->cap, hwant = P->hcap;
+            if (need > P->cap)
+                want = std::min<int64_t>(P->M_eff, std::max<int64_t>(need + need / 4, P->cap + P->cap / 2));
+            const int64_t hneed = 2 * P->h_st.a_live;
+            if (P->retire && hneed > P->hcap) hwant = std::max<int64_t>(hneed + hneed / 4, P->hcap + P->hcap / 2);
+            const int64_t extra = footprint_of(P, std::max(want, E->reserve), hwant) - P->footprint;
             if (b > 0 && extra > 0 && E->used + extra > E->budget) {
                 still.push_back(P);   // stays paused until the budget has room
                 continue;
             }
             // try only what can fit: the new list comes on top of the old one
             // for the copy; finished problems give their lists back first
-            const int64_t nbytes = pcba_footprint_bytes(P, want);
+            const int64_t nbytes = footprint_of(P, want, hwant);
             int rc = PCBA_E_NOMEM;
             if ((int64_t)pool_available_bytes() < nbytes) release_done_lists(E);
             if ((int64_t)pool_available_bytes() >= nbytes) {
-                rc = alloc_list(P, want, E->stream);
-                if (rc != PCBA_OK && release_done_lists(E) > 0) rc = alloc_list(P, want, E->stream);
+                rc = alloc_list(P, want, hwant, E->stream);
+                if (rc != PCBA_OK && release_done_lists(E) > 0) rc = alloc_list(P, want, hwant, E->stream);
             }
             InstState& st = P->h_st;
             if (rc == PCBA_OK) {
