@@ -9,6 +9,8 @@ namespace pcba {
 
 hipError_t launch_reset_root(const DevInst* d_insts, int n, const int* d_pre, int total_polys,
                              int max_S, hipStream_t s);
+hipError_t launch_racc(const DevInst* d_insts, int n, const int* d_pre, int total_polys, int max_S,
+                       hipStream_t s);
 hipError_t launch_plan(const DevInst* d_insts, int n, long long* plan, StepInfo* info, hipStream_t s);
 hipError_t launch_sub(const DevInst* d_insts, int n, const long long* plan, const StepInfo* info,
                       bool fp32, int maxm, int grid, size_t lds, hipStream_t s);

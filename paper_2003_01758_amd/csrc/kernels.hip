@@ -231,10 +231,11 @@ __device__ __forceinline__ void poly_kind(const DevInst& I, int poly, int& kind,
 // InitPatches: one workgroup per (problem, polynomial), blocks of problem b
 // are [pre[b], pre[b+1]).  Per axis r, the pre-map matrix A (x = lo + w t
 // substituted) then the conversion matrix U are applied; every output
-// coefficient is one thread's sum over i in increasing order.  A second pass
-// runs the same chain on |coefficients| with |matrices|; its largest value
-// times gamma bounds the FP64 rounding error.  The root item is written into
-// slot 0 of buffer 0 in the working precision, with its error bound in FP32 mode.
+// coefficient is one thread's sum over i in increasing order.  The result is
+// the list's root item in FP64 plain mode (slot 0 of buffer 0) and is kept in
+// `root`.  In FP32 mode the root item is formed from the accurate root racc
+// instead: its midrange as the FP64 base, FP32 offsets from it, and the bound
+// root_err plus the offsets' rounding.
 __global__ __launch_bounds__(256) void k_root(const DevInst* __restrict__ insts, int n,
                                              const int* __restrict__ pre)
 {
@@ -249,66 +250,130 @@ __global__ __launch_bounds__(256) void k_root(const DevInst* __restrict__ insts,
     const int64_t off = I.off[kind] + (int64_t)idx * S;
     double* x = sh;
     double* y = sh + S;
-    int q_total = 2;
-    double amax = 0.0, vmax = 0.0;
+    for (int e = threadIdx.x; e < S; e += blockDim.x) x[e] = I.mono[off + e];
+    __syncthreads();
+    for (int r = 0; r < I.l; ++r) {
+        FibreGeom g = fibre_geom(I.dims[kind], I.l, r, S);
+        const double* A = I.mats + I.matoff[kind * MAXL + r];
+        const double* U = A + g.m * g.m;
+        for (int pass = 0; pass < 2; ++pass) {
+            const double* Mx = pass ? U : A;
+            const double* src = pass ? y : x;
+            double* dst = pass ? x : y;
+            for (int o = threadIdx.x; o < S; o += blockDim.x) {
+                const int k = (o / g.stride) % g.m;
+                const int fb = o - k * g.stride;
+                double acc = 0.0;
+                for (int i = 0; i < g.m; ++i) acc += Mx[k * g.m + i] * src[fb + i * g.stride];
+                dst[o] = acc;
+            }
+            __syncthreads();
+        }
+    }
+    // the root item: slot 0 of buffer 0, or in retiring mode for an
+    // inequality its heap patch idx
+    const bool inheap = I.retire && kind == 1;
+    void* dbase = inheap ? I.heap[0] : I.buf[0];
+    const int64_t doff = inheap ? (int64_t)idx * S : I.soff[kind] + (int64_t)idx * S;
+    for (int e = threadIdx.x; e < S; e += blockDim.x) I.root[off + e] = x[e];
+    if (!I.fp32) {
+        for (int e = threadIdx.x; e < S; e += blockDim.x) ((double*)dbase)[doff + e] = x[e];
+        if (threadIdx.x == 0 && inheap) I.act[0][idx] = make_int2(idx, idx);
+        return;
+    }
+    // FP32: offsets from the midrange of the accurate root patch
+    const double* ra = I.racc + off;
+    double mn = INFINITY, mx = -INFINITY;
+    for (int e = threadIdx.x; e < S; e += blockDim.x) {
+        mn = fmin(mn, ra[e]);
+        mx = fmax(mx, ra[e]);
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        mn = fmin(mn, __shfl_xor(mn, o, 64));
+        mx = fmax(mx, __shfl_xor(mx, o, 64));
+    }
+    if ((threadIdx.x & 63) == 0) { red[0][threadIdx.x >> 6] = mn; red[1][threadIdx.x >> 6] = mx; }
+    __syncthreads();
+    mn = red[0][0];
+    mx = red[1][0];
+    for (int w = 1; w < (int)(blockDim.x >> 6); ++w) { mn = fmin(mn, red[0][w]); mx = fmax(mx, red[1][w]); }
+    const double pbase = 0.5 * mn + 0.5 * mx;
+    __syncthreads();
+    double hr = 0.0;
+    for (int e = threadIdx.x; e < S; e += blockDim.x) {
+        const float d = (float)(ra[e] - pbase);
+        hr = fmax(hr, fabs((double)d));
+        ((float*)dbase)[doff + e] = d;
+    }
+    for (int o = 32; o > 0; o >>= 1) hr = fmax(hr, __shfl_xor(hr, o, 64));
+    if ((threadIdx.x & 63) == 0) red[0][threadIdx.x >> 6] = hr;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < (int)(blockDim.x >> 6); ++w) hr = fmax(hr, red[0][w]);
+        if (inheap) I.act[0][idx] = make_int2(idx, idx);
+        // the accurate root's bound, the rounding of the offsets (the FP64
+        // difference and the conversion, 2^-23 of the largest), underflow
+        I.err[0][poly] = round_up_f(I.root_err[poly] + hr * 0x1p-23 + 0x1p-126);
+        I.base[0][poly] = pbase;
+    }
+}
+
+// The accurate root, once per problem: per axis r one product with the
+// combined matrix M (Bernstein coefficients on [lo, hi] of each monomial,
+// formed by the polar form: M[k][j] is the average of lo^(j-i) hi^i over the
+// hypergeometric weights C(k,i) C(n-k,j-i) / C(n,j), so no entry suffers
+// cancellation), then the same chain on |coefficients| with Mabs (the sums of
+// the terms' magnitudes).  Each entry of M is within gamma_46 Mabs of the exact
+// one (at most 31 roundings per term, 15 in the sum) and each product adds
+// gamma_m, so root_err = gamma_q times the |.| chain, q summing 47 + m per axis
+// plus a few, is a rigorous bound on |racc - exact|.
+__global__ __launch_bounds__(256) void k_racc(const DevInst* __restrict__ insts, int n,
+                                             const int* __restrict__ pre)
+{
+    extern __shared__ double sh[];
+    __shared__ double red[4];
+    const int bi = find_block(pre, n, blockIdx.x);
+    const DevInst& I = insts[bi];
+    const int poly = blockIdx.x - pre[bi];
+    int kind, idx;
+    poly_kind(I, poly, kind, idx);
+    const int S = I.S[kind];
+    const int64_t off = I.off[kind] + (int64_t)idx * S;
+    double* x = sh;
+    double* y = sh + S;
+    int q = 4;
+    double amax = 0.0;
     for (int absp = 0; absp < 2; ++absp) {
-        for (int e = threadIdx.x; e < S; e += blockDim.x)
-            x[e] = absp ? fabs(I.mono[off + e]) : I.mono[off + e];
+        for (int e = threadIdx.x; e < S; e += blockDim.x) x[e] = absp ? fabs(I.mono[off + e]) : I.mono[off + e];
         __syncthreads();
         for (int r = 0; r < I.l; ++r) {
             FibreGeom g = fibre_geom(I.dims[kind], I.l, r, S);
-            const double* A = I.mats + I.matoff[kind * MAXL + r];
-            const double* U = A + g.m * g.m;
-            if (absp) q_total += 2 * (g.m + 4);
-            for (int pass = 0; pass < 2; ++pass) {
-                const double* Mx = pass ? U : A;
-                const double* src = pass ? y : x;
-                double* dst = pass ? x : y;
-                for (int o = threadIdx.x; o < S; o += blockDim.x) {
-                    const int k = (o / g.stride) % g.m;
-                    const int base = o - k * g.stride;
-                    double acc = 0.0;
-                    for (int i = 0; i < g.m; ++i) {
-                        const double mk = absp ? fabs(Mx[k * g.m + i]) : Mx[k * g.m + i];
-                        acc += mk * src[base + i * g.stride];
-                    }
-                    dst[o] = acc;
-                }
-                __syncthreads();
+            const double* Mx = I.macc + I.matoff[kind * MAXL + r] + (absp ? g.m * g.m : 0);
+            if (absp) q += 47 + g.m;
+            for (int o = threadIdx.x; o < S; o += blockDim.x) {
+                const int k = (o / g.stride) % g.m;
+                const int fb = o - k * g.stride;
+                double acc = 0.0;
+                for (int i = 0; i < g.m; ++i) acc += Mx[k * g.m + i] * x[fb + i * g.stride];
+                y[o] = acc;
             }
+            __syncthreads();
+            for (int e = threadIdx.x; e < S; e += blockDim.x) x[e] = y[e];
+            __syncthreads();
         }
-        // the root item: slot 0 of buffer 0, or in retiring mode for an
-        // inequality its heap patch idx
-        const bool inheap = I.retire && kind == 1;
-        void* dbase = inheap ? I.heap[0] : I.buf[0];
-        const int64_t doff = inheap ? (int64_t)idx * S : I.soff[kind] + (int64_t)idx * S;
         for (int e = threadIdx.x; e < S; e += blockDim.x) {
-            if (absp) {
-                amax = fmax(amax, x[e]);
-            } else {
-                I.root[off + e] = x[e];
-                vmax = fmax(vmax, fabs(x[e]));
-                if (I.fp32) ((float*)dbase)[doff + e] = (float)x[e];
-                else ((double*)dbase)[doff + e] = x[e];
-            }
+            if (absp) amax = fmax(amax, x[e]);
+            else I.racc[off + e] = x[e];
         }
         __syncthreads();
     }
-    for (int o = 32; o > 0; o >>= 1) {
-        amax = fmax(amax, __shfl_xor(amax, o, 64));
-        vmax = fmax(vmax, __shfl_xor(vmax, o, 64));
-    }
-    if ((threadIdx.x & 63) == 0) { red[0][threadIdx.x >> 6] = amax; red[1][threadIdx.x >> 6] = vmax; }
+    for (int o = 32; o > 0; o >>= 1) amax = fmax(amax, __shfl_xor(amax, o, 64));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = amax;
     __syncthreads();
     if (threadIdx.x == 0) {
-        double m = 0.0, v = 0.0;
-        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) { m = fmax(m, red[0][w]); v = fmax(v, red[1][w]); }
-        const double e64 = gamma64(q_total) * m * 1.01;
-        I.root_err[poly] = e64;
-        // the root carries every inequality
-        if (I.retire && kind == 1) I.act[0][idx] = make_int2(idx, idx);
-        // FP32: the FP64 bound plus rounding to FP32 (u = 2^-23 relative) plus underflow
-        if (I.fp32) I.err[0][poly] = round_up_f(e64 + v * 0x1p-23 + 0x1p-126);
+        for (int w = 1; w < (int)(blockDim.x >> 6); ++w) amax = fmax(amax, red[w]);
+        // the |.| chain is itself rounded (below gamma_q relative): 1.01
+        I.root_err[poly] = gamma64(q) * amax * 1.01;
     }
 }
 
@@ -520,16 +585,20 @@ __device__ __forceinline__ int patch_of(int e, float invS)
     return (int)(((float)e + 0.5f) * invS);
 }
 
-// widened bound of one patch of a child: lo/hi in double
+// Bounds of one patch of a child in FP64.  FP64 plain mode (e == 0): the
+// exact min and max.  FP32 mode: the patch is base + stored values, and the
+// bounds are widened by the carried error e and by the rounding of the FP64
+// sums (below 2^-53 relative each), then one ulp outward.
 template <typename T>
-__device__ __forceinline__ void child_bounds(T mn, T mx, double e, double& lo, double& hi)
+__device__ __forceinline__ void child_bounds(T mn, T mx, double e, double base, double& lo, double& hi)
 {
     if (e == 0.0) {
         lo = (double)mn;
         hi = (double)mx;
     } else {
-        lo = nextafter((double)mn - e, -INFINITY);
-        hi = nextafter((double)mx + e, INFINITY);
+        const double a = base + (double)mn, b = base + (double)mx;
+        lo = nextafter(a - e - fabs(a) * 0x1p-52, -INFINITY);
+        hi = nextafter(b + e + fabs(b) * 0x1p-52, INFINITY);
     }
 }
 
@@ -722,17 +791,24 @@ __global__ __launch_bounds__(SUB_THREADS) void k_sub(const DevInst* __restrict__
             uint32_t fL = 0, fR = 0;
             for (int p = threadIdx.x; p < np; p += blockDim.x) {
                 const int poly = (kind == 0) ? 0 : I.count[0] + (kind == 2 ? I.count[1] + c.p0 + p : (gath ? L.id[p] : c.p0 + p));
-                double e = 0.0;
+                double e = 0.0, base = 0.0;
                 if (fp32) {
-                    const float ep = I.err[cur][(int64_t)pslot * I.n_polys + poly];
+                    // the stored values are offsets from the patch's FP64 base, which
+                    // subdivision keeps (rows sum to one); the error grows with them
+                    const int64_t pi = (int64_t)pslot * I.n_polys + poly;
+                    const float ep = I.err[cur][pi];
+                    base = I.base[cur][pi];
                     e = (double)round_up_f((double)ep + gamma32(g.m) * (double)funkey(L.key[5 * p + 4]) +
                                            (double)g.m * 0x1p-126);
-                    I.err[cur ^ 1][(int64_t)(2 * j) * I.n_polys + poly] = (float)e;
-                    I.err[cur ^ 1][(int64_t)(2 * j + 1) * I.n_polys + poly] = (float)e;
+                    for (int ch = 0; ch < 2; ++ch) {
+                        const int64_t ci = (int64_t)(2 * j + ch) * I.n_polys + poly;
+                        I.err[cur ^ 1][ci] = (float)e;
+                        I.base[cur ^ 1][ci] = base;
+                    }
                 }
                 double lo[2], hi[2];
                 for (int ch = 0; ch < 2; ++ch)
-                    child_bounds<T>(funkey(L.key[5 * p + 2 * ch]), funkey(L.key[5 * p + 2 * ch + 1]), e,
+                    child_bounds<T>(funkey(L.key[5 * p + 2 * ch]), funkey(L.key[5 * p + 2 * ch + 1]), e, base,
                                     lo[ch], hi[ch]);
                 if (kind == 0) {
                     // cost records, child ids, then the stamp that publishes the records
@@ -1045,11 +1121,11 @@ __global__ __launch_bounds__(SUB_THREADS) void k_rederive(const DevInst* __restr
             const double* tsrc = I.tmat + ((int64_t)j * 2 + c) * I.tmw + I.tmk[kind];
             copy_to_lds<double>(tm, tsrc, tmsz);
             if (!gath) {
-                copy_to_lds<double>(x, I.root + roff, TE);
+                copy_to_lds<double>(x, I.racc + roff, TE);
             } else {
                 for (int e = threadIdx.x; e < TE; e += blockDim.x) {
                     const int p = e / S;
-                    x[e] = I.root[roff + (int64_t)pact[p0 + q0 + p].x * S + (e - p * S)];
+                    x[e] = I.racc[roff + (int64_t)pact[p0 + q0 + p].x * S + (e - p * S)];
                 }
             }
             __syncthreads();
@@ -1061,27 +1137,40 @@ __global__ __launch_bounds__(SUB_THREADS) void k_rederive(const DevInst* __restr
             for (int p = wv; p < nq; p += blockDim.x >> 6) {
                 const int id = gath ? pact[p0 + q0 + p].x : p0 + q0 + p;
                 const int poly = (kind == 0 ? 0 : I.count[0] + (kind == 2 ? I.count[1] : 0) + id);
-                const double* rp = I.root + roff + (int64_t)(gath ? id : p) * S;
-                float mn = INFINITY, mx = -INFINITY;
-                double rmax = 0.0;
+                const double* rp = I.racc + roff + (int64_t)(gath ? id : p) * S;
+                // the FP64 patch's range and its base (the midrange), then the
+                // FP32 offsets from the base
+                double vmn = INFINITY, vmx = -INFINITY, rmax = 0.0;
                 for (int e = threadIdx.x & 63; e < S; e += 64) {
-                    const float v = (float)x[p * S + e];
-                    mn = fminf(mn, v);
-                    mx = fmaxf(mx, v);
+                    const double v = x[p * S + e];
+                    vmn = fmin(vmn, v);
+                    vmx = fmax(vmx, v);
                     rmax = fmax(rmax, fabs(rp[e]));
+                }
+                for (int o = 32; o > 0; o >>= 1) {
+                    vmn = fmin(vmn, __shfl_xor(vmn, o, 64));
+                    vmx = fmax(vmx, __shfl_xor(vmx, o, 64));
+                    rmax = fmax(rmax, __shfl_xor(rmax, o, 64));
+                }
+                const double base = 0.5 * vmn + 0.5 * vmx;
+                float mn = INFINITY, mx = -INFINITY;
+                for (int e = threadIdx.x & 63; e < S; e += 64) {
+                    const float d = (float)(x[p * S + e] - base);
+                    mn = fminf(mn, d);
+                    mx = fmaxf(mx, d);
                 }
                 for (int o = 32; o > 0; o >>= 1) {
                     mn = fminf(mn, __shfl_xor(mn, o, 64));
                     mx = fmaxf(mx, __shfl_xor(mx, o, 64));
-                    rmax = fmax(rmax, __shfl_xor(rmax, o, 64));
                 }
                 // root bound (rows of T sum to one) + transform rounding on
-                // |T||root| <= max|root| + rounding to FP32 + underflow
+                // |T||root| <= max|root| + rounding of the offsets (the FP64
+                // difference and the FP32 conversion) + underflow
                 const double amax = fmax(fabs((double)mn), fabs((double)mx));
                 const double e = (double)round_up_f(I.root_err[poly] + g64 * rmax * 1.01 +
                                                     amax * 0x1p-23 + 0x1p-126);
                 double lo, hi;
-                child_bounds<float>(mn, mx, e, lo, hi);
+                child_bounds<float>(mn, mx, e, base, lo, hi);
                 // retiring mode: an inequality certified satisfied is not carried;
                 // a carried one goes to a heap patch reserved by lane 0
                 const bool keep = !(gath && hi <= 0.0);
@@ -1094,10 +1183,11 @@ __global__ __launch_bounds__(SUB_THREADS) void k_rederive(const DevInst* __restr
                 hx = __shfl(hx, 0, 64);
                 if (keep) {
                     float* dp = gath ? hc + hx * S : child + soff + (int64_t)p * S;
-                    for (int q = threadIdx.x & 63; q < S; q += 64) dp[q] = (float)x[p * S + q];
+                    for (int q = threadIdx.x & 63; q < S; q += 64) dp[q] = (float)(x[p * S + q] - base);
                 }
                 if ((threadIdx.x & 63) == 0) {
                     I.err[cur ^ 1][(int64_t)(2 * j + c) * I.n_polys + poly] = (float)e;
+                    I.base[cur ^ 1][(int64_t)(2 * j + c) * I.n_polys + poly] = base;
                     if (kind == 0) {
                         I.minP[2 * j + c] = lo;
                         I.maxP[2 * j + c] = hi;
@@ -1328,7 +1418,7 @@ __global__ __launch_bounds__(256) void k_certify(const DevInst* __restrict__ ins
     for (int k = 0; k < l; ++k)
         build_tmat(tm + tmoff[k], tab, I.dims[kind][k], ldexp((double)st->x_index[k], -st->x_depth[k]),
                    ldexp((double)st->x_index[k] + 1.0, -st->x_depth[k]));
-    const double* rp = I.root + I.off[kind] + (int64_t)idx * S;
+    const double* rp = I.racc + I.off[kind] + (int64_t)idx * S;
     double gsum = 0.0;
     for (int r = 0; r < l; ++r) gsum += gamma64(6 * I.dims[kind][r] + 6);
     double mn = INFINITY, mx = -INFINITY, am = 0.0;
@@ -1415,12 +1505,16 @@ __global__ void k_pack(DevInst I, double* __restrict__ out, uint32_t* __restrict
     double* o = out + (int64_t)j * W;
     // cost and equalities from the slot; the inequalities from the slot, or in
     // retiring mode NaN except the carried ones, which come from the heap
+    // FP32 mode: a patch's coefficients are its FP64 base plus the stored values
     const double nan = __longlong_as_double(0x7ff8000000000000ll);
+    const double* pb = I.fp32 ? I.base[cur] + (int64_t)slot * I.n_polys : nullptr;
     for (int kind = 0; kind < KINDS; ++kind) {
         const int64_t n = (int64_t)I.count[kind] * I.S[kind];
         const bool inheap = I.retire && kind == 1;
+        const int p0 = kind == 0 ? 0 : I.count[0] + (kind == 2 ? I.count[1] : 0);
         for (int64_t e = threadIdx.x; e < n; e += blockDim.x)
-            o[I.off[kind] + e] = inheap ? nan : (double)src[I.soff[kind] + e];
+            o[I.off[kind] + e] = inheap ? nan
+                                        : (double)src[I.soff[kind] + e] + (pb ? pb[p0 + e / I.S[kind]] : 0.0);
     }
     if (I.retire) {
         __syncthreads();
@@ -1431,7 +1525,8 @@ __global__ void k_pack(DevInst I, double* __restrict__ out, uint32_t* __restrict
         for (int64_t e = threadIdx.x; e < (int64_t)na * S; e += blockDim.x) {
             const int64_t q = e / S;
             const int2 a = act[q];
-            o[I.off[1] + (int64_t)a.x * S + (e - q * S)] = (double)h[(int64_t)a.y * S + (e - q * S)];
+            o[I.off[1] + (int64_t)a.x * S + (e - q * S)] =
+                (double)h[(int64_t)a.y * S + (e - q * S)] + (pb ? pb[I.count[0] + a.x] : 0.0);
         }
     }
     if (threadIdx.x < (unsigned)I.l)
@@ -1456,6 +1551,14 @@ hipError_t launch_reset_root(const DevInst* d_insts, int n, const int* d_pre, in
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_root, dim3(total_polys), dim3(256), 2 * (size_t)max_S * sizeof(double), s,
+                       d_insts, n, d_pre);
+    return hipGetLastError();
+}
+
+hipError_t launch_racc(const DevInst* d_insts, int n, const int* d_pre, int total_polys, int max_S,
+                       hipStream_t s)
+{
+    hipLaunchKernelGGL(k_racc, dim3(total_polys), dim3(256), 2 * (size_t)max_S * sizeof(double), s,
                        d_insts, n, d_pre);
     return hipGetLastError();
 }

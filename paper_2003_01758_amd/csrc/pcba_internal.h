@@ -112,6 +112,8 @@ struct DevInst {
     void* buf[2];                  // item buffers (double or float), cap * stride each
     uint32_t* ids[2];              // cap * l box indices
     float* err[2];                 // FP32 mode: cap * n_polys error bounds
+    double* base[2];               // FP32 mode: cap * n_polys FP64 bases; a patch's
+                                   // coefficients are base + its stored FP32 values
     int32_t* live;                 // cap: slots of the live items, in list order
     double* minP;                  // child records, cap each
     double* maxP;
@@ -131,12 +133,16 @@ struct DevInst {
     int32_t tmw;                   // transform words per child: sum over kinds and axes of m^2
     int32_t tmk[KINDS];            // offset of each kind's transforms inside a child's block
     int32_t rows;                  // transform rows per child: sum over kinds and axes of m
-    double* root;                  // FP64 root patches (item layout, W doubles)
-    double* root_err;              // FP64 error bound of each root patch
+    double* root;                  // FP64 root patches (item layout, W doubles), converted in
+                                   // two stages per axis (pre-map, then basis change)
+    double* racc;                  // the same patches converted in one stage per axis with
+                                   // the combined matrices (an accurate root)
+    double* root_err;              // rigorous bound on |racc - exact| per patch
     double* cert;                  // certification scratch: n_polys * 3 doubles
     TraceRec* trace;               // MAX_TRACE step records
     const double* mono;            // monomials, zero-padded, item layout (W doubles)
     const double* mats;            // per kind and axis: pre-map A then conversion U (m x m each)
+    const double* macc;            // per kind and axis: combined matrix M then |terms| bound Mabs
     const int* matoff;             // KINDS * MAXL offsets into mats
     InstState* st;
 };

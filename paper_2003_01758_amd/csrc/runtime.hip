@@ -125,10 +125,13 @@ struct pcba_problem {
     // device
     double* d_root = nullptr;
     double* d_root_err = nullptr;
+    double* d_racc = nullptr;     // accurate root (one combined matrix per axis)
+    double* d_macc = nullptr;     // combined matrices M and Mabs per kind and axis
     double* d_cert = nullptr;
     void* d_buf[2] = {nullptr, nullptr};
     uint32_t* d_ids[2] = {nullptr, nullptr};
     float* d_err[2] = {nullptr, nullptr};
+    double* d_base[2] = {nullptr, nullptr};   // FP32 mode: per-patch FP64 bases
     int32_t* d_live = nullptr;
     double* d_minP = nullptr;
     double* d_maxP = nullptr;
@@ -211,6 +214,7 @@ static DevInst make_dev(const pcba_problem* P)
         I.buf[b] = P->d_buf[b];
         I.ids[b] = P->d_ids[b];
         I.err[b] = P->d_err[b];
+        I.base[b] = P->d_base[b];
         I.act[b] = P->d_act[b];
         I.na[b] = P->d_na[b];
         I.heap[b] = P->d_heap[b];
@@ -228,6 +232,8 @@ static DevInst make_dev(const pcba_problem* P)
     for (int t = 0; t < KINDS; ++t) I.tmk[t] = P->tmk[t];
     I.root = P->d_root;
     I.root_err = P->d_root_err;
+    I.racc = P->d_racc;
+    I.macc = P->d_macc;
     I.cert = P->d_cert;
     I.trace = P->d_trace;
     I.mono = P->d_mono;
@@ -239,7 +245,7 @@ static DevInst make_dev(const pcba_problem* P)
 
 static int64_t item_bytes(const pcba_problem* P)
 {
-    return P->stride * (int64_t)P->elem + (int64_t)P->l * 4 + (P->fp32 ? P->n_polys * 4 : 0) + 4 + 8 + 8 + 4 +
+    return P->stride * (int64_t)P->elem + (int64_t)P->l * 4 + (P->fp32 ? P->n_polys * 12 : 0) + 4 + 8 + 8 + 4 +
            (P->retire ? (int64_t)P->count[1] * 8 + 4 + 8 : 0);
 }
 
@@ -264,6 +270,8 @@ static void free_list(pcba_problem* P)
         if (P->d_buf[b]) pool_free(P->d_buf[b]);
         if (P->d_ids[b]) pool_free(P->d_ids[b]);
         if (P->d_err[b]) pool_free(P->d_err[b]);
+        if (P->d_base[b]) pool_free(P->d_base[b]);
+        P->d_base[b] = nullptr;
         if (P->d_act[b]) pool_free(P->d_act[b]);
         if (P->d_na[b]) pool_free(P->d_na[b]);
         if (P->d_heap[b]) pool_free(P->d_heap[b]);
@@ -300,6 +308,7 @@ static int alloc_list(pcba_problem* P, int64_t ncap, int64_t nhcap, hipStream_t 
     void* nb[2] = {nullptr, nullptr};
     uint32_t* ni[2] = {nullptr, nullptr};
     float* ne[2] = {nullptr, nullptr};
+    double* nbs[2] = {nullptr, nullptr};
     int32_t* nlive = nullptr;
     double *nmin = nullptr, *nmax = nullptr;
     uint32_t* nfl = nullptr;
@@ -319,6 +328,7 @@ static int alloc_list(pcba_problem* P, int64_t ncap, int64_t nhcap, hipStream_t 
             if (nb[b]) pool_free(nb[b]);
             if (ni[b]) pool_free(ni[b]);
             if (ne[b]) pool_free(ne[b]);
+            if (nbs[b]) pool_free(nbs[b]);
             if (nact[b]) pool_free(nact[b]);
             if (nna[b]) pool_free(nna[b]);
             if (nhp[b]) pool_free(nhp[b]);
@@ -333,7 +343,8 @@ static int alloc_list(pcba_problem* P, int64_t ncap, int64_t nhcap, hipStream_t 
         ok = pool_alloc(&nb[b], (size_t)ncap * P->stride * P->elem) == hipSuccess &&
              pool_alloc((void**)&ni[b], (size_t)ncap * P->l * sizeof(uint32_t)) == hipSuccess;
         if (ok && P->fp32)
-            ok = pool_alloc((void**)&ne[b], (size_t)ncap * P->n_polys * sizeof(float)) == hipSuccess;
+            ok = pool_alloc((void**)&ne[b], (size_t)ncap * P->n_polys * sizeof(float)) == hipSuccess &&
+                 pool_alloc((void**)&nbs[b], (size_t)ncap * P->n_polys * sizeof(double)) == hipSuccess;
         if (ok && P->retire)
             ok = pool_alloc((void**)&nact[b], (size_t)ncap * P->count[1] * sizeof(int2)) == hipSuccess &&
                  pool_alloc((void**)&nna[b], (size_t)ncap * sizeof(int32_t)) == hipSuccess &&
@@ -367,6 +378,9 @@ static int alloc_list(pcba_problem* P, int64_t ncap, int64_t nhcap, hipStream_t 
         if (e == hipSuccess && P->fp32)
             e = hipMemcpyAsync(ne[cur], P->d_err[cur], (size_t)used * P->n_polys * sizeof(float),
                                hipMemcpyDeviceToDevice, s);
+        if (e == hipSuccess && P->fp32)
+            e = hipMemcpyAsync(nbs[cur], P->d_base[cur], (size_t)used * P->n_polys * sizeof(double),
+                               hipMemcpyDeviceToDevice, s);
         if (e == hipSuccess)
             e = hipMemcpyAsync(nlive, P->d_live, (size_t)used * sizeof(int32_t),
                                hipMemcpyDeviceToDevice, s);
@@ -396,6 +410,7 @@ static int alloc_list(pcba_problem* P, int64_t ncap, int64_t nhcap, hipStream_t 
         P->d_buf[b] = nb[b];
         P->d_ids[b] = ni[b];
         P->d_err[b] = ne[b];
+        P->d_base[b] = nbs[b];
         P->d_act[b] = nact[b];
         P->d_na[b] = nna[b];
         P->d_heap[b] = nhp[b];
@@ -470,6 +485,20 @@ static int upload_descs(pcba_problem* const* probs, int n, Scratch& sc, hipStrea
     *d_insts = (DevInst*)sc.p;
     *d_pre = (int*)((char*)sc.p + off_pre);
     *total = pre[n];
+    return PCBA_OK;
+}
+
+// The accurate root and its error bound (once per problem: they depend only on
+// the problem's data).
+static int accurate_root(pcba_problem* P, hipStream_t s)
+{
+    DevInst* d_insts = nullptr;
+    int* d_pre = nullptr;
+    int total = 0, max_S = 1, tmw = 1;
+    int rc = upload_descs(&P, 1, t_scratch, s, &d_insts, &d_pre, &total, &max_S, &tmw);
+    if (rc != PCBA_OK) return rc;
+    HIP_TRY(launch_racc(d_insts, 1, d_pre, total, max_S, s));
+    HIP_TRY(hipStreamSynchronize(s));
     return PCBA_OK;
 }
 
@@ -662,7 +691,7 @@ int pcba_create_problem(int32_t l, const double* lo, const double* hi, const int
         }
     }
     // per kind and axis: pre-map matrix A (x = lo + w t) and conversion matrix U
-    std::vector<double> mats;
+    std::vector<double> mats, macc;
     std::vector<int> matoff(KINDS * MAXL, 0);
     for (int t = 0; t < KINDS; ++t)
         for (int r = 0; r < l; ++r) {
@@ -683,6 +712,25 @@ int pcba_create_problem(int32_t l, const double* lo, const double* hi, const int
                 for (int i = 0; i <= k; ++i) U[k * m + i] = binom(k, i) / binom(n, i);
             mats.insert(mats.end(), A.begin(), A.end());
             mats.insert(mats.end(), U.begin(), U.end());
+            // combined matrix M = U A by the polar form of x^j at (lo x (n-k), hi x k):
+            // a hypergeometric average of lo^(j-i) hi^i, and Mabs, the sum of the
+            // terms' magnitudes (same offsets as A and U)
+            std::vector<double> M(m * m, 0.0), Ma(m * m, 0.0);
+            for (int k = 0; k <= n; ++k)
+                for (int j = 0; j <= n; ++j) {
+                    double sum = 0.0, sabs = 0.0;
+                    for (int i = std::max(0, j - (n - k)); i <= std::min(j, k); ++i) {
+                        double t = binom(k, i) * binom(n - k, j - i) / binom(n, j);
+                        for (int q = 0; q < j - i; ++q) t *= lo[r];
+                        for (int q = 0; q < i; ++q) t *= hi[r];
+                        sum += t;
+                        sabs += std::fabs(t);
+                    }
+                    M[k * m + j] = sum;
+                    Ma[k * m + j] = sabs;
+                }
+            macc.insert(macc.end(), M.begin(), M.end());
+            macc.insert(macc.end(), Ma.begin(), Ma.end());
         }
 
     // memory-test bound: M, and no more than the device can hold for two buffers
@@ -704,6 +752,8 @@ int pcba_create_problem(int32_t l, const double* lo, const double* hi, const int
     bool ok = hipStreamCreateWithFlags(&s, hipStreamNonBlocking) == hipSuccess &&
               hipMalloc((void**)&P->d_root, P->W * sizeof(double)) == hipSuccess &&
               hipMalloc((void**)&P->d_root_err, P->n_polys * sizeof(double)) == hipSuccess &&
+              hipMalloc((void**)&P->d_racc, P->W * sizeof(double)) == hipSuccess &&
+              hipMalloc((void**)&P->d_macc, std::max<size_t>(1, macc.size()) * sizeof(double)) == hipSuccess &&
               hipMalloc((void**)&P->d_cert, 3 * P->n_polys * sizeof(double)) == hipSuccess &&
               hipMalloc((void**)&P->d_st, sizeof(InstState)) == hipSuccess &&
               hipMalloc((void**)&P->d_trace, MAX_TRACE * sizeof(TraceRec)) == hipSuccess &&
@@ -727,10 +777,13 @@ int pcba_create_problem(int32_t l, const double* lo, const double* hi, const int
     hipError_t e = hipMemcpyAsync(P->d_mono, mono.data(), P->W * sizeof(double), hipMemcpyHostToDevice, s);
     if (e == hipSuccess && !mats.empty())
         e = hipMemcpyAsync(P->d_mats, mats.data(), mats.size() * sizeof(double), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess && !macc.empty())
+        e = hipMemcpyAsync(P->d_macc, macc.data(), macc.size() * sizeof(double), hipMemcpyHostToDevice, s);
     if (e == hipSuccess)
         e = hipMemcpyAsync(P->d_matoff, matoff.data(), matoff.size() * sizeof(int), hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
-    if (e == hipSuccess) rc = reset_batch(&P, 1, s);
+    if (e == hipSuccess) rc = accurate_root(P, s);
+    if (e == hipSuccess && rc == PCBA_OK) rc = reset_batch(&P, 1, s);
     (void)hipStreamDestroy(s);
     if (e != hipSuccess || rc != PCBA_OK) {
         std::string m = e != hipSuccess ? std::string(hipGetErrorString(e)) : g_last_error;
@@ -808,6 +861,8 @@ void pcba_destroy_problem(pcba_problem* P)
     free_list(P);
     if (P->d_root) (void)hipFree(P->d_root);
     if (P->d_root_err) (void)hipFree(P->d_root_err);
+    if (P->d_racc) (void)hipFree(P->d_racc);
+    if (P->d_macc) (void)hipFree(P->d_macc);
     if (P->d_cert) (void)hipFree(P->d_cert);
     if (P->d_st) (void)hipFree(P->d_st);
     if (P->d_trace) (void)hipFree(P->d_trace);

@@ -89,9 +89,6 @@ def test_fp64_batch_matches_oracle(gpu, insts, golden, res64):
         _check_any_size(inst, r, gpu)
 
 
-@pytest.mark.skip(reason="FP32 bounds widened by the magnitude of the coefficients cannot close the "
-                         "1e-3 gap on some 3-variable instances near active constraints; the list "
-                         "then grows to the memory limit")
 def test_fp32_batch_within_eps_and_certified(gpu, insts, golden, res32, res64):
     for k, want in golden.items():
         r = res32[k]
