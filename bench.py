@@ -10,10 +10,11 @@ subdivision + bounds, cut-off test + compaction, stopping tests, FP64
 certification.  Inputs are resident in device memory when the timed region
 starts (pcba_reset recomputes the root patches from the resident monomials).
 
-Prints one JSON line: certified solves/s of the FP32 path (rigorously widened
-bounds, FP64 certification) with p50/p99 per-plan latency, the same for the
-plain FP64 path, the roofline of the dominant kernel (HIP events over the timed
-region), and the FP64 CPU oracle timed on a bounded sample.
+Prints one JSON line: certified solves/s of the better of the FP32 path
+(rigorously widened bounds, FP64 certification) and the plain FP64 path, with
+p50/p99 per-plan latency, both paths' figures, the roofline of the dominant
+kernel (HIP events around its launches over a second, instrumented pass of the
+same steps), and the FP64 CPU oracle timed on a bounded sample.
 """
 import argparse
 import json
@@ -68,30 +69,41 @@ def algorithmic_bytes(p, inst, precision):
 
 
 def run_mode(pcba, insts, precision, steps, warmup, **opts):
+    """Times `steps` batch solves (throughput and latency, no instrumentation),
+    then repeats them with HIP events around every kernel launch for the
+    per-kernel times and the roofline of the subdivide+bound kernel."""
     probs = [pcba.Problem(i, precision=precision, **opts) for i in insts]
     for w in range(warmup):
         pcba.reset_batch(probs)
         pcba.solve_batch(probs)
         log(f"[bench] {precision} warmup {w + 1}/{warmup} done")
-    pcba.profile_reset()
-    pcba.profile_enable(True)
     lat, cert, results = [], 0, []
-    bytes_sub = 0.0
-    sub_kernel = "sub_fp32" if precision == "fp32" else "sub_fp64"
     elapsed = 0.0
     for s in range(steps):
         t0 = time.perf_counter()
         pcba.reset_batch(probs)
         res = pcba.solve_batch(probs)
         elapsed += time.perf_counter() - t0
-        for p, i in zip(probs, insts):
-            bytes_sub += algorithmic_bytes(p, i, precision)
         lat += [r["seconds"] for r in res]
         cert += sum(1 for r in res if certified(r, pcba))
         results = res
         log(f"[bench] {precision} step {s + 1}/{steps}: {elapsed * 1e3 / (s + 1):.2f} ms/step")
+    # the same steps with every launch bracketed by HIP events on the library's stream
+    sub_kernel = "sub_fp32" if precision == "fp32" else "sub_fp64"
+    bytes_sub = 0.0
+    pcba.profile_reset()
+    pcba.profile_enable(True)
+    prof_elapsed = 0.0
+    for s in range(steps):
+        t0 = time.perf_counter()
+        pcba.reset_batch(probs)
+        pcba.solve_batch(probs)
+        prof_elapsed += time.perf_counter() - t0
+        for p, i in zip(probs, insts):
+            bytes_sub += algorithmic_bytes(p, i, precision)
     pcba.profile_enable(False)
     prof = pcba.profile_read()
+    log(f"[bench] {precision} instrumented pass: {prof_elapsed * 1e3 / steps:.2f} ms/step")
     for p in probs:
         p.close()
     ms_sub, n_sub = prof[sub_kernel]
@@ -103,7 +115,27 @@ def run_mode(pcba, insts, precision, steps, warmup, **opts):
         certified=cert, total=len(lat),
         results=results, profile=prof,
         sub_kernel=sub_kernel, bytes_sub=bytes_sub, ms_sub=ms_sub, launches_sub=n_sub,
+        instrumented_ms_per_step=prof_elapsed * 1e3 / steps,
     )
+
+
+def measured_traffic(sub_kernel):
+    """HBM bytes per launch of the subdivide kernel from the committed counter
+    summary (FETCH_SIZE and WRITE_SIZE runs scaled by a copy of known size),
+    or None when the kernel source has changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "k_sub_rtd32_hbm_bytes.md")
+    try:
+        line = [ln for ln in open(path) if ln.strip().startswith("{")][-1]
+        rec = json.loads(line)
+    except (OSError, IndexError, ValueError):
+        return None
+    src = os.path.join(ROOT, "paper_2003_01758_amd", "csrc", "kernels.hip")
+    if hashlib.sha256(open(src, "rb").read()).hexdigest() != rec.get("kernels_hip_sha256"):
+        return None
+    name = {"sub_fp64": "k_sub<double, 16, 14>", "sub_fp32": "k_sub<float, 16, 28>"}[sub_kernel]
+    k = rec["kernels"].get(name)
+    return float(k["bytes_per_dispatch"]) if k else None
 
 
 def cpu_baseline(insts, budget_s):
@@ -122,6 +154,25 @@ def cpu_baseline(insts, budget_s):
     return n / dt, n, dt, p_up
 
 
+def copy_calibration(mib: int, reps: int):
+    """Device-to-device copies of a known size: the reference reading for the
+    hardware byte counters (FETCH_SIZE, WRITE_SIZE) under rocprofv3."""
+    import ctypes as C
+    hip = C.CDLL("libamdhip64.so")
+    n = mib << 20
+    a, b = C.c_void_p(), C.c_void_p()
+    if hip.hipMalloc(C.byref(a), C.c_size_t(n)) or hip.hipMalloc(C.byref(b), C.c_size_t(n)):
+        sys.exit("hipMalloc failed")
+    hip.hipMemset(a, 1, C.c_size_t(n))
+    hip.hipDeviceSynchronize()
+    for _ in range(reps):
+        hip.hipMemcpy(b, a, C.c_size_t(n), 3)   # device to device
+    hip.hipDeviceSynchronize()
+    hip.hipFree(a)
+    hip.hipFree(b)
+    print(json.dumps({"copy_bytes": n, "copies": reps}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -132,9 +183,14 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--rederive", type=int, default=None, help="FP32 re-derivation period (steps)")
     ap.add_argument("--stale", type=int, default=None, help="1/0: stale-estimate write filter")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="only run device copies of this many MiB (counter calibration) and exit")
     ap.add_argument("--retire", type=int, default=1,
                     help="1/0: drop inequalities certified satisfied on a box from its descendants")
     args = ap.parse_args()
+    if args.copy_mib > 0:
+        copy_calibration(args.copy_mib, 2)
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU: this build has no multi-GPU path (asked for {args.gpus})",
               file=sys.stderr)
@@ -192,6 +248,7 @@ def main():
         "fp64_plain": {k: (round(v, 4) if isinstance(v, float) else v) for k, v in r64.items()
                        if k in ("solves_per_s", "ms_per_step", "p50_ms", "p99_ms", "certified", "total")},
         "max_abs_p_fp32_vs_fp64": dp,
+        "instrumented_ms_per_step": round(best["instrumented_ms_per_step"], 4),
         "kernel_ms": {k: round(v[0], 3) for k, v in best["profile"].items()},
         "kernel_launches": {k: v[1] for k, v in best["profile"].items()},
         "roofline": {
@@ -201,7 +258,7 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None,
-            "traffic": None,
+            "traffic": measured_traffic(dom["sub_kernel"]),
             "bytes_per_launch": round(dom["bytes_sub"] / max(1, dom["launches_sub"]), 1),
             "avg_launch_us": round(dom["ms_sub"] * 1e3 / max(1, dom["launches_sub"]), 3),
         },

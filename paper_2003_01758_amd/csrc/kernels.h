@@ -12,8 +12,10 @@ hipError_t launch_reset_root(const DevInst* d_insts, int n, const int* d_pre, in
 hipError_t launch_racc(const DevInst* d_insts, int n, const int* d_pre, int total_polys, int max_S,
                        hipStream_t s);
 hipError_t launch_plan(const DevInst* d_insts, int n, long long* plan, StepInfo* info, hipStream_t s);
+// ev0/ev1 (or null): events stamped at the subdivision kernel's start and end
 hipError_t launch_sub(const DevInst* d_insts, int n, const long long* plan, const StepInfo* info,
-                      bool fp32, int maxm, int grid, size_t lds, hipStream_t s);
+                      bool fp32, int maxm, int grid, size_t lds, hipStream_t s, hipEvent_t ev0,
+                      hipEvent_t ev1);
 hipError_t launch_rederive(const DevInst* d_insts, int n, const long long* plan, const StepInfo* info,
                            int grid, int tgrid, size_t lds, hipStream_t s);
 hipError_t launch_cut(const DevInst* d_insts, int n, hipStream_t s);

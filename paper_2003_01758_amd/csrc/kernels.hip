@@ -13,6 +13,8 @@
 //               Eliminate as an order-preserving stream compaction + the advance
 //               of direction and iteration count, one workgroup per problem.
 //   k_certify   FP64 re-derivation of x* with a rigorous error bound.
+#include <hip/hip_ext.h>
+
 #include "kernels.h"
 
 #include <float.h>
@@ -1569,26 +1571,33 @@ hipError_t launch_plan(const DevInst* d_insts, int n, long long* plan, StepInfo*
     return hipGetLastError();
 }
 
+// With ev0/ev1 the launch stamps them at the kernel's own start and end.
 template <typename T, int MM>
 static hipError_t launch_sub_t(const DevInst* d_insts, int n, const long long* plan,
-                               const StepInfo* info, int grid, size_t lds, hipStream_t s)
+                               const StepInfo* info, int grid, size_t lds, hipStream_t s,
+                               hipEvent_t ev0, hipEvent_t ev1)
 {
     // registers per thread for a tile in flight: the largest tile / 256 lanes
     constexpr int LB = (sizeof(T) == 8 ? MAX_TILE64 : MAX_TILE32) / SUB_THREADS;
-    hipLaunchKernelGGL((k_sub<T, MM, LB>), dim3(grid), dim3(SUB_THREADS), lds, s, d_insts, n, plan, info);
+    if (ev0)
+        hipExtLaunchKernelGGL((k_sub<T, MM, LB>), dim3(grid), dim3(SUB_THREADS), lds, s, ev0, ev1, 0,
+                              d_insts, n, plan, info);
+    else
+        hipLaunchKernelGGL((k_sub<T, MM, LB>), dim3(grid), dim3(SUB_THREADS), lds, s, d_insts, n, plan, info);
     return hipGetLastError();
 }
 
 hipError_t launch_sub(const DevInst* d_insts, int n, const long long* plan, const StepInfo* info,
-                      bool fp32, int maxm, int grid, size_t lds, hipStream_t s)
+                      bool fp32, int maxm, int grid, size_t lds, hipStream_t s, hipEvent_t ev0,
+                      hipEvent_t ev1)
 {
     if (grid <= 0) return hipSuccess;
     if (fp32) {
-        if (maxm <= 8) return launch_sub_t<float, 8>(d_insts, n, plan, info, grid, lds, s);
-        return launch_sub_t<float, 16>(d_insts, n, plan, info, grid, lds, s);
+        if (maxm <= 8) return launch_sub_t<float, 8>(d_insts, n, plan, info, grid, lds, s, ev0, ev1);
+        return launch_sub_t<float, 16>(d_insts, n, plan, info, grid, lds, s, ev0, ev1);
     }
-    if (maxm <= 8) return launch_sub_t<double, 8>(d_insts, n, plan, info, grid, lds, s);
-    return launch_sub_t<double, 16>(d_insts, n, plan, info, grid, lds, s);
+    if (maxm <= 8) return launch_sub_t<double, 8>(d_insts, n, plan, info, grid, lds, s, ev0, ev1);
+    return launch_sub_t<double, 16>(d_insts, n, plan, info, grid, lds, s, ev0, ev1);
 }
 
 hipError_t launch_rederive(const DevInst* d_insts, int n, const long long* plan, const StepInfo* info,

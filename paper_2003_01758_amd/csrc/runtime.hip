@@ -86,6 +86,28 @@ hipError_t prof_end(int kernel, hipStream_t s)
     g_prof.used += 1;
     return r;
 }
+// an event pair for a launch that stamps it itself (hipExtLaunchKernelGGL);
+// nulls when profiling is off
+hipError_t prof_pair(int kernel, hipEvent_t* ev0, hipEvent_t* ev1)
+{
+    *ev0 = *ev1 = nullptr;
+    if (!g_prof.on) return hipSuccess;
+    if (2 * (g_prof.used + 1) > g_prof.ev.size()) {
+        for (int q = 0; q < 2; ++q) {
+            hipEvent_t e;
+            hipError_t r = hipEventCreate(&e);
+            if (r != hipSuccess) return r;
+            g_prof.ev.push_back(e);
+        }
+    }
+    *ev0 = g_prof.ev[2 * g_prof.used];
+    *ev1 = g_prof.ev[2 * g_prof.used + 1];
+    if ((size_t)g_prof.kid.size() <= g_prof.used) g_prof.kid.resize(g_prof.used + 1);
+    g_prof.kid[g_prof.used] = kernel;
+    g_prof.used += 1;
+    return hipSuccess;
+}
+
 // after the stream is synchronised: fold the pending records into the totals
 void prof_collect()
 {
@@ -1079,16 +1101,16 @@ static int engine_steps(pcba_engine* E, int n_steps)
         HIP_TRY(launch_plan(E->d_insts, n, E->d_plan, E->d_info, E->stream));
         HIP_TRY(prof_end(4, E->stream));
         if (any64 && ub64 > 0) {
-            HIP_TRY(prof_begin(E->stream));
+            hipEvent_t e0, e1;
+            HIP_TRY(prof_pair(0, &e0, &e1));
             HIP_TRY(launch_sub(E->d_insts, n, E->d_plan, E->d_info, false, maxm64,
-                               (int)std::min<int64_t>(GRID_MAX, ub64), lds64, E->stream));
-            HIP_TRY(prof_end(0, E->stream));
+                               (int)std::min<int64_t>(GRID_MAX, ub64), lds64, E->stream, e0, e1));
         }
         if (any32 && ub32 > 0) {
-            HIP_TRY(prof_begin(E->stream));
+            hipEvent_t e0, e1;
+            HIP_TRY(prof_pair(1, &e0, &e1));
             HIP_TRY(launch_sub(E->d_insts, n, E->d_plan, E->d_info, true, maxm32,
-                               (int)std::min<int64_t>(GRID_MAX, ub32), lds32, E->stream));
-            HIP_TRY(prof_end(1, E->stream));
+                               (int)std::min<int64_t>(GRID_MAX, ub32), lds32, E->stream, e0, e1));
         }
         if (anyrd && ubrd > 0) {
             HIP_TRY(prof_begin(E->stream));
