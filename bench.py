@@ -248,7 +248,7 @@ def main():
             "workload": "rtd-shaped plans: l=2 on [-1,1]^2, goal-distance cost (6,6), "
                         "500 obstacle constraints (10,10), eps 1e-3, delta 1e-4, M 2^20, N 28",
             "batch": args.batch,
-            "rederive_every": args.rederive if args.rederive is not None else 8,
+            "rederive_every": args.rederive if args.rederive is not None else 16,
             "stale_filter": args.stale if args.stale is not None else 0,
             "retire_satisfied": args.retire,
             "path": "fp32 patches with rigorous widening + fp64 root, re-derivation and certification"

@@ -120,7 +120,8 @@ typedef struct {
 typedef struct pcba_problem pcba_problem;
 
 /* Fills *opt with defaults: eps 1e-3, delta 1e-4, eps_eq 1e-4, M 2^20, N 28,
- * FP64 plain, re-derivation every 8 steps, stale filter off, no time limit. */
+ * FP64 plain, re-derivation every 16 steps, retiring on, stale filter off, no
+ * time limit. */
 void pcba_default_options(pcba_options* opt);
 
 /* Builds problem (P) and its root item: every polynomial is zero-padded to the

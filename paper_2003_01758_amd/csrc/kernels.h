@@ -18,7 +18,8 @@ hipError_t launch_sub(const DevInst* d_insts, int n, const long long* plan, cons
                       hipEvent_t ev1);
 hipError_t launch_rederive(const DevInst* d_insts, int n, const long long* plan, const StepInfo* info,
                            int grid, int tgrid, size_t lds, hipStream_t s);
-hipError_t launch_cut(const DevInst* d_insts, int n, hipStream_t s);
+// max_children: an upper bound on 2K over the problems at this step
+hipError_t launch_cut(const DevInst* d_insts, int n, int64_t max_children, hipStream_t s);
 hipError_t launch_gather(const DevInst* d_insts, int n, InstState* out, hipStream_t s);
 hipError_t launch_certify(const DevInst* d_insts, int n, const int* d_pre, int total_polys,
                           int max_S, int tm_words, hipStream_t s);

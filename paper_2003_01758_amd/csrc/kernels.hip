@@ -432,6 +432,7 @@ struct SubLds {
     int* id;     // retiring mode, inequality tile: per patch its inequality index, then
     int* need;   // which children still carry it (bit 0 left, bit 1 right), then
     int* dst;    // its heap patch in the left child (np entries) and the right (np)
+    T* shift;    // FP32: per patch, each child's re-centring shift (left np, right np)
 };
 
 // One fibre of fixed length M: de Casteljau with parameter 1/2 in registers.
@@ -739,6 +740,7 @@ __global__ __launch_bounds__(SUB_THREADS) void k_sub(const DevInst* __restrict__
         L.id = (int*)(L.key + 5 * np);
         L.need = L.id + np;
         L.dst = L.need + np;
+        L.shift = (T*)(L.dst + 2 * np);
         // children already condemned by other tiles (infeasible), or, with the
         // stale filter, whose cost bound exceeds the previous solution estimate
         if (threadIdx.x == 0) {
@@ -796,16 +798,26 @@ __global__ __launch_bounds__(SUB_THREADS) void k_sub(const DevInst* __restrict__
                 double e = 0.0, base = 0.0;
                 if (fp32) {
                     // the stored values are offsets from the patch's FP64 base, which
-                    // subdivision keeps (rows sum to one); the error grows with them
+                    // subdivision keeps (rows sum to one); the split's error grows with
+                    // the offsets.  Each child is then re-centred: its base moves by
+                    // its midrange offset mc and its offsets become v - mc, so that they
+                    // shrink with the box; the shift adds the rounding of v - mc (below
+                    // 2^-24 (max - min)) and of the new FP64 base.
                     const int64_t pi = (int64_t)pslot * I.n_polys + poly;
                     const float ep = I.err[cur][pi];
                     base = I.base[cur][pi];
                     e = (double)round_up_f((double)ep + gamma32(g.m) * (double)funkey(L.key[5 * p + 4]) +
                                            (double)g.m * 0x1p-126);
                     for (int ch = 0; ch < 2; ++ch) {
+                        const float mn = (float)funkey(L.key[5 * p + 2 * ch]);
+                        const float mx = (float)funkey(L.key[5 * p + 2 * ch + 1]);
+                        const float mc = 0.5f * mn + 0.5f * mx;
+                        const double nb = base + (double)mc;
                         const int64_t ci = (int64_t)(2 * j + ch) * I.n_polys + poly;
-                        I.err[cur ^ 1][ci] = (float)e;
-                        I.base[cur ^ 1][ci] = base;
+                        I.err[cur ^ 1][ci] = round_up_f(e + ((double)mx - (double)mn) * 0x1p-23 +
+                                                        fabs(nb) * 0x1p-52 + 0x1p-126);
+                        I.base[cur ^ 1][ci] = nb;
+                        L.shift[ch * np + p] = (T)mc;
                     }
                 }
                 double lo[2], hi[2];
@@ -866,7 +878,15 @@ __global__ __launch_bounds__(SUB_THREADS) void k_sub(const DevInst* __restrict__
 #pragma unroll
                     for (int q = 0; q < SB; ++q) {
                         const int e = e0 + q * SUB_THREADS;
-                        if (e < TE) { va[q] = L.a[e]; vb[q] = L.b[e]; }
+                        if (e < TE) {
+                            va[q] = L.a[e];
+                            vb[q] = L.b[e];
+                            if (fp32) {
+                                const int p = patch_of(e, invS);
+                                va[q] -= L.shift[p];
+                                vb[q] -= L.shift[np + p];
+                            }
+                        }
                     }
 #pragma unroll
                     for (int q = 0; q < SB; ++q) {
@@ -930,8 +950,9 @@ __global__ __launch_bounds__(SUB_THREADS) void k_sub(const DevInst* __restrict__
                     const int p = patch_of(e, invS);
                     const int dl = L.dst[p], dr = L.dst[np + p];
                     const int r = e - p * S;
-                    if (dl >= 0) hc[(int64_t)dl * S + r] = L.a[e];
-                    if (dr >= 0) hc[(int64_t)dr * S + r] = L.b[e];
+                    const T sl = fp32 ? L.shift[p] : (T)0, sr = fp32 ? L.shift[np + p] : (T)0;
+                    if (dl >= 0) hc[(int64_t)dl * S + r] = L.a[e] - sl;
+                    if (dr >= 0) hc[(int64_t)dr * S + r] = L.b[e] - sr;
                 }
             }
             lds_barrier();
@@ -1567,7 +1588,9 @@ hipError_t launch_racc(const DevInst* d_insts, int n, const int* d_pre, int tota
 
 hipError_t launch_plan(const DevInst* d_insts, int n, long long* plan, StepInfo* info, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_plan, dim3(1), dim3(1024), 0, s, d_insts, n, plan, info);
+    // one lane per problem (the kernel loops over larger batches)
+    const int threads = std::min(1024, std::max(64, (n + 63) / 64 * 64));
+    hipLaunchKernelGGL(k_plan, dim3(1), dim3(threads), 0, s, d_insts, n, plan, info);
     return hipGetLastError();
 }
 
@@ -1579,6 +1602,19 @@ static hipError_t launch_sub_t(const DevInst* d_insts, int n, const long long* p
 {
     // registers per thread for a tile in flight: the largest tile / 256 lanes
     constexpr int LB = (sizeof(T) == 8 ? MAX_TILE64 : MAX_TILE32) / SUB_THREADS;
+    // no more workgroups than fit on the device at once: the rest would only
+    // queue, while resident ones walk the units with the next tile in flight
+    static int cus = 0;
+    static size_t cached_lds = (size_t)-1;
+    static int per_cu = 0;
+    if (!cus && hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, 0) != hipSuccess) cus = 0;
+    if (lds != cached_lds) {
+        int nb = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_sub<T, MM, LB>, SUB_THREADS, lds) == hipSuccess)
+            per_cu = nb;
+        cached_lds = lds;
+    }
+    if (cus > 0 && per_cu > 0) grid = std::min(grid, cus * per_cu);
     if (ev0)
         hipExtLaunchKernelGGL((k_sub<T, MM, LB>), dim3(grid), dim3(SUB_THREADS), lds, s, ev0, ev1, 0,
                               d_insts, n, plan, info);
@@ -1611,9 +1647,12 @@ hipError_t launch_rederive(const DevInst* d_insts, int n, const long long* plan,
     return hipGetLastError();
 }
 
-hipError_t launch_cut(const DevInst* d_insts, int n, hipStream_t s)
+hipError_t launch_cut(const DevInst* d_insts, int n, int64_t max_children, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_cut, dim3(n), dim3(CUT_THREADS), 0, s, d_insts, n);
+    // short lists: four waves walk the children in a few passes with cheaper
+    // barriers; long ones take the full workgroup
+    const int threads = max_children <= 4096 ? 256 : CUT_THREADS;
+    hipLaunchKernelGGL(k_cut, dim3(n), dim3(threads), 0, s, d_insts, n);
     return hipGetLastError();
 }
 

@@ -577,7 +577,7 @@ void pcba_default_options(pcba_options* o)
     o->max_boxes = 1 << 20;
     o->max_iters = 28;
     o->precision = PCBA_FP64_PLAIN;
-    o->rederive_every = 8;
+    o->rederive_every = 16;
     o->stale_filter = 0;
     o->retire_satisfied = 1;
     o->time_limit_s = 0.0;
@@ -1001,8 +1001,9 @@ static size_t sub_lds(const pcba_problem* P)
         }
     const size_t key = P->fp32 ? 4 : 8;
     // keys, and in retiring mode per patch its index, which children keep it,
-    // and its heap patch in each child (4 ints)
-    return 2 * (size_t)TE * P->elem + 5 * (size_t)TP * key + (P->retire ? 16 * (size_t)TP : 0) + 16;
+    // and its heap patch in each child (4 ints), then each child's re-centring
+    // shift (FP32)
+    return 2 * (size_t)TE * P->elem + 5 * (size_t)TP * key + 16 * (size_t)TP + 2 * (size_t)TP * P->elem + 16;
 }
 static size_t rederive_lds(const pcba_problem* P)
 {
@@ -1085,10 +1086,11 @@ static int engine_steps(pcba_engine* E, int n_steps)
     for (int s = 0; s < n_steps; ++s) {
         // upper bound of this step's units: K at most doubles per step, and a
         // problem never holds more than cap/2 parents
-        int64_t ub64 = 0, ub32 = 0, ubrd = 0, ubrows = 0;
+        int64_t ub64 = 0, ub32 = 0, ubrd = 0, ubrows = 0, maxc = 0;
         for (auto* P : E->active) {
             if (P->h_st.status != ST_RUNNING) continue;
             const int64_t k = std::min<int64_t>(P->cap / 2, (int64_t)P->h_st.K << std::min(s, 30));
+            maxc = std::max(maxc, 2 * k);
             const int64_t u = k * P->T;
             if (!P->fp32) ub64 += u;
             else {
@@ -1119,7 +1121,7 @@ static int engine_steps(pcba_engine* E, int n_steps)
             HIP_TRY(prof_end(2, E->stream));
         }
         HIP_TRY(prof_begin(E->stream));
-        HIP_TRY(launch_cut(E->d_insts, n, E->stream));
+        HIP_TRY(launch_cut(E->d_insts, n, maxc, E->stream));
         HIP_TRY(prof_end(3, E->stream));
     }
     HIP_TRY(launch_gather(E->d_insts, n, E->d_states, E->stream));

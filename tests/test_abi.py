@@ -39,7 +39,7 @@ def test_default_options_and_argument_validation_without_device():
     o = pcba.default_options()
     assert o.eps == 1e-3 and o.delta == 1e-4 and o.max_iters == 28 and o.max_boxes == 1 << 20
     # the C side fills every field: a layout mismatch would misplace these
-    assert o.rederive_every == 8 and o.stale_filter == 0 and o.retire_satisfied == 1
+    assert o.rederive_every == 16 and o.stale_filter == 0 and o.retire_satisfied == 1
     assert o.time_limit_s == 0.0 and ctypes.sizeof(o) == 64
     # argument errors are detected before any device call
     L = pcba.lib()
