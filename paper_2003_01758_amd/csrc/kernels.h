@@ -7,13 +7,17 @@
 
 namespace pcba {
 
-hipError_t launch_reset_root(const DevInst* d_insts, int n, const int* d_pre, int total_polys,
-                             int max_S, hipStream_t s);
+// polynomials per root-conversion workgroup that fit LDS (0: none)
+int root_run_length(int max_S, int tm_words);
+hipError_t launch_reset_root(const DevInst* d_insts, int n, const int* d_pre, int total_blocks, int max_S,
+                             int tm_words, int ppb, hipStream_t s);
 hipError_t launch_racc(const DevInst* d_insts, int n, const int* d_pre, int total_polys, int max_S,
                        hipStream_t s);
 hipError_t launch_plan(const DevInst* d_insts, int n, long long* plan, StepInfo* info, hipStream_t s);
-// ev0/ev1 (or null): events stamped at the subdivision kernel's start and end
-hipError_t launch_sub(const DevInst* d_insts, int n, const long long* plan, const StepInfo* info,
+// ev0/ev1 (or null): events stamped at the subdivision kernel's start and end.
+// fuse (n <= PLAN_FUSE_MAX): the kernel forms the step's plan itself, in place
+// of a k_plan launch before it, and writes it to plan / info.
+hipError_t launch_sub(const DevInst* d_insts, int n, long long* plan, StepInfo* info, bool fuse,
                       bool fp32, int maxm, int grid, size_t lds, hipStream_t s, hipEvent_t ev0,
                       hipEvent_t ev1);
 hipError_t launch_rederive(const DevInst* d_insts, int n, const long long* plan, const StepInfo* info,
@@ -21,8 +25,10 @@ hipError_t launch_rederive(const DevInst* d_insts, int n, const long long* plan,
 // max_children: an upper bound on 2K over the problems at this step
 hipError_t launch_cut(const DevInst* d_insts, int n, int64_t max_children, hipStream_t s);
 hipError_t launch_gather(const DevInst* d_insts, int n, InstState* out, hipStream_t s);
-hipError_t launch_certify(const DevInst* d_insts, int n, const int* d_pre, int total_polys,
-                          int max_S, int tm_words, hipStream_t s);
+// polynomials per certification workgroup that fit LDS (0: none)
+int certify_run_length(int max_S, int tm_words);
+hipError_t launch_certify(const DevInst* d_insts, int n, const int* d_pre, int total_blocks,
+                          int max_S, int tm_words, int ppb, hipStream_t s);
 hipError_t launch_pack(const DevInst& I, int K, double* out, uint32_t* ids, double* err, int64_t W,
                        hipStream_t s);
 

@@ -91,6 +91,39 @@ __device__ __forceinline__ long long step_units(const DevInst& I, const InstStat
     return I.retire ? (long long)st->K * (I.T - T1) + st->u1 : (long long)st->K * I.T;
 }
 
+// One problem's share of a step's plan: its units per class (v) and the
+// snapshot of its state that the step's kernels use (si).  The memory test of
+// Alg. PCBA runs at the start of the iteration: 2 length(L) > M ends the
+// solve; more than the device list holds pauses the problem until the host
+// grows the list.  With `commit` the outcome and the peak list length are
+// stored in the state; a caller without it reaches the same decision from the
+// same state (a status already moved off RUNNING gives no units either).
+__device__ __forceinline__ void plan_one(const DevInst& I, bool commit, long long (&v)[4], StepInfo& si)
+{
+    InstState* st = I.st;
+    v[0] = v[1] = v[2] = v[3] = 0;
+    const int K = st->K;
+    if (st->status == ST_RUNNING) {
+        if (commit && (int64_t)K > st->peak) st->peak = K;
+        if (2LL * K > (int64_t)I.M) {
+            if (commit) st->status = ST_MEMLIMIT;
+        } else if (2LL * K > (int64_t)I.cap || (I.retire && 2 * st->a_live > I.hcap)) {
+            if (commit) st->status = ST_GROW;
+        } else {
+            const int c = unit_class(I, st);
+            v[c] = step_units(I, st);
+            if (c == 2) v[3] = (long long)K * 2 * I.rows;
+        }
+    }
+    si.K = K;
+    si.cur = st->cur;
+    si.r = st->r;
+    si.steps = st->steps;
+    si.p_up = st->p_up;
+    si.stamp = step_stamp(st);
+    si.pad = 0;
+}
+
 __global__ __launch_bounds__(1024) void k_plan(const DevInst* __restrict__ insts, int n,
                                                long long* __restrict__ plan,
                                                StepInfo* __restrict__ info)
@@ -102,30 +135,8 @@ __global__ __launch_bounds__(1024) void k_plan(const DevInst* __restrict__ insts
         const int b = b0 + t;
         long long v[4] = {0, 0, 0, 0};
         if (b < n) {
-            const DevInst& I = insts[b];
-            InstState* st = I.st;
-            if (st->status == ST_RUNNING) {
-                // memory test of Alg. PCBA at the start of the iteration:
-                // 2 length(L) > M ends the solve; more than the device list
-                // holds pauses the problem until the host grows the list
-                if ((int64_t)st->K > st->peak) st->peak = st->K;
-                if (2LL * st->K > (int64_t)I.M) st->status = ST_MEMLIMIT;
-                else if (2LL * st->K > (int64_t)I.cap || (I.retire && 2 * st->a_live > I.hcap))
-                    st->status = ST_GROW;
-                else {
-                    const int c = unit_class(I, st);
-                    v[c] = step_units(I, st);
-                    if (c == 2) v[3] = (long long)st->K * 2 * I.rows;
-                }
-            }
             StepInfo si;
-            si.K = st->K;
-            si.cur = st->cur;
-            si.r = st->r;
-            si.steps = st->steps;
-            si.p_up = st->p_up;
-            si.stamp = step_stamp(st);
-            si.pad = 0;
+            plan_one(insts[b], true, v, si);
             info[b] = si;
         }
         for (int c = 0; c < 4; ++c) {
@@ -189,6 +200,91 @@ __device__ __forceinline__ int fibre_base(const FibreGeom& g, int q)
     return outer * g.m * g.stride + inner;
 }
 
+// The fibre geometry of every axis of one kind, staged once in LDS (by one
+// thread) by kernels that walk the axes many times: the descriptor fields
+// would otherwise be dependent global loads inside their loops.
+struct AxisGeo {
+    int m, stride, F, pad;
+};
+__device__ __forceinline__ void stage_geo(AxisGeo* g, const int* dims, int l, int S)
+{
+    int st = 1;
+    for (int r = l - 1; r >= 0; --r) {
+        const int m = dims[r];
+        g[r].m = m;
+        g[r].stride = st;
+        g[r].F = m > 0 ? S / m : 0;
+        g[r].pad = 0;
+        st *= m;
+    }
+}
+
+// One fibre of fixed length M transformed in place: out_k = sum_i T[k][i] x_i,
+// the sum taken over i in increasing order; T row-major in LDS.
+template <int M>
+__device__ __forceinline__ void transform_fibre(double* __restrict__ x, int base, int stride,
+                                                const double* __restrict__ T)
+{
+    double c[M];
+#pragma unroll
+    for (int i = 0; i < M; ++i) c[i] = x[base + i * stride];
+#pragma unroll
+    for (int k = 0; k < M; ++k) {
+        double acc = 0.0;
+#pragma unroll
+        for (int i = 0; i < M; ++i) acc += T[k * M + i] * c[i];
+        x[base + k * stride] = acc;
+    }
+}
+
+__device__ __forceinline__ void transform_fibre_m(int m, double* x, int base, int stride, const double* T)
+{
+    switch (m) {
+#define PCBA_TF_CASE(MV) \
+    case MV: transform_fibre<MV>(x, base, stride, T); break;
+        PCBA_TF_CASE(1) PCBA_TF_CASE(2) PCBA_TF_CASE(3) PCBA_TF_CASE(4)
+        PCBA_TF_CASE(5) PCBA_TF_CASE(6) PCBA_TF_CASE(7) PCBA_TF_CASE(8)
+        PCBA_TF_CASE(9) PCBA_TF_CASE(10) PCBA_TF_CASE(11) PCBA_TF_CASE(12)
+        PCBA_TF_CASE(13) PCBA_TF_CASE(14) PCBA_TF_CASE(15) PCBA_TF_CASE(16)
+#undef PCBA_TF_CASE
+    default: break;
+    }
+}
+
+// One axis of a run of polynomials staged in LDS slots (polynomial q of the
+// run at slot + q * slot_stride, a second chain at + chain_off when nchain is
+// 2): every (chain, polynomial, fibre) of the run is one work item of the
+// block, whatever its kind, so that all lanes stay busy.  The run [pb, pe)
+// spans at most the three kinds, whose polynomial indices are contiguous
+// (c0 cost, then c1 inequalities, then equalities).  Each item applies mat0,
+// then mat1 if given, to its fibre in place.
+__device__ __forceinline__ void run_axis(double* slot, int slot_stride, int chain_off, int nchain, int pb,
+                                         int pe, int c0, int c1, const AxisGeo (*geo)[MAXL], int r,
+                                         const double* const* mat0, const double* const* mat1)
+{
+    for (int kind = 0; kind < KINDS; ++kind) {
+        const int lo = kind == 0 ? 0 : (kind == 1 ? c0 : c0 + c1);
+        const int hi = kind == 0 ? c0 : (kind == 1 ? c0 + c1 : INT_MAX);
+        const int q0 = max(pb, lo), q1 = min(pe, hi);
+        if (q1 <= q0) continue;
+        const AxisGeo ag = geo[kind][r];
+        FibreGeom g;
+        g.m = ag.m;
+        g.stride = ag.stride;
+        g.F = ag.F;
+        const int per = g.F * nchain;
+        const int items = (q1 - q0) * per;
+        for (int it = threadIdx.x; it < items; it += blockDim.x) {
+            const int q = it / per, rem = it - q * per;
+            const int ch = rem / g.F, f = rem - ch * g.F;
+            double* x = slot + (q0 - pb + q) * slot_stride + ch * chain_off;
+            const int base = fibre_base(g, f);
+            transform_fibre_m(g.m, x, base, g.stride, mat0[kind]);
+            if (mat1) transform_fibre_m(g.m, x, base, g.stride, mat1[kind]);
+        }
+    }
+}
+
 // gamma_m = m u / (1 - m u) with u = 2^-23 (covers unknown internal rounding)
 __device__ __forceinline__ double gamma32(int m)
 {
@@ -230,93 +326,144 @@ __device__ __forceinline__ void poly_kind(const DevInst& I, int poly, int& kind,
     }
 }
 
-// InitPatches: one workgroup per (problem, polynomial), blocks of problem b
-// are [pre[b], pre[b+1]).  Per axis r, the pre-map matrix A (x = lo + w t
-// substituted) then the conversion matrix U are applied; every output
-// coefficient is one thread's sum over i in increasing order.  The result is
-// the list's root item in FP64 plain mode (slot 0 of buffer 0) and is kept in
-// `root`.  In FP32 mode the root item is formed from the accurate root racc
-// instead: its midrange as the FP64 base, FP32 offsets from it, and the bound
-// root_err plus the offsets' rounding.
+// InitPatches: one workgroup per (problem, run of ppb polynomials), blocks of
+// problem b are [pre[b], pre[b+1]).  Per axis r, the pre-map matrix A (x = lo +
+// w t substituted) then the conversion matrix U are applied; every output
+// coefficient sums over i in increasing order.  The result is the list's root
+// item in FP64 plain mode (slot 0 of buffer 0) and is kept in `root`.  In FP32
+// mode the root item is formed from the accurate root racc instead: its
+// midrange as the FP64 base, FP32 offsets from it, and the bound root_err plus
+// the offsets' rounding.
+//   The workgroup stages the matrices of every kind and axis and the monomials
+// of its run in LDS (loads all in flight at once); then each wave takes one
+// polynomial per round, each lane whole fibres.  LDS (doubles): mat_words of
+// matrices (A then U per kind and axis, the layout of `mats`), then ppb slots
+// of max_S.
 __global__ __launch_bounds__(256) void k_root(const DevInst* __restrict__ insts, int n,
-                                             const int* __restrict__ pre)
+                                             const int* __restrict__ pre, int max_S, int ppb,
+                                             int mat_words)
 {
     extern __shared__ double sh[];
-    __shared__ double red[2][4];
+    __shared__ AxisGeo s_geo[KINDS][MAXL];
+    __shared__ int s_mo[KINDS][MAXL];
     const int bi = find_block(pre, n, blockIdx.x);
     const DevInst& I = insts[bi];
-    const int poly = blockIdx.x - pre[bi];
-    int kind, idx;
-    poly_kind(I, poly, kind, idx);
-    const int S = I.S[kind];
-    const int64_t off = I.off[kind] + (int64_t)idx * S;
-    double* x = sh;
-    double* y = sh + S;
-    for (int e = threadIdx.x; e < S; e += blockDim.x) x[e] = I.mono[off + e];
-    __syncthreads();
-    for (int r = 0; r < I.l; ++r) {
-        FibreGeom g = fibre_geom(I.dims[kind], I.l, r, S);
-        const double* A = I.mats + I.matoff[kind * MAXL + r];
-        const double* U = A + g.m * g.m;
-        for (int pass = 0; pass < 2; ++pass) {
-            const double* Mx = pass ? U : A;
-            const double* src = pass ? y : x;
-            double* dst = pass ? x : y;
-            for (int o = threadIdx.x; o < S; o += blockDim.x) {
-                const int k = (o / g.stride) % g.m;
-                const int fb = o - k * g.stride;
-                double acc = 0.0;
-                for (int i = 0; i < g.m; ++i) acc += Mx[k * g.m + i] * src[fb + i * g.stride];
-                dst[o] = acc;
+    const int l = I.l, nw = blockDim.x >> 6, w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int pb = (blockIdx.x - pre[bi]) * ppb;
+    const int pe = min(I.n_polys, pb + ppb);
+    const int c0 = I.count[0], c1 = I.count[1];
+    const int S0 = I.S[0], S1 = I.S[1], S2 = I.S[2];
+    const int64_t o0 = I.off[0], o1 = I.off[1], o2 = I.off[2];
+    double* mats = sh;
+    double* slot = sh + mat_words;
+    int nmat = 0;
+    for (int t = 0; t < KINDS; ++t)
+        for (int r = 0; r < l; ++r) nmat += 2 * I.dims[t][r] * I.dims[t][r];
+    // matrices and monomials of the run into LDS, up to 8 loads in flight per thread
+    {
+        const int total = nmat + (pe - pb) * max_S;
+        for (int e0 = threadIdx.x; e0 < total; e0 += 8 * blockDim.x) {
+            double v[8];
+            int dst[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const int e = e0 + k * blockDim.x;
+                dst[k] = -1;
+                if (e < nmat) {
+                    v[k] = I.mats[e];
+                    dst[k] = e;
+                } else if (e < total) {
+                    const int q = (e - nmat) / max_S, i = (e - nmat) - q * max_S;
+                    int idx = pb + q, kind = 0;
+                    if (idx >= c0) {
+                        idx -= c0;
+                        kind = 1;
+                        if (idx >= c1) { idx -= c1; kind = 2; }
+                    }
+                    const int S = kind == 0 ? S0 : (kind == 1 ? S1 : S2);
+                    if (i < S) {
+                        v[k] = I.mono[(kind == 0 ? o0 : (kind == 1 ? o1 : o2)) + (int64_t)idx * S + i];
+                        dst[k] = mat_words + q * max_S + i;
+                    }
+                }
             }
-            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < 8; ++k)
+                if (dst[k] >= 0) sh[dst[k]] = v[k];
         }
     }
-    // the root item: slot 0 of buffer 0, or in retiring mode for an
-    // inequality its heap patch idx
-    const bool inheap = I.retire && kind == 1;
-    void* dbase = inheap ? I.heap[0] : I.buf[0];
-    const int64_t doff = inheap ? (int64_t)idx * S : I.soff[kind] + (int64_t)idx * S;
-    for (int e = threadIdx.x; e < S; e += blockDim.x) I.root[off + e] = x[e];
-    if (!I.fp32) {
-        for (int e = threadIdx.x; e < S; e += blockDim.x) ((double*)dbase)[doff + e] = x[e];
-        if (threadIdx.x == 0 && inheap) I.act[0][idx] = make_int2(idx, idx);
-        return;
+    if (threadIdx.x < KINDS) {
+        const int t = threadIdx.x;
+        stage_geo(s_geo[t], I.dims[t], l, I.S[t]);
+        int o = 0;
+        for (int t2 = 0; t2 < t; ++t2)
+            for (int r = 0; r < l; ++r) o += 2 * I.dims[t2][r] * I.dims[t2][r];
+        for (int r = 0; r < l; ++r) {
+            s_mo[t][r] = o;
+            o += 2 * I.dims[t][r] * I.dims[t][r];
+        }
     }
-    // FP32: offsets from the midrange of the accurate root patch
-    const double* ra = I.racc + off;
-    double mn = INFINITY, mx = -INFINITY;
-    for (int e = threadIdx.x; e < S; e += blockDim.x) {
-        mn = fmin(mn, ra[e]);
-        mx = fmax(mx, ra[e]);
-    }
-    for (int o = 32; o > 0; o >>= 1) {
-        mn = fmin(mn, __shfl_xor(mn, o, 64));
-        mx = fmax(mx, __shfl_xor(mx, o, 64));
-    }
-    if ((threadIdx.x & 63) == 0) { red[0][threadIdx.x >> 6] = mn; red[1][threadIdx.x >> 6] = mx; }
     __syncthreads();
-    mn = red[0][0];
-    mx = red[1][0];
-    for (int w = 1; w < (int)(blockDim.x >> 6); ++w) { mn = fmin(mn, red[0][w]); mx = fmax(mx, red[1][w]); }
-    const double pbase = 0.5 * mn + 0.5 * mx;
-    __syncthreads();
-    double hr = 0.0;
-    for (int e = threadIdx.x; e < S; e += blockDim.x) {
-        const float d = (float)(ra[e] - pbase);
-        hr = fmax(hr, fabs((double)d));
-        ((float*)dbase)[doff + e] = d;
+    for (int r = 0; r < l; ++r) {
+        const double* A[KINDS];
+        const double* U[KINDS];
+        for (int t = 0; t < KINDS; ++t) {
+            A[t] = mats + s_mo[t][r];
+            U[t] = A[t] + s_geo[t][r].m * s_geo[t][r].m;
+        }
+        run_axis(slot, max_S, 0, 1, pb, pe, c0, c1, s_geo, r, A, U);
+        __syncthreads();
     }
-    for (int o = 32; o > 0; o >>= 1) hr = fmax(hr, __shfl_xor(hr, o, 64));
-    if ((threadIdx.x & 63) == 0) red[0][threadIdx.x >> 6] = hr;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        for (int w = 1; w < (int)(blockDim.x >> 6); ++w) hr = fmax(hr, red[0][w]);
-        if (inheap) I.act[0][idx] = make_int2(idx, idx);
-        // the accurate root's bound, the rounding of the offsets (the FP64
-        // difference and the conversion, 2^-23 of the largest), underflow
-        I.err[0][poly] = round_up_f(I.root_err[poly] + hr * 0x1p-23 + 0x1p-126);
-        I.base[0][poly] = pbase;
+    for (int p0 = pb; p0 < pe; p0 += nw) {
+        const int poly = p0 + w;
+        const bool act = poly < pe;
+        int kind = 0, idx = poly;
+        if (idx >= c0) {
+            idx -= c0;
+            kind = 1;
+            if (idx >= c1) { idx -= c1; kind = 2; }
+        }
+        const int S = kind == 0 ? S0 : (kind == 1 ? S1 : S2);
+        const int64_t off = (kind == 0 ? o0 : (kind == 1 ? o1 : o2)) + (int64_t)idx * S;
+        double* x = slot + (poly - pb) * max_S;
+        if (!act) continue;
+        // the root item: slot 0 of buffer 0, or in retiring mode for an
+        // inequality its heap patch idx
+        const bool inheap = I.retire && kind == 1;
+        void* dbase = inheap ? I.heap[0] : I.buf[0];
+        const int64_t doff = inheap ? (int64_t)idx * S : I.soff[kind] + (int64_t)idx * S;
+        for (int e = lane; e < S; e += 64) I.root[off + e] = x[e];
+        if (!I.fp32) {
+            for (int e = lane; e < S; e += 64) ((double*)dbase)[doff + e] = x[e];
+            if (lane == 0 && inheap) I.act[0][idx] = make_int2(idx, idx);
+            continue;
+        }
+        // FP32: offsets from the midrange of the accurate root patch
+        const double* ra = I.racc + off;
+        double mn = INFINITY, mx = -INFINITY;
+        for (int e = lane; e < S; e += 64) {
+            mn = fmin(mn, ra[e]);
+            mx = fmax(mx, ra[e]);
+        }
+        for (int o = 32; o > 0; o >>= 1) {
+            mn = fmin(mn, __shfl_xor(mn, o, 64));
+            mx = fmax(mx, __shfl_xor(mx, o, 64));
+        }
+        const double pbase = 0.5 * mn + 0.5 * mx;
+        double hr = 0.0;
+        for (int e = lane; e < S; e += 64) {
+            const float d = (float)(ra[e] - pbase);
+            hr = fmax(hr, fabs((double)d));
+            ((float*)dbase)[doff + e] = d;
+        }
+        for (int o = 32; o > 0; o >>= 1) hr = fmax(hr, __shfl_xor(hr, o, 64));
+        if (lane == 0) {
+            if (inheap) I.act[0][idx] = make_int2(idx, idx);
+            // the accurate root's bound, the rounding of the offsets (the FP64
+            // difference and the conversion, 2^-23 of the largest), underflow
+            I.err[0][poly] = round_up_f(I.root_err[poly] + hr * 0x1p-23 + 0x1p-126);
+            I.base[0][poly] = pbase;
+        }
     }
 }
 
@@ -333,7 +480,7 @@ __global__ __launch_bounds__(256) void k_racc(const DevInst* __restrict__ insts,
                                              const int* __restrict__ pre)
 {
     extern __shared__ double sh[];
-    __shared__ double red[4];
+    __shared__ double red[8];
     const int bi = find_block(pre, n, blockIdx.x);
     const DevInst& I = insts[bi];
     const int poly = blockIdx.x - pre[bi];
@@ -344,7 +491,7 @@ __global__ __launch_bounds__(256) void k_racc(const DevInst* __restrict__ insts,
     double* x = sh;
     double* y = sh + S;
     int q = 4;
-    double amax = 0.0;
+    double amax = 0.0, rmax = 0.0;
     for (int absp = 0; absp < 2; ++absp) {
         for (int e = threadIdx.x; e < S; e += blockDim.x) x[e] = absp ? fabs(I.mono[off + e]) : I.mono[off + e];
         __syncthreads();
@@ -365,17 +512,30 @@ __global__ __launch_bounds__(256) void k_racc(const DevInst* __restrict__ insts,
         }
         for (int e = threadIdx.x; e < S; e += blockDim.x) {
             if (absp) amax = fmax(amax, x[e]);
-            else I.racc[off + e] = x[e];
+            else {
+                I.racc[off + e] = x[e];
+                rmax = fmax(rmax, fabs(x[e]));
+            }
         }
         __syncthreads();
     }
-    for (int o = 32; o > 0; o >>= 1) amax = fmax(amax, __shfl_xor(amax, o, 64));
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = amax;
+    for (int o = 32; o > 0; o >>= 1) {
+        amax = fmax(amax, __shfl_xor(amax, o, 64));
+        rmax = fmax(rmax, __shfl_xor(rmax, o, 64));
+    }
+    if ((threadIdx.x & 63) == 0) {
+        red[threadIdx.x >> 6] = amax;
+        red[4 + (threadIdx.x >> 6)] = rmax;
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
-        for (int w = 1; w < (int)(blockDim.x >> 6); ++w) amax = fmax(amax, red[w]);
+        for (int w = 1; w < (int)(blockDim.x >> 6); ++w) {
+            amax = fmax(amax, red[w]);
+            rmax = fmax(rmax, red[4 + w]);
+        }
         // the |.| chain is itself rounded (below gamma_q relative): 1.01
         I.root_err[poly] = gamma64(q) * amax * 1.01;
+        I.root_abs[poly] = rmax;
     }
 }
 
@@ -414,6 +574,7 @@ __global__ void k_reset(const DevInst* __restrict__ insts, int n)
         I.na[1][1] = 0;
         I.upre[0] = 0;
         I.upre[1] = T1;
+        for (int q = 0; q < T1; ++q) I.umap[q] = make_int4(0, 0, q, I.count[1]);
     }
     I.live[0] = 0;
     for (int k = 0; k < I.l; ++k) I.ids[0][k] = 0;
@@ -546,11 +707,16 @@ __device__ __forceinline__ long long uniform64(long long x)
 // Unit v of a problem with K parents: the K cost tiles first (so that the cost
 // bounds of most children are recorded before their constraint tiles start),
 // then the equality tiles parent by parent, then the inequality tiles parent by
-// parent.  In retiring mode parent j owns inequality units [upre[j], upre[j+1]).
-// t is the tile index in item terms: an inequality tile t covers positions
+// parent.  In retiring mode parent j owns inequality units [upre[j], upre[j+1]),
+// and the unit map gives, per inequality unit, the parent, its slot and its
+// carried count as well (slot and na; -1 where not known here).  t is the tile
+// index in item terms: an inequality tile t covers positions
 // (t - tile_start[1]) * tile_polys[1] ... of the parent's carried list.
-__device__ __forceinline__ void unit_of(const DevInst& I, long long v, int K, int& j, int& t)
+__device__ __forceinline__ void unit_of(const DevInst& I, long long v, int K, int& j, int& t, int& slot,
+                                        int& na)
 {
+    slot = -1;
+    na = -1;
     const int T1 = I.tile_start[2] - I.tile_start[1];
     const int T2 = I.T - I.tile_start[2];
     if (v < K) {
@@ -570,14 +736,13 @@ __device__ __forceinline__ void unit_of(const DevInst& I, long long v, int K, in
         t = I.tile_start[1] + (int)(v - (long long)j * T1);
         return;
     }
-    // v is uniform over the workgroup, so are the probes (kept in scalar registers)
-    int lo = 0, hi = K;  // upre[lo] <= v < upre[hi]
-    while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (uniform64(I.upre[mid]) <= v) lo = mid; else hi = mid;
-    }
-    j = lo;
-    t = I.tile_start[1] + (int)(v - uniform64(I.upre[lo]));
+    // the unit map that k_cut wrote: parent, its slot, tile, carried count
+    // (v is uniform over the workgroup, so is the entry)
+    const int4 m = I.umap[v];
+    j = __builtin_amdgcn_readfirstlane(m.x);
+    t = I.tile_start[1] + __builtin_amdgcn_readfirstlane(m.z);
+    slot = __builtin_amdgcn_readfirstlane(m.y);
+    na = __builtin_amdgcn_readfirstlane(m.w);
 }
 
 // Patch index of element e of a tile of patches of S coefficients: e / S,
@@ -615,6 +780,7 @@ struct SubCtx {
     float invS;
     double pprev;
     uint32_t stamp;
+    FibreGeom g;   // the split direction's fibres in this tile's patches
 };
 
 // Resolves unit u: the problem (hint only moves forward, since a block's
@@ -636,21 +802,22 @@ __device__ __forceinline__ void resolve_unit(const DevInst* __restrict__ insts, 
     const DevInst& I = insts[hint];
     const StepInfo si = info[hint];
     c.bi = hint;
-    unit_of(I, u - pre[hint], si.K, c.j, c.t);
+    int mslot, mna;
+    unit_of(I, u - pre[hint], si.K, c.j, c.t, mslot, mna);
     c.j = __builtin_amdgcn_readfirstlane(c.j);
     c.t = __builtin_amdgcn_readfirstlane(c.t);
     c.cur = si.cur;
     c.r = si.r;
     c.pprev = si.p_up;
     c.stamp = si.stamp;
-    c.pslot = __builtin_amdgcn_readfirstlane(I.live[c.j]);
+    c.pslot = mslot >= 0 ? mslot : __builtin_amdgcn_readfirstlane(I.live[c.j]);
     c.kind = (c.t < I.tile_start[1]) ? 0 : ((c.t < I.tile_start[2]) ? 1 : 2);
     c.p0 = (c.t - I.tile_start[c.kind]) * I.tile_polys[c.kind];
     c.S = I.S[c.kind];
     c.invS = 1.0f / (float)c.S;
     c.gath = I.retire && c.kind == 1;
     if (c.gath) {
-        const int na = __builtin_amdgcn_readfirstlane(I.na[c.cur][c.pslot]);
+        const int na = mna >= 0 ? mna : __builtin_amdgcn_readfirstlane(I.na[c.cur][c.pslot]);
         c.np = min(I.tile_polys[1], na - c.p0);
         c.act = I.act[c.cur] + (int64_t)c.pslot * I.count[1] + c.p0;
         c.toff = 0;
@@ -660,6 +827,7 @@ __device__ __forceinline__ void resolve_unit(const DevInst* __restrict__ insts, 
         c.toff = I.soff[c.kind] + (int64_t)c.p0 * c.S;
     }
     c.TE = c.np * c.S;
+    c.g = fibre_geom(I.dims[c.kind], I.l, c.r, c.S);
 }
 
 // Thread 0 only: flags already OR-ed into the unit's children by other tiles.
@@ -698,20 +866,76 @@ __device__ __forceinline__ void issue_tile(const DevInst& I, const SubCtx& c, T 
     }
 }
 
+// FP32 mode: thread p < np of the workgroup loads the carried error bound and
+// FP64 base of the parent's patch p of the unit (issued with the tile, so that
+// the loads are in flight while the previous unit is processed).
+__device__ __forceinline__ void issue_eb(const DevInst& I, const SubCtx& c, float& e, double& b)
+{
+    const int p = threadIdx.x;
+    if (p >= c.np) return;
+    const int poly = (c.kind == 0) ? 0
+                   : I.count[0] + (c.kind == 2 ? I.count[1] + c.p0 + p : (c.gath ? c.act[p].x : c.p0 + p));
+    const int64_t pi = (int64_t)c.pslot * I.n_polys + poly;
+    e = I.err[c.cur][pi];
+    b = I.base[c.cur][pi];
+}
+
 // k_sub: one unit = (parent, tile) per workgroup, software-pipelined: the next
 // unit's tile is in flight in registers while the current one is split in LDS.
-template <typename T, int MM, int LB>
+//
+// With FUSE (at most PLAN_FUSE_MAX problems) the step's plan is not read
+// from k_plan's output but formed by every workgroup in LDS from the problems'
+// states (one lane per problem); workgroup 0 alone commits the memory test's
+// outcome and writes the plan and snapshots for the step's later kernels.
+template <typename T, int MM, int LB, bool FUSE>
 __global__ __launch_bounds__(SUB_THREADS) void k_sub(const DevInst* __restrict__ insts, int n_inst,
-                                                    const long long* __restrict__ plan,
-                                                    const StepInfo* __restrict__ info)
+                                                    long long* __restrict__ plan,
+                                                    StepInfo* __restrict__ info)
 {
     typedef typename KeyOf<T>::type K;
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ uint32_t s_flag[2];
     __shared__ int s_dead[2];
+    __shared__ long long s_pre[PLAN_FUSE_MAX + 1];
+    __shared__ StepInfo s_info[PLAN_FUSE_MAX];
 
     const bool fp32 = sizeof(T) == 4;
-    const long long* pre = plan + (fp32 ? 1 : 0) * (n_inst + 1);
+    const int cls = fp32 ? 1 : 0;
+    const long long* pre = plan + cls * (n_inst + 1);
+    const StepInfo* sinfo = info;
+    if (FUSE) {
+        if (threadIdx.x < 64) {
+            const int b = threadIdx.x;
+            const bool commit = blockIdx.x == 0;
+            long long v[4] = {0, 0, 0, 0};
+            if (b < n_inst) {
+                StepInfo si;
+                plan_one(insts[b], commit, v, si);
+                s_info[b] = si;
+                if (commit) info[b] = si;
+            }
+            for (int c = 0; c < 4; ++c) {
+                if (!commit && c != cls) continue;
+                long long x = v[c];
+                for (int o = 1; o < 64; o <<= 1) {
+                    const long long y = __shfl_up(x, o, 64);
+                    if (b >= o) x += y;
+                }
+                // x: inclusive prefix; lane 63 holds the total
+                if (c == cls) {
+                    if (b < n_inst) s_pre[b] = x - v[c];
+                    if (b == 63) s_pre[n_inst] = x;
+                }
+                if (commit) {
+                    if (b < n_inst) plan[c * (n_inst + 1) + b] = x - v[c];
+                    if (b == 63) plan[c * (n_inst + 1) + n_inst] = x;
+                }
+            }
+        }
+        __syncthreads();
+        pre = s_pre;
+        sinfo = s_info;
+    }
     const long long total = pre[n_inst];
     long long u = blockIdx.x;
     if (u >= total) return;
@@ -719,9 +943,12 @@ __global__ __launch_bounds__(SUB_THREADS) void k_sub(const DevInst* __restrict__
     SubCtx c, nc;
     T v[LB];
     uint32_t hfl, hfr;   // thread 0: flag hints of the current unit's children
-    resolve_unit(insts, n_inst, pre, info, u, hint, c);
+    resolve_unit(insts, n_inst, pre, sinfo, u, hint, c);
     issue_tile<T, LB>(insts[c.bi], c, v);
     load_hint(insts[c.bi], c, hfl, hfr);
+    float ce = 0.0f, ne = 0.0f;     // FP32: this thread's patch's carried error (current, next unit)
+    double cb = 0.0, nb = 0.0;      // and its FP64 base
+    if (fp32) issue_eb(insts[c.bi], c, ce, cb);
 
     for (;;) {
         const DevInst& I = insts[c.bi];
@@ -779,15 +1006,16 @@ __global__ __launch_bounds__(SUB_THREADS) void k_sub(const DevInst* __restrict__
         const long long un = u + gridDim.x;
         const bool more = un < total;
         if (more) {
-            resolve_unit(insts, n_inst, pre, info, un, hint, nc);
+            resolve_unit(insts, n_inst, pre, sinfo, un, hint, nc);
             issue_tile<T, LB>(insts[nc.bi], nc, v);
             load_hint(insts[nc.bi], nc, hfl, hfr);
+            if (fp32) issue_eb(insts[nc.bi], nc, ne, nb);
         }
         lds_barrier();
         // block-uniform: every wave reads the same LDS words after the barrier
         const bool deadL = s_dead[0] != 0, deadR = s_dead[1] != 0;
         if (!(deadL && deadR)) {
-            FibreGeom g = fibre_geom(I.dims[kind], l, r, S);
+            const FibreGeom g = c.g;
             tile_split<T, MM>(np, S, g, L);
             lds_barrier();
 
@@ -804,8 +1032,9 @@ __global__ __launch_bounds__(SUB_THREADS) void k_sub(const DevInst* __restrict__
                     // shrink with the box; the shift adds the rounding of v - mc (below
                     // 2^-24 (max - min)) and of the new FP64 base.
                     const int64_t pi = (int64_t)pslot * I.n_polys + poly;
-                    const float ep = I.err[cur][pi];
-                    base = I.base[cur][pi];
+                    const bool pre_ld = p < (int)blockDim.x;   // prefetched by this thread
+                    const float ep = pre_ld ? ce : I.err[cur][pi];
+                    base = pre_ld ? cb : I.base[cur][pi];
                     e = (double)round_up_f((double)ep + gamma32(g.m) * (double)funkey(L.key[5 * p + 4]) +
                                            (double)g.m * 0x1p-126);
                     for (int ch = 0; ch < 2; ++ch) {
@@ -962,67 +1191,32 @@ __global__ __launch_bounds__(SUB_THREADS) void k_sub(const DevInst* __restrict__
         if (!more) break;
         c = nc;
         u = un;
+        ce = ne;
+        cb = nb;
     }
 }
 
 // ------------------------------------------------------------------ k_rederive
 
-// Bernstein sub-interval transform on [a,b] inside [0,1] for degree n = m-1:
-// T[k][j] = sum_s b^{n-k}_s(a) b^k_{j-s}(b), the polar form of the basis
-// polynomial b^n_j at (a,..,a, b,..,b) (n-k copies of a, k of b); rows are
-// non-negative and sum to one.  The basis values come from the recurrence
-// b^q_s(t) = (1-t) b^{q-1}_s(t) + t b^{q-1}_{s-1}(t) (all terms non-negative,
-// so each table entry carries a relative error below gamma_{2q}); with the
-// products and the sum, |T~ - T| <= gamma_{5m} T entrywise.
-// tab holds 2*m*m doubles of scratch; all threads call it.
-__device__ void build_tmat(double* __restrict__ tm, double* __restrict__ tab, int m, double a, double b)
-{
-    const int n = m - 1;
-    double* Ba = tab;
-    double* Bb = tab + m * m;
-    if (threadIdx.x < 2) {
-        double* B = threadIdx.x ? Bb : Ba;
-        const double t = threadIdx.x ? b : a;
-        B[0] = 1.0;
-        for (int q = 1; q <= n; ++q) {
-            B[q * m + q] = t * B[(q - 1) * m + (q - 1)];
-            for (int s = q - 1; s >= 1; --s)
-                B[q * m + s] = (1.0 - t) * B[(q - 1) * m + s] + t * B[(q - 1) * m + (s - 1)];
-            B[q * m + 0] = (1.0 - t) * B[(q - 1) * m + 0];
-        }
-    }
-    __syncthreads();
-    for (int e = threadIdx.x; e < m * m; e += blockDim.x) {
-        const int k = e / m, j = e - k * m;
-        const int s0 = max(0, j - k), s1 = min(n - k, j);
-        double acc = 0.0;
-        for (int q = s0; q <= s1; ++q) acc += Ba[(n - k) * m + q] * Bb[k * m + (j - q)];
-        tm[e] = acc;
-    }
-    __syncthreads();
-}
-
-// Applies tmat (one m x m matrix per axis) to a patch in LDS (FP64), axis by
-// axis; x and y are two LDS buffers of S doubles; the result ends in x.
-__device__ void apply_tmats(double* x, double* y, const double* tm, const int* tmoff,
-                            const int* dims, int l, int S, int np)
+// Applies tmat (one m x m matrix per axis) to np patches in LDS (FP64), axis
+// by axis, in place: each thread takes whole fibres, reads one into registers
+// and writes the transformed fibre back (every output sums over i in order).
+__device__ void apply_tmats(double* x, const double* tm, const int* tmoff, const AxisGeo* geo, int l,
+                            int S, int np)
 {
     for (int r = 0; r < l; ++r) {
-        FibreGeom g = fibre_geom(dims, l, r, S);
+        const AxisGeo ag = geo[r];
+        FibreGeom g;
+        g.m = ag.m;
+        g.stride = ag.stride;
+        g.F = ag.F;
         const double* Tm = tm + tmoff[r];
         const int TF = np * g.F;
         for (int f = threadIdx.x; f < TF; f += blockDim.x) {
             const int p = f / g.F;
             const int base = p * S + fibre_base(g, f - p * g.F);
-            for (int k = 0; k < g.m; ++k) {
-                double acc = 0.0;
-                for (int i = 0; i < g.m; ++i) acc += Tm[k * g.m + i] * x[base + i * g.stride];
-                y[base + k * g.stride] = acc;
-            }
+            transform_fibre_m(g.m, x, base, g.stride, Tm);
         }
-        __syncthreads();
-        const int TE = np * S;
-        for (int e = threadIdx.x; e < TE; e += blockDim.x) x[e] = y[e];
         __syncthreads();
     }
 }
@@ -1101,35 +1295,41 @@ __global__ __launch_bounds__(SUB_THREADS) void k_rederive(const DevInst* __restr
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ uint32_t s_flag[2];
     __shared__ int s_tmoff[MAXL];
+    __shared__ AxisGeo s_geo[MAXL];
+    __shared__ double s_base[REDERIVE_CHUNK];   // per patch of a chunk: FP64 base,
+    __shared__ int s_keep[REDERIVE_CHUNK];      // whether the child carries it,
+    __shared__ int s_dst[REDERIVE_CHUNK];       // and its heap patch (retiring mode)
     const long long* pre = plan + 2 * (n_inst + 1);
     const long long total = pre[n_inst];
     for (long long u = blockIdx.x; u < total; u += gridDim.x) {
         const int bi = find_inst_uniform(pre, n_inst, u);
         const DevInst& I = insts[bi];
         const StepInfo si = info[bi];
-        int j, t;
-        unit_of(I, u - pre[bi], si.K, j, t);
+        int j, t, mslot, mna;
+        unit_of(I, u - pre[bi], si.K, j, t, mslot, mna);
         const int cur = si.cur, r = si.r, l = I.l;
-        const int pslot = __builtin_amdgcn_readfirstlane(I.live[j]);
+        const int pslot = mslot >= 0 ? mslot : __builtin_amdgcn_readfirstlane(I.live[j]);
         const int kind = (t < I.tile_start[1]) ? 0 : ((t < I.tile_start[2]) ? 1 : 2);
         const int p0 = (t - I.tile_start[kind]) * I.tile_polys[kind];
         // retiring mode: an inequality tile covers positions p0.. of the parent's carried list
         const bool gath = I.retire && kind == 1;
         const int2* pact = gath ? I.act[cur] + (int64_t)pslot * I.count[1] : nullptr;
-        const int navail = gath ? __builtin_amdgcn_readfirstlane(I.na[cur][pslot]) : I.count[kind];
+        const int navail = gath ? (mna >= 0 ? mna : __builtin_amdgcn_readfirstlane(I.na[cur][pslot]))
+                                : I.count[kind];
         const int np = min(I.tile_polys[kind], navail - p0);
         const int S = I.S[kind];
         // the tile is processed in chunks of at most MAX_TILE64 coefficients
-        const int cp = max(1, MAX_TILE64 / S);
+        // and REDERIVE_CHUNK patches
+        const int cp = min(REDERIVE_CHUNK, max(1, MAX_TILE64 / S));
         int tmsz = 0;
         for (int k = 0; k < l; ++k) tmsz += I.dims[kind][k] * I.dims[kind][k];
         double* x = (double*)smem;
-        double* y = x + min(np, cp) * S;
-        double* tm = y + min(np, cp) * S;
+        double* tm = x + min(np, cp) * S;
         if (threadIdx.x < 2) s_flag[threadIdx.x] = 0;
         if (threadIdx.x == 0) {
             int o = 0;
             for (int k = 0; k < l; ++k) { s_tmoff[k] = o; o += I.dims[kind][k] * I.dims[kind][k]; }
+            stage_geo(s_geo, I.dims[kind], l, S);
         }
         double g64 = 0.0;
         for (int k = 0; k < l; ++k) g64 += gamma64(6 * I.dims[kind][k] + 6);
@@ -1152,32 +1352,30 @@ __global__ __launch_bounds__(SUB_THREADS) void k_rederive(const DevInst* __restr
                 }
             }
             __syncthreads();
-            apply_tmats(x, y, tm, s_tmoff, I.dims[kind], l, S, nq);
+            apply_tmats(x, tm, s_tmoff, s_geo, l, S, nq);
             float* child = (float*)I.buf[cur ^ 1] + (int64_t)(2 * j + c) * I.stride;
             float* hc = (float*)I.heap[cur ^ 1];
             uint32_t fl = 0;
-            const int wv = threadIdx.x >> 6;
+            const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+            // each patch: its FP64 range and base (the midrange), the FP32
+            // offsets' range, the error bound and the child's bounds (one wave
+            // per patch; lane 0 records them)
             for (int p = wv; p < nq; p += blockDim.x >> 6) {
                 const int id = gath ? pact[p0 + q0 + p].x : p0 + q0 + p;
                 const int poly = (kind == 0 ? 0 : I.count[0] + (kind == 2 ? I.count[1] : 0) + id);
-                const double* rp = I.racc + roff + (int64_t)(gath ? id : p) * S;
-                // the FP64 patch's range and its base (the midrange), then the
-                // FP32 offsets from the base
-                double vmn = INFINITY, vmx = -INFINITY, rmax = 0.0;
-                for (int e = threadIdx.x & 63; e < S; e += 64) {
+                double vmn = INFINITY, vmx = -INFINITY;
+                for (int e = lane; e < S; e += 64) {
                     const double v = x[p * S + e];
                     vmn = fmin(vmn, v);
                     vmx = fmax(vmx, v);
-                    rmax = fmax(rmax, fabs(rp[e]));
                 }
                 for (int o = 32; o > 0; o >>= 1) {
                     vmn = fmin(vmn, __shfl_xor(vmn, o, 64));
                     vmx = fmax(vmx, __shfl_xor(vmx, o, 64));
-                    rmax = fmax(rmax, __shfl_xor(rmax, o, 64));
                 }
                 const double base = 0.5 * vmn + 0.5 * vmx;
                 float mn = INFINITY, mx = -INFINITY;
-                for (int e = threadIdx.x & 63; e < S; e += 64) {
+                for (int e = lane; e < S; e += 64) {
                     const float d = (float)(x[p * S + e] - base);
                     mn = fminf(mn, d);
                     mx = fmaxf(mx, d);
@@ -1186,29 +1384,18 @@ __global__ __launch_bounds__(SUB_THREADS) void k_rederive(const DevInst* __restr
                     mn = fminf(mn, __shfl_xor(mn, o, 64));
                     mx = fmaxf(mx, __shfl_xor(mx, o, 64));
                 }
-                // root bound (rows of T sum to one) + transform rounding on
-                // |T||root| <= max|root| + rounding of the offsets (the FP64
-                // difference and the FP32 conversion) + underflow
-                const double amax = fmax(fabs((double)mn), fabs((double)mx));
-                const double e = (double)round_up_f(I.root_err[poly] + g64 * rmax * 1.01 +
-                                                    amax * 0x1p-23 + 0x1p-126);
-                double lo, hi;
-                child_bounds<float>(mn, mx, e, base, lo, hi);
-                // retiring mode: an inequality certified satisfied is not carried;
-                // a carried one goes to a heap patch reserved by lane 0
-                const bool keep = !(gath && hi <= 0.0);
-                long long hx = 0;
-                if (gath && keep && (threadIdx.x & 63) == 0) {
-                    const int pos = atomicAdd(&I.na[cur ^ 1][2 * j + c], 1);
-                    hx = (long long)atomicAdd((unsigned long long*)&I.st->htop[cur ^ 1], 1ull);
-                    I.act[cur ^ 1][(int64_t)(2 * j + c) * I.count[1] + pos] = make_int2(id, (int)hx);
-                }
-                hx = __shfl(hx, 0, 64);
-                if (keep) {
-                    float* dp = gath ? hc + hx * S : child + soff + (int64_t)p * S;
-                    for (int q = threadIdx.x & 63; q < S; q += 64) dp[q] = (float)(x[p * S + q] - base);
-                }
-                if ((threadIdx.x & 63) == 0) {
+                if (lane == 0) {
+                    // root bound (rows of T sum to one) + transform rounding on
+                    // |T||root| <= max|root| + rounding of the offsets (the FP64
+                    // difference and the FP32 conversion) + underflow
+                    const double amax = fmax(fabs((double)mn), fabs((double)mx));
+                    const double e = (double)round_up_f(I.root_err[poly] + g64 * I.root_abs[poly] * 1.01 +
+                                                        amax * 0x1p-23 + 0x1p-126);
+                    double lo, hi;
+                    child_bounds<float>(mn, mx, e, base, lo, hi);
+                    // retiring mode: an inequality certified satisfied is not carried
+                    s_keep[p] = !(gath && hi <= 0.0);
+                    s_base[p] = base;
                     I.err[cur ^ 1][(int64_t)(2 * j + c) * I.n_polys + poly] = (float)e;
                     I.base[cur ^ 1][(int64_t)(2 * j + c) * I.n_polys + poly] = base;
                     if (kind == 0) {
@@ -1223,6 +1410,44 @@ __global__ __launch_bounds__(SUB_THREADS) void k_rederive(const DevInst* __restr
                             fl |= F_NOTFEAS;
                     }
                 }
+            }
+            __syncthreads();
+            // retiring mode: wave 0 reserves the kept patches of the chunk in
+            // the child's carried list and in the heap (one reservation each),
+            // ranks them by ballot and records each one's heap patch
+            if (gath && wv == 0) {
+                int cnt = 0;
+                for (int q = 0; q < nq; q += 64) cnt += __popcll(__ballot(q + lane < nq && s_keep[q + lane]));
+                int pos = 0;
+                long long hb = 0;
+                if (lane == 0 && cnt) {
+                    pos = atomicAdd(&I.na[cur ^ 1][2 * j + c], cnt);
+                    hb = (long long)atomicAdd((unsigned long long*)&I.st->htop[cur ^ 1], (unsigned long long)cnt);
+                }
+                pos = __shfl(pos, 0, 64);
+                hb = __shfl(hb, 0, 64);
+                const unsigned long long below = (1ull << lane) - 1ull;
+                for (int q = 0; q < nq; q += 64) {
+                    const int p = q + lane;
+                    const bool k = p < nq && s_keep[p];
+                    const unsigned long long bal = __ballot(k);
+                    const int rank = __popcll(bal & below);
+                    if (k) {
+                        I.act[cur ^ 1][(int64_t)(2 * j + c) * I.count[1] + pos + rank] =
+                            make_int2(pact[p0 + q0 + p].x, (int)(hb + rank));
+                        s_dst[p] = (int)(hb + rank);
+                    }
+                    pos += __popcll(bal);
+                    hb += __popcll(bal);
+                }
+            }
+            __syncthreads();
+            // the kept patches' FP32 offsets: to the child's slot, or its heap patch
+            for (int e = threadIdx.x; e < TE; e += blockDim.x) {
+                const int p = e / S;
+                if (!s_keep[p]) continue;
+                float* dp = gath ? hc + (int64_t)s_dst[p] * S : child + soff + (int64_t)p * S;
+                dp[e - p * S] = (float)(x[e] - s_base[p]);
             }
             if (fl) atomicOr(&s_flag[c], fl);
             __syncthreads();
@@ -1262,9 +1487,37 @@ __global__ __launch_bounds__(CUT_THREADS) void k_cut(const DevInst* __restrict__
     const bool fin = pprev < INFINITY;
     const int tid = threadIdx.x;
 
+    // the child records, read once: the first CUT_CACHE * blockDim children are
+    // kept in registers for the three passes below, any further ones are read
+    // again in each pass
+    const bool ret = I.retire != 0;
+    const int bd = blockDim.x;
+    double cmn[CUT_CACHE], cmx[CUT_CACHE];
+    uint32_t cfl[CUT_CACHE];
+    int cna[CUT_CACHE];
+#pragma unroll
+    for (int q = 0; q < CUT_CACHE; ++q) {
+        const int c = tid + q * bd;
+        cmn[q] = INFINITY;
+        cmx[q] = INFINITY;
+        cfl[q] = F_INFEAS;
+        cna[q] = 0;
+        if (c < C) {
+            cmn[q] = I.minP[c];
+            cmx[q] = I.maxP[c];
+            cfl[q] = I.flags[c];
+            if (ret) cna[q] = I.na[cur ^ 1][c];
+        }
+    }
+
     // solution estimate: least max B_p over feasible children
     double m = INFINITY;
-    for (int c = tid; c < C; c += blockDim.x) {
+#pragma unroll
+    for (int q = 0; q < CUT_CACHE; ++q) {
+        const bool dead = fin && cmn[q] > pprev;
+        if (!dead && !(cfl[q] & (F_INFEAS | F_NOTFEAS))) m = fmin(m, cmx[q]);
+    }
+    for (int c = tid + CUT_CACHE * bd; c < C; c += bd) {
         const double mnp = I.minP[c];
         const bool dead = fin && mnp > pprev;
         if (!dead && !(I.flags[c] & (F_INFEAS | F_NOTFEAS))) m = fmin(m, I.maxP[c]);
@@ -1273,7 +1526,13 @@ __global__ __launch_bounds__(CUT_THREADS) void k_cut(const DevInst* __restrict__
     const bool update = (m < INFINITY) && (m <= pprev);
     int arg = INT_MAX;
     if (update) {
-        for (int c = tid; c < C; c += blockDim.x) {
+#pragma unroll
+        for (int q = 0; q < CUT_CACHE; ++q) {
+            const int c = tid + q * bd;
+            const bool dead = fin && cmn[q] > pprev;
+            if (c < C && !dead && !(cfl[q] & (F_INFEAS | F_NOTFEAS)) && cmx[q] == m) arg = min(arg, c);
+        }
+        for (int c = tid + CUT_CACHE * bd; c < C; c += bd) {
             const double mnp = I.minP[c];
             const bool dead = fin && mnp > pprev;
             if (!dead && !(I.flags[c] & (F_INFEAS | F_NOTFEAS)) && I.maxP[c] == m) arg = min(arg, c);
@@ -1288,20 +1547,20 @@ __global__ __launch_bounds__(CUT_THREADS) void k_cut(const DevInst* __restrict__
     int base = 0;
     long long ubase = 0, asum = 0;
     const int lane = tid & 63, w = tid >> 6, nw = blockDim.x >> 6;
-    for (int c0 = 0; c0 < C; c0 += blockDim.x) {
+    // one chunk of blockDim children starting at c0 (uniform trip count: every
+    // thread runs every chunk, so the barriers inside are reached by all)
+    auto chunk = [&](int c0, double mnp, uint32_t fl, int a) {
         const int c = c0 + tid;
         bool keep = false;
         if (c < C) {
-            const double mnp = I.minP[c];
             const bool dead = fin && mnp > pprev;
-            if (!dead && !(I.flags[c] & F_INFEAS)) {
+            if (!dead && !(fl & F_INFEAS)) {
                 plo = fmin(plo, mnp);
                 keep = mnp <= p_up;
             }
         }
         long long ti = 0;
-        if (keep && I.retire) {
-            const int a = I.na[cur ^ 1][c];
+        if (keep && ret) {
             ti = (a + TP1 - 1) / TP1;
             asum += a;
         }
@@ -1331,12 +1590,34 @@ __global__ __launch_bounds__(CUT_THREADS) void k_cut(const DevInst* __restrict__
         }
         __syncthreads();
         if (keep) {
-            I.live[base + wsum[w] + before] = c;
-            if (I.retire) I.upre[base + wsum[w] + before] = ubase + wun[w] + ui - ti;
+            const int jn = base + wsum[w] + before;
+            I.live[jn] = c;
+            if (ret) {
+                const long long u0 = ubase + wun[w] + ui - ti;
+                I.upre[jn] = u0;
+                for (int q = 0; q < (int)ti; ++q) I.umap[u0 + q] = make_int4(jn, c, q, a);
+            }
         }
         base += wsum[nw];
         ubase += wun[nw];
         __syncthreads();
+    };
+#pragma unroll
+    for (int q = 0; q < CUT_CACHE; ++q) {
+        if (q * bd >= C) break;
+        chunk(q * bd, cmn[q], cfl[q], cna[q]);
+    }
+    for (int c0 = CUT_CACHE * bd; c0 < C; c0 += bd) {
+        const int c = c0 + tid;
+        double mnp = INFINITY;
+        uint32_t fl = F_INFEAS;
+        int a = 0;
+        if (c < C) {
+            mnp = I.minP[c];
+            fl = I.flags[c];
+            if (ret) a = I.na[cur ^ 1][c];
+        }
+        chunk(c0, mnp, fl, a);
     }
     plo = block_min(plo, shd);
     const int Kn = base;
@@ -1409,69 +1690,160 @@ __global__ __launch_bounds__(CUT_THREADS) void k_cut(const DevInst* __restrict__
 
 // ------------------------------------------------------------------ certification
 
-// One workgroup per (problem, polynomial): FP64 patch of x* from the root with
-// the sub-interval transforms, its min / max and a rigorous error bound: the
-// root's own bound (rows of T sum to one) plus, per axis, gamma_{6m+6} times the
-// |T| |x| chain (transform entries within gamma_{5m} relative, one product more).
+// Certification of x*, one workgroup per (problem, run of ppb polynomials): the
+// FP64 patch of x* from the accurate root with the sub-interval transforms, its
+// min / max and a rigorous error bound: the root's own bound (rows of T sum to
+// one) plus, per axis, gamma_{6m+6} times the |T| |root| chain (transform
+// entries within gamma_{5m} relative, one product more).
+//   The workgroup first puts the root patches of its run into LDS (all loads in
+// flight at once) while it builds the transforms of every kind and axis; then
+// each wave takes one polynomial per round and each lane whole fibres, the
+// signed chain and the |.| chain side by side.  The basis values come from
+// b^q_s(t) = C(q,s) t^s (1-t)^(q-s): 1 - t is exact (t is dyadic), so each
+// carries at most q+1 roundings, within the gamma_{2q} that the bound on T
+// assumes.
+// LDS (doubles): transforms, KINDS * l blocks of mm^2 (mm: the problem's longest
+// fibre); basis tables, 2 KINDS l mm^2; then 2 ppb slots of max_S.
 __global__ __launch_bounds__(256) void k_certify(const DevInst* __restrict__ insts, int n,
-                                                const int* __restrict__ pre)
+                                                const int* __restrict__ pre, int max_S, int ppb,
+                                                int tm_words)
 {
     extern __shared__ double shc[];
-    __shared__ int tmoff[MAXL];
-    __shared__ double red[3 * 4];
+    __shared__ AxisGeo s_geo[KINDS][MAXL];
+    __shared__ int s_S[KINDS], s_cnt[KINDS];
+    __shared__ long long s_off[KINDS];
     const int bi = find_block(pre, n, blockIdx.x);
     const DevInst& I = insts[bi];
     const InstState* st = I.st;
     if (!st->has_x) return;
-    const int poly = blockIdx.x - pre[bi];
-    int kind, idx;
-    poly_kind(I, poly, kind, idx);
-    const int S = I.S[kind], l = I.l;
+    const int l = I.l, nw = blockDim.x >> 6, w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int pb = (blockIdx.x - pre[bi]) * ppb;
+    const int pe = min(I.n_polys, pb + ppb);
+    const int c0 = I.count[0], c1 = I.count[1];
+    double* tm = shc;
+    double* tab = shc + tm_words;
+    double* slot = tab + 2 * tm_words;   // polynomial q of the run: signed at 2q, |.| at 2q+1
+    // root patches of the run into LDS, up to 8 loads in flight per thread
+    {
+        const int S0 = I.S[0], S1 = I.S[1], S2 = I.S[2];
+        const int64_t o0 = I.off[0], o1 = I.off[1], o2 = I.off[2];
+        const int total = (pe - pb) * max_S;
+        for (int e0 = threadIdx.x; e0 < total; e0 += 8 * blockDim.x) {
+            double v[8];
+            int dst[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const int e = e0 + k * blockDim.x;
+                dst[k] = -1;
+                if (e < total) {
+                    const int q = e / max_S, i = e - q * max_S;
+                    int poly = pb + q, kind = 0;
+                    if (poly >= c0) {
+                        poly -= c0;
+                        kind = 1;
+                        if (poly >= c1) { poly -= c1; kind = 2; }
+                    }
+                    const int S = kind == 0 ? S0 : (kind == 1 ? S1 : S2);
+                    if (i < S) {
+                        v[k] = I.racc[(kind == 0 ? o0 : (kind == 1 ? o1 : o2)) + (int64_t)poly * S + i];
+                        dst[k] = 2 * q * max_S + i;
+                    }
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < 8; ++k)
+                if (dst[k] >= 0) {
+                    slot[dst[k]] = v[k];
+                    slot[dst[k] + max_S] = fabs(v[k]);
+                }
+        }
+    }
+    if (threadIdx.x < KINDS) {
+        const int kind = threadIdx.x;
+        s_S[kind] = I.S[kind];
+        s_cnt[kind] = I.count[kind];
+        s_off[kind] = I.off[kind];
+        stage_geo(s_geo[kind], I.dims[kind], l, I.S[kind]);
+    }
     int mm = 1;
-    for (int k = 0; k < l; ++k) mm = max(mm, I.dims[kind][k]);
-    double* x = shc;
-    double* y = x + S;
-    double* tm = y + S;
-    double* tab = tm + l * mm * mm;
-    if (threadIdx.x == 0) {
-        int o = 0;
-        for (int k = 0; k < l; ++k) { tmoff[k] = o; o += I.dims[kind][k] * I.dims[kind][k]; }
+    for (int kind = 0; kind < KINDS; ++kind)
+        if (I.count[kind] > 0)
+            for (int k = 0; k < l; ++k) mm = max(mm, I.dims[kind][k]);
+    const int mm2 = mm * mm;
+    const int nb = KINDS * l;
+    // basis tables: block 2 (kind * l + axis) + side holds b^q_s(t) at q * m + s,
+    // t = a (side 0) or b (side 1) of axis k of x*
+    for (int e = threadIdx.x; e < 2 * nb * mm2; e += blockDim.x) {
+        const int bk = e / mm2, ka = bk >> 1, side = bk & 1, kind = ka / l, k = ka - kind * l;
+        const int q2 = e - bk * mm2;
+        if (I.count[kind] == 0) continue;
+        const int m = I.dims[kind][k];
+        const int q = q2 / m, s2 = q2 - q * m;
+        if (q >= m || s2 > q) continue;
+        const double t = ldexp((double)st->x_index[k] + (double)side, -st->x_depth[k]);
+        const double u = 1.0 - t;
+        double v = 1.0;
+        for (int i = 0; i < s2; ++i) v *= t;
+        double v2 = 1.0;
+        for (int i = 0; i < q - s2; ++i) v2 *= u;
+        // C(q, s2), exact in FP64 for q < 16
+        double cq = 1.0;
+        for (int i = 1; i <= s2; ++i) cq = cq * (double)(q - s2 + i) / (double)i;
+        tab[e] = cq * v * v2;
     }
     __syncthreads();
-    for (int k = 0; k < l; ++k)
-        build_tmat(tm + tmoff[k], tab, I.dims[kind][k], ldexp((double)st->x_index[k], -st->x_depth[k]),
-                   ldexp((double)st->x_index[k] + 1.0, -st->x_depth[k]));
-    const double* rp = I.racc + I.off[kind] + (int64_t)idx * S;
-    double gsum = 0.0;
-    for (int r = 0; r < l; ++r) gsum += gamma64(6 * I.dims[kind][r] + 6);
-    double mn = INFINITY, mx = -INFINITY, am = 0.0;
-    for (int absp = 0; absp < 2; ++absp) {
-        for (int e = threadIdx.x; e < S; e += blockDim.x) x[e] = absp ? fabs(rp[e]) : rp[e];
-        __syncthreads();
-        apply_tmats(x, y, tm, tmoff, I.dims[kind], l, S, 1);
-        for (int e = threadIdx.x; e < S; e += blockDim.x) {
-            if (absp) am = fmax(am, x[e]);
-            else { mn = fmin(mn, x[e]); mx = fmax(mx, x[e]); }
-        }
-        __syncthreads();
+    // T[k][j] = sum_s b^{n-k}_s(a) b^k_{j-s}(b), one entry per thread
+    for (int e = threadIdx.x; e < nb * mm2; e += blockDim.x) {
+        const int ka = e / mm2, kind = ka / l, k = ka - kind * l, q = e - ka * mm2;
+        if (s_cnt[kind] == 0) continue;
+        const int m = s_geo[kind][k].m, nd = m - 1;
+        if (q >= m * m) continue;
+        const int row = q / m, j = q - row * m;
+        const double* Ba = tab + (2 * ka) * mm2;
+        const double* Bb = Ba + mm2;
+        const int s0 = max(0, j - row), s1 = min(nd - row, j);
+        double acc = 0.0;
+        for (int s2 = s0; s2 <= s1; ++s2) acc += Ba[(nd - row) * m + s2] * Bb[row * m + (j - s2)];
+        tm[ka * mm2 + q] = acc;
     }
-    for (int o = 32; o > 0; o >>= 1) {
-        mn = fmin(mn, __shfl_xor(mn, o, 64));
-        mx = fmax(mx, __shfl_xor(mx, o, 64));
-        am = fmax(am, __shfl_xor(am, o, 64));
-    }
-    const int w = threadIdx.x >> 6;
-    if ((threadIdx.x & 63) == 0) { red[3 * w] = mn; red[3 * w + 1] = mx; red[3 * w + 2] = am; }
     __syncthreads();
-    if (threadIdx.x == 0) {
-        for (int q = 1; q < (int)(blockDim.x >> 6); ++q) {
-            mn = fmin(mn, red[3 * q]);
-            mx = fmax(mx, red[3 * q + 1]);
-            am = fmax(am, red[3 * q + 2]);
+    for (int r = 0; r < l; ++r) {
+        const double* Tm[KINDS];
+        for (int t = 0; t < KINDS; ++t) Tm[t] = tm + (t * l + r) * mm2;
+        run_axis(slot, 2 * max_S, max_S, 2, pb, pe, c0, c1, s_geo, r, Tm, nullptr);
+        __syncthreads();
+    }
+    for (int p0 = pb; p0 < pe; p0 += nw) {
+        const int poly = p0 + w;
+        const bool act = poly < pe;
+        int kind = 0, idx = poly;
+        if (idx >= c0) {
+            idx -= c0;
+            kind = 1;
+            if (idx >= c1) { idx -= c1; kind = 2; }
         }
-        I.cert[3 * poly + 0] = mn;
-        I.cert[3 * poly + 1] = mx;
-        I.cert[3 * poly + 2] = I.root_err[poly] + gsum * am * 1.01;
+        const int S = s_S[kind];
+        double* x = slot + 2 * (poly - pb) * max_S;
+        double* xa = x + max_S;
+        double mn = INFINITY, mx = -INFINITY, am = 0.0;
+        if (act)
+            for (int e = lane; e < S; e += 64) {
+                mn = fmin(mn, x[e]);
+                mx = fmax(mx, x[e]);
+                am = fmax(am, xa[e]);
+            }
+        for (int o = 32; o > 0; o >>= 1) {
+            mn = fmin(mn, __shfl_xor(mn, o, 64));
+            mx = fmax(mx, __shfl_xor(mx, o, 64));
+            am = fmax(am, __shfl_xor(am, o, 64));
+        }
+        if (act && lane == 0) {
+            double gsum = 0.0;
+            for (int r = 0; r < l; ++r) gsum += gamma64(6 * s_geo[kind][r].m + 6);
+            I.cert[3 * poly + 0] = mn;
+            I.cert[3 * poly + 1] = mx;
+            I.cert[3 * poly + 2] = I.root_err[poly] + gsum * am * 1.01;
+        }
     }
 }
 
@@ -1567,14 +1939,40 @@ __global__ void k_gather(const DevInst* __restrict__ insts, int n, InstState* __
 
 // ------------------------------------------------------------------ host launchers
 
-hipError_t launch_reset_root(const DevInst* d_insts, int n, const int* d_pre, int total_polys,
-                             int max_S, hipStream_t s)
+// LDS bytes a workgroup may use on the current device
+static size_t lds_per_block()
 {
+    static size_t cached = 0;
+    if (!cached) {
+        int dev = 0, v = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && v > 0)
+            cached = (size_t)v;
+        else
+            cached = 65536;
+    }
+    return cached;
+}
+
+
+int root_run_length(int max_S, int tm_words)
+{
+    // polynomials per workgroup: one slot each beside the matrices in the
+    // workgroup's LDS, at most 16
+    const long long room = (long long)(lds_per_block() / sizeof(double)) - 2LL * tm_words;
+    return (int)std::max(0LL, std::min(16LL, room / std::max(1, max_S)));
+}
+
+hipError_t launch_reset_root(const DevInst* d_insts, int n, const int* d_pre, int total_blocks, int max_S,
+                             int tm_words, int ppb, hipStream_t s)
+{
+    if (ppb < 1 || ppb > root_run_length(max_S, tm_words)) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_reset, dim3((n + 63) / 64), dim3(64), 0, s, d_insts, n);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_root, dim3(total_polys), dim3(256), 2 * (size_t)max_S * sizeof(double), s,
-                       d_insts, n, d_pre);
+    const int mat_words = 2 * tm_words;
+    const size_t lds = ((size_t)mat_words + (size_t)ppb * max_S) * sizeof(double);
+    hipLaunchKernelGGL(k_root, dim3(total_blocks), dim3(256), lds, s, d_insts, n, d_pre, max_S, ppb, mat_words);
     return hipGetLastError();
 }
 
@@ -1595,10 +1993,9 @@ hipError_t launch_plan(const DevInst* d_insts, int n, long long* plan, StepInfo*
 }
 
 // With ev0/ev1 the launch stamps them at the kernel's own start and end.
-template <typename T, int MM>
-static hipError_t launch_sub_t(const DevInst* d_insts, int n, const long long* plan,
-                               const StepInfo* info, int grid, size_t lds, hipStream_t s,
-                               hipEvent_t ev0, hipEvent_t ev1)
+template <typename T, int MM, bool FUSE>
+static hipError_t launch_sub_t(const DevInst* d_insts, int n, long long* plan, StepInfo* info, int grid,
+                               size_t lds, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1)
 {
     // registers per thread for a tile in flight: the largest tile / 256 lanes
     constexpr int LB = (sizeof(T) == 8 ? MAX_TILE64 : MAX_TILE32) / SUB_THREADS;
@@ -1610,30 +2007,44 @@ static hipError_t launch_sub_t(const DevInst* d_insts, int n, const long long* p
     if (!cus && hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, 0) != hipSuccess) cus = 0;
     if (lds != cached_lds) {
         int nb = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_sub<T, MM, LB>, SUB_THREADS, lds) == hipSuccess)
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_sub<T, MM, LB, FUSE>, SUB_THREADS, lds) ==
+            hipSuccess)
             per_cu = nb;
         cached_lds = lds;
     }
     if (cus > 0 && per_cu > 0) grid = std::min(grid, cus * per_cu);
     if (ev0)
-        hipExtLaunchKernelGGL((k_sub<T, MM, LB>), dim3(grid), dim3(SUB_THREADS), lds, s, ev0, ev1, 0,
+        hipExtLaunchKernelGGL((k_sub<T, MM, LB, FUSE>), dim3(grid), dim3(SUB_THREADS), lds, s, ev0, ev1, 0,
                               d_insts, n, plan, info);
     else
-        hipLaunchKernelGGL((k_sub<T, MM, LB>), dim3(grid), dim3(SUB_THREADS), lds, s, d_insts, n, plan, info);
+        hipLaunchKernelGGL((k_sub<T, MM, LB, FUSE>), dim3(grid), dim3(SUB_THREADS), lds, s, d_insts, n, plan,
+                           info);
     return hipGetLastError();
 }
 
-hipError_t launch_sub(const DevInst* d_insts, int n, const long long* plan, const StepInfo* info,
+template <typename T, int MM>
+static hipError_t launch_sub_f(const DevInst* d_insts, int n, long long* plan, StepInfo* info, bool fuse,
+                               int grid, size_t lds, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1)
+{
+    if (fuse) return launch_sub_t<T, MM, true>(d_insts, n, plan, info, grid, lds, s, ev0, ev1);
+    return launch_sub_t<T, MM, false>(d_insts, n, plan, info, grid, lds, s, ev0, ev1);
+}
+
+hipError_t launch_sub(const DevInst* d_insts, int n, long long* plan, StepInfo* info, bool fuse,
                       bool fp32, int maxm, int grid, size_t lds, hipStream_t s, hipEvent_t ev0,
                       hipEvent_t ev1)
 {
-    if (grid <= 0) return hipSuccess;
-    if (fp32) {
-        if (maxm <= 8) return launch_sub_t<float, 8>(d_insts, n, plan, info, grid, lds, s, ev0, ev1);
-        return launch_sub_t<float, 16>(d_insts, n, plan, info, grid, lds, s, ev0, ev1);
+    if (fuse && n > PLAN_FUSE_MAX) return hipErrorInvalidValue;
+    if (grid <= 0) {
+        if (!fuse) return hipSuccess;
+        grid = 1;   // the plan is still formed and written
     }
-    if (maxm <= 8) return launch_sub_t<double, 8>(d_insts, n, plan, info, grid, lds, s, ev0, ev1);
-    return launch_sub_t<double, 16>(d_insts, n, plan, info, grid, lds, s, ev0, ev1);
+    if (fp32) {
+        if (maxm <= 8) return launch_sub_f<float, 8>(d_insts, n, plan, info, fuse, grid, lds, s, ev0, ev1);
+        return launch_sub_f<float, 16>(d_insts, n, plan, info, fuse, grid, lds, s, ev0, ev1);
+    }
+    if (maxm <= 8) return launch_sub_f<double, 8>(d_insts, n, plan, info, fuse, grid, lds, s, ev0, ev1);
+    return launch_sub_f<double, 16>(d_insts, n, plan, info, fuse, grid, lds, s, ev0, ev1);
 }
 
 hipError_t launch_rederive(const DevInst* d_insts, int n, const long long* plan, const StepInfo* info,
@@ -1662,11 +2073,21 @@ hipError_t launch_gather(const DevInst* d_insts, int n, InstState* out, hipStrea
     return hipGetLastError();
 }
 
-hipError_t launch_certify(const DevInst* d_insts, int n, const int* d_pre, int total_polys,
-                          int max_S, int tm_words, hipStream_t s)
+int certify_run_length(int max_S, int tm_words)
 {
-    const size_t lds = (2 * (size_t)max_S + (size_t)tm_words) * sizeof(double);
-    hipLaunchKernelGGL(k_certify, dim3(total_polys), dim3(256), lds, s, d_insts, n, d_pre);
+    // polynomials per workgroup: two slots each beside the transforms and the
+    // basis tables in the workgroup's LDS, at most 16
+    const long long room = (long long)(lds_per_block() / sizeof(double)) - 3LL * tm_words;
+    return (int)std::max(0LL, std::min(16LL, room / (2LL * std::max(1, max_S))));
+}
+
+hipError_t launch_certify(const DevInst* d_insts, int n, const int* d_pre, int total_blocks,
+                          int max_S, int tm_words, int ppb, hipStream_t s)
+{
+    if (ppb < 1 || ppb > certify_run_length(max_S, tm_words)) return hipErrorInvalidValue;
+    const size_t lds = (3 * (size_t)tm_words + 2 * (size_t)ppb * max_S) * sizeof(double);
+    hipLaunchKernelGGL(k_certify, dim3(total_blocks), dim3(256), lds, s, d_insts, n, d_pre, max_S, ppb,
+                       tm_words);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_certify_final, dim3(n), dim3(256), 0, s, d_insts, n);

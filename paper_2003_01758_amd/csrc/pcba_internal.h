@@ -19,7 +19,11 @@ constexpr int KINDS = 3;      // 0 cost p, 1 inequalities g_i, 2 equalities h_j
 constexpr int MAXL = 8;       // PCBA_MAX_DIM
 constexpr int MAXM = 16;      // longest fibre: degree 15 + 1
 constexpr int SUB_THREADS = 256;
+constexpr int CERT_PPB = 16;    // polynomials per certification workgroup
+constexpr int PLAN_FUSE_MAX = 64;  // batches up to this size form the plan inside k_sub
 constexpr int CUT_THREADS = 1024;
+constexpr int CUT_CACHE = 4;      // children per thread k_cut keeps in registers
+constexpr int REDERIVE_CHUNK = 256;  // patches per re-derivation chunk
 constexpr int MAX_BATCH = 2048;   // problems per launch
 constexpr int MAX_TILE64 = 3584;  // largest tile (coefficients) of an FP64 unit: 14 per lane
 constexpr int MAX_TILE32 = 7168;  // largest tile of an FP32 unit: 28 per lane
@@ -129,6 +133,8 @@ struct DevInst {
     void* heap[2];
     int64_t hcap;                  // patches each heap holds
     int64_t* upre;                 // cap + 1: first inequality unit of each live item, then the total
+    int4* umap;                    // hcap entries: inequality unit v of the step -> (parent, its slot,
+                                   // tile of its carried list, carried count), written by k_cut
     double* tmat;                  // FP32 re-derivation: cap/2 parents x 2 children x tmw doubles
     int32_t tmw;                   // transform words per child: sum over kinds and axes of m^2
     int32_t tmk[KINDS];            // offset of each kind's transforms inside a child's block
@@ -138,6 +144,7 @@ struct DevInst {
     double* racc;                  // the same patches converted in one stage per axis with
                                    // the combined matrices (an accurate root)
     double* root_err;              // rigorous bound on |racc - exact| per patch
+    double* root_abs;              // max |racc| over each patch
     double* cert;                  // certification scratch: n_polys * 3 doubles
     TraceRec* trace;               // MAX_TRACE step records
     const double* mono;            // monomials, zero-padded, item layout (W doubles)

@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -164,6 +165,7 @@ struct pcba_problem {
     void* d_heap[2] = {nullptr, nullptr};  // retiring mode: the carried inequality patches
     int64_t hcap = 0;                      // patches per heap
     int64_t* d_upre = nullptr;
+    int4* d_umap = nullptr;                // retiring mode: hcap entries
     bool retire = false;
     double* d_tmat = nullptr;
     int tmw = 0, rows = 0, tmk[KINDS] = {};
@@ -183,25 +185,119 @@ struct pcba_problem {
     int host_steps = 0;      // steps known on the host (for re-derivation planning)
 };
 
-struct pcba_engine {
-    hipStream_t stream = nullptr;
-    bool own_stream = false;
-    int64_t budget = 0, used = 0;
-    int64_t reserve = 0;      // list items charged to every admitted problem at least
-    std::vector<pcba_problem*> active;
-    std::vector<pcba_problem*> done;
+// Per-step buffers of an engine (descriptors, plan, step snapshots, states and
+// their pinned staging), sized for `cap` problems on `dev`.
+struct EngineBufs {
+    int dev = -1;
+    int cap = 0;
     DevInst* d_insts = nullptr;
-    int d_insts_cap = 0;
     long long* d_plan = nullptr;
     StepInfo* d_info = nullptr;
     InstState* d_states = nullptr;
     InstState* h_states = nullptr;
     DevInst* h_insts = nullptr;    // pinned staging of the descriptors (outlives the async copy)
-    int states_cap = 0;
+};
+
+struct pcba_engine {
+    hipStream_t stream = nullptr;
+    int64_t budget = 0, used = 0;
+    int64_t reserve = 0;      // list items charged to every admitted problem at least
+    std::vector<pcba_problem*> active;
+    std::vector<pcba_problem*> done;
+    EngineBufs b;
     bool dirty = true;
 };
 
 // ------------------------------------------------------------------ helpers
+
+// The library's stream of the calling thread on the current device, created on
+// first use and kept for the life of the process (default priority,
+// non-blocking).
+static hipError_t library_stream(hipStream_t* out)
+{
+    constexpr int kMaxDev = 64;
+    thread_local hipStream_t streams[kMaxDev] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDev) return hipErrorInvalidDevice;
+    if (!streams[dev]) {
+        e = hipStreamCreateWithFlags(&streams[dev], hipStreamNonBlocking);
+        if (e != hipSuccess) {
+            streams[dev] = nullptr;
+            return e;
+        }
+    }
+    *out = streams[dev];
+    return hipSuccess;
+}
+
+// Engine buffers are kept for reuse: a batch solve creates an engine per call,
+// and the device and pinned allocations would otherwise cost more than the
+// first steps.  A few sets are cached per process.
+std::mutex g_bufs_mu;
+std::vector<EngineBufs> g_bufs_cache;
+
+static void bufs_free(EngineBufs& b)
+{
+    if (b.d_insts) (void)hipFree(b.d_insts);
+    if (b.d_plan) (void)hipFree(b.d_plan);
+    if (b.d_info) (void)hipFree(b.d_info);
+    if (b.d_states) (void)hipFree(b.d_states);
+    if (b.h_states) (void)hipHostFree(b.h_states);
+    if (b.h_insts) (void)hipHostFree(b.h_insts);
+    b = EngineBufs();
+}
+
+// Gives a set back to the cache (the caller has synchronised every stream that
+// used it); `b` is left empty.
+static void bufs_put(EngineBufs& b)
+{
+    if (b.cap == 0) return;
+    {
+        std::lock_guard<std::mutex> lk(g_bufs_mu);
+        if (g_bufs_cache.size() < 8) {
+            g_bufs_cache.push_back(b);
+            b = EngineBufs();
+            return;
+        }
+    }
+    bufs_free(b);
+}
+
+// A set for at least `cap` problems on the current device: a cached one if
+// one is large enough, else a new one.
+static hipError_t bufs_get(int cap, EngineBufs* out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    {
+        std::lock_guard<std::mutex> lk(g_bufs_mu);
+        for (size_t i = 0; i < g_bufs_cache.size(); ++i)
+            if (g_bufs_cache[i].dev == dev && g_bufs_cache[i].cap >= cap) {
+                *out = g_bufs_cache[i];
+                g_bufs_cache.erase(g_bufs_cache.begin() + i);
+                return hipSuccess;
+            }
+    }
+    EngineBufs b;
+    b.dev = dev;
+    const int c = std::max(cap, 64);
+    e = hipMalloc((void**)&b.d_insts, c * sizeof(DevInst));
+    if (e == hipSuccess) e = hipMalloc((void**)&b.d_plan, 4 * (size_t)(c + 1) * sizeof(long long));
+    if (e == hipSuccess) e = hipMalloc((void**)&b.d_info, (size_t)c * sizeof(StepInfo));
+    if (e == hipSuccess) e = hipMalloc((void**)&b.d_states, c * sizeof(InstState));
+    if (e == hipSuccess) e = hipHostMalloc((void**)&b.h_states, c * sizeof(InstState), hipHostMallocDefault);
+    if (e == hipSuccess) e = hipHostMalloc((void**)&b.h_insts, c * sizeof(DevInst), hipHostMallocDefault);
+    if (e != hipSuccess) {
+        bufs_free(b);
+        return e;
+    }
+    b.cap = c;
+    *out = b;
+    return hipSuccess;
+}
 
 static DevInst make_dev(const pcba_problem* P)
 {
@@ -242,6 +338,7 @@ static DevInst make_dev(const pcba_problem* P)
         I.heap[b] = P->d_heap[b];
     }
     I.hcap = P->hcap;
+    I.umap = P->d_umap;
     I.upre = P->d_upre;
     I.live = P->d_live;
     I.minP = P->d_minP;
@@ -254,6 +351,7 @@ static DevInst make_dev(const pcba_problem* P)
     for (int t = 0; t < KINDS; ++t) I.tmk[t] = P->tmk[t];
     I.root = P->d_root;
     I.root_err = P->d_root_err;
+    I.root_abs = P->d_root_err + P->n_polys;
     I.racc = P->d_racc;
     I.macc = P->d_macc;
     I.cert = P->d_cert;
@@ -275,7 +373,8 @@ static int64_t item_bytes(const pcba_problem* P)
 // patches: two buffers of slots, two heaps, the root and records.
 static int64_t footprint_of(const pcba_problem* P, int64_t boxes, int64_t hcap)
 {
-    return 2 * boxes * item_bytes(P) + (P->retire ? 2 * hcap * P->S[1] * (int64_t)P->elem : 0) +
+    return 2 * boxes * item_bytes(P) +
+           (P->retire ? 2 * hcap * P->S[1] * (int64_t)P->elem + hcap * (int64_t)sizeof(int4) : 0) +
            P->W * 8 + P->n_polys * 32 + (int64_t)sizeof(InstState);
 }
 
@@ -306,6 +405,8 @@ static void free_list(pcba_problem* P)
     }
     if (P->d_upre) pool_free(P->d_upre);
     P->d_upre = nullptr;
+    if (P->d_umap) pool_free(P->d_umap);
+    P->d_umap = nullptr;
     if (P->d_live) pool_free(P->d_live);
     if (P->d_minP) pool_free(P->d_minP);
     if (P->d_maxP) pool_free(P->d_maxP);
@@ -340,12 +441,14 @@ static int alloc_list(pcba_problem* P, int64_t ncap, int64_t nhcap, hipStream_t 
     int32_t* nna[2] = {nullptr, nullptr};
     void* nhp[2] = {nullptr, nullptr};
     int64_t* nup = nullptr;
+    int4* num = nullptr;
     const bool need_tm = P->fp32 && P->opt.rederive_every > 0;
     const int64_t n_up = ncap + 1;   // kept children (up to ncap) plus the end
     auto cleanup = [&]() {
         if (nst) pool_free(nst);
         if (ntm) pool_free(ntm);
         if (nup) pool_free(nup);
+        if (num) pool_free(num);
         for (int b = 0; b < 2; ++b) {
             if (nb[b]) pool_free(nb[b]);
             if (ni[b]) pool_free(ni[b]);
@@ -372,7 +475,9 @@ static int alloc_list(pcba_problem* P, int64_t ncap, int64_t nhcap, hipStream_t 
                  pool_alloc((void**)&nna[b], (size_t)ncap * sizeof(int32_t)) == hipSuccess &&
                  pool_alloc(&nhp[b], (size_t)nhcap * P->S[1] * P->elem) == hipSuccess;
     }
-    if (ok && P->retire) ok = pool_alloc((void**)&nup, (size_t)n_up * sizeof(int64_t)) == hipSuccess;
+    if (ok && P->retire)
+        ok = pool_alloc((void**)&nup, (size_t)n_up * sizeof(int64_t)) == hipSuccess &&
+             pool_alloc((void**)&num, (size_t)nhcap * sizeof(int4)) == hipSuccess;
     ok = ok && pool_alloc((void**)&nlive, (size_t)ncap * sizeof(int32_t)) == hipSuccess &&
          pool_alloc((void**)&nmin, (size_t)ncap * sizeof(double)) == hipSuccess &&
          pool_alloc((void**)&nmax, (size_t)ncap * sizeof(double)) == hipSuccess &&
@@ -420,6 +525,9 @@ static int alloc_list(pcba_problem* P, int64_t ncap, int64_t nhcap, hipStream_t 
             if (e == hipSuccess)
                 e = hipMemcpyAsync(nup, P->d_upre, (size_t)std::min<int64_t>(n_up, P->cap + 1) * sizeof(int64_t),
                                    hipMemcpyDeviceToDevice, s);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(num, P->d_umap, (size_t)std::min(P->hcap, nhcap) * sizeof(int4),
+                                   hipMemcpyDeviceToDevice, s);
         }
         if (e == hipSuccess) e = hipStreamSynchronize(s);
     }
@@ -439,6 +547,7 @@ static int alloc_list(pcba_problem* P, int64_t ncap, int64_t nhcap, hipStream_t 
     }
     P->hcap = P->retire ? nhcap : 0;
     P->d_upre = nup;
+    P->d_umap = num;
     P->d_live = nlive;
     P->d_minP = nmin;
     P->d_maxP = nmax;
@@ -475,15 +584,17 @@ struct Scratch {
 };
 thread_local Scratch t_scratch;
 
+// LDS words of the certification transforms of a problem: every kind and
+// axis, in blocks of its longest fibre squared
 static size_t tm_words(const pcba_problem* P)
 {
-    return (size_t)(P->l + 2) * P->maxm * P->maxm;
+    return (size_t)KINDS * P->l * P->maxm * P->maxm;
 }
 
-// Uploads the descriptors of probs and the prefix sum of their polynomial
-// counts into `sc`; returns the total polynomial count in *total.
+// Uploads the descriptors of probs and the prefix sum of their workgroup
+// counts (one per `per` polynomials) into `sc`; returns the total in *total.
 static int upload_descs(pcba_problem* const* probs, int n, Scratch& sc, hipStream_t s,
-                        DevInst** d_insts, int** d_pre, int* total, int* max_S, int* tmw)
+                        DevInst** d_insts, int** d_pre, int* total, int* max_S, int* tmw, int per = 1)
 {
     std::vector<DevInst> h(n);
     std::vector<int> pre(n + 1, 0);
@@ -491,7 +602,7 @@ static int upload_descs(pcba_problem* const* probs, int n, Scratch& sc, hipStrea
     *tmw = 1;
     for (int b = 0; b < n; ++b) {
         h[b] = make_dev(probs[b]);
-        pre[b + 1] = pre[b] + probs[b]->n_polys;
+        pre[b + 1] = pre[b] + (probs[b]->n_polys + per - 1) / per;
         *max_S = std::max(*max_S, probs[b]->max_S);
         *tmw = std::max(*tmw, (int)tm_words(probs[b]));
     }
@@ -536,12 +647,19 @@ static int reset_batch(pcba_problem* const* probs, int n, hipStream_t s)
         if (rc != PCBA_OK) return rc;
         P->list_released = false;
     }
+    int max_S = 1, tmw = 1;
+    for (int b = 0; b < n; ++b) {
+        max_S = std::max(max_S, probs[b]->max_S);
+        tmw = std::max(tmw, (int)tm_words(probs[b]));
+    }
+    const int ppb = root_run_length(max_S, tmw);
+    if (ppb < 1) return fail(PCBA_E_DEVICE, "root patches exceed the workgroup's LDS");
     DevInst* d_insts = nullptr;
     int* d_pre = nullptr;
-    int total = 0, max_S = 1, tmw = 1;
-    int rc = upload_descs(probs, n, t_scratch, s, &d_insts, &d_pre, &total, &max_S, &tmw);
+    int total = 0;
+    int rc = upload_descs(probs, n, t_scratch, s, &d_insts, &d_pre, &total, &max_S, &tmw, ppb);
     if (rc != PCBA_OK) return rc;
-    HIP_TRY(launch_reset_root(d_insts, n, d_pre, total, max_S, s));
+    HIP_TRY(launch_reset_root(d_insts, n, d_pre, total, max_S, tmw, ppb, s));
     HIP_TRY(hipStreamSynchronize(s));   // the host descriptors above are pageable
     for (int b = 0; b < n; ++b) {
         pcba_problem* P = probs[b];
@@ -771,9 +889,9 @@ int pcba_create_problem(int32_t l, const double* lo, const double* hi, const int
     }
 
     hipStream_t s = nullptr;
-    bool ok = hipStreamCreateWithFlags(&s, hipStreamNonBlocking) == hipSuccess &&
+    bool ok = library_stream(&s) == hipSuccess &&
               hipMalloc((void**)&P->d_root, P->W * sizeof(double)) == hipSuccess &&
-              hipMalloc((void**)&P->d_root_err, P->n_polys * sizeof(double)) == hipSuccess &&
+              hipMalloc((void**)&P->d_root_err, 2 * P->n_polys * sizeof(double)) == hipSuccess &&
               hipMalloc((void**)&P->d_racc, P->W * sizeof(double)) == hipSuccess &&
               hipMalloc((void**)&P->d_macc, std::max<size_t>(1, macc.size()) * sizeof(double)) == hipSuccess &&
               hipMalloc((void**)&P->d_cert, 3 * P->n_polys * sizeof(double)) == hipSuccess &&
@@ -784,7 +902,6 @@ int pcba_create_problem(int32_t l, const double* lo, const double* hi, const int
               hipMalloc((void**)&P->d_matoff, matoff.size() * sizeof(int)) == hipSuccess;
     if (!ok) {
         (void)hipGetLastError();
-        if (s) (void)hipStreamDestroy(s);
         pcba_destroy_problem(P);
         return fail(PCBA_E_NOMEM, "device allocation failed");
     }
@@ -792,7 +909,6 @@ int pcba_create_problem(int32_t l, const double* lo, const double* hi, const int
     int rc = alloc_list(P, std::max<int64_t>(2, cap0), hcap0(P), s);
     if (rc != PCBA_OK) {
         std::string m = g_last_error;
-        (void)hipStreamDestroy(s);
         pcba_destroy_problem(P);
         return fail(rc, m);
     }
@@ -806,7 +922,6 @@ int pcba_create_problem(int32_t l, const double* lo, const double* hi, const int
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e == hipSuccess) rc = accurate_root(P, s);
     if (e == hipSuccess && rc == PCBA_OK) rc = reset_batch(&P, 1, s);
-    (void)hipStreamDestroy(s);
     if (e != hipSuccess || rc != PCBA_OK) {
         std::string m = e != hipSuccess ? std::string(hipGetErrorString(e)) : g_last_error;
         pcba_destroy_problem(P);
@@ -908,18 +1023,12 @@ int64_t pcba_footprint_bytes(const pcba_problem* P, int64_t boxes)
 int pcba_engine_create(int64_t budget_bytes, int64_t reserve_boxes, void* stream, pcba_engine** out)
 {
     if (!out || reserve_boxes < 0) return fail(PCBA_E_ARG, "bad engine arguments");
+    hipStream_t s = (hipStream_t)stream;
+    if (!s && library_stream(&s) != hipSuccess) return fail(PCBA_E_DEVICE, "stream creation failed");
     pcba_engine* E = new pcba_engine();
     E->budget = budget_bytes > 0 ? budget_bytes : INT64_MAX;
     E->reserve = reserve_boxes;
-    if (stream) {
-        E->stream = (hipStream_t)stream;
-    } else {
-        if (hipStreamCreateWithFlags(&E->stream, hipStreamNonBlocking) != hipSuccess) {
-            delete E;
-            return fail(PCBA_E_DEVICE, "stream creation failed");
-        }
-        E->own_stream = true;
-    }
+    E->stream = s;
     *out = E;
     return PCBA_OK;
 }
@@ -928,13 +1037,7 @@ void pcba_engine_destroy(pcba_engine* E)
 {
     if (!E) return;
     if (E->stream) (void)hipStreamSynchronize(E->stream);
-    if (E->d_insts) (void)hipFree(E->d_insts);
-    if (E->d_plan) (void)hipFree(E->d_plan);
-    if (E->d_info) (void)hipFree(E->d_info);
-    if (E->d_states) (void)hipFree(E->d_states);
-    if (E->h_states) (void)hipHostFree(E->h_states);
-    if (E->h_insts) (void)hipHostFree(E->h_insts);
-    if (E->own_stream) (void)hipStreamDestroy(E->stream);
+    bufs_put(E->b);
     delete E;
 }
 
@@ -960,32 +1063,14 @@ int pcba_engine_submit(pcba_engine* E, pcba_problem* P, int32_t* admitted)
 static int engine_upload(pcba_engine* E)
 {
     const int n = (int)E->active.size();
-    if (n > E->d_insts_cap) {
-        if (E->d_insts) (void)hipFree(E->d_insts);
-        if (E->d_plan) (void)hipFree(E->d_plan);
-        if (E->d_info) (void)hipFree(E->d_info);
-        if (E->d_states) (void)hipFree(E->d_states);
-        if (E->h_states) (void)hipHostFree(E->h_states);
-        if (E->h_insts) (void)hipHostFree(E->h_insts);
-        E->h_insts = nullptr;
-        E->d_info = nullptr;
-        E->d_insts = nullptr;
-        E->d_plan = nullptr;
-        E->d_states = nullptr;
-        E->h_states = nullptr;
-        const int c = std::max(n, 2 * E->d_insts_cap);
-        HIP_TRY(hipMalloc((void**)&E->d_insts, c * sizeof(DevInst)));
-        HIP_TRY(hipMalloc((void**)&E->d_plan, 4 * (size_t)(c + 1) * sizeof(long long)));
-        HIP_TRY(hipMalloc((void**)&E->d_info, (size_t)c * sizeof(StepInfo)));
-        HIP_TRY(hipMalloc((void**)&E->d_states, c * sizeof(InstState)));
-        HIP_TRY(hipHostMalloc((void**)&E->h_states, c * sizeof(InstState), hipHostMallocDefault));
-        HIP_TRY(hipHostMalloc((void**)&E->h_insts, c * sizeof(DevInst), hipHostMallocDefault));
-        E->d_insts_cap = c;
+    if (n > E->b.cap) {
+        bufs_put(E->b);
+        HIP_TRY(bufs_get(std::max(n, 2 * E->b.cap), &E->b));
     }
     // every earlier use of the staging buffer has completed: the engine
     // synchronises its stream at the end of each batch of steps
-    for (int b = 0; b < n; ++b) E->h_insts[b] = make_dev(E->active[b]);
-    if (n) HIP_TRY(hipMemcpyAsync(E->d_insts, E->h_insts, n * sizeof(DevInst), hipMemcpyHostToDevice, E->stream));
+    for (int b = 0; b < n; ++b) E->b.h_insts[b] = make_dev(E->active[b]);
+    if (n) HIP_TRY(hipMemcpyAsync(E->b.d_insts, E->b.h_insts, n * sizeof(DevInst), hipMemcpyHostToDevice, E->stream));
     E->dirty = false;
     return PCBA_OK;
 }
@@ -1010,10 +1095,10 @@ static size_t rederive_lds(const pcba_problem* P)
     int TE = P->S[0];
     for (int t = 1; t < KINDS; ++t)
         if (P->count[t]) {
-            const int cp = std::max(1, MAX_TILE64 / P->S[t]);
+            const int cp = std::min(REDERIVE_CHUNK, std::max(1, MAX_TILE64 / P->S[t]));
             TE = std::max(TE, std::min(P->tile_polys[t], cp) * P->S[t]);
         }
-    return (2 * (size_t)TE + (size_t)P->l * P->maxm * P->maxm) * 8 + 16;
+    return ((size_t)TE + (size_t)P->l * P->maxm * P->maxm) * 8 + 16;
 }
 
 // FP64 certification of every finished problem in one launch, then their states.
@@ -1021,19 +1106,26 @@ static int certify_batch(pcba_engine* E, std::vector<pcba_problem*>& fin)
 {
     const int n = (int)fin.size();
     if (n == 0) return PCBA_OK;
+    int max_S = 1, tmw = 1;
+    for (auto* P : fin) {
+        max_S = std::max(max_S, P->max_S);
+        tmw = std::max(tmw, (int)tm_words(P));
+    }
+    const int ppb = certify_run_length(max_S, tmw);
+    if (ppb < 1) return fail(PCBA_E_DEVICE, "certification patches exceed the workgroup's LDS");
     DevInst* d_insts = nullptr;
     int* d_pre = nullptr;
-    int total = 0, max_S = 1, tmw = 1;
-    int rc = upload_descs(fin.data(), n, t_scratch, E->stream, &d_insts, &d_pre, &total, &max_S, &tmw);
+    int total = 0;
+    int rc = upload_descs(fin.data(), n, t_scratch, E->stream, &d_insts, &d_pre, &total, &max_S, &tmw, ppb);
     if (rc != PCBA_OK) return rc;
-    HIP_TRY(launch_certify(d_insts, n, d_pre, total, max_S, tmw, E->stream));
-    HIP_TRY(launch_gather(d_insts, n, E->d_states, E->stream));
-    HIP_TRY(hipMemcpyAsync(E->h_states, E->d_states, n * sizeof(InstState), hipMemcpyDeviceToHost,
+    HIP_TRY(launch_certify(d_insts, n, d_pre, total, max_S, tmw, ppb, E->stream));
+    HIP_TRY(launch_gather(d_insts, n, E->b.d_states, E->stream));
+    HIP_TRY(hipMemcpyAsync(E->b.h_states, E->b.d_states, n * sizeof(InstState), hipMemcpyDeviceToHost,
                            E->stream));
     HIP_TRY(hipStreamSynchronize(E->stream));
     const double t = now_s();
     for (int b = 0; b < n; ++b) {
-        fin[b]->h_st = E->h_states[b];
+        fin[b]->h_st = E->b.h_states[b];
         fin[b]->certified_done = true;
         fin[b]->seconds = t - fin[b]->t_start;
     }
@@ -1099,33 +1191,42 @@ static int engine_steps(pcba_engine* E, int n_steps)
                 if (due) { ubrd += u; ubrows += k * 2 * P->rows; } else ub32 += u;
             }
         }
-        HIP_TRY(prof_begin(E->stream));
-        HIP_TRY(launch_plan(E->d_insts, n, E->d_plan, E->d_info, E->stream));
-        HIP_TRY(prof_end(4, E->stream));
-        if (any64 && ub64 > 0) {
+        // the plan of the step: formed inside the first subdivision launch for
+        // small batches, else by its own launch
+        const bool l64 = any64 && ub64 > 0, l32 = any32 && ub32 > 0;
+        bool planned = false;
+        if (n > PLAN_FUSE_MAX || !(l64 || l32)) {
+            HIP_TRY(prof_begin(E->stream));
+            HIP_TRY(launch_plan(E->b.d_insts, n, E->b.d_plan, E->b.d_info, E->stream));
+            HIP_TRY(prof_end(4, E->stream));
+            planned = true;
+        }
+        if (l64) {
             hipEvent_t e0, e1;
             HIP_TRY(prof_pair(0, &e0, &e1));
-            HIP_TRY(launch_sub(E->d_insts, n, E->d_plan, E->d_info, false, maxm64,
+            HIP_TRY(launch_sub(E->b.d_insts, n, E->b.d_plan, E->b.d_info, !planned, false, maxm64,
                                (int)std::min<int64_t>(GRID_MAX, ub64), lds64, E->stream, e0, e1));
+            planned = true;
         }
-        if (any32 && ub32 > 0) {
+        if (l32) {
             hipEvent_t e0, e1;
             HIP_TRY(prof_pair(1, &e0, &e1));
-            HIP_TRY(launch_sub(E->d_insts, n, E->d_plan, E->d_info, true, maxm32,
+            HIP_TRY(launch_sub(E->b.d_insts, n, E->b.d_plan, E->b.d_info, !planned, true, maxm32,
                                (int)std::min<int64_t>(GRID_MAX, ub32), lds32, E->stream, e0, e1));
+            planned = true;
         }
         if (anyrd && ubrd > 0) {
             HIP_TRY(prof_begin(E->stream));
-            HIP_TRY(launch_rederive(E->d_insts, n, E->d_plan, E->d_info, (int)std::min<int64_t>(GRID_MAX, ubrd),
+            HIP_TRY(launch_rederive(E->b.d_insts, n, E->b.d_plan, E->b.d_info, (int)std::min<int64_t>(GRID_MAX, ubrd),
                                     (int)std::min<int64_t>(4096, (ubrows + 255) / 256), ldsrd, E->stream));
             HIP_TRY(prof_end(2, E->stream));
         }
         HIP_TRY(prof_begin(E->stream));
-        HIP_TRY(launch_cut(E->d_insts, n, maxc, E->stream));
+        HIP_TRY(launch_cut(E->b.d_insts, n, maxc, E->stream));
         HIP_TRY(prof_end(3, E->stream));
     }
-    HIP_TRY(launch_gather(E->d_insts, n, E->d_states, E->stream));
-    HIP_TRY(hipMemcpyAsync(E->h_states, E->d_states, n * sizeof(InstState), hipMemcpyDeviceToHost,
+    HIP_TRY(launch_gather(E->b.d_insts, n, E->b.d_states, E->stream));
+    HIP_TRY(hipMemcpyAsync(E->b.h_states, E->b.d_states, n * sizeof(InstState), hipMemcpyDeviceToHost,
                            E->stream));
     HIP_TRY(hipStreamSynchronize(E->stream));
     prof_collect();
@@ -1136,10 +1237,10 @@ static int engine_steps(pcba_engine* E, int n_steps)
     // some problem will step again, or finish, without growing
     bool progress = false;
     for (int b = 0; b < n; ++b)
-        if (E->h_states[b].status != ST_GROW) progress = true;
+        if (E->b.h_states[b].status != ST_GROW) progress = true;
     for (int b = 0; b < n; ++b) {
         pcba_problem* P = E->active[b];
-        P->h_st = E->h_states[b];
+        P->h_st = E->b.h_states[b];
         P->host_steps = P->h_st.steps;
         if (P->h_st.status == ST_GROW) {
             // room for this step's children with a quarter to spare, and at least
@@ -1343,7 +1444,7 @@ static int read_list_impl(const pcba_problem* P, uint32_t* ids, double* patches,
     if (cap < K) return fail(PCBA_E_ARG, "capacity smaller than the list");
     if (K == 0) return PCBA_OK;
     hipStream_t s = nullptr;
-    HIP_TRY(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+    HIP_TRY(library_stream(&s));
     double* d_out = nullptr;
     uint32_t* d_ids = nullptr;
     double* d_err = nullptr;
@@ -1361,7 +1462,6 @@ static int read_list_impl(const pcba_problem* P, uint32_t* ids, double* patches,
     if (d_out) (void)hipFree(d_out);
     if (d_ids) (void)hipFree(d_ids);
     if (d_err) (void)hipFree(d_err);
-    (void)hipStreamDestroy(s);
     if (e != hipSuccess) return fail(PCBA_E_DEVICE, std::string("read list: ") + hipGetErrorString(e));
     return PCBA_OK;
 }
