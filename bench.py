@@ -119,6 +119,24 @@ def run_mode(pcba, insts, precision, steps, warmup, **opts):
     )
 
 
+def single_plan(pcba, inst, precision, reps, **opts):
+    """One plan solved alone, `reps` times (after one warm-up): per-solve wall
+    time from reset to certified result, and whether every solve certified."""
+    p = pcba.Problem(inst, precision=precision, **opts)
+    pcba.reset_batch([p])
+    pcba.solve_batch([p])
+    t, ok = [], True
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        pcba.reset_batch([p])
+        r = pcba.solve_batch([p])[0]
+        t.append(time.perf_counter() - t0)
+        ok = ok and certified(r, pcba)
+    p.close()
+    return {"p50_ms": round(float(np.percentile(t, 50)) * 1e3, 4),
+            "p99_ms": round(float(np.percentile(t, 99)) * 1e3, 4), "certified": ok, "reps": reps}
+
+
 def measured_traffic(sub_kernel):
     """HBM bytes per launch of the subdivide kernel from the committed counter
     summary (FETCH_SIZE and WRITE_SIZE runs scaled by a copy of known size),
@@ -133,7 +151,7 @@ def measured_traffic(sub_kernel):
     src = os.path.join(ROOT, "paper_2003_01758_amd", "csrc", "kernels.hip")
     if hashlib.sha256(open(src, "rb").read()).hexdigest() != rec.get("kernels_hip_sha256"):
         return None
-    name = {"sub_fp64": "k_sub<double, 16, 14>", "sub_fp32": "k_sub<float, 16, 28>"}[sub_kernel]
+    name = {"sub_fp64": "k_sub<double, 16, 14, true>", "sub_fp32": "k_sub<float, 16, 28, true>"}[sub_kernel]
     k = rec["kernels"].get(name)
     return float(k["bytes_per_dispatch"]) if k else None
 
@@ -224,6 +242,10 @@ def main():
         opts["rederive_every"] = args.rederive
     r32 = run_mode(pcba, insts, "fp32", args.steps, args.warmup, **opts)
 
+    single = {"fp64_plain": single_plan(pcba, insts[0], "fp64", 20, **{k: v for k, v in opts.items()
+                                                                    if k != "rederive_every"}),
+              "fp32": single_plan(pcba, insts[0], "fp32", 20, **opts)}
+
     # parity of the two GPU paths on the last step (both provably within eps of f*)
     dp = max(abs(a["p_up"] - b["p_up"]) for a, b in zip(r32["results"], r64["results"])
              if a["outcome"] == b["outcome"] == pcba.OPTIMAL)
@@ -262,6 +284,7 @@ def main():
         "fp64_plain": {k: (round(v, 4) if isinstance(v, float) else v) for k, v in r64.items()
                        if k in ("solves_per_s", "ms_per_step", "p50_ms", "p99_ms", "certified", "total")},
         "max_abs_p_fp32_vs_fp64": dp,
+        "single_plan": single,
         "instrumented_ms_per_step": round(best["instrumented_ms_per_step"], 4),
         "kernel_ms": {k: round(v[0], 3) for k, v in best["profile"].items()},
         "kernel_launches": {k: v[1] for k, v in best["profile"].items()},

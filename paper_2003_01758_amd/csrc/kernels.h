@@ -16,10 +16,13 @@ hipError_t launch_racc(const DevInst* d_insts, int n, const int* d_pre, int tota
 hipError_t launch_plan(const DevInst* d_insts, int n, long long* plan, StepInfo* info, hipStream_t s);
 // ev0/ev1 (or null): events stamped at the subdivision kernel's start and end.
 // fuse (n <= PLAN_FUSE_MAX): the kernel forms the step's plan itself, in place
-// of a k_plan launch before it, and writes it to plan / info.
+// of a k_plan launch before it, and writes it to plan / info.  tem / tpm: the
+// largest tile (coefficients, patches) of the problems launched.
 hipError_t launch_sub(const DevInst* d_insts, int n, long long* plan, StepInfo* info, bool fuse,
-                      bool fp32, int maxm, int grid, size_t lds, hipStream_t s, hipEvent_t ev0,
+                      bool fp32, int maxm, int grid, int tem, int tpm, hipStream_t s, hipEvent_t ev0,
                       hipEvent_t ev1);
+// dynamic LDS bytes of k_sub for those tiles
+size_t sub_lds_bytes(int tem, int tpm, bool fp32);
 hipError_t launch_rederive(const DevInst* d_insts, int n, const long long* plan, const StepInfo* info,
                            int grid, int tgrid, size_t lds, hipStream_t s);
 // max_children: an upper bound on 2K over the problems at this step

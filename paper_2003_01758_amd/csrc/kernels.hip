@@ -69,6 +69,28 @@ __device__ int block_min_i(int v, int* sh)
     return r;
 }
 
+// Min over the workgroup with one barrier: each wave's min to sh[w], then
+// every thread reduces the waves' values.  A call site needs its own sh (or a
+// barrier before sh is written again).
+__device__ __forceinline__ double block_min1(double v, double* sh)
+{
+    v = wave_min(v);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double r = sh[0];
+    for (int q = 1; q < (int)(blockDim.x >> 6); ++q) r = fmin(r, sh[q]);
+    return r;
+}
+__device__ __forceinline__ int block_min1_i(int v, int* sh)
+{
+    v = wave_min_i(v);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    int r = sh[0];
+    for (int q = 1; q < (int)(blockDim.x >> 6); ++q) r = min(r, sh[q]);
+    return r;
+}
+
 // Units of work of one step, per class of problem:
 //   class 0: FP64 problems (k_sub<double>)
 //   class 1: FP32 problems splitting their FP32 parents (k_sub<float>)
@@ -82,9 +104,21 @@ __device__ __forceinline__ int unit_class(const DevInst& I, const InstState* st)
     return due ? 2 : 1;
 }
 
-// Units of one step of a problem: every parent has one cost tile and its
-// equality tiles; its inequality tiles are all of them, or in retiring mode as
-// many as the inequalities it still carries need (their sum is st->u1).
+// Tiles of k_sub in one step of a problem: the cost patches, the equality
+// patches, then the inequality patches of all parents (all of them, or in
+// retiring mode the carried ones), each cut into tiles of ptp[kind] patches.
+__device__ __forceinline__ long long step_tiles(const DevInst& I, const InstState* st)
+{
+    const long long K = st->K;
+    const long long A = I.retire ? st->a_live : K * I.count[1];
+    return (K + I.ptp[0] - 1) / I.ptp[0] + (K * I.count[2] + I.ptp[2] - 1) / I.ptp[2] +
+           (A + I.ptp[1] - 1) / I.ptp[1];
+}
+
+// Units of one FP32 re-derivation step of a problem: every parent has one cost
+// tile and its equality tiles; its inequality tiles are all of them, or in
+// retiring mode as many as the inequalities it still carries need (their sum
+// is st->u1).
 __device__ __forceinline__ long long step_units(const DevInst& I, const InstState* st)
 {
     const int T1 = I.tile_start[2] - I.tile_start[1];
@@ -111,7 +145,7 @@ __device__ __forceinline__ void plan_one(const DevInst& I, bool commit, long lon
             if (commit) st->status = ST_GROW;
         } else {
             const int c = unit_class(I, st);
-            v[c] = step_units(I, st);
+            v[c] = c == 2 ? step_units(I, st) : step_tiles(I, st);
             if (c == 2) v[3] = (long long)K * 2 * I.rows;
         }
     }
@@ -121,7 +155,7 @@ __device__ __forceinline__ void plan_one(const DevInst& I, bool commit, long lon
     si.steps = st->steps;
     si.p_up = st->p_up;
     si.stamp = step_stamp(st);
-    si.pad = 0;
+    si.A = (int)st->a_live;
 }
 
 __global__ __launch_bounds__(1024) void k_plan(const DevInst* __restrict__ insts, int n,
@@ -435,7 +469,10 @@ __global__ __launch_bounds__(256) void k_root(const DevInst* __restrict__ insts,
         for (int e = lane; e < S; e += 64) I.root[off + e] = x[e];
         if (!I.fp32) {
             for (int e = lane; e < S; e += 64) ((double*)dbase)[doff + e] = x[e];
-            if (lane == 0 && inheap) I.act[0][idx] = make_int2(idx, idx);
+            if (lane == 0 && inheap) {
+                I.act[0][idx] = make_int2(idx, idx);
+                I.pmap[idx] = make_int4(0, 0, idx, idx);
+            }
             continue;
         }
         // FP32: offsets from the midrange of the accurate root patch
@@ -458,7 +495,10 @@ __global__ __launch_bounds__(256) void k_root(const DevInst* __restrict__ insts,
         }
         for (int o = 32; o > 0; o >>= 1) hr = fmax(hr, __shfl_xor(hr, o, 64));
         if (lane == 0) {
-            if (inheap) I.act[0][idx] = make_int2(idx, idx);
+            if (inheap) {
+                I.act[0][idx] = make_int2(idx, idx);
+                I.pmap[idx] = make_int4(0, 0, idx, idx);
+            }
             // the accurate root's bound, the rounding of the offsets (the FP64
             // difference and the conversion, 2^-23 of the largest), underflow
             I.err[0][poly] = round_up_f(I.root_err[poly] + hr * 0x1p-23 + 0x1p-126);
@@ -583,18 +623,16 @@ __global__ void k_reset(const DevInst* __restrict__ insts, int n)
 }
 
 // ------------------------------------------------------------------ k_sub
-
-template <typename T>
-struct SubLds {
-    // layout inside dynamic LDS
-    T* a;        // parent tile, overwritten by the left child
-    T* b;        // right child
-    typename KeyOf<T>::type* key;  // per patch: minL, maxL, minR, maxR, maxabs(parent)
-    int* id;     // retiring mode, inequality tile: per patch its inequality index, then
-    int* need;   // which children still carry it (bit 0 left, bit 1 right), then
-    int* dst;    // its heap patch in the left child (np entries) and the right (np)
-    T* shift;    // FP32: per patch, each child's re-centring shift (left np, right np)
-};
+//
+// Work units of k_sub are tiles of consecutive patches of one kind of one
+// problem, taken from the patches of all its parents in parent order: the cost
+// patches (one per parent), then the equality patches (beta per parent), then
+// the inequality patches (alpha per parent, or in retiring mode each parent's
+// carried ones).  A tile therefore spans several parents when their patches
+// are few, which with retiring is the common case: units are full tiles
+// instead of one short tile per parent.  Per patch the workgroup stages in LDS
+// its parent j, the parent's slot, its index in its kind and where its
+// coefficients are.
 
 // One fibre of fixed length M: de Casteljau with parameter 1/2 in registers.
 // After level lev, c[0] is the left child's coefficient lev and c[M-1-lev] the
@@ -633,8 +671,6 @@ __device__ __forceinline__ void lds_barrier()
     asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
 }
 
-// Stages a tile of np patches (TE = np*S coefficients at `src`) into LDS and
-// resets the per-patch keys.  Callers follow with lds_barrier().
 // global -> LDS copy with LB independent loads in flight per thread
 template <typename T, int LB = 12>
 __device__ __forceinline__ void copy_to_lds(T* __restrict__ dst, const T* __restrict__ src, int n)
@@ -654,25 +690,13 @@ __device__ __forceinline__ void copy_to_lds(T* __restrict__ dst, const T* __rest
     }
 }
 
-template <typename T>
-__device__ __forceinline__ void tile_load(const T* __restrict__ src, int np, int TE, SubLds<T> L)
-{
-    typedef typename KeyOf<T>::type K;
-    copy_to_lds<T>(L.a, src, TE);
-    for (int p = threadIdx.x; p < np; p += blockDim.x) {
-        L.key[5 * p + 0] = ~(K)0;  // min left
-        L.key[5 * p + 1] = 0;      // max left
-        L.key[5 * p + 2] = ~(K)0;  // min right
-        L.key[5 * p + 3] = 0;      // max right
-        L.key[5 * p + 4] = 0;      // max |parent|
-    }
-}
-
-// Splits the staged tile along the fibres of geometry g: left child in place
-// in L.a, right child in L.b, per-patch min/max of both children and max
-// |parent| folded into the keys.  Callers follow with lds_barrier().
+// Splits the staged tile (np patches of S coefficients at a) along the fibres
+// of geometry g: left child in place in a, right child in b, per-patch min/max
+// of both children and max |parent| folded into key.  Callers follow with
+// lds_barrier().
 template <typename T, int MM>
-__device__ __forceinline__ void tile_split(int np, int S, const FibreGeom& g, SubLds<T> L)
+__device__ __forceinline__ void tile_split(int np, int S, const FibreGeom& g, T* a, T* b,
+                                           typename KeyOf<T>::type* key)
 {
     const int TF = np * g.F;
     for (int f = threadIdx.x; f < TF; f += blockDim.x) {
@@ -681,7 +705,7 @@ __device__ __forceinline__ void tile_split(int np, int S, const FibreGeom& g, Su
         T mnL, mxL, mnR, mxR, amax = (T)0;
         switch (g.m) {
 #define PCBA_SPLIT_CASE(MV) \
-        case MV: if (MV <= MM) split_fibre<T, MV>(L.a, L.b, base, g.stride, mnL, mxL, mnR, mxR, amax); break;
+        case MV: if (MV <= MM) split_fibre<T, MV>(a, b, base, g.stride, mnL, mxL, mnR, mxR, amax); break;
             PCBA_SPLIT_CASE(1) PCBA_SPLIT_CASE(2) PCBA_SPLIT_CASE(3) PCBA_SPLIT_CASE(4)
             PCBA_SPLIT_CASE(5) PCBA_SPLIT_CASE(6) PCBA_SPLIT_CASE(7) PCBA_SPLIT_CASE(8)
             PCBA_SPLIT_CASE(9) PCBA_SPLIT_CASE(10) PCBA_SPLIT_CASE(11) PCBA_SPLIT_CASE(12)
@@ -689,11 +713,11 @@ __device__ __forceinline__ void tile_split(int np, int S, const FibreGeom& g, Su
 #undef PCBA_SPLIT_CASE
         default: mnL = mxL = mnR = mxR = (T)0; break;
         }
-        atomicMin(&L.key[5 * p + 0], fkey(mnL));
-        atomicMax(&L.key[5 * p + 1], fkey(mxL));
-        atomicMin(&L.key[5 * p + 2], fkey(mnR));
-        atomicMax(&L.key[5 * p + 3], fkey(mxR));
-        atomicMax(&L.key[5 * p + 4], fkey(amax));
+        atomicMin(&key[5 * p + 0], fkey(mnL));
+        atomicMax(&key[5 * p + 1], fkey(mxL));
+        atomicMin(&key[5 * p + 2], fkey(mnR));
+        atomicMax(&key[5 * p + 3], fkey(mxR));
+        atomicMax(&key[5 * p + 4], fkey(amax));
     }
 }
 
@@ -770,25 +794,23 @@ __device__ __forceinline__ void child_bounds(T mn, T mx, double e, double base, 
     }
 }
 
-// Where one unit of k_sub / k_rederive lives (all fields wave-uniform).  With
-// gath set (retiring mode, inequality tile) the tile's patches are not
-// contiguous: patch q of the tile is inequality act[q] at toff + act[q] * S.
-struct SubCtx {
-    int bi, j, t, kind, p0, np, S, TE, pslot, cur, r, gath;
-    int64_t toff;
-    const int2* act;
+// One tile of k_sub (all fields uniform over the workgroup).
+struct PackUnit {
+    int bi, kind, np, S, TE, cur, r, gath;
+    long long P0;     // first patch of the tile in the problem's sequence of this kind
     float invS;
     double pprev;
     uint32_t stamp;
-    FibreGeom g;   // the split direction's fibres in this tile's patches
+    FibreGeom g;
 };
 
 // Resolves unit u: the problem (hint only moves forward, since a block's
-// units increase), the parent and tile, and the child flags seen so far.
-__device__ __forceinline__ void resolve_unit(const DevInst* __restrict__ insts, int n,
-                                             const long long* __restrict__ pre,
-                                             const StepInfo* __restrict__ info, long long u,
-                                             int& hint, SubCtx& c)
+// units increase), the kind and the tile's first patch.  Per problem the
+// units are ceil(K / ptp0) cost tiles, ceil(K beta / ptp2) equality tiles,
+// then ceil(A / ptp1) inequality tiles, A the patches the parents carry.
+__device__ __forceinline__ void resolve_packed(const DevInst* __restrict__ insts, int n,
+                                               const long long* pre, const StepInfo* info, long long u,
+                                               int& hint, PackUnit& c)
 {
     if (pre[hint + 1] <= u) {
         int lo = hint + 1, hi = n;  // pre[lo] <= u < pre[hi]
@@ -802,86 +824,108 @@ __device__ __forceinline__ void resolve_unit(const DevInst* __restrict__ insts, 
     const DevInst& I = insts[hint];
     const StepInfo si = info[hint];
     c.bi = hint;
-    int mslot, mna;
-    unit_of(I, u - pre[hint], si.K, c.j, c.t, mslot, mna);
-    c.j = __builtin_amdgcn_readfirstlane(c.j);
-    c.t = __builtin_amdgcn_readfirstlane(c.t);
+    long long v = u - pre[hint];
+    const long long K = si.K;
+    long long total;
+    const long long U0 = (K + I.ptp[0] - 1) / I.ptp[0];
+    if (v < U0) {
+        c.kind = 0;
+        total = K;
+    } else {
+        v -= U0;
+        const long long n2 = K * I.count[2];
+        const long long U2 = (n2 + I.ptp[2] - 1) / I.ptp[2];
+        if (v < U2) {
+            c.kind = 2;
+            total = n2;
+        } else {
+            v -= U2;
+            c.kind = 1;
+            total = I.retire ? (long long)si.A : K * I.count[1];
+        }
+    }
+    c.P0 = uniform64(v * I.ptp[c.kind]);
+    c.np = __builtin_amdgcn_readfirstlane((int)min((long long)I.ptp[c.kind], total - c.P0));
     c.cur = si.cur;
     c.r = si.r;
     c.pprev = si.p_up;
     c.stamp = si.stamp;
-    c.pslot = mslot >= 0 ? mslot : __builtin_amdgcn_readfirstlane(I.live[c.j]);
-    c.kind = (c.t < I.tile_start[1]) ? 0 : ((c.t < I.tile_start[2]) ? 1 : 2);
-    c.p0 = (c.t - I.tile_start[c.kind]) * I.tile_polys[c.kind];
     c.S = I.S[c.kind];
     c.invS = 1.0f / (float)c.S;
-    c.gath = I.retire && c.kind == 1;
-    if (c.gath) {
-        const int na = mna >= 0 ? mna : __builtin_amdgcn_readfirstlane(I.na[c.cur][c.pslot]);
-        c.np = min(I.tile_polys[1], na - c.p0);
-        c.act = I.act[c.cur] + (int64_t)c.pslot * I.count[1] + c.p0;
-        c.toff = 0;
-    } else {
-        c.np = min(I.tile_polys[c.kind], I.count[c.kind] - c.p0);
-        c.act = nullptr;
-        c.toff = I.soff[c.kind] + (int64_t)c.p0 * c.S;
-    }
     c.TE = c.np * c.S;
+    c.gath = I.retire && c.kind == 1;
     c.g = fibre_geom(I.dims[c.kind], I.l, c.r, c.S);
 }
 
-// Thread 0 only: flags already OR-ed into the unit's children by other tiles.
-// The value is a hint (other tiles may set more flags later); it reaches the
-// other threads through LDS, so every wave of the block takes the same branch.
-__device__ __forceinline__ void load_hint(const DevInst& I, const SubCtx& c, uint32_t& fl, uint32_t& fr)
+// Patch p of a tile: its parent j, the parent's slot, its index in its kind,
+// and the element offset of its coefficients in the source (the slot buffer,
+// or in retiring mode for inequalities the heap).  Lanes p < np only.
+__device__ __forceinline__ void patch_info(const DevInst& I, const PackUnit& c, int p, int4& inf,
+                                           long long& src)
 {
-    fl = fr = 0;
-    if (threadIdx.x == 0 && c.kind != 0) {
-        fl = __hip_atomic_load(&I.flags[2 * c.j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        fr = __hip_atomic_load(&I.flags[2 * c.j + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-}
-
-// Issues the global loads of a unit's parent tile into registers.
-template <typename T, int LB>
-__device__ __forceinline__ void issue_tile(const DevInst& I, const SubCtx& c, T (&v)[LB])
-{
+    const long long P = c.P0 + p;
     if (c.gath) {
-        const T* hsrc = (const T*)I.heap[c.cur];
-#pragma unroll
-        for (int q = 0; q < LB; ++q) {
-            const int e = threadIdx.x + q * SUB_THREADS;
-            if (e < c.TE) {
-                const int p = patch_of(e, c.invS);
-                v[q] = hsrc[(int64_t)c.act[p].y * c.S + (e - p * c.S)];
-            }
-        }
+        const int4 m = I.pmap[P];
+        inf = make_int4(m.x, m.y, m.z, 0);
+        src = (long long)m.w * c.S;
         return;
     }
-    const T* src = (const T*)I.buf[c.cur] + (int64_t)c.pslot * I.stride + c.toff;
+    const int cnt = c.kind == 0 ? 1 : I.count[c.kind];
+    const int j = (int)(P / cnt), id = (int)(P - (long long)j * cnt);
+    const int slot = I.live[j];
+    inf = make_int4(j, slot, id, 0);
+    src = (long long)slot * I.stride + I.soff[c.kind] + (long long)id * c.S;
+}
+
+// Issues the global loads of a tile into registers; the patches' source
+// offsets come from LDS.
+template <typename T, int LB>
+__device__ __forceinline__ void issue_packed(const DevInst& I, const PackUnit& c, const long long* src,
+                                             T (&v)[LB])
+{
+    const T* base = (const T*)(c.gath ? I.heap[c.cur] : I.buf[c.cur]);
 #pragma unroll
     for (int q = 0; q < LB; ++q) {
         const int e = threadIdx.x + q * SUB_THREADS;
-        if (e < c.TE) v[q] = src[e];
+        if (e < c.TE) {
+            const int p = patch_of(e, c.invS);
+            v[q] = base[src[p] + (e - p * c.S)];
+        }
     }
 }
 
-// FP32 mode: thread p < np of the workgroup loads the carried error bound and
-// FP64 base of the parent's patch p of the unit (issued with the tile, so that
-// the loads are in flight while the previous unit is processed).
-__device__ __forceinline__ void issue_eb(const DevInst& I, const SubCtx& c, float& e, double& b)
+// Exclusive scans over the workgroup of three counts per thread at once;
+// returns the totals.  sc: LDS of 3 * (waves) ints.  Every thread calls it.
+__device__ __forceinline__ int3 block_scan3(int3 x, int3& excl, int* sc)
 {
-    const int p = threadIdx.x;
-    if (p >= c.np) return;
-    const int poly = (c.kind == 0) ? 0
-                   : I.count[0] + (c.kind == 2 ? I.count[1] + c.p0 + p : (c.gath ? c.act[p].x : c.p0 + p));
-    const int64_t pi = (int64_t)c.pslot * I.n_polys + poly;
-    e = I.err[c.cur][pi];
-    b = I.base[c.cur][pi];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    int a = x.x, b = x.y, d = x.z;
+    for (int o = 1; o < 64; o <<= 1) {
+        const int ya = __shfl_up(a, o, 64), yb = __shfl_up(b, o, 64), yd = __shfl_up(d, o, 64);
+        if (lane >= o) { a += ya; b += yb; d += yd; }
+    }
+    if (lane == 63) { sc[3 * w] = a; sc[3 * w + 1] = b; sc[3 * w + 2] = d; }
+    lds_barrier();
+    int3 before = make_int3(0, 0, 0), tot = make_int3(0, 0, 0);
+    for (int q = 0; q < nw; ++q) {
+        if (q < w) { before.x += sc[3 * q]; before.y += sc[3 * q + 1]; before.z += sc[3 * q + 2]; }
+        tot.x += sc[3 * q];
+        tot.y += sc[3 * q + 1];
+        tot.z += sc[3 * q + 2];
+    }
+    lds_barrier();
+    excl = make_int3(before.x + a - x.x, before.y + b - x.y, before.z + d - x.z);
+    return tot;
 }
 
-// k_sub: one unit = (parent, tile) per workgroup, software-pipelined: the next
-// unit's tile is in flight in registers while the current one is split in LDS.
+// k_sub: one tile per workgroup at a time, software-pipelined: while a tile is
+// split in LDS, the next tile's patch table is loaded and then its
+// coefficients are in flight in registers.  Dynamic LDS, for tiles of at most
+// tem coefficients and tpm patches (tpm <= SUB_THREADS: patch p is thread p's):
+// the tile and the right child (tem each), the keys (5 tpm), two patch tables
+// (source offsets, then (j, slot, index)), the FP32 shifts (2 tpm), then per
+// patch or segment: write masks, scan values, heap patches, flags, positions,
+// segment starts.
 //
 // With FUSE (at most PLAN_FUSE_MAX problems) the step's plan is not read
 // from k_plan's output but formed by every workgroup in LDS from the problems'
@@ -890,14 +934,15 @@ __device__ __forceinline__ void issue_eb(const DevInst& I, const SubCtx& c, floa
 template <typename T, int MM, int LB, bool FUSE>
 __global__ __launch_bounds__(SUB_THREADS) void k_sub(const DevInst* __restrict__ insts, int n_inst,
                                                     long long* __restrict__ plan,
-                                                    StepInfo* __restrict__ info)
+                                                    StepInfo* __restrict__ info, int tem, int tpm)
 {
     typedef typename KeyOf<T>::type K;
     extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ uint32_t s_flag[2];
-    __shared__ int s_dead[2];
     __shared__ long long s_pre[PLAN_FUSE_MAX + 1];
     __shared__ StepInfo s_info[PLAN_FUSE_MAX];
+    __shared__ int s_sc[3 * (SUB_THREADS / 64)];
+    __shared__ int s_nseg;
+    __shared__ long long s_hb;
 
     const bool fp32 = sizeof(T) == 4;
     const int cls = fp32 ? 1 : 0;
@@ -939,260 +984,311 @@ __global__ __launch_bounds__(SUB_THREADS) void k_sub(const DevInst* __restrict__
     const long long total = pre[n_inst];
     long long u = blockIdx.x;
     if (u >= total) return;
+
+    // LDS carve-up (16-byte aligned pieces)
+    unsigned char* q8 = smem;
+    auto carve = [&](size_t bytes) {
+        unsigned char* r = q8;
+        q8 += (bytes + 15) & ~(size_t)15;
+        return r;
+    };
+    T* La = (T*)carve((size_t)tem * sizeof(T));
+    T* Lb = (T*)carve((size_t)tem * sizeof(T));
+    K* Lkey = (K*)carve((size_t)5 * tpm * sizeof(K));
+    long long* Lsrc[2];
+    Lsrc[0] = (long long*)carve((size_t)tpm * 8);
+    Lsrc[1] = (long long*)carve((size_t)tpm * 8);
+    T* Lshift = (T*)carve((size_t)2 * tpm * sizeof(T));
+    int4* Linf[2];
+    Linf[0] = (int4*)carve((size_t)tpm * 16);
+    Linf[1] = (int4*)carve((size_t)tpm * 16);
+    int* Lwm = (int*)carve((size_t)tpm * 4);          // per patch: children to write (bit c)
+    int* Lpre = (int*)carve((size_t)(2 * tpm + 2) * 4);  // per patch: scan of kept (child 0, child 1)
+    int* Ldst = (int*)carve((size_t)2 * tpm * 4);     // per patch and child: heap patch or -1
+    uint32_t* Lsfl = (uint32_t*)carve((size_t)2 * tpm * 4);  // per segment and child: flags
+    int* Lpos = (int*)carve((size_t)2 * tpm * 4);     // per segment and child: list position
+    int* Lseg = (int*)carve((size_t)(tpm + 1) * 4);   // per segment: first patch
+
+    const int tid = threadIdx.x;
     int hint = 0;
-    SubCtx c, nc;
+    PackUnit c, nc;
     T v[LB];
-    uint32_t hfl, hfr;   // thread 0: flag hints of the current unit's children
-    resolve_unit(insts, n_inst, pre, sinfo, u, hint, c);
-    issue_tile<T, LB>(insts[c.bi], c, v);
-    load_hint(insts[c.bi], c, hfl, hfr);
-    float ce = 0.0f, ne = 0.0f;     // FP32: this thread's patch's carried error (current, next unit)
+    float ce = 0.0f, ne = 0.0f;     // FP32: this thread's patch's carried error (current, next tile)
     double cb = 0.0, nb = 0.0;      // and its FP64 base
-    if (fp32) issue_eb(insts[c.bi], c, ce, cb);
+    int bufi = 0;
+
+    // the first tile: patch table, then its coefficients in flight
+    resolve_packed(insts, n_inst, pre, sinfo, u, hint, c);
+    if (tid < c.np) {
+        int4 inf;
+        long long src;
+        patch_info(insts[c.bi], c, tid, inf, src);
+        Linf[0][tid] = inf;
+        Lsrc[0][tid] = src;
+    }
+    __syncthreads();
+    issue_packed<T, LB>(insts[c.bi], c, Lsrc[0], v);
+    if (fp32 && tid < c.np) {
+        const DevInst& I0 = insts[c.bi];
+        const int4 inf = Linf[0][tid];
+        const int poly = c.kind == 0 ? 0 : I0.count[0] + (c.kind == 2 ? I0.count[1] : 0) + inf.z;
+        const int64_t pi = (int64_t)inf.y * I0.n_polys + poly;
+        ce = I0.err[c.cur][pi];
+        cb = I0.base[c.cur][pi];
+    }
 
     for (;;) {
         const DevInst& I = insts[c.bi];
-        const int j = c.j, l = I.l, kind = c.kind, np = c.np, S = c.S, TE = c.TE;
-        const int cur = c.cur, r = c.r, pslot = c.pslot;
-        const int64_t toff = c.toff;
-        T* childL = (T*)I.buf[cur ^ 1] + (int64_t)(2 * j) * I.stride;
-        T* childR = childL + I.stride;
-
-        const int gath = c.gath;
-        const float invS = c.invS;
-        SubLds<T> L;
-        L.a = (T*)smem;
-        L.b = L.a + TE;
-        L.key = (K*)(L.b + TE);
-        L.id = (int*)(L.key + 5 * np);
-        L.need = L.id + np;
-        L.dst = L.need + np;
-        L.shift = (T*)(L.dst + 2 * np);
-        // children already condemned by other tiles (infeasible), or, with the
-        // stale filter, whose cost bound exceeds the previous solution estimate
-        if (threadIdx.x == 0) {
-            int dl = (hfl & F_INFEAS) != 0, dr = (hfr & F_INFEAS) != 0;
-            if (kind != 0 && I.stale && c.pprev < INFINITY) {
-                for (int q = 0; q < 2; ++q) {
-                    const int ch = 2 * j + q;
-                    if (__hip_atomic_load(&I.stamp[ch], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == c.stamp &&
-                        __hip_atomic_load(&I.minP[ch], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) > c.pprev) {
-                        if (q) dr = 1; else dl = 1;
-                    }
-                }
-            }
-            s_dead[0] = dl;
-            s_dead[1] = dr;
-            s_flag[0] = 0;
-            s_flag[1] = 0;
-        }
-        // current tile: registers -> LDS
+        const int kind = c.kind, np = c.np, S = c.S, TE = c.TE, cur = c.cur, r = c.r, l = I.l;
+        const int4* inf = Linf[bufi];
+        // current tile: registers -> LDS; keys and segment flags reset
 #pragma unroll
         for (int q = 0; q < LB; ++q) {
-            const int e = threadIdx.x + q * SUB_THREADS;
-            if (e < TE) L.a[e] = v[q];
+            const int e = tid + q * SUB_THREADS;
+            if (e < TE) La[e] = v[q];
         }
-        for (int p = threadIdx.x; p < np; p += blockDim.x) {
-            L.key[5 * p + 0] = ~(K)0;
-            L.key[5 * p + 1] = 0;
-            L.key[5 * p + 2] = ~(K)0;
-            L.key[5 * p + 3] = 0;
-            L.key[5 * p + 4] = 0;
-            if (gath) L.id[p] = c.act[p].x;
+        if (tid < np) {
+            Lkey[5 * tid + 0] = ~(K)0;
+            Lkey[5 * tid + 1] = 0;
+            Lkey[5 * tid + 2] = ~(K)0;
+            Lkey[5 * tid + 3] = 0;
+            Lkey[5 * tid + 4] = 0;
+            Lsfl[2 * tid] = 0;
+            Lsfl[2 * tid + 1] = 0;
         }
-        const double pprev = c.pprev;
-        const uint32_t stamp = c.stamp;
-        // next unit: resolve it and put its tile in flight
+        // next tile: resolve it and start loading its patch table
         const long long un = u + gridDim.x;
         const bool more = un < total;
+        int4 ninf = make_int4(0, 0, 0, 0);
+        long long nsrc = 0;
         if (more) {
-            resolve_unit(insts, n_inst, pre, sinfo, un, hint, nc);
-            issue_tile<T, LB>(insts[nc.bi], nc, v);
-            load_hint(insts[nc.bi], nc, hfl, hfr);
-            if (fp32) issue_eb(insts[nc.bi], nc, ne, nb);
+            resolve_packed(insts, n_inst, pre, sinfo, un, hint, nc);
+            if (tid < nc.np) patch_info(insts[nc.bi], nc, tid, ninf, nsrc);
         }
         lds_barrier();
-        // block-uniform: every wave reads the same LDS words after the barrier
-        const bool deadL = s_dead[0] != 0, deadR = s_dead[1] != 0;
-        if (!(deadL && deadR)) {
-            const FibreGeom g = c.g;
-            tile_split<T, MM>(np, S, g, L);
-            lds_barrier();
+        tile_split<T, MM>(np, S, c.g, La, Lb, Lkey);
+        // the next patch table to LDS (its loads had the split to arrive)
+        if (more && tid < nc.np) {
+            Linf[bufi ^ 1][tid] = ninf;
+            Lsrc[bufi ^ 1][tid] = nsrc;
+        }
+        lds_barrier();
+        // next tile's coefficients (and FP32 error bounds and bases) in flight
+        if (more) {
+            const DevInst& In = insts[nc.bi];
+            issue_packed<T, LB>(In, nc, Lsrc[bufi ^ 1], v);
+            if (fp32 && tid < nc.np) {
+                const int poly = nc.kind == 0 ? 0 : In.count[0] + (nc.kind == 2 ? In.count[1] : 0) + ninf.z;
+                const int64_t pi = (int64_t)ninf.y * In.n_polys + poly;
+                ne = In.err[nc.cur][pi];
+                nb = In.base[nc.cur][pi];
+            }
+        }
 
-            // per-patch bounds (widened in FP32 mode) -> records or flags of both children
-            uint32_t fL = 0, fR = 0;
-            for (int p = threadIdx.x; p < np; p += blockDim.x) {
-                const int poly = (kind == 0) ? 0 : I.count[0] + (kind == 2 ? I.count[1] + c.p0 + p : (gath ? L.id[p] : c.p0 + p));
-                double e = 0.0, base = 0.0;
-                if (fp32) {
-                    // the stored values are offsets from the patch's FP64 base, which
-                    // subdivision keeps (rows sum to one); the split's error grows with
-                    // the offsets.  Each child is then re-centred: its base moves by
-                    // its midrange offset mc and its offsets become v - mc, so that they
-                    // shrink with the box; the shift adds the rounding of v - mc (below
-                    // 2^-24 (max - min)) and of the new FP64 base.
-                    const int64_t pi = (int64_t)pslot * I.n_polys + poly;
-                    const bool pre_ld = p < (int)blockDim.x;   // prefetched by this thread
-                    const float ep = pre_ld ? ce : I.err[cur][pi];
-                    base = pre_ld ? cb : I.base[cur][pi];
-                    e = (double)round_up_f((double)ep + gamma32(g.m) * (double)funkey(L.key[5 * p + 4]) +
-                                           (double)g.m * 0x1p-126);
-                    for (int ch = 0; ch < 2; ++ch) {
-                        const float mn = (float)funkey(L.key[5 * p + 2 * ch]);
-                        const float mx = (float)funkey(L.key[5 * p + 2 * ch + 1]);
-                        const float mc = 0.5f * mn + 0.5f * mx;
-                        const double nb = base + (double)mc;
-                        const int64_t ci = (int64_t)(2 * j + ch) * I.n_polys + poly;
-                        I.err[cur ^ 1][ci] = round_up_f(e + ((double)mx - (double)mn) * 0x1p-23 +
-                                                        fabs(nb) * 0x1p-52 + 0x1p-126);
-                        I.base[cur ^ 1][ci] = nb;
-                        L.shift[ch * np + p] = (T)mc;
-                    }
-                }
-                double lo[2], hi[2];
-                for (int ch = 0; ch < 2; ++ch)
-                    child_bounds<T>(funkey(L.key[5 * p + 2 * ch]), funkey(L.key[5 * p + 2 * ch + 1]), e, base,
-                                    lo[ch], hi[ch]);
-                if (kind == 0) {
-                    // cost records, child ids, then the stamp that publishes the records
-                    I.minP[2 * j] = lo[0];
-                    I.maxP[2 * j] = hi[0];
-                    I.minP[2 * j + 1] = lo[1];
-                    I.maxP[2 * j + 1] = hi[1];
-                    const uint32_t* pid = I.ids[cur] + (int64_t)pslot * l;
-                    uint32_t* cid = I.ids[cur ^ 1] + (int64_t)(2 * j) * l;
-                    for (int k = 0; k < l; ++k) {
-                        const uint32_t vv = pid[k];
-                        cid[k] = (k == r) ? 2u * vv : vv;
-                        cid[l + k] = (k == r) ? 2u * vv + 1u : vv;
-                    }
-                    if (I.stale) {
-                        __hip_atomic_store(&I.stamp[2 * j], stamp, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-                        __hip_atomic_store(&I.stamp[2 * j + 1], stamp, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-                    }
-                    s_dead[0] = I.stale && lo[0] > pprev;
-                    s_dead[1] = I.stale && lo[1] > pprev;
-                } else {
-                    for (int ch = 0; ch < 2; ++ch) {
-                        uint32_t f = 0;
-                        if (kind == 1) {
-                            if (lo[ch] > 0.0) f |= F_INFEAS;
-                            if (!(hi[ch] <= 0.0)) f |= F_NOTFEAS;
-                        } else {
-                            if (lo[ch] > 0.0 || hi[ch] < 0.0) f |= F_INFEAS;
-                            if (!(-I.eps_eq <= lo[ch] && lo[ch] <= 0.0 && 0.0 <= hi[ch] && hi[ch] <= I.eps_eq))
-                                f |= F_NOTFEAS;
-                        }
-                        if (ch == 0) fL |= f; else fR |= f;
-                    }
-                    // an inequality certified satisfied on a child (max B <= 0)
-                    // stays satisfied on all its sub-boxes: the child drops it
-                    if (gath) L.need[p] = (hi[0] <= 0.0 ? 0 : 1) | (hi[1] <= 0.0 ? 0 : 2);
+        // per patch (thread p): bounds of both children (widened in FP32 mode),
+        // records (cost) or flags (constraints)
+        const bool act = tid < np;
+        const int p = tid;
+        int j = 0, slot = 0, id = 0, poly = 0;
+        uint32_t f2[2] = {0, 0};
+        double lo[2] = {0.0, 0.0}, hi[2] = {0.0, 0.0};
+        if (act) {
+            const int4 ip = inf[p];
+            j = ip.x;
+            slot = ip.y;
+            id = ip.z;
+            poly = kind == 0 ? 0 : I.count[0] + (kind == 2 ? I.count[1] : 0) + id;
+            double e = 0.0, base = 0.0;
+            if (fp32) {
+                // the stored values are offsets from the patch's FP64 base, which
+                // subdivision keeps (rows sum to one); the split's error grows with
+                // the offsets.  Each child is then re-centred: its base moves by
+                // its midrange offset mc and its offsets become v - mc, so that they
+                // shrink with the box; the shift adds the rounding of v - mc (below
+                // 2^-24 (max - min)) and of the new FP64 base.
+                base = cb;
+                e = (double)round_up_f((double)ce + gamma32(c.g.m) * (double)funkey(Lkey[5 * p + 4]) +
+                                       (double)c.g.m * 0x1p-126);
+                for (int ch = 0; ch < 2; ++ch) {
+                    const float mn = (float)funkey(Lkey[5 * p + 2 * ch]);
+                    const float mx = (float)funkey(Lkey[5 * p + 2 * ch + 1]);
+                    const float mc = 0.5f * mn + 0.5f * mx;
+                    const double nbs = base + (double)mc;
+                    const int64_t ci = (int64_t)(2 * j + ch) * I.n_polys + poly;
+                    I.err[cur ^ 1][ci] = round_up_f(e + ((double)mx - (double)mn) * 0x1p-23 +
+                                                    fabs(nbs) * 0x1p-52 + 0x1p-126);
+                    I.base[cur ^ 1][ci] = nbs;
+                    Lshift[ch * tpm + p] = (T)mc;
                 }
             }
-            if (fL) atomicOr(&s_flag[0], fL);
-            if (fR) atomicOr(&s_flag[1], fR);
-            lds_barrier();
-            if (threadIdx.x == 0) {
-                if (s_flag[0]) atomicOr(&I.flags[2 * j], s_flag[0]);
-                if (s_flag[1]) atomicOr(&I.flags[2 * j + 1], s_flag[1]);
-            }
-            // children patches (skipped when the child is already known dead)
-            const bool wl = !deadL && !s_dead[0] && !(s_flag[0] & F_INFEAS);
-            const bool wr = !deadR && !s_dead[1] && !(s_flag[1] & F_INFEAS);
-            constexpr int SB = 8;
-            if (!gath) {
-                for (int e0 = threadIdx.x; e0 < TE; e0 += SB * SUB_THREADS) {
-                    T va[SB], vb[SB];
-#pragma unroll
-                    for (int q = 0; q < SB; ++q) {
-                        const int e = e0 + q * SUB_THREADS;
-                        if (e < TE) {
-                            va[q] = L.a[e];
-                            vb[q] = L.b[e];
-                            if (fp32) {
-                                const int p = patch_of(e, invS);
-                                va[q] -= L.shift[p];
-                                vb[q] -= L.shift[np + p];
-                            }
-                        }
-                    }
-#pragma unroll
-                    for (int q = 0; q < SB; ++q) {
-                        const int e = e0 + q * SUB_THREADS;
-                        if (e < TE) {
-                            if (wl) childL[toff + e] = va[q];
-                            if (wr) childR[toff + e] = vb[q];
-                        }
-                    }
+            for (int ch = 0; ch < 2; ++ch)
+                child_bounds<T>(funkey(Lkey[5 * p + 2 * ch]), funkey(Lkey[5 * p + 2 * ch + 1]), e, base, lo[ch],
+                                hi[ch]);
+            if (kind == 0) {
+                // cost records, child ids, then the stamp that publishes the records
+                I.minP[2 * j] = lo[0];
+                I.maxP[2 * j] = hi[0];
+                I.minP[2 * j + 1] = lo[1];
+                I.maxP[2 * j + 1] = hi[1];
+                const uint32_t* pid = I.ids[cur] + (int64_t)slot * l;
+                uint32_t* cid = I.ids[cur ^ 1] + (int64_t)(2 * j) * l;
+                for (int k = 0; k < l; ++k) {
+                    const uint32_t vv = pid[k];
+                    cid[k] = (k == r) ? 2u * vv : vv;
+                    cid[l + k] = (k == r) ? 2u * vv + 1u : vv;
+                }
+                if (I.stale) {
+                    __hip_atomic_store(&I.stamp[2 * j], c.stamp, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                    __hip_atomic_store(&I.stamp[2 * j + 1], c.stamp, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
                 }
             } else {
-                // wave 0 appends the kept inequalities to each live child: one
-                // reservation per child and tile in its carried list and in the
-                // heap of buffer cur^1, ranks by wave ballot, and the heap patch
-                // of every (patch, child) into LDS for the stores below
-                if (threadIdx.x < 64) {
-                    const int lane = threadIdx.x;
-                    const bool w2[2] = {wl, wr};
-                    int cnt[2] = {0, 0};
-                    for (int q0 = 0; q0 < np; q0 += 64) {
-                        const int nd = (q0 + lane < np) ? L.need[q0 + lane] : 0;
-                        cnt[0] += __popcll(__ballot(nd & 1));
-                        cnt[1] += __popcll(__ballot(nd & 2));
+                for (int ch = 0; ch < 2; ++ch) {
+                    uint32_t f = 0;
+                    if (kind == 1) {
+                        if (lo[ch] > 0.0) f |= F_INFEAS;
+                        if (!(hi[ch] <= 0.0)) f |= F_NOTFEAS;
+                    } else {
+                        if (lo[ch] > 0.0 || hi[ch] < 0.0) f |= F_INFEAS;
+                        if (!(-I.eps_eq <= lo[ch] && lo[ch] <= 0.0 && 0.0 <= hi[ch] && hi[ch] <= I.eps_eq))
+                            f |= F_NOTFEAS;
                     }
-                    int pos[2] = {0, 0};
-                    long long hb[2] = {0, 0};
-                    if (lane == 0)
-                        for (int ch = 0; ch < 2; ++ch)
-                            if (w2[ch] && cnt[ch]) {
-                                pos[ch] = atomicAdd(&I.na[cur ^ 1][2 * j + ch], cnt[ch]);
-                                hb[ch] = (long long)atomicAdd((unsigned long long*)&I.st->htop[cur ^ 1],
-                                                              (unsigned long long)cnt[ch]);
-                            }
-                    for (int ch = 0; ch < 2; ++ch) {
-                        pos[ch] = __shfl(pos[ch], 0, 64);
-                        hb[ch] = __shfl(hb[ch], 0, 64);
+                    f2[ch] = f;
+                }
+            }
+        }
+        // constraint tiles: segments (runs of patches of one parent) and, in
+        // retiring mode, which children keep each patch (an inequality
+        // certified satisfied on a child, max B <= 0, stays satisfied on all its
+        // sub-boxes, and the child drops it), in one workgroup scan
+        int seg = 0, k0 = 0, k1 = 0;
+        int3 ex = make_int3(0, 0, 0), tot = make_int3(0, 0, 0);
+        if (kind != 0) {
+            const int start = act && (p == 0 || inf[p - 1].x != j);
+            if (c.gath && act) {
+                k0 = hi[0] > 0.0;
+                k1 = hi[1] > 0.0;
+            }
+            tot = block_scan3(make_int3(start, k0, k1), ex, s_sc);
+            seg = ex.x + start - 1;
+            if (act) {
+                if (start) Lseg[seg] = p;
+                if (f2[0]) atomicOr(&Lsfl[2 * seg], f2[0]);
+                if (f2[1]) atomicOr(&Lsfl[2 * seg + 1], f2[1]);
+                Lpre[2 * p] = ex.y;
+                Lpre[2 * p + 1] = ex.z;
+            }
+            if (tid == 0) {
+                Lseg[tot.x] = np;
+                s_nseg = tot.x;
+                Lpre[2 * np] = tot.y;
+                Lpre[2 * np + 1] = tot.z;
+            }
+            lds_barrier();
+            // per segment and child: the flags to the child's record; in
+            // retiring mode its kept patches' place in the child's carried list,
+            // and the tile's heap patches, reserved together
+            if (tid < s_nseg) {
+                const int a0 = Lseg[tid], a1 = Lseg[tid + 1];
+                const int js = inf[a0].x;
+                for (int ch = 0; ch < 2; ++ch) {
+                    const uint32_t f = Lsfl[2 * tid + ch];
+                    if (f) atomicOr(&I.flags[2 * js + ch], f);
+                    if (c.gath) {
+                        const int cnt = Lpre[2 * a1 + ch] - Lpre[2 * a0 + ch];
+                        Lpos[2 * tid + ch] = cnt ? atomicAdd(&I.na[cur ^ 1][2 * js + ch], cnt) : 0;
                     }
-                    const unsigned long long below = (1ull << lane) - 1ull;
-                    for (int q0 = 0; q0 < np; q0 += 64) {
-                        const int p = q0 + lane;
-                        const int nd = (p < np) ? L.need[p] : 0;
-                        const int id = (p < np) ? L.id[p] : 0;
-                        for (int ch = 0; ch < 2; ++ch) {
-                            const bool k = w2[ch] && ((nd >> ch) & 1);
-                            const unsigned long long bal = __ballot(k);
-                            const int rank = __popcll(bal & below);
-                            if (k)
-                                I.act[cur ^ 1][(int64_t)(2 * j + ch) * I.count[1] + pos[ch] + rank] =
-                                    make_int2(id, (int)(hb[ch] + rank));
-                            if (p < np) L.dst[ch * np + p] = k ? (int)(hb[ch] + rank) : -1;
-                            pos[ch] += __popcll(bal);
-                            hb[ch] += __popcll(bal);
+                }
+            }
+            if (c.gath && tid == SUB_THREADS - 1)
+                s_hb = (tot.y + tot.z) ? (long long)atomicAdd((unsigned long long*)&I.st->htop[cur ^ 1],
+                                                              (unsigned long long)(tot.y + tot.z))
+                                       : 0;
+        }
+        if (!c.gath) {
+            // children patches to the children's slots, not to a child already
+            // condemned (infeasible from this tile, or with the stale filter a
+            // cost bound above the previous solution estimate)
+            if (act) {
+                int wm = 0;
+                for (int ch = 0; ch < 2; ++ch) {
+                    const bool w = kind == 0 ? !(I.stale && lo[ch] > c.pprev) : !(Lsfl[2 * seg + ch] & F_INFEAS);
+                    if (w) wm |= 1 << ch;
+                }
+                Lwm[p] = wm;
+            }
+            lds_barrier();
+            T* dbuf = (T*)I.buf[cur ^ 1];
+            constexpr int SB = 8;
+            for (int e0 = tid; e0 < TE; e0 += SB * SUB_THREADS) {
+                T va[SB], vb[SB];
+                int pp[SB];
+#pragma unroll
+                for (int q = 0; q < SB; ++q) {
+                    const int e = e0 + q * SUB_THREADS;
+                    pp[q] = -1;
+                    if (e < TE) {
+                        const int pq = patch_of(e, c.invS);
+                        pp[q] = pq;
+                        va[q] = La[e];
+                        vb[q] = Lb[e];
+                        if (fp32) {
+                            va[q] -= Lshift[pq];
+                            vb[q] -= Lshift[tpm + pq];
                         }
                     }
                 }
-                lds_barrier();
-                // each kept patch to its heap patch
-                T* hc = (T*)I.heap[cur ^ 1];
-#pragma unroll 2
-                for (int e = threadIdx.x; e < TE; e += SUB_THREADS) {
-                    const int p = patch_of(e, invS);
-                    const int dl = L.dst[p], dr = L.dst[np + p];
-                    const int r = e - p * S;
-                    const T sl = fp32 ? L.shift[p] : (T)0, sr = fp32 ? L.shift[np + p] : (T)0;
-                    if (dl >= 0) hc[(int64_t)dl * S + r] = L.a[e] - sl;
-                    if (dr >= 0) hc[(int64_t)dr * S + r] = L.b[e] - sr;
+#pragma unroll
+                for (int q = 0; q < SB; ++q) {
+                    const int e = e0 + q * SUB_THREADS;
+                    if (pp[q] >= 0) {
+                        const int pq = pp[q];
+                        const int4 ip = inf[pq];
+                        const int w2 = Lwm[pq];
+                        const int64_t o = (int64_t)(2 * ip.x) * I.stride + I.soff[kind] + (int64_t)ip.z * S +
+                                          (e - pq * S);
+                        if (w2 & 1) dbuf[o] = va[q];
+                        if (w2 & 2) dbuf[o + I.stride] = vb[q];
+                    }
+                }
+            }
+        } else {
+            // retiring mode: every kept (patch, child) gets its heap patch and
+            // its entry in the child's carried list
+            lds_barrier();
+            if (act) {
+                const long long hb = s_hb;
+                const int sp = Lseg[seg];
+                for (int ch = 0; ch < 2; ++ch) {
+                    int d = -1;
+                    if (ch ? k1 : k0) {
+                        const int rank = Lpre[2 * p + ch] - Lpre[2 * sp + ch];
+                        d = (int)(hb + (ch ? tot.y + ex.z : ex.y));
+                        I.act[cur ^ 1][(int64_t)(2 * j + ch) * I.count[1] + Lpos[2 * seg + ch] + rank] =
+                            make_int2(id, d);
+                    }
+                    Ldst[ch * tpm + p] = d;
                 }
             }
             lds_barrier();
-        } else {
-            lds_barrier();   // s_dead is read above before the next unit rewrites it
+            // each kept patch to its heap patch
+            T* hc = (T*)I.heap[cur ^ 1];
+#pragma unroll 2
+            for (int e = tid; e < TE; e += SUB_THREADS) {
+                const int pq = patch_of(e, c.invS);
+                const int dl = Ldst[pq], dr = Ldst[tpm + pq];
+                const int rr = e - pq * S;
+                const T sl = fp32 ? Lshift[pq] : (T)0, sr = fp32 ? Lshift[tpm + pq] : (T)0;
+                if (dl >= 0) hc[(int64_t)dl * S + rr] = La[e] - sl;
+                if (dr >= 0) hc[(int64_t)dr * S + rr] = Lb[e] - sr;
+            }
         }
+        lds_barrier();
         if (!more) break;
         c = nc;
         u = un;
         ce = ne;
         cb = nb;
+        bufi ^= 1;
     }
 }
 
@@ -1477,15 +1573,27 @@ __global__ __launch_bounds__(CUT_THREADS) void k_cut(const DevInst* __restrict__
     __shared__ int shi[CUT_THREADS / 64];
     __shared__ int wsum[CUT_THREADS / 64 + 1];
     __shared__ long long wun[CUT_THREADS / 64 + 1];
+    __shared__ long long wap[CUT_THREADS / 64 + 1];
+    __shared__ int s_kc[CUT_THREADS];   // retiring mode: a chunk's kept children's slots
+    __shared__ int s_ka[CUT_THREADS];   // and the offsets of their carried patches
     __shared__ long long wact[CUT_THREADS / 64];
+    __shared__ double s_plo[CUT_THREADS / 64];
     const DevInst& I = insts[blockIdx.x];
     InstState* st = I.st;
     if (st->status != ST_RUNNING) return;
-    const int K = st->K, C = 2 * K, r = st->r, cur = st->cur;
+    const int K = st->K, C = 2 * K, r = st->r, cur = st->cur, l = I.l;
     const int TP1 = I.tile_polys[1];
     const double pprev = st->p_up;
     const bool fin = pprev < INFINITY;
     const int tid = threadIdx.x;
+    // state the final updates need, read before the passes: the step count,
+    // carried patches, iteration count, per axis (thread k) its depth, and the
+    // children's width
+    const int steps0 = st->steps, n0 = st->n;
+    const long long alive0 = st->a_live;
+    const int depth_k = tid < l ? st->depth[tid] + (tid == r ? 1 : 0) : 0;
+    double width = 0.0;
+    for (int k = 0; k < l; ++k) width = fmax(width, ldexp(I.width0[k], -(st->depth[k] + (k == r ? 1 : 0))));
 
     // the child records, read once: the first CUT_CACHE * blockDim children are
     // kept in registers for the three passes below, any further ones are read
@@ -1522,7 +1630,7 @@ __global__ __launch_bounds__(CUT_THREADS) void k_cut(const DevInst* __restrict__
         const bool dead = fin && mnp > pprev;
         if (!dead && !(I.flags[c] & (F_INFEAS | F_NOTFEAS))) m = fmin(m, I.maxP[c]);
     }
-    m = block_min(m, shd);
+    m = block_min1(m, shd);
     const bool update = (m < INFINITY) && (m <= pprev);
     int arg = INT_MAX;
     if (update) {
@@ -1537,7 +1645,7 @@ __global__ __launch_bounds__(CUT_THREADS) void k_cut(const DevInst* __restrict__
             const bool dead = fin && mnp > pprev;
             if (!dead && !(I.flags[c] & (F_INFEAS | F_NOTFEAS)) && I.maxP[c] == m) arg = min(arg, c);
         }
-        arg = block_min_i(arg, shi);
+        arg = block_min1_i(arg, shi);
     }
     const double p_up = update ? m : pprev;
 
@@ -1545,7 +1653,7 @@ __global__ __launch_bounds__(CUT_THREADS) void k_cut(const DevInst* __restrict__
     // in retiring mode also the prefix of the kept children's inequality units
     double plo = INFINITY;
     int base = 0;
-    long long ubase = 0, asum = 0;
+    long long ubase = 0, abase = 0, asum = 0;
     const int lane = tid & 63, w = tid >> 6, nw = blockDim.x >> 6;
     // one chunk of blockDim children starting at c0 (uniform trip count: every
     // thread runs every chunk, so the barriers inside are reached by all)
@@ -1564,19 +1672,20 @@ __global__ __launch_bounds__(CUT_THREADS) void k_cut(const DevInst* __restrict__
             ti = (a + TP1 - 1) / TP1;
             asum += a;
         }
-        long long ui = ti;   // inclusive scan of the unit counts within the wave
+        const long long ak = (keep && ret) ? a : 0;
+        long long ui = ti, ai = ak;   // inclusive scans of the unit and patch counts within the wave
         for (int o = 1; o < 64; o <<= 1) {
-            const long long y = __shfl_up(ui, o, 64);
-            if (lane >= o) ui += y;
+            const long long y = __shfl_up(ui, o, 64), z = __shfl_up(ai, o, 64);
+            if (lane >= o) { ui += y; ai += z; }
         }
         const unsigned long long bal = __ballot(keep);
         const int before = __popcll(bal & ((1ull << lane) - 1ull));
         if (lane == 0) wsum[w] = __popcll(bal);
-        if (lane == 63) wun[w] = ui;
+        if (lane == 63) { wun[w] = ui; wap[w] = ai; }
         __syncthreads();
         if (tid == 0) {
             int acc = 0;
-            long long uacc = 0;
+            long long uacc = 0, aacc = 0;
             for (int q = 0; q < nw; ++q) {
                 const int v = wsum[q];
                 wsum[q] = acc;
@@ -1584,13 +1693,18 @@ __global__ __launch_bounds__(CUT_THREADS) void k_cut(const DevInst* __restrict__
                 const long long uv = wun[q];
                 wun[q] = uacc;
                 uacc += uv;
+                const long long av = wap[q];
+                wap[q] = aacc;
+                aacc += av;
             }
             wsum[nw] = acc;
             wun[nw] = uacc;
+            wap[nw] = aacc;
         }
         __syncthreads();
+        const int jn = base + wsum[w] + before;
+        const long long exl = ai - ak;   // this lane's patches before it in the wave
         if (keep) {
-            const int jn = base + wsum[w] + before;
             I.live[jn] = c;
             if (ret) {
                 const long long u0 = ubase + wun[w] + ui - ti;
@@ -1598,8 +1712,45 @@ __global__ __launch_bounds__(CUT_THREADS) void k_cut(const DevInst* __restrict__
                 for (int q = 0; q < (int)ti; ++q) I.umap[u0 + q] = make_int4(jn, c, q, a);
             }
         }
+        if (ret) {
+            // the kept children's carried patches, in order, for the next step's
+            // tiles: the chunk's kept children (their slots and patch offsets)
+            // go to LDS, then every lane copies patches, finding each one's
+            // child by a binary search over the offsets
+            if (keep) {
+                s_kc[jn - base] = c;
+                s_ka[jn - base] = (int)(wap[w] + exl);
+            }
+            __syncthreads();
+            const int kc = wsum[nw];
+            const int ctot = (int)wap[nw];
+            for (int e0 = tid; e0 < ctot; e0 += 4 * bd) {
+                int2 got[4];
+                int dst[4], jk[4], ck[4];
+#pragma unroll
+                for (int h = 0; h < 4; ++h) {
+                    const int e = e0 + h * bd;
+                    dst[h] = -1;
+                    if (e < ctot) {
+                        int lo = 0, hi = kc - 1;   // last kept child starting at or before e
+                        while (lo < hi) {
+                            const int mid = (lo + hi + 1) >> 1;
+                            if (s_ka[mid] <= e) lo = mid; else hi = mid - 1;
+                        }
+                        ck[h] = s_kc[lo];
+                        jk[h] = base + lo;
+                        got[h] = I.act[cur ^ 1][(int64_t)ck[h] * I.count[1] + (e - s_ka[lo])];
+                        dst[h] = e;
+                    }
+                }
+#pragma unroll
+                for (int h = 0; h < 4; ++h)
+                    if (dst[h] >= 0) I.pmap[abase + dst[h]] = make_int4(jk[h], ck[h], got[h].x, got[h].y);
+            }
+        }
         base += wsum[nw];
         ubase += wun[nw];
+        abase += wap[nw];
         __syncthreads();
     };
 #pragma unroll
@@ -1619,18 +1770,23 @@ __global__ __launch_bounds__(CUT_THREADS) void k_cut(const DevInst* __restrict__
         }
         chunk(c0, mnp, fl, a);
     }
-    plo = block_min(plo, shd);
-    const int Kn = base;
-    // inequality patches carried by the kept children
-    if (I.retire) {
-        for (int o = 32; o > 0; o >>= 1) asum += __shfl_xor(asum, o, 64);
-        if (lane == 0) wact[w] = asum;
-        __syncthreads();
-        asum = 0;
-        for (int q = 0; q < nw; ++q) asum += wact[q];
-    } else {
-        asum = (long long)Kn * I.count[1];
+    // least lower bound and the inequality patches the kept children carry,
+    // in one reduction
+    plo = wave_min(plo);
+    for (int o = 32; o > 0; o >>= 1) asum += __shfl_xor(asum, o, 64);
+    if (lane == 0) {
+        s_plo[w] = plo;
+        wact[w] = asum;
     }
+    __syncthreads();
+    plo = s_plo[0];
+    asum = 0;
+    for (int q = 0; q < nw; ++q) {
+        plo = fmin(plo, s_plo[q]);
+        asum += wact[q];
+    }
+    const int Kn = base;
+    if (!I.retire) asum = (long long)Kn * I.count[1];
 
     // clear the flags of the next step's children, and in retiring mode their
     // carried counts (they go to the buffer of this step's parents)
@@ -1639,16 +1795,25 @@ __global__ __launch_bounds__(CUT_THREADS) void k_cut(const DevInst* __restrict__
         if (I.retire) I.na[cur][c] = 0;
     }
 
+    // per axis (thread k): its depth, and x*'s box if the estimate moved
+    const int nxt = cur ^ 1;
+    if (tid < l) {
+        if (tid == r) st->depth[tid] = depth_k;
+        if (update) {
+            st->x_index[tid] = I.ids[nxt][(int64_t)arg * l + tid];
+            st->x_depth[tid] = depth_k;
+        }
+    }
     if (tid == 0) {
-        if (st->steps < MAX_TRACE) {
+        if (steps0 < MAX_TRACE) {
             TraceRec tr;
             tr.k_in = K;
             tr.k_kept = Kn;
             tr.p_up = p_up;
             tr.p_lo = plo;
-            tr.a_in = st->a_live;
+            tr.a_in = alive0;
             tr.a_kept = asum;
-            I.trace[st->steps] = tr;
+            I.trace[steps0] = tr;
         }
         st->a_live = asum;
         if (I.retire) {
@@ -1656,34 +1821,22 @@ __global__ __launch_bounds__(CUT_THREADS) void k_cut(const DevInst* __restrict__
             st->u1 = ubase;
             st->htop[cur] = 0;   // this step's parents' heap takes the next children
         }
-        st->depth[r] += 1;
-        st->steps += 1;
-        const int nxt = st->cur ^ 1;
-        if (update) {
-            const uint32_t* cid = I.ids[nxt] + (int64_t)arg * I.l;
-            for (int k = 0; k < I.l; ++k) {
-                st->x_index[k] = cid[k];
-                st->x_depth[k] = st->depth[k];
-            }
-            st->has_x = 1;
-        }
+        st->steps = steps0 + 1;
+        if (update) st->has_x = 1;
         st->p_up = p_up;
         st->p_lo = plo;
         st->K = Kn;
         st->cur = nxt;
         if (Kn == 0) {
             st->status = ST_INFEASIBLE;
+        } else if (p_up < INFINITY && p_up - plo <= I.eps && width <= I.delta) {
+            st->status = ST_OPTIMAL;
         } else {
-            double width = 0.0;
-            for (int k = 0; k < I.l; ++k) width = fmax(width, ldexp(I.width0[k], -st->depth[k]));
-            if (p_up < INFINITY && p_up - plo <= I.eps && width <= I.delta) {
-                st->status = ST_OPTIMAL;
-            } else {
-                int rn = (r + 1) % I.l;
-                st->r = rn;
-                if (rn == 0) st->n += 1;
-                if (st->n == I.N) st->status = ST_MAXITER;
-            }
+            const int rn = (r + 1) % l;
+            st->r = rn;
+            const int nn = n0 + (rn == 0 ? 1 : 0);
+            st->n = nn;
+            if (nn == I.N) st->status = ST_MAXITER;
         }
     }
 }
@@ -1992,13 +2145,26 @@ hipError_t launch_plan(const DevInst* d_insts, int n, long long* plan, StepInfo*
     return hipGetLastError();
 }
 
+// Dynamic LDS bytes of k_sub for tiles of at most tem coefficients and tpm
+// patches (the carve-up at the kernel's start, 16-byte aligned pieces).
+size_t sub_lds_bytes(int tem, int tpm, bool fp32)
+{
+    const size_t el = fp32 ? 4 : 8;
+    auto r16 = [](size_t b) { return (b + 15) & ~(size_t)15; };
+    return 2 * r16((size_t)tem * el) + r16((size_t)5 * tpm * el) + 2 * r16((size_t)tpm * 8) +
+           r16((size_t)2 * tpm * el) + 2 * r16((size_t)tpm * 16) + r16((size_t)tpm * 4) +
+           r16((size_t)(2 * tpm + 2) * 4) + 3 * r16((size_t)2 * tpm * 4) + r16((size_t)(tpm + 1) * 4);
+}
+
 // With ev0/ev1 the launch stamps them at the kernel's own start and end.
 template <typename T, int MM, bool FUSE>
 static hipError_t launch_sub_t(const DevInst* d_insts, int n, long long* plan, StepInfo* info, int grid,
-                               size_t lds, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1)
+                               int tem, int tpm, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1)
 {
     // registers per thread for a tile in flight: the largest tile / 256 lanes
     constexpr int LB = (sizeof(T) == 8 ? MAX_TILE64 : MAX_TILE32) / SUB_THREADS;
+    if (tem > LB * SUB_THREADS || tpm < 1 || tpm > SUB_THREADS) return hipErrorInvalidValue;
+    const size_t lds = sub_lds_bytes(tem, tpm, sizeof(T) == 4);
     // no more workgroups than fit on the device at once: the rest would only
     // queue, while resident ones walk the units with the next tile in flight
     static int cus = 0;
@@ -2015,23 +2181,23 @@ static hipError_t launch_sub_t(const DevInst* d_insts, int n, long long* plan, S
     if (cus > 0 && per_cu > 0) grid = std::min(grid, cus * per_cu);
     if (ev0)
         hipExtLaunchKernelGGL((k_sub<T, MM, LB, FUSE>), dim3(grid), dim3(SUB_THREADS), lds, s, ev0, ev1, 0,
-                              d_insts, n, plan, info);
+                              d_insts, n, plan, info, tem, tpm);
     else
         hipLaunchKernelGGL((k_sub<T, MM, LB, FUSE>), dim3(grid), dim3(SUB_THREADS), lds, s, d_insts, n, plan,
-                           info);
+                           info, tem, tpm);
     return hipGetLastError();
 }
 
 template <typename T, int MM>
 static hipError_t launch_sub_f(const DevInst* d_insts, int n, long long* plan, StepInfo* info, bool fuse,
-                               int grid, size_t lds, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1)
+                               int grid, int tem, int tpm, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1)
 {
-    if (fuse) return launch_sub_t<T, MM, true>(d_insts, n, plan, info, grid, lds, s, ev0, ev1);
-    return launch_sub_t<T, MM, false>(d_insts, n, plan, info, grid, lds, s, ev0, ev1);
+    if (fuse) return launch_sub_t<T, MM, true>(d_insts, n, plan, info, grid, tem, tpm, s, ev0, ev1);
+    return launch_sub_t<T, MM, false>(d_insts, n, plan, info, grid, tem, tpm, s, ev0, ev1);
 }
 
 hipError_t launch_sub(const DevInst* d_insts, int n, long long* plan, StepInfo* info, bool fuse,
-                      bool fp32, int maxm, int grid, size_t lds, hipStream_t s, hipEvent_t ev0,
+                      bool fp32, int maxm, int grid, int tem, int tpm, hipStream_t s, hipEvent_t ev0,
                       hipEvent_t ev1)
 {
     if (fuse && n > PLAN_FUSE_MAX) return hipErrorInvalidValue;
@@ -2040,11 +2206,11 @@ hipError_t launch_sub(const DevInst* d_insts, int n, long long* plan, StepInfo* 
         grid = 1;   // the plan is still formed and written
     }
     if (fp32) {
-        if (maxm <= 8) return launch_sub_f<float, 8>(d_insts, n, plan, info, fuse, grid, lds, s, ev0, ev1);
-        return launch_sub_f<float, 16>(d_insts, n, plan, info, fuse, grid, lds, s, ev0, ev1);
+        if (maxm <= 8) return launch_sub_f<float, 8>(d_insts, n, plan, info, fuse, grid, tem, tpm, s, ev0, ev1);
+        return launch_sub_f<float, 16>(d_insts, n, plan, info, fuse, grid, tem, tpm, s, ev0, ev1);
     }
-    if (maxm <= 8) return launch_sub_f<double, 8>(d_insts, n, plan, info, fuse, grid, lds, s, ev0, ev1);
-    return launch_sub_f<double, 16>(d_insts, n, plan, info, fuse, grid, lds, s, ev0, ev1);
+    if (maxm <= 8) return launch_sub_f<double, 8>(d_insts, n, plan, info, fuse, grid, tem, tpm, s, ev0, ev1);
+    return launch_sub_f<double, 16>(d_insts, n, plan, info, fuse, grid, tem, tpm, s, ev0, ev1);
 }
 
 hipError_t launch_rederive(const DevInst* d_insts, int n, const long long* plan, const StepInfo* info,

@@ -74,7 +74,7 @@ struct StepInfo {
     int32_t K, cur, r, steps;
     double p_up;
     uint32_t stamp;
-    int32_t pad;
+    int32_t A;          // inequality patches the parents carry (retiring mode)
 };
 
 // stamp of the child records written in the current step of a problem
@@ -99,7 +99,8 @@ struct DevInst {
     int32_t dims[KINDS][MAXL];     // fibre length (degree + 1) per axis and kind
     int32_t S[KINDS];              // coefficients per patch of each kind
     int32_t count[KINDS];          // 1, alpha, beta
-    int32_t tile_polys[KINDS];     // patches per tile
+    int32_t tile_polys[KINDS];     // patches per tile of an item (re-derivation units)
+    int32_t ptp[KINDS];            // patches per k_sub tile (tiles span parents)
     int32_t tile_start[KINDS + 1]; // first tile of each kind; tile_start[KINDS] = T
     int64_t off[KINDS];            // element offset of each kind inside an item (root layout)
     int64_t soff[KINDS];           // the same inside a list slot (retiring mode keeps the
@@ -133,8 +134,11 @@ struct DevInst {
     void* heap[2];
     int64_t hcap;                  // patches each heap holds
     int64_t* upre;                 // cap + 1: first inequality unit of each live item, then the total
-    int4* umap;                    // hcap entries: inequality unit v of the step -> (parent, its slot,
-                                   // tile of its carried list, carried count), written by k_cut
+    int4* umap;                    // hcap entries: re-derivation inequality unit v of the step ->
+                                   // (parent, its slot, tile of its carried list, carried count)
+    int4* pmap;                    // hcap entries: carried inequality patch P of the step, in parent
+                                   // order -> (parent, its slot, inequality, heap patch); both
+                                   // written by k_cut for the next step
     double* tmat;                  // FP32 re-derivation: cap/2 parents x 2 children x tmw doubles
     int32_t tmw;                   // transform words per child: sum over kinds and axes of m^2
     int32_t tmk[KINDS];            // offset of each kind's transforms inside a child's block

@@ -138,6 +138,7 @@ struct pcba_problem {
     bool fp32 = false;
     size_t elem = 8;
     int tile_polys[KINDS] = {};
+    int ptp[KINDS] = {};       // patches per k_sub tile
     int tile_start[KINDS + 1] = {};
     int T = 0;
     int64_t stride = 0;
@@ -166,6 +167,7 @@ struct pcba_problem {
     int64_t hcap = 0;                      // patches per heap
     int64_t* d_upre = nullptr;
     int4* d_umap = nullptr;                // retiring mode: hcap entries
+    int4* d_pmap = nullptr;                // retiring mode: hcap entries
     bool retire = false;
     double* d_tmat = nullptr;
     int tmw = 0, rows = 0, tmk[KINDS] = {};
@@ -312,6 +314,7 @@ static DevInst make_dev(const pcba_problem* P)
         I.S[t] = P->S[t];
         I.count[t] = P->count[t];
         I.tile_polys[t] = P->tile_polys[t];
+        I.ptp[t] = P->ptp[t];
         I.tile_start[t] = P->tile_start[t];
         I.off[t] = P->off[t];
         I.soff[t] = P->soff[t];
@@ -339,6 +342,7 @@ static DevInst make_dev(const pcba_problem* P)
     }
     I.hcap = P->hcap;
     I.umap = P->d_umap;
+    I.pmap = P->d_pmap;
     I.upre = P->d_upre;
     I.live = P->d_live;
     I.minP = P->d_minP;
@@ -374,7 +378,7 @@ static int64_t item_bytes(const pcba_problem* P)
 static int64_t footprint_of(const pcba_problem* P, int64_t boxes, int64_t hcap)
 {
     return 2 * boxes * item_bytes(P) +
-           (P->retire ? 2 * hcap * P->S[1] * (int64_t)P->elem + hcap * (int64_t)sizeof(int4) : 0) +
+           (P->retire ? 2 * hcap * P->S[1] * (int64_t)P->elem + 2 * hcap * (int64_t)sizeof(int4) : 0) +
            P->W * 8 + P->n_polys * 32 + (int64_t)sizeof(InstState);
 }
 
@@ -382,7 +386,19 @@ static int64_t footprint_of(const pcba_problem* P, int64_t boxes, int64_t hcap)
 // children of the root (and a little more) before the first growth.
 static int64_t hcap0(const pcba_problem* P)
 {
-    return P->retire ? std::max<int64_t>(2, 4 * (int64_t)P->count[1]) : 0;
+    if (!P->retire) return 0;
+    // 4 alpha patches, or up to 16 alpha while one heap stays within 8 MiB
+    const int64_t by_bytes = ((int64_t)8 << 20) / std::max<int64_t>(1, (int64_t)P->S[1] * (int64_t)P->elem);
+    return std::max<int64_t>(2, std::max<int64_t>(4 * (int64_t)P->count[1],
+                                                  std::min<int64_t>(16 * (int64_t)P->count[1], by_bytes)));
+}
+
+// Slots of a fresh list: CAP0, or up to 1024 while the two buffers stay within
+// 16 MiB, so that most problems never pause to grow; never beyond M.
+static int64_t cap0_of(const pcba_problem* P)
+{
+    const int64_t by_bytes = ((int64_t)16 << 20) / std::max<int64_t>(1, 2 * item_bytes(P));
+    return std::max<int64_t>(2, std::min<int64_t>(P->M_eff, std::max<int64_t>(CAP0, std::min<int64_t>(1024, by_bytes))));
 }
 
 static void free_list(pcba_problem* P)
@@ -407,6 +423,8 @@ static void free_list(pcba_problem* P)
     P->d_upre = nullptr;
     if (P->d_umap) pool_free(P->d_umap);
     P->d_umap = nullptr;
+    if (P->d_pmap) pool_free(P->d_pmap);
+    P->d_pmap = nullptr;
     if (P->d_live) pool_free(P->d_live);
     if (P->d_minP) pool_free(P->d_minP);
     if (P->d_maxP) pool_free(P->d_maxP);
@@ -442,6 +460,7 @@ static int alloc_list(pcba_problem* P, int64_t ncap, int64_t nhcap, hipStream_t 
     void* nhp[2] = {nullptr, nullptr};
     int64_t* nup = nullptr;
     int4* num = nullptr;
+    int4* npm = nullptr;
     const bool need_tm = P->fp32 && P->opt.rederive_every > 0;
     const int64_t n_up = ncap + 1;   // kept children (up to ncap) plus the end
     auto cleanup = [&]() {
@@ -449,6 +468,7 @@ static int alloc_list(pcba_problem* P, int64_t ncap, int64_t nhcap, hipStream_t 
         if (ntm) pool_free(ntm);
         if (nup) pool_free(nup);
         if (num) pool_free(num);
+        if (npm) pool_free(npm);
         for (int b = 0; b < 2; ++b) {
             if (nb[b]) pool_free(nb[b]);
             if (ni[b]) pool_free(ni[b]);
@@ -477,7 +497,8 @@ static int alloc_list(pcba_problem* P, int64_t ncap, int64_t nhcap, hipStream_t 
     }
     if (ok && P->retire)
         ok = pool_alloc((void**)&nup, (size_t)n_up * sizeof(int64_t)) == hipSuccess &&
-             pool_alloc((void**)&num, (size_t)nhcap * sizeof(int4)) == hipSuccess;
+             pool_alloc((void**)&num, (size_t)nhcap * sizeof(int4)) == hipSuccess &&
+             pool_alloc((void**)&npm, (size_t)nhcap * sizeof(int4)) == hipSuccess;
     ok = ok && pool_alloc((void**)&nlive, (size_t)ncap * sizeof(int32_t)) == hipSuccess &&
          pool_alloc((void**)&nmin, (size_t)ncap * sizeof(double)) == hipSuccess &&
          pool_alloc((void**)&nmax, (size_t)ncap * sizeof(double)) == hipSuccess &&
@@ -528,6 +549,9 @@ static int alloc_list(pcba_problem* P, int64_t ncap, int64_t nhcap, hipStream_t 
             if (e == hipSuccess)
                 e = hipMemcpyAsync(num, P->d_umap, (size_t)std::min(P->hcap, nhcap) * sizeof(int4),
                                    hipMemcpyDeviceToDevice, s);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(npm, P->d_pmap, (size_t)std::min(P->hcap, nhcap) * sizeof(int4),
+                                   hipMemcpyDeviceToDevice, s);
         }
         if (e == hipSuccess) e = hipStreamSynchronize(s);
     }
@@ -548,6 +572,7 @@ static int alloc_list(pcba_problem* P, int64_t ncap, int64_t nhcap, hipStream_t 
     P->hcap = P->retire ? nhcap : 0;
     P->d_upre = nup;
     P->d_umap = num;
+    P->d_pmap = npm;
     P->d_live = nlive;
     P->d_minP = nmin;
     P->d_maxP = nmax;
@@ -643,7 +668,7 @@ static int reset_batch(pcba_problem* const* probs, int n, hipStream_t s)
     for (int b = 0; b < n; ++b) {
         pcba_problem* P = probs[b];
         if (!P->list_released) continue;
-        int rc = alloc_list(P, std::max<int64_t>(2, std::min<int64_t>(P->M_eff, CAP0)), hcap0(P), s);
+        int rc = alloc_list(P, cap0_of(P), hcap0(P), s);
         if (rc != PCBA_OK) return rc;
         P->list_released = false;
     }
@@ -794,6 +819,12 @@ int pcba_create_problem(int32_t l, const double* lo, const double* hi, const int
     }
     P->tile_start[KINDS] = T;
     P->T = T;
+    // k_sub tiles: runs of ~TILE_ELEMS coefficients of one kind across parents,
+    // at most one patch per lane
+    for (int t = 0; t < KINDS; ++t) {
+        const int target = P->fp32 ? 2 * TILE_ELEMS : TILE_ELEMS;
+        P->ptp[t] = P->count[t] ? std::max(1, std::min(SUB_THREADS, target / std::max(1, P->S[t]))) : 1;
+    }
     // sub-interval transforms per child (FP32 re-derivation): m^2 words and m rows per kind and axis
     for (int t = 0; t < KINDS; ++t) {
         P->tmk[t] = P->tmw;
@@ -905,7 +936,7 @@ int pcba_create_problem(int32_t l, const double* lo, const double* hi, const int
         pcba_destroy_problem(P);
         return fail(PCBA_E_NOMEM, "device allocation failed");
     }
-    const int64_t cap0 = std::min<int64_t>(P->M_eff, CAP0);
+    const int64_t cap0 = cap0_of(P);
     int rc = alloc_list(P, std::max<int64_t>(2, cap0), hcap0(P), s);
     if (rc != PCBA_OK) {
         std::string m = g_last_error;
@@ -1075,20 +1106,14 @@ static int engine_upload(pcba_engine* E)
     return PCBA_OK;
 }
 
-// LDS bytes of the subdivision kernel for a problem (its largest tile)
-static size_t sub_lds(const pcba_problem* P)
+// The largest k_sub tile of a problem: coefficients and patches
+static void sub_tile(const pcba_problem* P, int* tem, int* tpm)
 {
-    int TE = P->S[0], TP = 1;
-    for (int t = 1; t < KINDS; ++t)
-        if (P->count[t]) {
-            TE = std::max(TE, P->tile_polys[t] * P->S[t]);
-            TP = std::max(TP, P->tile_polys[t]);
+    for (int t = 0; t < KINDS; ++t)
+        if (t == 0 || P->count[t]) {
+            *tem = std::max(*tem, P->ptp[t] * P->S[t]);
+            *tpm = std::max(*tpm, P->ptp[t]);
         }
-    const size_t key = P->fp32 ? 4 : 8;
-    // keys, and in retiring mode per patch its index, which children keep it,
-    // and its heap patch in each child (4 ints), then each child's re-centring
-    // shift (FP32)
-    return 2 * (size_t)TE * P->elem + 5 * (size_t)TP * key + 16 * (size_t)TP + 2 * (size_t)TP * P->elem + 16;
 }
 static size_t rederive_lds(const pcba_problem* P)
 {
@@ -1159,12 +1184,13 @@ static int engine_steps(pcba_engine* E, int n_steps)
     const int n = (int)E->active.size();
     bool any64 = false, any32 = false, anyrd = false;
     int maxm64 = 1, maxm32 = 1;
-    size_t lds64 = 0, lds32 = 0, ldsrd = 0;
+    size_t ldsrd = 0;
+    int tem64 = 1, tpm64 = 1, tem32 = 1, tpm32 = 1;
     for (auto* P : E->active) {
         if (P->fp32) {
             any32 = true;
             maxm32 = std::max(maxm32, P->maxm);
-            lds32 = std::max(lds32, sub_lds(P));
+            sub_tile(P, &tem32, &tpm32);
             if (P->opt.rederive_every > 0) {
                 anyrd = true;
                 ldsrd = std::max(ldsrd, rederive_lds(P));
@@ -1172,7 +1198,7 @@ static int engine_steps(pcba_engine* E, int n_steps)
         } else {
             any64 = true;
             maxm64 = std::max(maxm64, P->maxm);
-            lds64 = std::max(lds64, sub_lds(P));
+            sub_tile(P, &tem64, &tpm64);
         }
     }
     for (int s = 0; s < n_steps; ++s) {
@@ -1205,14 +1231,14 @@ static int engine_steps(pcba_engine* E, int n_steps)
             hipEvent_t e0, e1;
             HIP_TRY(prof_pair(0, &e0, &e1));
             HIP_TRY(launch_sub(E->b.d_insts, n, E->b.d_plan, E->b.d_info, !planned, false, maxm64,
-                               (int)std::min<int64_t>(GRID_MAX, ub64), lds64, E->stream, e0, e1));
+                               (int)std::min<int64_t>(GRID_MAX, ub64), tem64, tpm64, E->stream, e0, e1));
             planned = true;
         }
         if (l32) {
             hipEvent_t e0, e1;
             HIP_TRY(prof_pair(1, &e0, &e1));
             HIP_TRY(launch_sub(E->b.d_insts, n, E->b.d_plan, E->b.d_info, !planned, true, maxm32,
-                               (int)std::min<int64_t>(GRID_MAX, ub32), lds32, E->stream, e0, e1));
+                               (int)std::min<int64_t>(GRID_MAX, ub32), tem32, tpm32, E->stream, e0, e1));
             planned = true;
         }
         if (anyrd && ubrd > 0) {
@@ -1363,8 +1389,28 @@ int pcba_solve_batch(pcba_problem* const* probs, int32_t n, void* stream)
     size_t free_b = 0, total_b = 0;
     if (hipMemGetInfo(&free_b, &total_b) == hipSuccess)
         E->budget = E->used + (int64_t)(0.85 * ((double)free_b + (double)pool_cached_bytes()));
+    // no problem can stop with an optimum before every axis is split down to
+    // the step tolerance (one axis per step): the first host check waits for
+    // the earliest such step, unless a time limit needs watching
+    int first = STEPS_PER_SYNC;
+    {
+        int earliest = INT_MAX;
+        bool timed = false;
+        for (auto* P : E->active) {
+            timed = timed || P->opt.time_limit_s > 0;
+            int need = 0;
+            for (int k = 0; k < P->l; ++k) {
+                int d = 0;
+                while (d < 64 && std::ldexp(P->hi[k] - P->lo[k], -d) > P->opt.delta) ++d;
+                need += std::max(0, d - P->h_st.depth[k]);
+            }
+            earliest = std::min(earliest, need);
+        }
+        if (!timed && earliest != INT_MAX) first = std::max(first, std::min(earliest, 4 * STEPS_PER_SYNC));
+    }
     while (!E->active.empty()) {
-        rc = engine_steps(E, STEPS_PER_SYNC);
+        rc = engine_steps(E, first);
+        first = STEPS_PER_SYNC;
         if (rc != PCBA_OK) break;
     }
     pcba_engine_destroy(E);

@@ -248,7 +248,8 @@ def test_list_growth_keeps_parity(gpu):
 def test_engine_admission_by_footprint(gpu):
     insts = [make_instance(0, k) for k in range(6)]
     probs = [gpu.Problem(i) for i in insts]
-    one = probs[0].footprint(128)
+    # each admitted problem is charged for max(its list capacity, the reserve)
+    one = probs[0].footprint(max(128, probs[0].result()["capacity"]))
     budget = int(one * 2.5)
     eng = gpu.Engine(budget_bytes=budget, reserve_boxes=128)
     queue = list(probs)
