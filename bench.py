@@ -203,6 +203,26 @@ def cpu_baseline(insts, budget_s, workers):
     return done / dt, done, dt, p_up
 
 
+def copy_calibration(mib: int, reps: int):
+    """Device-to-device copies of a known size: the reference reading for the
+    hardware byte counters (FETCH_SIZE, WRITE_SIZE) under rocprofv3."""
+    import ctypes as C
+    hip = C.CDLL("libamdhip64.so")
+    n = mib << 20
+    a, b = C.c_void_p(), C.c_void_p()
+    if hip.hipMalloc(C.byref(a), C.c_size_t(n)) or hip.hipMalloc(C.byref(b), C.c_size_t(n)):
+        sys.exit("hipMalloc failed")
+    hip.hipMemset(a, 1, C.c_size_t(n))
+    hip.hipDeviceSynchronize()
+    for _ in range(reps):
+        hip.hipMemcpy(b, a, C.c_size_t(n), 3)   # device to device
+    hip.hipDeviceSynchronize()
+    hip.hipFree(a)
+    hip.hipFree(b)
+    print(json.dumps({"copy_bytes": n, "copies": reps}), flush=True)
+
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -217,6 +237,8 @@ def main():
     ap.add_argument("--stale", type=int, default=None, help="1/0: stale-estimate write filter")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="only run device copies of this many MiB (counter calibration) and exit")
+    ap.add_argument("--single-reps", type=int, default=20,
+                    help="solves of one plan alone per precision for the single-plan latency (0: skip)")
     ap.add_argument("--retire", type=int, default=1,
                     help="1/0: drop inequalities certified satisfied on a box from its descendants")
     args = ap.parse_args()
@@ -242,9 +264,11 @@ def main():
         opts["rederive_every"] = args.rederive
     r32 = run_mode(pcba, insts, "fp32", args.steps, args.warmup, **opts)
 
-    single = {"fp64_plain": single_plan(pcba, insts[0], "fp64", 20, **{k: v for k, v in opts.items()
-                                                                    if k != "rederive_every"}),
-              "fp32": single_plan(pcba, insts[0], "fp32", 20, **opts)}
+    single = None
+    if args.single_reps > 0:
+        single = {"fp64_plain": single_plan(pcba, insts[0], "fp64", args.single_reps,
+                                            **{k: v for k, v in opts.items() if k != "rederive_every"}),
+                  "fp32": single_plan(pcba, insts[0], "fp32", args.single_reps, **opts)}
 
     # parity of the two GPU paths on the last step (both provably within eps of f*)
     dp = max(abs(a["p_up"] - b["p_up"]) for a, b in zip(r32["results"], r64["results"])
