@@ -91,6 +91,14 @@ __device__ __forceinline__ int block_min1_i(int v, int* sh)
     return r;
 }
 
+// Tells the host that a problem left the running state (finished, or paused
+// for list growth): one word of pinned host memory per engine, written with a
+// vector store at system scope (null outside an engine).
+__device__ __forceinline__ void signal_host(const DevInst& I)
+{
+    if (I.hostflag) __hip_atomic_store(I.hostflag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
 // Units of work of one step, per class of problem:
 //   class 0: FP64 problems (k_sub<double>)
 //   class 1: FP32 problems splitting their FP32 parents (k_sub<float>)
@@ -140,9 +148,15 @@ __device__ __forceinline__ void plan_one(const DevInst& I, bool commit, long lon
     if (st->status == ST_RUNNING) {
         if (commit && (int64_t)K > st->peak) st->peak = K;
         if (2LL * K > (int64_t)I.M) {
-            if (commit) st->status = ST_MEMLIMIT;
+            if (commit) {
+                st->status = ST_MEMLIMIT;
+                signal_host(I);
+            }
         } else if (2LL * K > (int64_t)I.cap || (I.retire && 2 * st->a_live > I.hcap)) {
-            if (commit) st->status = ST_GROW;
+            if (commit) {
+                st->status = ST_GROW;
+                signal_host(I);
+            }
         } else {
             const int c = unit_class(I, st);
             v[c] = c == 2 ? step_units(I, st) : step_tiles(I, st);
@@ -929,7 +943,7 @@ __device__ __forceinline__ int3 block_scan3(int3 x, int3& excl, int* sc)
 //
 // With FUSE (at most PLAN_FUSE_MAX problems) the step's plan is not read
 // from k_plan's output but formed by every workgroup in LDS from the problems'
-// states (one lane per problem); workgroup 0 alone commits the memory test's
+// states (one thread per problem); workgroup 0 alone commits the memory test's
 // outcome and writes the plan and snapshots for the step's later kernels.
 template <typename T, int MM, int LB, bool FUSE>
 __global__ __launch_bounds__(SUB_THREADS) void k_sub(const DevInst* __restrict__ insts, int n_inst,
@@ -940,6 +954,7 @@ __global__ __launch_bounds__(SUB_THREADS) void k_sub(const DevInst* __restrict__
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ long long s_pre[PLAN_FUSE_MAX + 1];
     __shared__ StepInfo s_info[PLAN_FUSE_MAX];
+    __shared__ long long s_wt[4][SUB_THREADS / 64];
     __shared__ int s_sc[3 * (SUB_THREADS / 64)];
     __shared__ int s_nseg;
     __shared__ long long s_hb;
@@ -949,32 +964,42 @@ __global__ __launch_bounds__(SUB_THREADS) void k_sub(const DevInst* __restrict__
     const long long* pre = plan + cls * (n_inst + 1);
     const StepInfo* sinfo = info;
     if (FUSE) {
-        if (threadIdx.x < 64) {
-            const int b = threadIdx.x;
-            const bool commit = blockIdx.x == 0;
-            long long v[4] = {0, 0, 0, 0};
-            if (b < n_inst) {
-                StepInfo si;
-                plan_one(insts[b], commit, v, si);
-                s_info[b] = si;
-                if (commit) info[b] = si;
+        // one thread per problem: its share of the plan, then workgroup scans of
+        // the four classes (wave scans, then the waves' totals through LDS)
+        const int b = threadIdx.x, lane = b & 63, w = b >> 6;
+        const bool commit = blockIdx.x == 0;
+        long long v[4] = {0, 0, 0, 0};
+        if (b < n_inst) {
+            StepInfo si;
+            plan_one(insts[b], commit, v, si);
+            s_info[b] = si;
+            if (commit) info[b] = si;
+        }
+        long long x[4];
+        for (int c = 0; c < 4; ++c) {
+            x[c] = v[c];
+            for (int o = 1; o < 64; o <<= 1) {
+                const long long y = __shfl_up(x[c], o, 64);
+                if (lane >= o) x[c] += y;
             }
-            for (int c = 0; c < 4; ++c) {
-                if (!commit && c != cls) continue;
-                long long x = v[c];
-                for (int o = 1; o < 64; o <<= 1) {
-                    const long long y = __shfl_up(x, o, 64);
-                    if (b >= o) x += y;
-                }
-                // x: inclusive prefix; lane 63 holds the total
-                if (c == cls) {
-                    if (b < n_inst) s_pre[b] = x - v[c];
-                    if (b == 63) s_pre[n_inst] = x;
-                }
-                if (commit) {
-                    if (b < n_inst) plan[c * (n_inst + 1) + b] = x - v[c];
-                    if (b == 63) plan[c * (n_inst + 1) + n_inst] = x;
-                }
+            if (lane == 63) s_wt[c][w] = x[c];
+        }
+        __syncthreads();
+        for (int c = 0; c < 4; ++c) {
+            if (!commit && c != cls) continue;
+            long long before = 0, tot = 0;
+            for (int q = 0; q < SUB_THREADS / 64; ++q) {
+                if (q < w) before += s_wt[c][q];
+                tot += s_wt[c][q];
+            }
+            const long long ex = before + x[c] - v[c];
+            if (c == cls) {
+                if (b < n_inst) s_pre[b] = ex;
+                if (b == 0) s_pre[n_inst] = tot;
+            }
+            if (commit) {
+                if (b < n_inst) plan[c * (n_inst + 1) + b] = ex;
+                if (b == 0) plan[c * (n_inst + 1) + n_inst] = tot;
             }
         }
         __syncthreads();
@@ -1829,14 +1854,19 @@ __global__ __launch_bounds__(CUT_THREADS) void k_cut(const DevInst* __restrict__
         st->cur = nxt;
         if (Kn == 0) {
             st->status = ST_INFEASIBLE;
+            signal_host(I);
         } else if (p_up < INFINITY && p_up - plo <= I.eps && width <= I.delta) {
             st->status = ST_OPTIMAL;
+            signal_host(I);
         } else {
             const int rn = (r + 1) % l;
             st->r = rn;
             const int nn = n0 + (rn == 0 ? 1 : 0);
             st->n = nn;
-            if (nn == I.N) st->status = ST_MAXITER;
+            if (nn == I.N) {
+                st->status = ST_MAXITER;
+                signal_host(I);
+            }
         }
     }
 }

@@ -20,7 +20,7 @@ constexpr int MAXL = 8;       // PCBA_MAX_DIM
 constexpr int MAXM = 16;      // longest fibre: degree 15 + 1
 constexpr int SUB_THREADS = 256;
 constexpr int CERT_PPB = 16;    // polynomials per certification workgroup
-constexpr int PLAN_FUSE_MAX = 64;  // batches up to this size form the plan inside k_sub
+constexpr int PLAN_FUSE_MAX = 256;  // batches up to this size form the plan inside k_sub (<= SUB_THREADS)
 constexpr int CUT_THREADS = 1024;
 constexpr int CUT_CACHE = 4;      // children per thread k_cut keeps in registers
 constexpr int REDERIVE_CHUNK = 256;  // patches per re-derivation chunk
@@ -134,6 +134,7 @@ struct DevInst {
     void* heap[2];
     int64_t hcap;                  // patches each heap holds
     int64_t* upre;                 // cap + 1: first inequality unit of each live item, then the total
+    int* hostflag;                 // engine's pinned host word: set when the problem stops running
     int4* umap;                    // hcap entries: re-derivation inequality unit v of the step ->
                                    // (parent, its slot, tile of its carried list, carried count)
     int4* pmap;                    // hcap entries: carried inequality patch P of the step, in parent

@@ -36,6 +36,8 @@ int fail(int code, const std::string& msg)
 
 constexpr int GRID_MAX = 2048;
 constexpr int STEPS_PER_SYNC = 8;
+constexpr int CHECK_STEPS = 4;      // steps between looks at the kernels' stop flag
+constexpr int MAX_STEPS_PER_SYNC = 64;
 constexpr int TILE_ELEMS = 2816;   // target coefficients per FP64 tile (per LDS region)
 constexpr int MAX_PATCH = 3584;    // largest patch (coefficients): LDS stays within 64 KB
 constexpr int CAP0 = 64;           // initial list capacity (items per buffer)
@@ -198,6 +200,9 @@ struct EngineBufs {
     InstState* d_states = nullptr;
     InstState* h_states = nullptr;
     DevInst* h_insts = nullptr;    // pinned staging of the descriptors (outlives the async copy)
+    int* h_flag = nullptr;         // pinned word the kernels set when a problem stops running
+    int* d_flag = nullptr;         // its device address
+    hipEvent_t ev[2] = {nullptr, nullptr};   // ends of the last two chunks of steps
 };
 
 struct pcba_engine {
@@ -248,6 +253,9 @@ static void bufs_free(EngineBufs& b)
     if (b.d_states) (void)hipFree(b.d_states);
     if (b.h_states) (void)hipHostFree(b.h_states);
     if (b.h_insts) (void)hipHostFree(b.h_insts);
+    if (b.h_flag) (void)hipHostFree(b.h_flag);
+    for (int k = 0; k < 2; ++k)
+        if (b.ev[k]) (void)hipEventDestroy(b.ev[k]);
     b = EngineBufs();
 }
 
@@ -292,6 +300,9 @@ static hipError_t bufs_get(int cap, EngineBufs* out)
     if (e == hipSuccess) e = hipMalloc((void**)&b.d_states, c * sizeof(InstState));
     if (e == hipSuccess) e = hipHostMalloc((void**)&b.h_states, c * sizeof(InstState), hipHostMallocDefault);
     if (e == hipSuccess) e = hipHostMalloc((void**)&b.h_insts, c * sizeof(DevInst), hipHostMallocDefault);
+    if (e == hipSuccess) e = hipHostMalloc((void**)&b.h_flag, sizeof(int), hipHostMallocDefault);
+    if (e == hipSuccess) e = hipHostGetDevicePointer((void**)&b.d_flag, b.h_flag, 0);
+    for (int k = 0; k < 2 && e == hipSuccess; ++k) e = hipEventCreateWithFlags(&b.ev[k], hipEventDisableTiming);
     if (e != hipSuccess) {
         bufs_free(b);
         return e;
@@ -1100,7 +1111,10 @@ static int engine_upload(pcba_engine* E)
     }
     // every earlier use of the staging buffer has completed: the engine
     // synchronises its stream at the end of each batch of steps
-    for (int b = 0; b < n; ++b) E->b.h_insts[b] = make_dev(E->active[b]);
+    for (int b = 0; b < n; ++b) {
+        E->b.h_insts[b] = make_dev(E->active[b]);
+        E->b.h_insts[b].hostflag = E->b.d_flag;
+    }
     if (n) HIP_TRY(hipMemcpyAsync(E->b.d_insts, E->b.h_insts, n * sizeof(DevInst), hipMemcpyHostToDevice, E->stream));
     E->dirty = false;
     return PCBA_OK;
@@ -1201,7 +1215,20 @@ static int engine_steps(pcba_engine* E, int n_steps)
             sub_tile(P, &tem64, &tpm64);
         }
     }
+    // The steps go out in chunks of CHECK_STEPS; after each chunk the host
+    // waits for the end of the chunk before it (the newest one keeps the GPU
+    // busy) and stops early when a kernel has flagged a problem that finished
+    // or paused for growth.
+    __atomic_store_n(E->b.h_flag, 0, __ATOMIC_RELEASE);
     for (int s = 0; s < n_steps; ++s) {
+        if (s > 0 && s % CHECK_STEPS == 0) {
+            const int k = (s / CHECK_STEPS) & 1;
+            HIP_TRY(hipEventRecord(E->b.ev[k], E->stream));
+            if (s >= 2 * CHECK_STEPS) {
+                HIP_TRY(hipEventSynchronize(E->b.ev[k ^ 1]));
+                if (__atomic_load_n(E->b.h_flag, __ATOMIC_ACQUIRE)) break;
+            }
+        }
         // upper bound of this step's units: K at most doubles per step, and a
         // problem never holds more than cap/2 parents
         int64_t ub64 = 0, ub32 = 0, ubrd = 0, ubrows = 0, maxc = 0;
@@ -1389,28 +1416,13 @@ int pcba_solve_batch(pcba_problem* const* probs, int32_t n, void* stream)
     size_t free_b = 0, total_b = 0;
     if (hipMemGetInfo(&free_b, &total_b) == hipSuccess)
         E->budget = E->used + (int64_t)(0.85 * ((double)free_b + (double)pool_cached_bytes()));
-    // no problem can stop with an optimum before every axis is split down to
-    // the step tolerance (one axis per step): the first host check waits for
-    // the earliest such step, unless a time limit needs watching
-    int first = STEPS_PER_SYNC;
-    {
-        int earliest = INT_MAX;
-        bool timed = false;
-        for (auto* P : E->active) {
-            timed = timed || P->opt.time_limit_s > 0;
-            int need = 0;
-            for (int k = 0; k < P->l; ++k) {
-                int d = 0;
-                while (d < 64 && std::ldexp(P->hi[k] - P->lo[k], -d) > P->opt.delta) ++d;
-                need += std::max(0, d - P->h_st.depth[k]);
-            }
-            earliest = std::min(earliest, need);
-        }
-        if (!timed && earliest != INT_MAX) first = std::max(first, std::min(earliest, 4 * STEPS_PER_SYNC));
-    }
+    // between host checks the steps run until a kernel flags a problem that
+    // stopped or paused (at most MAX_STEPS_PER_SYNC), or STEPS_PER_SYNC when a
+    // time limit needs watching
+    bool timed = false;
+    for (auto* P : E->active) timed = timed || P->opt.time_limit_s > 0;
     while (!E->active.empty()) {
-        rc = engine_steps(E, first);
-        first = STEPS_PER_SYNC;
+        rc = engine_steps(E, timed ? STEPS_PER_SYNC : MAX_STEPS_PER_SYNC);
         if (rc != PCBA_OK) break;
     }
     pcba_engine_destroy(E);
