@@ -17,6 +17,7 @@ kernel (HIP events around its launches over a second, instrumented pass of the
 same steps), and the FP64 CPU oracle timed on a bounded sample.
 """
 import argparse
+import gc
 import json
 import math
 import os
@@ -68,17 +69,25 @@ def algorithmic_bytes(p, inst, precision):
     return total
 
 
-def run_mode(pcba, insts, precision, steps, warmup, **opts):
-    """Times `steps` batch solves (throughput and latency, no instrumentation),
-    then repeats them with HIP events around every kernel launch for the
-    per-kernel times and the roofline of the subdivide+bound kernel."""
+def warm(pcba, insts, precision, warmup, **opts):
+    """The batch's problems, created and solved `warmup` times (untimed)."""
     probs = [pcba.Problem(i, precision=precision, **opts) for i in insts]
     for w in range(warmup):
         pcba.reset_batch(probs)
         pcba.solve_batch(probs)
         log(f"[bench] {precision} warmup {w + 1}/{warmup} done")
+    return probs
+
+
+def run_mode(pcba, probs, insts, precision, steps):
+    """Times `steps` batch solves (throughput and latency, no instrumentation),
+    then repeats them with HIP events around every kernel launch for the
+    per-kernel times and the roofline of the subdivide+bound kernel."""
     lat, cert, results = [], 0, []
     elapsed = 0.0
+    # the timed solves measure the library: no Python garbage collection inside
+    gc.collect()
+    gc.disable()
     for s in range(steps):
         t0 = time.perf_counter()
         pcba.reset_batch(probs)
@@ -88,6 +97,7 @@ def run_mode(pcba, insts, precision, steps, warmup, **opts):
         cert += sum(1 for r in res if certified(r, pcba))
         results = res
         log(f"[bench] {precision} step {s + 1}/{steps}: {elapsed * 1e3 / (s + 1):.2f} ms/step")
+    gc.enable()
     # the same steps with every launch bracketed by HIP events on the library's stream
     sub_kernel = "sub_fp32" if precision == "fp32" else "sub_fp64"
     bytes_sub = 0.0
@@ -126,12 +136,15 @@ def single_plan(pcba, inst, precision, reps, **opts):
     pcba.reset_batch([p])
     pcba.solve_batch([p])
     t, ok = [], True
+    gc.collect()
+    gc.disable()
     for _ in range(reps):
         t0 = time.perf_counter()
         pcba.reset_batch([p])
         r = pcba.solve_batch([p])[0]
         t.append(time.perf_counter() - t0)
         ok = ok and certified(r, pcba)
+    gc.enable()
     p.close()
     return {"p50_ms": round(float(np.percentile(t, 50)) * 1e3, 4),
             "p99_ms": round(float(np.percentile(t, 99)) * 1e3, 4), "certified": ok, "reps": reps}
@@ -142,7 +155,7 @@ def measured_traffic(sub_kernel):
     summary (FETCH_SIZE and WRITE_SIZE runs scaled by a copy of known size),
     or None when the kernel source has changed since the counters were taken."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "k_sub_rtd32_hbm_bytes.md")
+    path = os.path.join(ROOT, "profiles", "k_sub_rtd256_hbm_bytes.md")
     try:
         line = [ln for ln in open(path) if ln.strip().startswith("{")][-1]
         rec = json.loads(line)
@@ -226,9 +239,9 @@ def copy_calibration(mib: int, reps: int):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--batch", type=int, default=32)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--batch", type=int, default=256)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-workers", type=int, default=min(16, os.cpu_count() or 1),
@@ -259,16 +272,19 @@ def main():
     opts = {"retire_satisfied": args.retire}
     if args.stale is not None:
         opts["stale_filter"] = args.stale
-    r64 = run_mode(pcba, insts, "fp64", args.steps, args.warmup, **opts)
+    # both precisions are created and warmed up before either is timed
+    p64 = warm(pcba, insts, "fp64", args.warmup, **opts)
+    opts32 = dict(opts)
     if args.rederive is not None:
-        opts["rederive_every"] = args.rederive
-    r32 = run_mode(pcba, insts, "fp32", args.steps, args.warmup, **opts)
+        opts32["rederive_every"] = args.rederive
+    p32 = warm(pcba, insts, "fp32", args.warmup, **opts32)
+    r64 = run_mode(pcba, p64, insts, "fp64", args.steps)
+    r32 = run_mode(pcba, p32, insts, "fp32", args.steps)
 
     single = None
     if args.single_reps > 0:
-        single = {"fp64_plain": single_plan(pcba, insts[0], "fp64", args.single_reps,
-                                            **{k: v for k, v in opts.items() if k != "rederive_every"}),
-                  "fp32": single_plan(pcba, insts[0], "fp32", args.single_reps, **opts)}
+        single = {"fp64_plain": single_plan(pcba, insts[0], "fp64", args.single_reps, **opts),
+                  "fp32": single_plan(pcba, insts[0], "fp32", args.single_reps, **opts32)}
 
     # parity of the two GPU paths on the last step (both provably within eps of f*)
     dp = max(abs(a["p_up"] - b["p_up"]) for a, b in zip(r32["results"], r64["results"])

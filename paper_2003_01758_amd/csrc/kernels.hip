@@ -353,14 +353,11 @@ __device__ __forceinline__ float round_up_f(double x)
 
 // ------------------------------------------------------------------ k_root
 
+// The problem of workgroup u: the host appends each workgroup's problem after
+// the prefix of workgroup counts (pre[n + 1 + u]), one load instead of a search.
 __device__ __forceinline__ int find_block(const int* __restrict__ pre, int n, int u)
 {
-    int lo = 0, hi = n;  // pre[lo] <= u < pre[hi]
-    while (hi - lo > 1) {
-        int mid = (lo + hi) >> 1;
-        if (pre[mid] <= u) lo = mid; else hi = mid;
-    }
-    return lo;
+    return pre[n + 1 + u];
 }
 
 __device__ __forceinline__ void poly_kind(const DevInst& I, int poly, int& kind, int& idx)

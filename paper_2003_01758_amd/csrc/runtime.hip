@@ -628,7 +628,8 @@ static size_t tm_words(const pcba_problem* P)
 }
 
 // Uploads the descriptors of probs and the prefix sum of their workgroup
-// counts (one per `per` polynomials) into `sc`; returns the total in *total.
+// counts (one per `per` polynomials) into `sc`, followed by each workgroup's
+// problem (pre[n + 1 + w]); returns the total in *total.
 static int upload_descs(pcba_problem* const* probs, int n, Scratch& sc, hipStream_t s,
                         DevInst** d_insts, int** d_pre, int* total, int* max_S, int* tmw, int per = 1)
 {
@@ -642,14 +643,16 @@ static int upload_descs(pcba_problem* const* probs, int n, Scratch& sc, hipStrea
         *max_S = std::max(*max_S, probs[b]->max_S);
         *tmw = std::max(*tmw, (int)tm_words(probs[b]));
     }
+    for (int b = 0; b < n; ++b)
+        for (int w = pre[b]; w < pre[b + 1]; ++w) pre.push_back(b);
     const size_t bytes_i = n * sizeof(DevInst);
     const size_t off_pre = (bytes_i + 255) / 256 * 256;
-    const size_t total_b = off_pre + (n + 1) * sizeof(int);
+    const size_t total_b = off_pre + pre.size() * sizeof(int);
     // the staging buffer may still feed an earlier copy on this stream
     HIP_TRY(hipStreamSynchronize(s));
     HIP_TRY(sc.ensure(total_b));
     memcpy(sc.hp, h.data(), bytes_i);
-    memcpy((char*)sc.hp + off_pre, pre.data(), (n + 1) * sizeof(int));
+    memcpy((char*)sc.hp + off_pre, pre.data(), pre.size() * sizeof(int));
     HIP_TRY(hipMemcpyAsync(sc.p, sc.hp, total_b, hipMemcpyHostToDevice, s));
     *d_insts = (DevInst*)sc.p;
     *d_pre = (int*)((char*)sc.p + off_pre);

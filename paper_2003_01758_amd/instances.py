@@ -233,7 +233,7 @@ def _obstacle_constraints(rng, l: int, deg: int, count: int, q0) -> list:
 
 
 def make_instance(config: int, index: int = 0, **overrides) -> Instance:
-    """Instance `index` of workload `config` (0..4), seeded PCG64(1_000_003*c + k)."""
+    """Instance `index` of workload `config` (0..5), seeded PCG64(1_000_003*c + k)."""
     rng = np.random.Generator(np.random.PCG64(SEED_STRIDE * config + index))
     if config == 0:
         l = 2
@@ -274,6 +274,27 @@ def make_instance(config: int, index: int = 0, **overrides) -> Instance:
         ineq = _obstacle_constraints(rng, l, deg, count, q0)
         inst = Instance("batch" if config == 3 else "serve", l, -np.ones(l), np.ones(l),
                         cost, ineq, [], max_boxes=1 << 20, q0=q0)
+    elif config == 5:
+        # a plan through waypoints (the multi-waypoint cost of Sec. V): the
+        # product over two waypoints x_n of the squared distance of the
+        # endpoint map e(q) (multi-degree (3,3) per component) from x_n, which
+        # has a minimum near each waypoint's preimage; 100 obstacle
+        # constraints (10,10) as in the rtd workload
+        l = 2
+        q0 = rng.uniform(-1.0, 1.0, size=l)
+        e = [_scaled_normal(rng, (4, 4), 1.5) for _ in range(2)]
+        cost = np.ones((1, 1))
+        for _ in range(2):
+            xn = rng.uniform(-2.0, 2.0, size=2)
+            d = np.zeros((7, 7))
+            for c in range(2):
+                ec = e[c].copy()
+                ec[0, 0] -= xn[c]
+                d += poly_mul(ec, ec)
+            cost = poly_mul(cost, d)
+        ineq = _obstacle_constraints(rng, l, 10, 100, q0)
+        inst = Instance("waypoints", l, -np.ones(l), np.ones(l), cost, ineq, [],
+                        max_boxes=1 << 20, q0=q0)
     else:
         raise ValueError(f"unknown workload {config}")
     if overrides:
