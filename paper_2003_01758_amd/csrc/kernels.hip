@@ -24,6 +24,23 @@ namespace pcba {
 
 // ------------------------------------------------------------------ small helpers
 
+// A device pointer taken from a descriptor is generic to the compiler, and its
+// loads and stores become FLAT instructions, which count on the LDS counter
+// as well: a later wait for an LDS read then also waits for them, and loads
+// issued early to overlap LDS work would complete before it.  Accesses
+// through this view of the pointer are plain global-memory instructions.
+template <typename T>
+using gmem_t = __attribute__((address_space(1))) T*;
+template <typename T>
+__device__ __forceinline__ gmem_t<T> as_global(T* p)
+{
+    return (gmem_t<T>)p;
+}
+// the HIP vector classes cannot be copied out of a global-memory lvalue: the
+// clang vector types of the same layout stand in for them
+typedef int vec2i __attribute__((ext_vector_type(2)));
+typedef int vec4i __attribute__((ext_vector_type(4)));
+
 __device__ __forceinline__ double wave_min(double v)
 {
     for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
@@ -304,12 +321,19 @@ __device__ __forceinline__ void transform_fibre_m(int m, double* x, int base, in
 // 2): every (chain, polynomial, fibre) of the run is one work item of the
 // block, whatever its kind, so that all lanes stay busy.  The run [pb, pe)
 // spans at most the three kinds, whose polynomial indices are contiguous
-// (c0 cost, then c1 inequalities, then equalities).  Each item applies mat0,
-// then mat1 if given, to its fibre in place.
+// (c0 cost, then c1 inequalities, then equalities).  Each item applies the
+// matrix at mats + mo.first[kind], then the one at mats + mo.second[kind] if
+// that offset is not negative, to its fibre in place.  The matrices are given
+// as offsets from the LDS array itself (not as pointers kept in a per-thread
+// array), so that every read of them compiles to an LDS instruction.
+struct MatOffs {
+    int first[KINDS], second[KINDS];
+};
 __device__ __forceinline__ void run_axis(double* slot, int slot_stride, int chain_off, int nchain, int pb,
                                          int pe, int c0, int c1, const AxisGeo (*geo)[MAXL], int r,
-                                         const double* const* mat0, const double* const* mat1)
+                                         const double* mats, const MatOffs& mo)
 {
+#pragma unroll
     for (int kind = 0; kind < KINDS; ++kind) {
         const int lo = kind == 0 ? 0 : (kind == 1 ? c0 : c0 + c1);
         const int hi = kind == 0 ? c0 : (kind == 1 ? c0 + c1 : INT_MAX);
@@ -320,6 +344,12 @@ __device__ __forceinline__ void run_axis(double* slot, int slot_stride, int chai
         g.m = ag.m;
         g.stride = ag.stride;
         g.F = ag.F;
+        // selects rather than an indexed read, which would place mo in scratch
+        const int o0 = kind == 0 ? mo.first[0] : (kind == 1 ? mo.first[1] : mo.first[2]);
+        const int o1 = kind == 0 ? mo.second[0] : (kind == 1 ? mo.second[1] : mo.second[2]);
+        const double* T0 = mats + o0;
+        const double* T1 = mats + o1;
+        const bool two = o1 >= 0;
         const int per = g.F * nchain;
         const int items = (q1 - q0) * per;
         for (int it = threadIdx.x; it < items; it += blockDim.x) {
@@ -327,8 +357,8 @@ __device__ __forceinline__ void run_axis(double* slot, int slot_stride, int chai
             const int ch = rem / g.F, f = rem - ch * g.F;
             double* x = slot + (q0 - pb + q) * slot_stride + ch * chain_off;
             const int base = fibre_base(g, f);
-            transform_fibre_m(g.m, x, base, g.stride, mat0[kind]);
-            if (mat1) transform_fibre_m(g.m, x, base, g.stride, mat1[kind]);
+            transform_fibre_m(g.m, x, base, g.stride, T0);
+            if (two) transform_fibre_m(g.m, x, base, g.stride, T1);
         }
     }
 }
@@ -415,7 +445,7 @@ __global__ __launch_bounds__(256) void k_root(const DevInst* __restrict__ insts,
                 const int e = e0 + k * blockDim.x;
                 dst[k] = -1;
                 if (e < nmat) {
-                    v[k] = I.mats[e];
+                    v[k] = as_global(I.mats)[e];
                     dst[k] = e;
                 } else if (e < total) {
                     const int q = (e - nmat) / max_S, i = (e - nmat) - q * max_S;
@@ -427,7 +457,7 @@ __global__ __launch_bounds__(256) void k_root(const DevInst* __restrict__ insts,
                     }
                     const int S = kind == 0 ? S0 : (kind == 1 ? S1 : S2);
                     if (i < S) {
-                        v[k] = I.mono[(kind == 0 ? o0 : (kind == 1 ? o1 : o2)) + (int64_t)idx * S + i];
+                        v[k] = as_global(I.mono)[(kind == 0 ? o0 : (kind == 1 ? o1 : o2)) + (int64_t)idx * S + i];
                         dst[k] = mat_words + q * max_S + i;
                     }
                 }
@@ -450,13 +480,12 @@ __global__ __launch_bounds__(256) void k_root(const DevInst* __restrict__ insts,
     }
     __syncthreads();
     for (int r = 0; r < l; ++r) {
-        const double* A[KINDS];
-        const double* U[KINDS];
+        MatOffs mo;
         for (int t = 0; t < KINDS; ++t) {
-            A[t] = mats + s_mo[t][r];
-            U[t] = A[t] + s_geo[t][r].m * s_geo[t][r].m;
+            mo.first[t] = s_mo[t][r];
+            mo.second[t] = s_mo[t][r] + s_geo[t][r].m * s_geo[t][r].m;
         }
-        run_axis(slot, max_S, 0, 1, pb, pe, c0, c1, s_geo, r, A, U);
+        run_axis(slot, max_S, 0, 1, pb, pe, c0, c1, s_geo, r, mats, mo);
         __syncthreads();
     }
     for (int p0 = pb; p0 < pe; p0 += nw) {
@@ -477,9 +506,10 @@ __global__ __launch_bounds__(256) void k_root(const DevInst* __restrict__ insts,
         const bool inheap = I.retire && kind == 1;
         void* dbase = inheap ? I.heap[0] : I.buf[0];
         const int64_t doff = inheap ? (int64_t)idx * S : I.soff[kind] + (int64_t)idx * S;
-        for (int e = lane; e < S; e += 64) I.root[off + e] = x[e];
+        if (I.root)   // the readback copy, written by the problem's first reset only
+            for (int e = lane; e < S; e += 64) as_global(I.root)[off + e] = x[e];
         if (!I.fp32) {
-            for (int e = lane; e < S; e += 64) ((double*)dbase)[doff + e] = x[e];
+            for (int e = lane; e < S; e += 64) as_global((double*)dbase)[doff + e] = x[e];
             if (lane == 0 && inheap) {
                 I.act[0][idx] = make_int2(idx, idx);
                 I.pmap[idx] = make_int4(0, 0, idx, idx);
@@ -876,33 +906,40 @@ __device__ __forceinline__ void patch_info(const DevInst& I, const PackUnit& c, 
 {
     const long long P = c.P0 + p;
     if (c.gath) {
-        const int4 m = I.pmap[P];
+        const vec4i m = ((gmem_t<const vec4i>)I.pmap)[P];
         inf = make_int4(m.x, m.y, m.z, 0);
         src = (long long)m.w * c.S;
         return;
     }
     const int cnt = c.kind == 0 ? 1 : I.count[c.kind];
     const int j = (int)(P / cnt), id = (int)(P - (long long)j * cnt);
-    const int slot = I.live[j];
+    const int slot = as_global(I.live)[j];
     inf = make_int4(j, slot, id, 0);
     src = (long long)slot * I.stride + I.soff[c.kind] + (long long)id * c.S;
 }
 
 // Issues the global loads of a tile into registers; the patches' source
-// offsets come from LDS.
+// offsets come from LDS.  The offsets are read first and the loads then issued
+// back to back; the buffer's address is made wave-uniform (it is), so no load
+// waits on the one before it.
 template <typename T, int LB>
 __device__ __forceinline__ void issue_packed(const DevInst& I, const PackUnit& c, const long long* src,
                                              T (&v)[LB])
 {
-    const T* base = (const T*)(c.gath ? I.heap[c.cur] : I.buf[c.cur]);
+    const unsigned long long bu = (unsigned long long)(c.gath ? I.heap[c.cur] : I.buf[c.cur]);
+    const unsigned blo = __builtin_amdgcn_readfirstlane((unsigned)bu);
+    const unsigned bhi = __builtin_amdgcn_readfirstlane((unsigned)(bu >> 32));
+    const gmem_t<const T> base = as_global((const T*)(((unsigned long long)bhi << 32) | blo));
+    long long o[LB];
 #pragma unroll
     for (int q = 0; q < LB; ++q) {
-        const int e = threadIdx.x + q * SUB_THREADS;
-        if (e < c.TE) {
-            const int p = patch_of(e, c.invS);
-            v[q] = base[src[p] + (e - p * c.S)];
-        }
+        const int e = min((int)threadIdx.x + q * SUB_THREADS, max(c.TE - 1, 0));
+        const int p = patch_of(e, c.invS);
+        o[q] = src[p] + (e - p * c.S);
     }
+#pragma unroll
+    for (int q = 0; q < LB; ++q)
+        if ((int)threadIdx.x + q * SUB_THREADS < c.TE) v[q] = base[o[q]];
 }
 
 // Exclusive scans over the workgroup of three counts per thread at once;
@@ -1017,13 +1054,13 @@ __global__ __launch_bounds__(SUB_THREADS) void k_sub(const DevInst* __restrict__
     T* La = (T*)carve((size_t)tem * sizeof(T));
     T* Lb = (T*)carve((size_t)tem * sizeof(T));
     K* Lkey = (K*)carve((size_t)5 * tpm * sizeof(K));
-    long long* Lsrc[2];
-    Lsrc[0] = (long long*)carve((size_t)tpm * 8);
-    Lsrc[1] = (long long*)carve((size_t)tpm * 8);
+    // the two patch tables (current and next tile) are chosen by selects, not
+    // by an indexed per-thread array, so that their accesses stay LDS ones
+    long long* Lsrc0 = (long long*)carve((size_t)tpm * 8);
+    long long* Lsrc1 = (long long*)carve((size_t)tpm * 8);
     T* Lshift = (T*)carve((size_t)2 * tpm * sizeof(T));
-    int4* Linf[2];
-    Linf[0] = (int4*)carve((size_t)tpm * 16);
-    Linf[1] = (int4*)carve((size_t)tpm * 16);
+    int4* Linf0 = (int4*)carve((size_t)tpm * 16);
+    int4* Linf1 = (int4*)carve((size_t)tpm * 16);
     int* Lwm = (int*)carve((size_t)tpm * 4);          // per patch: children to write (bit c)
     int* Lpre = (int*)carve((size_t)(2 * tpm + 2) * 4);  // per patch: scan of kept (child 0, child 1)
     int* Ldst = (int*)carve((size_t)2 * tpm * 4);     // per patch and child: heap patch or -1
@@ -1045,24 +1082,24 @@ __global__ __launch_bounds__(SUB_THREADS) void k_sub(const DevInst* __restrict__
         int4 inf;
         long long src;
         patch_info(insts[c.bi], c, tid, inf, src);
-        Linf[0][tid] = inf;
-        Lsrc[0][tid] = src;
+        Linf0[tid] = inf;
+        Lsrc0[tid] = src;
     }
     __syncthreads();
-    issue_packed<T, LB>(insts[c.bi], c, Lsrc[0], v);
+    issue_packed<T, LB>(insts[c.bi], c, Lsrc0, v);
     if (fp32 && tid < c.np) {
         const DevInst& I0 = insts[c.bi];
-        const int4 inf = Linf[0][tid];
+        const int4 inf = Linf0[tid];
         const int poly = c.kind == 0 ? 0 : I0.count[0] + (c.kind == 2 ? I0.count[1] : 0) + inf.z;
         const int64_t pi = (int64_t)inf.y * I0.n_polys + poly;
-        ce = I0.err[c.cur][pi];
-        cb = I0.base[c.cur][pi];
+        ce = as_global(I0.err[c.cur])[pi];
+        cb = as_global(I0.base[c.cur])[pi];
     }
 
     for (;;) {
         const DevInst& I = insts[c.bi];
         const int kind = c.kind, np = c.np, S = c.S, TE = c.TE, cur = c.cur, r = c.r, l = I.l;
-        const int4* inf = Linf[bufi];
+        const int4* inf = bufi ? Linf1 : Linf0;
         // current tile: registers -> LDS; keys and segment flags reset
 #pragma unroll
         for (int q = 0; q < LB; ++q) {
@@ -1091,19 +1128,19 @@ __global__ __launch_bounds__(SUB_THREADS) void k_sub(const DevInst* __restrict__
         tile_split<T, MM>(np, S, c.g, La, Lb, Lkey);
         // the next patch table to LDS (its loads had the split to arrive)
         if (more && tid < nc.np) {
-            Linf[bufi ^ 1][tid] = ninf;
-            Lsrc[bufi ^ 1][tid] = nsrc;
+            (bufi ? Linf0 : Linf1)[tid] = ninf;
+            (bufi ? Lsrc0 : Lsrc1)[tid] = nsrc;
         }
         lds_barrier();
         // next tile's coefficients (and FP32 error bounds and bases) in flight
         if (more) {
             const DevInst& In = insts[nc.bi];
-            issue_packed<T, LB>(In, nc, Lsrc[bufi ^ 1], v);
+            issue_packed<T, LB>(In, nc, bufi ? Lsrc0 : Lsrc1, v);
             if (fp32 && tid < nc.np) {
                 const int poly = nc.kind == 0 ? 0 : In.count[0] + (nc.kind == 2 ? In.count[1] : 0) + ninf.z;
                 const int64_t pi = (int64_t)ninf.y * In.n_polys + poly;
-                ne = In.err[nc.cur][pi];
-                nb = In.base[nc.cur][pi];
+                ne = as_global(In.err[nc.cur])[pi];
+                nb = as_global(In.base[nc.cur])[pi];
             }
         }
 
@@ -1137,9 +1174,9 @@ __global__ __launch_bounds__(SUB_THREADS) void k_sub(const DevInst* __restrict__
                     const float mc = 0.5f * mn + 0.5f * mx;
                     const double nbs = base + (double)mc;
                     const int64_t ci = (int64_t)(2 * j + ch) * I.n_polys + poly;
-                    I.err[cur ^ 1][ci] = round_up_f(e + ((double)mx - (double)mn) * 0x1p-23 +
-                                                    fabs(nbs) * 0x1p-52 + 0x1p-126);
-                    I.base[cur ^ 1][ci] = nbs;
+                    as_global(I.err[cur ^ 1])[ci] = round_up_f(e + ((double)mx - (double)mn) * 0x1p-23 +
+                                                               fabs(nbs) * 0x1p-52 + 0x1p-126);
+                    as_global(I.base[cur ^ 1])[ci] = nbs;
                     Lshift[ch * tpm + p] = (T)mc;
                 }
             }
@@ -1148,12 +1185,12 @@ __global__ __launch_bounds__(SUB_THREADS) void k_sub(const DevInst* __restrict__
                                 hi[ch]);
             if (kind == 0) {
                 // cost records, child ids, then the stamp that publishes the records
-                I.minP[2 * j] = lo[0];
-                I.maxP[2 * j] = hi[0];
-                I.minP[2 * j + 1] = lo[1];
-                I.maxP[2 * j + 1] = hi[1];
-                const uint32_t* pid = I.ids[cur] + (int64_t)slot * l;
-                uint32_t* cid = I.ids[cur ^ 1] + (int64_t)(2 * j) * l;
+                as_global(I.minP)[2 * j] = lo[0];
+                as_global(I.maxP)[2 * j] = hi[0];
+                as_global(I.minP)[2 * j + 1] = lo[1];
+                as_global(I.maxP)[2 * j + 1] = hi[1];
+                const gmem_t<const uint32_t> pid = as_global((const uint32_t*)I.ids[cur]) + (int64_t)slot * l;
+                const gmem_t<uint32_t> cid = as_global(I.ids[cur ^ 1]) + (int64_t)(2 * j) * l;
                 for (int k = 0; k < l; ++k) {
                     const uint32_t vv = pid[k];
                     cid[k] = (k == r) ? 2u * vv : vv;
@@ -1239,7 +1276,7 @@ __global__ __launch_bounds__(SUB_THREADS) void k_sub(const DevInst* __restrict__
                 Lwm[p] = wm;
             }
             lds_barrier();
-            T* dbuf = (T*)I.buf[cur ^ 1];
+            const gmem_t<T> dbuf = as_global((T*)I.buf[cur ^ 1]);
             constexpr int SB = 8;
             for (int e0 = tid; e0 < TE; e0 += SB * SUB_THREADS) {
                 T va[SB], vb[SB];
@@ -1285,15 +1322,18 @@ __global__ __launch_bounds__(SUB_THREADS) void k_sub(const DevInst* __restrict__
                     if (ch ? k1 : k0) {
                         const int rank = Lpre[2 * p + ch] - Lpre[2 * sp + ch];
                         d = (int)(hb + (ch ? tot.y + ex.z : ex.y));
-                        I.act[cur ^ 1][(int64_t)(2 * j + ch) * I.count[1] + Lpos[2 * seg + ch] + rank] =
-                            make_int2(id, d);
+                        vec2i a;
+                        a.x = id;
+                        a.y = d;
+                        ((gmem_t<vec2i>)I.act[cur ^ 1])[(int64_t)(2 * j + ch) * I.count[1] + Lpos[2 * seg + ch] +
+                                                        rank] = a;
                     }
                     Ldst[ch * tpm + p] = d;
                 }
             }
             lds_barrier();
             // each kept patch to its heap patch
-            T* hc = (T*)I.heap[cur ^ 1];
+            const gmem_t<T> hc = as_global((T*)I.heap[cur ^ 1]);
 #pragma unroll 2
             for (int e = tid; e < TE; e += SUB_THREADS) {
                 const int pq = patch_of(e, c.invS);
@@ -1633,10 +1673,10 @@ __global__ __launch_bounds__(CUT_THREADS) void k_cut(const DevInst* __restrict__
         cfl[q] = F_INFEAS;
         cna[q] = 0;
         if (c < C) {
-            cmn[q] = I.minP[c];
-            cmx[q] = I.maxP[c];
-            cfl[q] = I.flags[c];
-            if (ret) cna[q] = I.na[cur ^ 1][c];
+            cmn[q] = as_global(I.minP)[c];
+            cmx[q] = as_global(I.maxP)[c];
+            cfl[q] = as_global(I.flags)[c];
+            if (ret) cna[q] = as_global(I.na[cur ^ 1])[c];
         }
     }
 
@@ -1727,11 +1767,18 @@ __global__ __launch_bounds__(CUT_THREADS) void k_cut(const DevInst* __restrict__
         const int jn = base + wsum[w] + before;
         const long long exl = ai - ak;   // this lane's patches before it in the wave
         if (keep) {
-            I.live[jn] = c;
+            as_global(I.live)[jn] = c;
             if (ret) {
                 const long long u0 = ubase + wun[w] + ui - ti;
-                I.upre[jn] = u0;
-                for (int q = 0; q < (int)ti; ++q) I.umap[u0 + q] = make_int4(jn, c, q, a);
+                as_global(I.upre)[jn] = u0;
+                for (int q = 0; q < (int)ti; ++q) {
+                    vec4i um;
+                    um.x = jn;
+                    um.y = c;
+                    um.z = q;
+                    um.w = a;
+                    ((gmem_t<vec4i>)I.umap)[u0 + q] = um;
+                }
             }
         }
         if (ret) {
@@ -1747,7 +1794,7 @@ __global__ __launch_bounds__(CUT_THREADS) void k_cut(const DevInst* __restrict__
             const int kc = wsum[nw];
             const int ctot = (int)wap[nw];
             for (int e0 = tid; e0 < ctot; e0 += 4 * bd) {
-                int2 got[4];
+                vec2i got[4];
                 int dst[4], jk[4], ck[4];
 #pragma unroll
                 for (int h = 0; h < 4; ++h) {
@@ -1761,13 +1808,21 @@ __global__ __launch_bounds__(CUT_THREADS) void k_cut(const DevInst* __restrict__
                         }
                         ck[h] = s_kc[lo];
                         jk[h] = base + lo;
-                        got[h] = I.act[cur ^ 1][(int64_t)ck[h] * I.count[1] + (e - s_ka[lo])];
+                        got[h] = ((gmem_t<const vec2i>)I.act[cur ^ 1])[(int64_t)ck[h] * I.count[1] +
+                                                                        (e - s_ka[lo])];
                         dst[h] = e;
                     }
                 }
 #pragma unroll
                 for (int h = 0; h < 4; ++h)
-                    if (dst[h] >= 0) I.pmap[abase + dst[h]] = make_int4(jk[h], ck[h], got[h].x, got[h].y);
+                    if (dst[h] >= 0) {
+                        vec4i pm;
+                        pm.x = jk[h];
+                        pm.y = ck[h];
+                        pm.z = got[h].x;
+                        pm.w = got[h].y;
+                        ((gmem_t<vec4i>)I.pmap)[abase + dst[h]] = pm;
+                    }
             }
         }
         base += wsum[nw];
@@ -1786,9 +1841,9 @@ __global__ __launch_bounds__(CUT_THREADS) void k_cut(const DevInst* __restrict__
         uint32_t fl = F_INFEAS;
         int a = 0;
         if (c < C) {
-            mnp = I.minP[c];
-            fl = I.flags[c];
-            if (ret) a = I.na[cur ^ 1][c];
+            mnp = as_global(I.minP)[c];
+            fl = as_global(I.flags)[c];
+            if (ret) a = as_global(I.na[cur ^ 1])[c];
         }
         chunk(c0, mnp, fl, a);
     }
@@ -1813,8 +1868,8 @@ __global__ __launch_bounds__(CUT_THREADS) void k_cut(const DevInst* __restrict__
     // clear the flags of the next step's children, and in retiring mode their
     // carried counts (they go to the buffer of this step's parents)
     for (int c = tid; c < 2 * Kn && c < I.cap; c += blockDim.x) {
-        I.flags[c] = 0;
-        if (I.retire) I.na[cur][c] = 0;
+        as_global(I.flags)[c] = 0;
+        if (I.retire) as_global(I.na[cur])[c] = 0;
     }
 
     // per axis (thread k): its depth, and x*'s box if the estimate moved
@@ -1925,7 +1980,7 @@ __global__ __launch_bounds__(256) void k_certify(const DevInst* __restrict__ ins
                     }
                     const int S = kind == 0 ? S0 : (kind == 1 ? S1 : S2);
                     if (i < S) {
-                        v[k] = I.racc[(kind == 0 ? o0 : (kind == 1 ? o1 : o2)) + (int64_t)poly * S + i];
+                        v[k] = as_global(I.racc)[(kind == 0 ? o0 : (kind == 1 ? o1 : o2)) + (int64_t)poly * S + i];
                         dst[k] = 2 * q * max_S + i;
                     }
                 }
@@ -1988,9 +2043,12 @@ __global__ __launch_bounds__(256) void k_certify(const DevInst* __restrict__ ins
     }
     __syncthreads();
     for (int r = 0; r < l; ++r) {
-        const double* Tm[KINDS];
-        for (int t = 0; t < KINDS; ++t) Tm[t] = tm + (t * l + r) * mm2;
-        run_axis(slot, 2 * max_S, max_S, 2, pb, pe, c0, c1, s_geo, r, Tm, nullptr);
+        MatOffs mo;
+        for (int t = 0; t < KINDS; ++t) {
+            mo.first[t] = (t * l + r) * mm2;
+            mo.second[t] = -1;
+        }
+        run_axis(slot, 2 * max_S, max_S, 2, pb, pe, c0, c1, s_geo, r, tm, mo);
         __syncthreads();
     }
     for (int p0 = pb; p0 < pe; p0 += nw) {

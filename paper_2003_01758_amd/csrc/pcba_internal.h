@@ -145,7 +145,8 @@ struct DevInst {
     int32_t tmk[KINDS];            // offset of each kind's transforms inside a child's block
     int32_t rows;                  // transform rows per child: sum over kinds and axes of m
     double* root;                  // FP64 root patches (item layout, W doubles), converted in
-                                   // two stages per axis (pre-map, then basis change)
+                                   // two stages per axis (pre-map, then basis change): a
+                                   // readback copy, null after the problem's first reset
     double* racc;                  // the same patches converted in one stage per axis with
                                    // the combined matrices (an accurate root)
     double* root_err;              // rigorous bound on |racc - exact| per patch

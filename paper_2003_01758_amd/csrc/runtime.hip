@@ -186,6 +186,7 @@ struct pcba_problem {
     double t_start = 0.0;
     int64_t footprint = 0;   // bytes charged by an engine
     bool list_released = false;  // finished, and its list freed for other problems
+    bool root_written = false;   // d_root holds the root patches (written by the first reset)
     int host_steps = 0;      // steps known on the host (for re-derivation planning)
 };
 
@@ -364,7 +365,7 @@ static DevInst make_dev(const pcba_problem* P)
     I.tmw = P->tmw;
     I.rows = P->rows;
     for (int t = 0; t < KINDS; ++t) I.tmk[t] = P->tmk[t];
-    I.root = P->d_root;
+    I.root = P->root_written ? nullptr : P->d_root;
     I.root_err = P->d_root_err;
     I.root_abs = P->d_root_err + P->n_polys;
     I.racc = P->d_racc;
@@ -700,6 +701,7 @@ static int reset_batch(pcba_problem* const* probs, int n, hipStream_t s)
     if (rc != PCBA_OK) return rc;
     HIP_TRY(launch_reset_root(d_insts, n, d_pre, total, max_S, tmw, ppb, s));
     HIP_TRY(hipStreamSynchronize(s));   // the host descriptors above are pageable
+    for (int b = 0; b < n; ++b) probs[b]->root_written = true;
     for (int b = 0; b < n; ++b) {
         pcba_problem* P = probs[b];
         InstState st0;
