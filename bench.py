@@ -7,8 +7,9 @@ multi-degree (10,10); eps 1e-3, delta 1e-4, M 2^20, N 28), seeded synthetic
 instances.  One step = every problem of the batch solved from its root item to
 a certified outcome: root conversion on the device, then memory test,
 subdivision + bounds, cut-off test + compaction, stopping tests, FP64
-certification.  Inputs are resident in device memory when the timed region
-starts (pcba_reset recomputes the root patches from the resident monomials).
+certification, then every plan's result record copied into one host array.
+Inputs are resident in device memory when the timed region starts
+(pcba_reset recomputes the root patches from the resident monomials).
 
 Prints one JSON line: certified solves/s of the better of the FP32 path
 (rigorously widened bounds, FP64 certification) and the plain FP64 path, with
@@ -40,6 +41,12 @@ def log(*a):
 
 def certified(r, pcba):
     return (r["outcome"] == pcba.OPTIMAL and r["certified"]) or r["outcome"] == pcba.INFEASIBLE
+
+
+def count_certified(res, pcba):
+    """certified() over a structured result array."""
+    ok = ((res["outcome"] == pcba.OPTIMAL) & (res["certified"] != 0)) | (res["outcome"] == pcba.INFEASIBLE)
+    return int(np.count_nonzero(ok))
 
 
 def patch_words(inst):
@@ -85,16 +92,19 @@ def run_mode(pcba, probs, insts, precision, steps):
     per-kernel times and the roofline of the subdivide+bound kernel."""
     lat, cert, results = [], 0, []
     elapsed = 0.0
-    # the timed solves measure the library: no Python garbage collection inside
+    # the timed solves measure the library: no Python garbage collection
+    # inside, the handle array built once, and every plan's result copied
+    # into one host array by a single call (pcba_result_batch)
+    batch = pcba.Batch(probs)
     gc.collect()
     gc.disable()
     for s in range(steps):
         t0 = time.perf_counter()
-        pcba.reset_batch(probs)
-        res = pcba.solve_batch(probs)
+        pcba.reset_batch(batch)
+        res = pcba.solve_batch(batch, as_array=True)
         elapsed += time.perf_counter() - t0
-        lat += [r["seconds"] for r in res]
-        cert += sum(1 for r in res if certified(r, pcba))
+        lat += res["seconds"].tolist()
+        cert += count_certified(res, pcba)
         results = res
         log(f"[bench] {precision} step {s + 1}/{steps}: {elapsed * 1e3 / (s + 1):.2f} ms/step")
     gc.enable()
@@ -106,8 +116,8 @@ def run_mode(pcba, probs, insts, precision, steps):
     prof_elapsed = 0.0
     for s in range(steps):
         t0 = time.perf_counter()
-        pcba.reset_batch(probs)
-        pcba.solve_batch(probs)
+        pcba.reset_batch(batch)
+        pcba.solve_batch(batch, as_array=True)
         prof_elapsed += time.perf_counter() - t0
         for p, i in zip(probs, insts):
             bytes_sub += algorithmic_bytes(p, i, precision)

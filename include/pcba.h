@@ -151,6 +151,10 @@ int pcba_solve_batch(pcba_problem* const* probs, int32_t n, void* stream);
 
 /* Copies the outcome and statistics of the last solve into *out (host). */
 int pcba_result(const pcba_problem* prob, pcba_result_t* out);
+/* pcba_result for n problems at once: out[b] (host array of n records) gets
+ * the result of probs[b].  Reads host-side state only (no device call).
+ * Returns PCBA_E_ARG, with out untouched, if any pointer is NULL or n < 0. */
+int pcba_result_batch(const pcba_problem* const* probs, int32_t n, pcba_result_t* out);
 
 /* Current list: length, then ids (host, len*l uint32: index per axis) and the
  * patches converted to FP64 (host, len*words doubles; words = pcba_patch_words).

@@ -2312,8 +2312,9 @@ hipError_t launch_rederive(const DevInst* d_insts, int n, const long long* plan,
 hipError_t launch_cut(const DevInst* d_insts, int n, int64_t max_children, hipStream_t s)
 {
     // short lists: four waves walk the children in a few passes with cheaper
-    // barriers; long ones take the full workgroup
-    const int threads = max_children <= 4096 ? 256 : CUT_THREADS;
+    // barriers; longer ones take eight waves (fewer passes, the carried-patch
+    // copy twice as wide), the longest the full workgroup
+    const int threads = max_children <= 1024 ? 256 : (max_children <= 8192 ? 512 : CUT_THREADS);
     hipLaunchKernelGGL(k_cut, dim3(n), dim3(threads), 0, s, d_insts, n);
     return hipGetLastError();
 }

@@ -1492,6 +1492,18 @@ int pcba_result(const pcba_problem* P, pcba_result_t* out)
     return PCBA_OK;
 }
 
+int pcba_result_batch(const pcba_problem* const* probs, int32_t n, pcba_result_t* out)
+{
+    if (n < 0 || (n > 0 && (!probs || !out))) return fail(PCBA_E_ARG, "NULL argument or n < 0");
+    for (int32_t b = 0; b < n; ++b)
+        if (!probs[b]) return fail(PCBA_E_ARG, "NULL problem in the batch");
+    for (int32_t b = 0; b < n; ++b) {
+        const int rc = pcba_result(probs[b], &out[b]);
+        if (rc != PCBA_OK) return rc;
+    }
+    return PCBA_OK;
+}
+
 int pcba_list_size(const pcba_problem* P, int64_t* len)
 {
     if (!P || !len) return fail(PCBA_E_ARG, "NULL argument");

@@ -75,6 +75,8 @@ def lib():
         L.pcba_solve_batch.restype = C.c_int
         L.pcba_result.argtypes = [vp, C.POINTER(Result)]
         L.pcba_result.restype = C.c_int
+        L.pcba_result_batch.argtypes = [C.POINTER(vp), i32, vp]
+        L.pcba_result_batch.restype = C.c_int
         L.pcba_list_size.argtypes = [vp, C.POINTER(i64)]
         L.pcba_list_size.restype = C.c_int
         L.pcba_read_list.argtypes = [vp, vp, vp, i64]
@@ -289,14 +291,49 @@ def profile_read() -> dict:
     return {k: (float(ms[i]), int(n[i])) for i, k in enumerate(KERNELS)}
 
 
+RESULT_DTYPE = np.dtype(Result)
+
+
+class Batch:
+    """A fixed sequence of problems whose handle array is built once, for
+    repeated batch calls (reset_batch, solve_batch and results accept it in
+    place of a list)."""
+
+    def __init__(self, problems):
+        self.problems = list(problems)
+        self.handles = (C.c_void_p * len(self.problems))(*[p.h for p in self.problems])
+
+    def __len__(self):
+        return len(self.problems)
+
+    def __iter__(self):
+        return iter(self.problems)
+
+
+def _handles(problems):
+    if isinstance(problems, Batch):
+        return problems.handles
+    return (C.c_void_p * len(problems))(*[p.h for p in problems])
+
+
 def reset_batch(problems, stream=None):
-    arr = (C.c_void_p * len(problems))(*[p.h for p in problems])
-    _check(lib().pcba_reset_batch(arr, len(problems), _stream_ptr(stream)))
+    _check(lib().pcba_reset_batch(_handles(problems), len(problems), _stream_ptr(stream)))
 
 
-def solve_batch(problems, stream=None):
-    arr = (C.c_void_p * len(problems))(*[p.h for p in problems])
-    _check(lib().pcba_solve_batch(arr, len(problems), _stream_ptr(stream)))
+def results(problems) -> np.ndarray:
+    """The results of the problems' last solves in one call, as a structured
+    array with the fields of pcba_result_t (record b belongs to problem b)."""
+    out = np.zeros(len(problems), dtype=RESULT_DTYPE)
+    _check(lib().pcba_result_batch(_handles(problems), len(problems), out.ctypes.data))
+    return out
+
+
+def solve_batch(problems, stream=None, as_array=False):
+    """Solves the problems together.  Returns one dict per problem (as
+    Problem.result), or with as_array the structured array of `results`."""
+    _check(lib().pcba_solve_batch(_handles(problems), len(problems), _stream_ptr(stream)))
+    if as_array:
+        return results(problems)
     return [p.result() for p in problems]
 
 

@@ -74,3 +74,17 @@ def test_default_options_and_argument_validation_without_device():
                                np.ones(34).ctypes.data, 0, None, None, 0, None, None, None,
                                ctypes.byref(h))
     assert rc == pcba.E_ARG
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_result_batch_argument_checks_without_device():
+    from paper_2003_01758_amd import pcba
+    L = pcba.lib()
+    out = (pcba.Result * 2)()
+    assert L.pcba_result_batch(None, 2, ctypes.addressof(out)) == pcba.E_ARG
+    arr = (ctypes.c_void_p * 2)(None, None)
+    assert L.pcba_result_batch(arr, 2, ctypes.addressof(out)) == pcba.E_ARG
+    assert L.pcba_result_batch(arr, -1, ctypes.addressof(out)) == pcba.E_ARG
+    assert L.pcba_result_batch(arr, 0, None) == 0
+    # the record layout the binding's structured array uses is the C one
+    assert pcba.RESULT_DTYPE.itemsize == ctypes.sizeof(pcba.Result)

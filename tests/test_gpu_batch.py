@@ -47,7 +47,16 @@ def _solve(gpu, insts, precision):
     probs = [gpu.Problem(i, precision=precision) for i in insts]
     print(f"[c3] {precision}: {len(probs)} problems created in {time.perf_counter() - t0:.1f} s", flush=True)
     t0 = time.perf_counter()
-    res = gpu.solve_batch(probs)
+    batch = gpu.Batch(probs)
+    res = gpu.solve_batch(batch)
+    # the one-call result array (pcba_result_batch) holds the same records
+    arr = gpu.results(batch)
+    for r, a in zip(res, arr):
+        for k in ("outcome", "has_x", "p_up", "p_lo", "steps", "rounds", "list_len", "peak_len",
+                  "certified", "p_cert", "seconds", "capacity"):
+            assert r[k] == a[k] or (np.isnan(r[k]) and np.isnan(a[k])), k
+        l = len(r["x_lo"])
+        assert np.array_equal(r["x_lo"], a["x_lo"][:l]) and np.array_equal(r["x_index"], a["x_index"][:l])
     for p in probs:
         p.close()
     print(f"[c3] {precision}: solved in {time.perf_counter() - t0:.1f} s", flush=True)
