@@ -122,20 +122,45 @@ __device__ __forceinline__ void signal_host(const DevInst& I)
 //   class 2: FP32 problems whose step re-derives the children from the root
 //   class 3: the transform rows of those problems (k_tmat, one thread per row)
 // plan[c*(n+1) + b] = first unit of problem b in class c; plan[c*(n+1) + n] = total.
-__device__ __forceinline__ int unit_class(const DevInst& I, const InstState* st)
+// What a step's plan reads of a problem's state, loaded at once (the fields
+// share the state's first cache line) through a global-memory view.
+struct PlanState {
+    int32_t status, K, steps, cur, r;
+    uint32_t epoch;
+    double p_up;
+    int64_t peak, u1, a_live;
+};
+__device__ __forceinline__ PlanState load_plan_state(const InstState* st)
+{
+    const gmem_t<const InstState> g = as_global(st);
+    PlanState ps;
+    ps.status = g->status;
+    ps.K = g->K;
+    ps.steps = g->steps;
+    ps.cur = g->cur;
+    ps.r = g->r;
+    ps.epoch = g->epoch;
+    ps.p_up = g->p_up;
+    ps.peak = g->peak;
+    ps.u1 = g->u1;
+    ps.a_live = g->a_live;
+    return ps;
+}
+
+__device__ __forceinline__ int unit_class(const DevInst& I, const PlanState& st)
 {
     if (!I.fp32) return 0;
-    const bool due = I.rederive > 0 && ((st->steps + 1) % I.rederive) == 0;
+    const bool due = I.rederive > 0 && ((st.steps + 1) % I.rederive) == 0;
     return due ? 2 : 1;
 }
 
 // Tiles of k_sub in one step of a problem: the cost patches, the equality
 // patches, then the inequality patches of all parents (all of them, or in
 // retiring mode the carried ones), each cut into tiles of ptp[kind] patches.
-__device__ __forceinline__ long long step_tiles(const DevInst& I, const InstState* st)
+__device__ __forceinline__ long long step_tiles(const DevInst& I, const PlanState& st)
 {
-    const long long K = st->K;
-    const long long A = I.retire ? st->a_live : K * I.count[1];
+    const long long K = st.K;
+    const long long A = I.retire ? st.a_live : K * I.count[1];
     return (K + I.ptp[0] - 1) / I.ptp[0] + (K * I.count[2] + I.ptp[2] - 1) / I.ptp[2] +
            (A + I.ptp[1] - 1) / I.ptp[1];
 }
@@ -143,11 +168,11 @@ __device__ __forceinline__ long long step_tiles(const DevInst& I, const InstStat
 // Units of one FP32 re-derivation step of a problem: every parent has one cost
 // tile and its equality tiles; its inequality tiles are all of them, or in
 // retiring mode as many as the inequalities it still carries need (their sum
-// is st->u1).
-__device__ __forceinline__ long long step_units(const DevInst& I, const InstState* st)
+// is the state's u1).
+__device__ __forceinline__ long long step_units(const DevInst& I, const PlanState& st)
 {
     const int T1 = I.tile_start[2] - I.tile_start[1];
-    return I.retire ? (long long)st->K * (I.T - T1) + st->u1 : (long long)st->K * I.T;
+    return I.retire ? (long long)st.K * (I.T - T1) + st.u1 : (long long)st.K * I.T;
 }
 
 // One problem's share of a step's plan: its units per class (v) and the
@@ -159,34 +184,35 @@ __device__ __forceinline__ long long step_units(const DevInst& I, const InstStat
 // same state (a status already moved off RUNNING gives no units either).
 __device__ __forceinline__ void plan_one(const DevInst& I, bool commit, long long (&v)[4], StepInfo& si)
 {
-    InstState* st = I.st;
+    const PlanState ps = load_plan_state(I.st);
+    const gmem_t<InstState> st = as_global(I.st);
     v[0] = v[1] = v[2] = v[3] = 0;
-    const int K = st->K;
-    if (st->status == ST_RUNNING) {
-        if (commit && (int64_t)K > st->peak) st->peak = K;
+    const int K = ps.K;
+    if (ps.status == ST_RUNNING) {
+        if (commit && (int64_t)K > ps.peak) st->peak = K;
         if (2LL * K > (int64_t)I.M) {
             if (commit) {
                 st->status = ST_MEMLIMIT;
                 signal_host(I);
             }
-        } else if (2LL * K > (int64_t)I.cap || (I.retire && 2 * st->a_live > I.hcap)) {
+        } else if (2LL * K > (int64_t)I.cap || (I.retire && 2 * ps.a_live > I.hcap)) {
             if (commit) {
                 st->status = ST_GROW;
                 signal_host(I);
             }
         } else {
-            const int c = unit_class(I, st);
-            v[c] = c == 2 ? step_units(I, st) : step_tiles(I, st);
+            const int c = unit_class(I, ps);
+            v[c] = c == 2 ? step_units(I, ps) : step_tiles(I, ps);
             if (c == 2) v[3] = (long long)K * 2 * I.rows;
         }
     }
     si.K = K;
-    si.cur = st->cur;
-    si.r = st->r;
-    si.steps = st->steps;
-    si.p_up = st->p_up;
-    si.stamp = step_stamp(st);
-    si.A = (int)st->a_live;
+    si.cur = ps.cur;
+    si.r = ps.r;
+    si.steps = ps.steps;
+    si.p_up = ps.p_up;
+    si.stamp = ps.epoch * 65536u + (uint32_t)ps.steps + 1u;   // step_stamp of the state
+    si.A = (int)ps.a_live;
 }
 
 __global__ __launch_bounds__(1024) void k_plan(const DevInst* __restrict__ insts, int n,

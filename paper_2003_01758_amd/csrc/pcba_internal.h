@@ -46,6 +46,8 @@ enum : int32_t {
 
 // Device-resident solver state of one problem (written by the cut kernel).
 struct InstState {
+    // what a step's plan reads (every subdivision workgroup reads it for every
+    // problem): kept within the first 128 bytes
     int32_t status;
     int32_t K;          // live parents
     int32_t r;          // direction of the next split (0-based)
@@ -55,17 +57,17 @@ struct InstState {
     int32_t has_x;
     int32_t cert_ok;
     double p_up, p_lo;
-    int32_t depth[MAXL];
-    uint32_t x_index[MAXL];
-    int32_t x_depth[MAXL];
     int64_t peak;
-    double p_cert, cert_err;
-    double err_max;
     uint32_t epoch;     // incremented by every reset: makes record stamps unique per solve
     uint32_t pad1;
     int64_t u1;         // retiring mode: inequality units of the next step (sum of tiles)
     int64_t a_live;     // inequality patches carried by the live parents
     int64_t htop[2];    // retiring mode: patches appended to each buffer's heap
+    int32_t depth[MAXL];
+    uint32_t x_index[MAXL];
+    int32_t x_depth[MAXL];
+    double p_cert, cert_err;
+    double err_max;
 };
 
 // What the step kernels need of a problem's state, published by the plan
@@ -96,7 +98,6 @@ struct TraceRec {
 // Read-only description of one problem for a launch.
 struct DevInst {
     int32_t l, n_polys, T, fp32;
-    int32_t dims[KINDS][MAXL];     // fibre length (degree + 1) per axis and kind
     int32_t S[KINDS];              // coefficients per patch of each kind
     int32_t count[KINDS];          // 1, alpha, beta
     int32_t tile_polys[KINDS];     // patches per tile of an item (re-derivation units)
@@ -112,6 +113,12 @@ struct DevInst {
     int32_t stale;                 // stale-estimate write filter on
     int32_t rederive;              // FP32: re-derive from the FP64 root every this many steps
     int32_t retire;                // retire inequalities certified satisfied on a box
+    int32_t rows;                  // transform rows per child: sum over kinds and axes of m
+    int32_t pad0;
+    int64_t hcap;                  // patches each heap holds
+    InstState* st;                 // the fields from T to here are what a step's plan reads
+    int* hostflag;                 // engine's pinned host word: set when the problem stops running
+    int32_t dims[KINDS][MAXL];     // fibre length (degree + 1) per axis and kind
     double eps, delta, eps_eq;
     double width0[MAXL];           // hi - lo of D
     void* buf[2];                  // item buffers (double or float), cap * stride each
@@ -132,9 +139,7 @@ struct DevInst {
     int2* act[2];
     int32_t* na[2];
     void* heap[2];
-    int64_t hcap;                  // patches each heap holds
     int64_t* upre;                 // cap + 1: first inequality unit of each live item, then the total
-    int* hostflag;                 // engine's pinned host word: set when the problem stops running
     int4* umap;                    // hcap entries: re-derivation inequality unit v of the step ->
                                    // (parent, its slot, tile of its carried list, carried count)
     int4* pmap;                    // hcap entries: carried inequality patch P of the step, in parent
@@ -143,7 +148,6 @@ struct DevInst {
     double* tmat;                  // FP32 re-derivation: cap/2 parents x 2 children x tmw doubles
     int32_t tmw;                   // transform words per child: sum over kinds and axes of m^2
     int32_t tmk[KINDS];            // offset of each kind's transforms inside a child's block
-    int32_t rows;                  // transform rows per child: sum over kinds and axes of m
     double* root;                  // FP64 root patches (item layout, W doubles), converted in
                                    // two stages per axis (pre-map, then basis change): a
                                    // readback copy, null after the problem's first reset
@@ -157,8 +161,11 @@ struct DevInst {
     const double* mats;            // per kind and axis: pre-map A then conversion U (m x m each)
     const double* macc;            // per kind and axis: combined matrix M then |terms| bound Mabs
     const int* matoff;             // KINDS * MAXL offsets into mats
-    InstState* st;
+    // padding to a multiple of 128 bytes: in a device array (256-byte aligned)
+    // every problem's plan fields (the first 192 bytes) then span two cache lines
+    char pad_end[112];
 };
+static_assert(sizeof(DevInst) % 128 == 0, "DevInst: keep the size a multiple of 128 bytes");
 
 // ordered integer keys: key(a) < key(b) iff a < b (non-NaN), so min/max of
 // floating values can use integer atomics
