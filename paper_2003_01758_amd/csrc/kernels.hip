@@ -1038,6 +1038,8 @@ __global__ __launch_bounds__(SUB_THREADS) void k_sub(const DevInst* __restrict__
         long long x[4];
         for (int c = 0; c < 4; ++c) {
             x[c] = v[c];
+            // a workgroup that does not commit needs its own class's scan only
+            if (!commit && c != cls) continue;
             for (int o = 1; o < 64; o <<= 1) {
                 const long long y = __shfl_up(x[c], o, 64);
                 if (lane >= o) x[c] += y;

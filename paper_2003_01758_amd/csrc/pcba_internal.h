@@ -97,16 +97,11 @@ struct TraceRec {
 
 // Read-only description of one problem for a launch.
 struct DevInst {
+    // what a step's plan reads, in the first 128 bytes (one cache line)
     int32_t l, n_polys, T, fp32;
-    int32_t S[KINDS];              // coefficients per patch of each kind
     int32_t count[KINDS];          // 1, alpha, beta
-    int32_t tile_polys[KINDS];     // patches per tile of an item (re-derivation units)
     int32_t ptp[KINDS];            // patches per k_sub tile (tiles span parents)
     int32_t tile_start[KINDS + 1]; // first tile of each kind; tile_start[KINDS] = T
-    int64_t off[KINDS];            // element offset of each kind inside an item (root layout)
-    int64_t soff[KINDS];           // the same inside a list slot (retiring mode keeps the
-                                   // inequalities out of the slots, in the heaps)
-    int64_t stride;                // elements per item slot
     int32_t M;                     // memory-test bound
     int32_t cap;                   // slots per buffer
     int32_t N;                     // iteration cap
@@ -116,8 +111,15 @@ struct DevInst {
     int32_t rows;                  // transform rows per child: sum over kinds and axes of m
     int32_t pad0;
     int64_t hcap;                  // patches each heap holds
-    InstState* st;                 // the fields from T to here are what a step's plan reads
+    InstState* st;
     int* hostflag;                 // engine's pinned host word: set when the problem stops running
+    // the rest
+    int32_t S[KINDS];              // coefficients per patch of each kind
+    int32_t tile_polys[KINDS];     // patches per tile of an item (re-derivation units)
+    int64_t off[KINDS];            // element offset of each kind inside an item (root layout)
+    int64_t soff[KINDS];           // the same inside a list slot (retiring mode keeps the
+                                   // inequalities out of the slots, in the heaps)
+    int64_t stride;                // elements per item slot
     int32_t dims[KINDS][MAXL];     // fibre length (degree + 1) per axis and kind
     double eps, delta, eps_eq;
     double width0[MAXL];           // hi - lo of D
@@ -162,7 +164,7 @@ struct DevInst {
     const double* macc;            // per kind and axis: combined matrix M then |terms| bound Mabs
     const int* matoff;             // KINDS * MAXL offsets into mats
     // padding to a multiple of 128 bytes: in a device array (256-byte aligned)
-    // every problem's plan fields (the first 192 bytes) then span two cache lines
+    // every problem's plan fields (the first 112 bytes) then share one cache line
     char pad_end[112];
 };
 static_assert(sizeof(DevInst) % 128 == 0, "DevInst: keep the size a multiple of 128 bytes");
