@@ -198,8 +198,9 @@ struct EngineBufs {
     DevInst* d_insts = nullptr;
     long long* d_plan = nullptr;
     StepInfo* d_info = nullptr;
-    InstState* d_states = nullptr;
-    InstState* h_states = nullptr;
+    InstState* h_states = nullptr;  // pinned, coherent: the gather kernel writes the states here
+    InstState* d_states = nullptr;  // its device address (no device-to-host copy call: such a
+                                    // small asynchronous copy has stalled the host for ms)
     DevInst* h_insts = nullptr;    // pinned staging of the descriptors (outlives the async copy)
     int* h_flag = nullptr;         // pinned word the kernels set when a problem stops running
     int* d_flag = nullptr;         // its device address
@@ -251,7 +252,6 @@ static void bufs_free(EngineBufs& b)
     if (b.d_insts) (void)hipFree(b.d_insts);
     if (b.d_plan) (void)hipFree(b.d_plan);
     if (b.d_info) (void)hipFree(b.d_info);
-    if (b.d_states) (void)hipFree(b.d_states);
     if (b.h_states) (void)hipHostFree(b.h_states);
     if (b.h_insts) (void)hipHostFree(b.h_insts);
     if (b.h_flag) (void)hipHostFree(b.h_flag);
@@ -298,8 +298,8 @@ static hipError_t bufs_get(int cap, EngineBufs* out)
     e = hipMalloc((void**)&b.d_insts, c * sizeof(DevInst));
     if (e == hipSuccess) e = hipMalloc((void**)&b.d_plan, 4 * (size_t)(c + 1) * sizeof(long long));
     if (e == hipSuccess) e = hipMalloc((void**)&b.d_info, (size_t)c * sizeof(StepInfo));
-    if (e == hipSuccess) e = hipMalloc((void**)&b.d_states, c * sizeof(InstState));
-    if (e == hipSuccess) e = hipHostMalloc((void**)&b.h_states, c * sizeof(InstState), hipHostMallocDefault);
+    if (e == hipSuccess) e = hipHostMalloc((void**)&b.h_states, c * sizeof(InstState), hipHostMallocCoherent);
+    if (e == hipSuccess) e = hipHostGetDevicePointer((void**)&b.d_states, b.h_states, 0);
     if (e == hipSuccess) e = hipHostMalloc((void**)&b.h_insts, c * sizeof(DevInst), hipHostMallocDefault);
     if (e == hipSuccess) e = hipHostMalloc((void**)&b.h_flag, sizeof(int), hipHostMallocDefault);
     if (e == hipSuccess) e = hipHostGetDevicePointer((void**)&b.d_flag, b.h_flag, 0);
@@ -1163,9 +1163,7 @@ static int certify_batch(pcba_engine* E, std::vector<pcba_problem*>& fin)
     int rc = upload_descs(fin.data(), n, t_scratch, E->stream, &d_insts, &d_pre, &total, &max_S, &tmw, ppb);
     if (rc != PCBA_OK) return rc;
     HIP_TRY(launch_certify(d_insts, n, d_pre, total, max_S, tmw, ppb, E->stream));
-    HIP_TRY(launch_gather(d_insts, n, E->b.d_states, E->stream));
-    HIP_TRY(hipMemcpyAsync(E->b.h_states, E->b.d_states, n * sizeof(InstState), hipMemcpyDeviceToHost,
-                           E->stream));
+    HIP_TRY(launch_gather(d_insts, n, E->b.d_states, E->stream));   // into host memory
     HIP_TRY(hipStreamSynchronize(E->stream));
     const double t = now_s();
     for (int b = 0; b < n; ++b) {
@@ -1283,9 +1281,7 @@ static int engine_steps(pcba_engine* E, int n_steps)
         HIP_TRY(launch_cut(E->b.d_insts, n, maxc, E->stream));
         HIP_TRY(prof_end(3, E->stream));
     }
-    HIP_TRY(launch_gather(E->b.d_insts, n, E->b.d_states, E->stream));
-    HIP_TRY(hipMemcpyAsync(E->b.h_states, E->b.d_states, n * sizeof(InstState), hipMemcpyDeviceToHost,
-                           E->stream));
+    HIP_TRY(launch_gather(E->b.d_insts, n, E->b.d_states, E->stream));   // into host memory
     HIP_TRY(hipStreamSynchronize(E->stream));
     prof_collect();
 
