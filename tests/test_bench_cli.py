@@ -55,3 +55,14 @@ def test_algorithmic_bytes_follow_the_definition():
     # FP32: half the coefficient bytes plus one 4-byte error bound per patch
     got32 = bench.algorithmic_bytes(_Fake(), _Inst(), "fp32")
     assert got32 == 4 * (9 * items + 9 * ineq) + 4 * (items + ineq)
+
+
+def test_count_certified_over_the_result_array():
+    # the timed loop counts certified plans on the structured array of
+    # pcba_result_batch; it must agree with certified() record by record
+    from paper_2003_01758_amd import pcba
+    res = np.zeros(6, dtype=pcba.RESULT_DTYPE)
+    res["outcome"] = [pcba.OPTIMAL, pcba.OPTIMAL, pcba.INFEASIBLE, pcba.MAX_ITER, pcba.MEMORY_LIMIT,
+                      pcba.OPTIMAL]
+    res["certified"] = [1, 0, 0, 0, 1, 1]
+    assert bench.count_certified(res, pcba) == sum(1 for r in res if bench.certified(r, pcba)) == 3
