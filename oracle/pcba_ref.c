@@ -41,6 +41,14 @@
  *   R8 list order: children replace their parent, left before right.  The
  *      paper's elimination reorders the list; no result here depends on order
  *      except the x* tie-break, which R6 fixes.
+ *   R9 round mode (not in the paper, which splits one direction per pass): a
+ *      pass splits every item along all l directions, axis 0 first.  A
+ *      child's coefficients are convex combinations of its parent's, so the
+ *      children of an infeasible or suboptimal half are themselves infeasible
+ *      or suboptimal: at the end of each round the estimate, the kept list and
+ *      x* are those of the one-direction passes, except where those would have
+ *      stopped or hit the memory test mid-round.  The memory test asks
+ *      2^l * length(L) <= M; `steps` counts passes (rounds).
  */
 #include "pcba_ref.h"
 
@@ -75,6 +83,7 @@ struct pcba_ref {
     unsigned x_index[PCBA_REF_MAX_DIM];
     int x_depth[PCBA_REF_MAX_DIM];
     long long peak;
+    int fused;                          /* 1: every pass splits along all l axes */
 };
 
 /* ---- small helpers ---------------------------------------------------------------- */
@@ -191,6 +200,36 @@ int pcba_ref_split(int l, const int* deg, int r, const double* parent,
                 right[base + (n - m) * stride] = c[n - m];
             }
         }
+    return 0;
+}
+
+/*
+ * Round split: bisect along axis 0, then each half along axis 1, and so on.
+ * After the split along axis k the children are ordered with the new bit
+ * least significant, so the final order has axis 0's bit most significant.
+ */
+int pcba_ref_split_round(int l, const int* deg, const double* parent, double* children)
+{
+    if (l < 1 || l > PCBA_REF_MAX_DIM || !deg || !parent || !children) return -1;
+    long long S = patch_size(l, deg);
+    long long nc = 1LL << l;
+    double* a = (double*)malloc(sizeof(double) * (size_t)(S * nc));
+    double* b = (double*)malloc(sizeof(double) * (size_t)(S * nc));
+    if (!a || !b) { free(a); free(b); return -1; }
+    memcpy(a, parent, sizeof(double) * (size_t)S);
+    long long have = 1;
+    for (int k = 0; k < l; ++k) {
+        for (long long c = 0; c < have; ++c)
+            if (pcba_ref_split(l, deg, k, a + c * S, b + (2 * c) * S, b + (2 * c + 1) * S) != 0) {
+                free(a); free(b);
+                return -1;
+            }
+        have *= 2;
+        double* t = a; a = b; b = t;
+    }
+    memcpy(children, a, sizeof(double) * (size_t)(S * nc));
+    free(a);
+    free(b);
     return 0;
 }
 
@@ -351,13 +390,17 @@ int pcba_ref_step(pcba_ref* h)
     const int l = h->l, r = h->r;
     const long long K = h->K, W = h->W;
 
+    /* children per item: 2, or 2^l when a pass is a whole round */
+    const long long nc = h->fused ? (1LL << l) : 2;
+
     /* memory test */
     if (K > h->peak) h->peak = K;
-    if (2 * K > h->M) { h->status = PCBA_REF_MEMORY_LIMIT; return h->status; }
+    if (nc * K > h->M) { h->status = PCBA_REF_MEMORY_LIMIT; return h->status; }
 
     /* Subdivision (parallel in the paper): each item is replaced by its left
-     * then right child along direction r. */
-    const long long C = 2 * K;
+     * then right child along direction r, or in round mode by its 2^l
+     * children, in the order of their id bits (axis 0 most significant). */
+    const long long C = nc * K;
     unsigned* cids = (unsigned*)malloc(sizeof(unsigned) * (size_t)(C * l));
     double* cpat = (double*)malloc(sizeof(double) * (size_t)(C * W));
     bounds_t* bd = (bounds_t*)malloc(sizeof(bounds_t) * (size_t)C);
@@ -367,23 +410,51 @@ int pcba_ref_step(pcba_ref* h)
         h->status = PCBA_REF_MEMORY_LIMIT;
         return h->status;
     }
+    long long maxS = 0;
+    for (int t = 0; t < KINDS; ++t)
+        if (h->size[t] > maxS) maxS = h->size[t];
+    double* round_out = h->fused ? (double*)malloc(sizeof(double) * (size_t)(nc * (maxS ? maxS : 1))) : NULL;
+    if (h->fused && !round_out) {
+        free(cids); free(cpat); free(bd); free(keep);
+        h->status = PCBA_REF_MEMORY_LIMIT;
+        return h->status;
+    }
     for (long long k = 0; k < K; ++k) {
         const double* parent = h->pat + k * W;
-        double* left = cpat + (2 * k) * W;
-        double* right = cpat + (2 * k + 1) * W;
+        if (!h->fused) {
+            double* left = cpat + (2 * k) * W;
+            double* right = cpat + (2 * k + 1) * W;
+            for (int t = 0; t < KINDS; ++t)
+                for (int i = 0; i < h->count[t]; ++i) {
+                    long long off = kind_offset(h, t, i);
+                    pcba_ref_split(l, h->deg[t], r, parent + off, left + off, right + off);
+                }
+            for (int q = 0; q < l; ++q) {
+                cids[(2 * k) * l + q] = h->ids[k * l + q];
+                cids[(2 * k + 1) * l + q] = h->ids[k * l + q];
+            }
+            cids[(2 * k) * l + r] = 2u * h->ids[k * l + r];
+            cids[(2 * k + 1) * l + r] = 2u * h->ids[k * l + r] + 1u;
+            continue;
+        }
+        /* round mode: every patch to its 2^l children, scattered to the items */
         for (int t = 0; t < KINDS; ++t)
             for (int i = 0; i < h->count[t]; ++i) {
                 long long off = kind_offset(h, t, i);
-                pcba_ref_split(l, h->deg[t], r, parent + off, left + off, right + off);
+                pcba_ref_split_round(l, h->deg[t], parent + off, round_out);
+                for (long long c = 0; c < nc; ++c)
+                    memcpy(cpat + (nc * k + c) * W + off, round_out + c * h->size[t],
+                           sizeof(double) * (size_t)h->size[t]);
             }
-        for (int q = 0; q < l; ++q) {
-            cids[(2 * k) * l + q] = h->ids[k * l + q];
-            cids[(2 * k + 1) * l + q] = h->ids[k * l + q];
-        }
-        cids[(2 * k) * l + r] = 2u * h->ids[k * l + r];
-        cids[(2 * k + 1) * l + r] = 2u * h->ids[k * l + r] + 1u;
+        for (long long c = 0; c < nc; ++c)
+            for (int q = 0; q < l; ++q)
+                cids[(nc * k + c) * l + q] = 2u * h->ids[k * l + q] + (unsigned)((c >> (l - 1 - q)) & 1);
     }
-    h->depth[r] += 1;
+    free(round_out);
+    if (h->fused)
+        for (int q = 0; q < l; ++q) h->depth[q] += 1;
+    else
+        h->depth[r] += 1;
     h->steps += 1;
 
     /* FindBounds (parallel in the paper) */
@@ -447,11 +518,18 @@ int pcba_ref_step(pcba_ref* h)
         return h->status;
     }
 
-    /* prepare the next iteration */
-    h->r = (r + 1) % l;
+    /* prepare the next iteration (a round-mode pass is a whole round) */
+    h->r = h->fused ? 0 : (r + 1) % l;
     if (h->r == 0) h->n += 1;
     if (h->n == h->N) { h->status = PCBA_REF_MAX_ITER; return h->status; }
     return PCBA_REF_RUNNING;
+}
+
+int pcba_ref_set_fused(pcba_ref* h, int on)
+{
+    if (!h || h->steps > 0 || h->status != PCBA_REF_RUNNING) return -1;
+    h->fused = on ? 1 : 0;
+    return 0;
 }
 
 int pcba_ref_solve(pcba_ref* h)

@@ -70,6 +70,14 @@ int pcba_ref_to_bernstein(int l, const int* deg, const double* lo, const double*
 int pcba_ref_split(int l, const int* deg, int r, const double* parent,
                    double* left, double* right);
 
+/* Round split: the patch bisected along every axis in turn, axis 0 first
+ * (each of Sec. II-E's constant-matrix products along one axis, applied l
+ * times), giving the 2^l children of the sub-boxes in the order of their id
+ * bits, axis 0 most significant: child c takes the right half along axis k iff
+ * bit (l-1-k) of c is set.  `children` holds 2^l patches of the parent's
+ * layout.  Returns 0 or -1. */
+int pcba_ref_split_round(int l, const int* deg, const double* parent, double* children);
+
 /* ---- the algorithm (Alg. PCBA and its subroutines, Sec. III) ---------------------- */
 
 /* Copies every input.  Degrees: cost_deg[l], ineq_deg[n_ineq*l], eq_deg[n_eq*l].
@@ -87,6 +95,14 @@ pcba_ref* pcba_ref_create(int l, const double* lo, const double* hi,
  * advance of direction and iteration count.  Returns PCBA_REF_RUNNING or the
  * final outcome (further calls return it again). */
 int pcba_ref_step(pcba_ref* h);
+
+/* Round mode, chosen before the first pass: 0 (default) splits along one
+ * direction per pass, as Alg. PCBA does; 1 makes every pass a whole round,
+ * splitting each item along all l directions at once (pcba_ref_split_round):
+ * the memory test then asks 2^l * length(L) <= M, the cut-off, elimination
+ * and stopping tests run once per round, and the iteration count advances
+ * every pass.  Returns 0, or -1 once the problem has stepped. */
+int pcba_ref_set_fused(pcba_ref* h, int on);
 
 /* Steps until an outcome is reached; returns it. */
 int pcba_ref_solve(pcba_ref* h);

@@ -54,6 +54,10 @@ def load(path):
         L.pcba_ref_to_bernstein.restype = C.c_int
         L.pcba_ref_split.argtypes = [C.c_int, ip, C.c_int, dp, dp, dp]
         L.pcba_ref_split.restype = C.c_int
+        L.pcba_ref_split_round.argtypes = [C.c_int, ip, dp, dp]
+        L.pcba_ref_split_round.restype = C.c_int
+        L.pcba_ref_set_fused.argtypes = [C.c_void_p, C.c_int]
+        L.pcba_ref_set_fused.restype = C.c_int
         L.pcba_ref_create.argtypes = [C.c_int, dp, dp, ip, dp, C.c_int, C.c_void_p, C.c_void_p,
                                       C.c_int, C.c_void_p, C.c_void_p, C.c_double, C.c_double,
                                       C.c_double, C.c_longlong, C.c_int]
@@ -103,6 +107,18 @@ def split(patch: np.ndarray, r: int, L=None):
     return left, right
 
 
+def split_round(patch: np.ndarray, L=None) -> np.ndarray:
+    """The 2^l children of a patch bisected along every axis, axis 0 first;
+    child c (axis 0's bit most significant) at out[c]."""
+    patch = np.ascontiguousarray(patch, dtype=np.float64)
+    deg = np.array([s - 1 for s in patch.shape], dtype=np.int32)
+    out = np.empty((1 << patch.ndim,) + patch.shape)
+    rc = (L or lib()).pcba_ref_split_round(patch.ndim, deg, patch.reshape(-1), out.reshape(-1))
+    if rc != 0:
+        raise ValueError("pcba_ref_split_round rejected its arguments")
+    return out
+
+
 def _ptr(a):
     return None if a is None or a.size == 0 else a.ctypes.data
 
@@ -112,7 +128,7 @@ class RefSolver:
     object (l, lo, hi, cost_deg, cost_flat, ineq_deg, ineq_flat, eq_deg, eq_flat,
     eps, delta, eps_eq, max_boxes, max_iters)."""
 
-    def __init__(self, inst, L=None, **override):
+    def __init__(self, inst, L=None, fused=False, **override):
         L = L or lib()
         self.L = L
         g = lambda k: override.get(k, getattr(inst, k))
@@ -133,6 +149,8 @@ class RefSolver:
             raise ValueError("pcba_ref_create rejected the problem")
         self.h = h
         self.words = int(L.pcba_ref_patch_words(h))
+        if fused and L.pcba_ref_set_fused(h, 1) != 0:
+            raise ValueError("pcba_ref_set_fused failed")
 
     def close(self):
         if getattr(self, "h", None):

@@ -20,6 +20,9 @@
 #include <float.h>
 #include <math.h>
 
+#include <mutex>
+#include <vector>
+
 namespace pcba {
 
 // ------------------------------------------------------------------ small helpers
@@ -2205,19 +2208,68 @@ __global__ void k_gather(const DevInst* __restrict__ insts, int n, InstState* __
 
 // ------------------------------------------------------------------ host launchers
 
-// LDS bytes a workgroup may use on the current device
-static size_t lds_per_block()
+// Device properties the launchers need, cached per device (the current device
+// of the calling thread) under a lock: distinct problem handles may be driven
+// from distinct threads and devices.
+constexpr int MAX_DEVICES = 64;
+struct DevProps {
+    bool ok = false;
+    int cus = 0;
+    size_t lds = 65536;
+};
+static std::mutex g_props_mu;
+static DevProps g_props[MAX_DEVICES];
+
+static int current_device()
 {
-    static size_t cached = 0;
-    if (!cached) {
-        int dev = 0, v = 0;
-        if (hipGetDevice(&dev) == hipSuccess &&
-            hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && v > 0)
-            cached = (size_t)v;
-        else
-            cached = 65536;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= MAX_DEVICES) dev = 0;
+    return dev;
+}
+
+static DevProps device_props(int dev)
+{
+    std::lock_guard<std::mutex> lk(g_props_mu);
+    DevProps& p = g_props[dev];
+    if (!p.ok) {
+        int v = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && v > 0)
+            p.lds = (size_t)v;
+        v = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
+            p.cus = v;
+        p.ok = true;
     }
-    return cached;
+    return p;
+}
+
+// LDS bytes a workgroup may use on the current device
+static size_t lds_per_block() { return device_props(current_device()).lds; }
+
+// Resident workgroups per CU of `kernel` with `lds` dynamic LDS bytes on the
+// current device, cached per (device, kernel, lds) under a lock; 0 if unknown.
+static int occupancy_per_cu(const void* kernel, int threads, size_t lds)
+{
+    struct Entry {
+        int dev;
+        const void* k;
+        int threads;
+        size_t lds;
+        int per_cu;
+    };
+    static std::mutex mu;
+    static std::vector<Entry> cache;
+    const int dev = current_device();
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        for (const Entry& e : cache)
+            if (e.dev == dev && e.k == kernel && e.threads == threads && e.lds == lds) return e.per_cu;
+    }
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, threads, lds) != hipSuccess) nb = 0;
+    std::lock_guard<std::mutex> lk(mu);
+    cache.push_back(Entry{dev, kernel, threads, lds, nb});
+    return nb;
 }
 
 
@@ -2280,17 +2332,8 @@ static hipError_t launch_sub_t(const DevInst* d_insts, int n, long long* plan, S
     const size_t lds = sub_lds_bytes(tem, tpm, sizeof(T) == 4);
     // no more workgroups than fit on the device at once: the rest would only
     // queue, while resident ones walk the units with the next tile in flight
-    static int cus = 0;
-    static size_t cached_lds = (size_t)-1;
-    static int per_cu = 0;
-    if (!cus && hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, 0) != hipSuccess) cus = 0;
-    if (lds != cached_lds) {
-        int nb = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_sub<T, MM, LB, FUSE>, SUB_THREADS, lds) ==
-            hipSuccess)
-            per_cu = nb;
-        cached_lds = lds;
-    }
+    const int cus = device_props(current_device()).cus;
+    const int per_cu = occupancy_per_cu((const void*)k_sub<T, MM, LB, FUSE>, SUB_THREADS, lds);
     if (cus > 0 && per_cu > 0) grid = std::min(grid, cus * per_cu);
     if (ev0)
         hipExtLaunchKernelGGL((k_sub<T, MM, LB, FUSE>), dim3(grid), dim3(SUB_THREADS), lds, s, ev0, ev1, 0,

@@ -275,7 +275,7 @@ def make_instance(config: int, index: int = 0, **overrides) -> Instance:
         inst = Instance("batch" if config == 3 else "serve", l, -np.ones(l), np.ones(l),
                         cost, ineq, [], max_boxes=1 << 20, q0=q0)
     elif config == 5:
-        # a plan through waypoints (the multi-waypoint cost of Sec. V): the
+        # a plan through waypoints (the multi-waypoint cost of Sec. VI): the
         # product over two waypoints x_n of the squared distance of the
         # endpoint map e(q) (multi-degree (3,3) per component) from x_n, which
         # has a minimum near each waypoint's preimage; 100 obstacle

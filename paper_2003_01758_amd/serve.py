@@ -7,7 +7,7 @@ Every engine round advances all admitted, unfinished plans together by a few
 PCBA steps; finished plans are certified and handed back, freeing their share
 of the budget for the next admissions.  The replanning period of the paper's
 receding-horizon planner (a new plan every 0.5 s, a solver budget of 0.4 s,
-Sec. V) motivates the per-plan deadline.
+Sec. VI) motivates the per-plan deadline.
 
 Usage: python -m paper_2003_01758_amd.serve --rate 200 --duration 60
 """
@@ -79,10 +79,12 @@ class Server:
                     ta, i, _ = inflight.pop(prob.h.value)
                     r = prob.result()
                     lat = tdone - ta
+                    # an infeasibility verdict is rigorous only on widened (FP32) bounds
                     certified = (r["outcome"] == pcba.OPTIMAL and r["certified"]) or \
-                        r["outcome"] == pcba.INFEASIBLE
+                        (r["outcome"] == pcba.INFEASIBLE and self.precision == "fp32")
                     records[i] = dict(arrival=ta, done=tdone, latency=lat, outcome=r["outcome"],
-                                      certified=bool(certified), p_up=r["p_up"], steps=r["steps"],
+                                      certified=bool(certified), p_up=r["p_up"], p_lo=r["p_lo"],
+                                      steps=r["steps"], x_index=[int(v) for v in r["x_index"]],
                                       deadline_missed=bool(lat > self.deadline or not certified))
                     prob.close()
                     n_done += 1

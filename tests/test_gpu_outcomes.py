@@ -1,0 +1,161 @@
+"""Outcomes and paths the other GPU tests leave out, each checked against the
+FP64 oracle or against what the paper's definitions fix.
+
+- A batch of more than 256 problems mixing FP64 and FP32 problems: the step's
+  plan comes from its own launch, and both subdivision launches read it.
+- A mixed batch of at most 256: the FP64 subdivision launch forms the plan,
+  the FP32 launch after it reads the plan the first one wrote.
+- The full 4-D workload (100 inequalities, 2 equalities) run to an outcome at
+  the same M as the stored oracle run: FP64 identical step by step, FP32 the
+  same outcome.
+- The time limit: a solve stopped by time_limit_s reports TIMEOUT.
+- A certification that must fail: an incumbent box on which an inequality's
+  largest Bernstein coefficient is exactly 0 is feasible by the definition
+  (max B_g <= 0) in FP64 plain mode, but no rigorous bound can certify it.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+from oracle import ref
+from paper_2003_01758_amd.instances import Instance, make_instance, poly_eval, truncate
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    from paper_2003_01758_amd import pcba
+    pcba.lib()
+    return pcba
+
+
+def _oracle(inst):
+    o = ref.RefSolver(inst)
+    o.solve()
+    return o.result()
+
+
+def _mixed(n):
+    """n problems: small workload and rtd plans cut to 40 constraints, FP64
+    and FP32 interleaved."""
+    insts, precs = [], []
+    for k in range(n):
+        insts.append(make_instance(0, k // 2) if k % 4 < 2 else truncate(make_instance(1, k // 4), 40))
+        precs.append("fp64" if k % 2 == 0 else "fp32")
+    return insts, precs
+
+
+def _check_against_oracle(gpu, insts, precs, res):
+    for k, (inst, prec, r) in enumerate(zip(insts, precs, res)):
+        o = _oracle(inst)
+        assert r["outcome"] == o["outcome"] == gpu.OPTIMAL, k
+        if prec == "fp64":
+            assert r["p_up"] == o["p_up"] and r["p_lo"] == o["p_lo"], k
+            assert r["steps"] == o["steps"] and r["peak_len"] == o["peak_len"], k
+            assert np.array_equal(r["x_index"], o["x_index"]), k
+        else:
+            assert abs(r["p_up"] - o["p_up"]) <= inst.eps, k
+        assert r["certified"], k
+
+
+@pytest.mark.parametrize("n", [300, 40])
+def test_mixed_precision_batch_matches_oracle(gpu, n):
+    insts, precs = _mixed(n)
+    print(f"[mixed batch] {n} problems", flush=True)
+    probs = [gpu.Problem(i, precision=p) for i, p in zip(insts, precs)]
+    res = gpu.solve_batch(probs)
+    for p in probs:
+        p.close()
+    _check_against_oracle(gpu, insts, precs, res)
+
+
+@pytest.fixture(scope="module")
+def d4_golden():
+    with open(os.path.join(HERE, "golden", "d4_outcome.json")) as f:
+        return json.load(f)
+
+
+@pytest.mark.parametrize("k", [0, 1])
+def test_d4_full_fp64_to_outcome_matches_oracle(gpu, d4_golden, k):
+    want = d4_golden["runs"][str(k)]
+    inst = make_instance(2, k).with_options(max_boxes=d4_golden["max_boxes"])
+    print(f"[d4 full fp64] {k}", flush=True)
+    g = gpu.Problem(inst)
+    r = g.solve()
+    assert r["outcome"] == want["outcome"]
+    assert r["steps"] == want["steps"] and r["peak_len"] == want["peak_len"]
+    assert r["p_lo"] == want["p_lo"]
+    assert (math.isinf(r["p_up"]) and math.isinf(want["p_up"])) or r["p_up"] == want["p_up"]
+    tr = g.trace()
+    n = min(len(tr["k_kept"]), len(want["trace"]))
+    assert n == len(want["trace"])
+    for s in range(n):
+        row = want["trace"][s]
+        assert tr["k_kept"][s] == row["k"], s
+        assert tr["p_lo"][s] == row["p_lo"], s
+        assert (math.isinf(tr["p_up"][s]) and math.isinf(row["p_up"])) or tr["p_up"][s] == row["p_up"], s
+
+
+@pytest.mark.parametrize("k", [0, 1])
+def test_d4_full_fp32_reaches_oracle_outcome(gpu, d4_golden, k):
+    want = d4_golden["runs"][str(k)]
+    inst = make_instance(2, k).with_options(max_boxes=d4_golden["max_boxes"])
+    print(f"[d4 full fp32] {k}", flush=True)
+    r = gpu.Problem(inst, precision="fp32").solve()
+    assert r["outcome"] == want["outcome"]
+    # the least lower bound is rigorous in FP32 (widened) and can only be
+    # lower than or equal to the unwidened FP64 one up to the bracket
+    assert r["p_lo"] <= want["p_lo"] + inst.eps
+    if want["has_x"]:
+        assert abs(r["p_up"] - want["p_up"]) <= inst.eps
+
+
+def test_time_limit_reports_timeout(gpu):
+    # the full 4-D workload at a large M takes far longer than 20 ms
+    inst = make_instance(2, 0).with_options(max_boxes=1 << 18)
+    g = gpu.Problem(inst, time_limit_s=0.02)
+    r = g.solve()
+    assert r["outcome"] == gpu.TIMEOUT
+    assert r["steps"] > 0 and r["list_len"] > 0
+    assert not r["certified"]
+    # the same problem without the limit runs past the steps the limit allowed
+    r2 = gpu.Problem(inst.with_options(max_boxes=1 << 13)).solve()
+    assert r2["outcome"] != gpu.TIMEOUT
+
+
+def _edge_instance():
+    # minimise -x1 subject to x1 - 1/2 <= 0 on [0,1]^2
+    cost = np.zeros((2, 1))
+    cost[1, 0] = -1.0
+    g = np.zeros((2, 1))
+    g[0, 0], g[1, 0] = -0.5, 1.0
+    return Instance("edge", 2, np.zeros(2), np.ones(2), cost, [g], [],
+                    eps=1e-3, delta=1e-3, eps_eq=1e-4, max_boxes=1 << 12, max_iters=28)
+
+
+def test_certification_fails_on_a_boundary_incumbent(gpu):
+    inst = _edge_instance()
+    o = _oracle(inst)
+    r = gpu.Problem(inst).solve()
+    # FP64 plain follows the definitions: the box [1/2 - w, 1/2] x [..] has
+    # max B_g = 0 exactly, so it is feasible and holds the estimate
+    assert r["outcome"] == o["outcome"] == gpu.OPTIMAL
+    assert r["p_up"] == o["p_up"] and r["steps"] == o["steps"]
+    assert o["x_hi"][0] == 0.5 and r["x_hi"][0] == 0.5
+    # no rigorous bound can show g <= 0 there: the certificate needs
+    # max B_g + e <= 0 with an error bound e > 0
+    assert not r["certified"]
+    assert r["cert_err"] > 0.0
+    # with rigorously widened bounds (FP32), the boundary box is never
+    # feasible, and the estimate comes from a box strictly inside
+    r32 = gpu.Problem(inst, precision="fp32").solve()
+    if r32["outcome"] == gpu.OPTIMAL:
+        assert r32["certified"]
+        assert r32["x_hi"][0] < 0.5
+        assert abs(r32["p_up"] - o["p_up"]) <= inst.eps

@@ -1,6 +1,6 @@
 """The paper's own problems through the HIP library's C ABI.
 
-The benchmark problems of Sec. V-A (appendix statements, tests/golden) with the
+The benchmark problems of Sec. V-B (appendix statements, tests/golden) with the
 paper's relative tolerance, and the objectives of the increasing-constraints
 study (Sec. V-C) with random degree-2 constraints planted feasible at the
 printed minimiser.  FP64 plain mode must reproduce the oracle's solve exactly

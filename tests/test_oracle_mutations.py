@@ -39,13 +39,18 @@ MUTATIONS = {
     "feasible_uses_min": ("if (!(mx <= 0.0)) b.feasible = 0;", "if (!(mn <= 0.0)) b.feasible = 0;"),
     "keep_uses_max": ("keep[c] = (char)(!bd[c].infeasible && bd[c].minP <= h->p_up);",
                       "keep[c] = (char)(!bd[c].infeasible && bd[c].maxP <= h->p_up);"),
-    "direction_stuck": ("h->r = (r + 1) % l;", "h->r = r;"),
+    "direction_stuck": ("h->r = h->fused ? 0 : (r + 1) % l;", "h->r = h->fused ? 0 : r;"),
     "right_child_id": ("cids[(2 * k + 1) * l + r] = 2u * h->ids[k * l + r] + 1u;",
                        "cids[(2 * k + 1) * l + r] = 2u * h->ids[k * l + r];"),
     "eq_band_upper": ("if (!(-h->eps_eq <= mn && mn <= 0.0 && 0.0 <= mx && mx <= h->eps_eq))",
                       "if (!(-h->eps_eq <= mn && mn <= 0.0 && 0.0 <= mx))"),
     "width_off_by_one": ("double wq = ldexp(h->hi[q] - h->lo[q], -h->depth[q]);",
                          "double wq = ldexp(h->hi[q] - h->lo[q], -h->depth[q] - 2);"),
+    "round_id_bit_order": ("cids[(nc * k + c) * l + q] = 2u * h->ids[k * l + q] + (unsigned)((c >> (l - 1 - q)) & 1);",
+                           "cids[(nc * k + c) * l + q] = 2u * h->ids[k * l + q] + (unsigned)((c >> q) & 1);"),
+    "round_depth_one_axis": ("for (int q = 0; q < l; ++q) h->depth[q] += 1;", "h->depth[0] += 1;"),
+    "round_memory_test": ("if (nc * K > h->M)", "if (2 * K > h->M)"),
+    "round_axis_order": ("if (pcba_ref_split(l, deg, k, a + c * S,", "if (pcba_ref_split(l, deg, l - 1 - k, a + c * S,"),
     "p_up_uses_min": ("if (bd[c].feasible && (arg < 0 || bd[c].maxP < m)) { m = bd[c].maxP; arg = c; }",
                       "if (bd[c].feasible && (arg < 0 || bd[c].minP < m)) { m = bd[c].minP; arg = c; }"),
 }
@@ -211,6 +216,45 @@ def battery(L):
             np.max(r["x_hi"] - r["x_lo"]) > inst.delta / 4 and \
             r["p_lo"] - 1e-12 <= poly_eval(inst.cost, c) <= r["p_up"] + 1e-12
     check("small_invariants", small)
+
+    # round mode: the round split against exact sub-boxes, the round-end state
+    # against the one-direction passes, and its memory test
+    def round_split():
+        rng = np.random.default_rng(6)
+        mono = rng.integers(-5, 6, size=(4, 6))
+        P = ref.to_bernstein(mono.astype(float), [-1.0, -1.0], [1.0, 1.0], L=L)
+        kids = ref.split_round(P, L=L)
+        for c in range(4):
+            blo = [0.0 if (c >> (1 - k)) & 1 else -1.0 for k in range(2)]
+            bhi = [1.0 if (c >> (1 - k)) & 1 else 0.0 for k in range(2)]
+            want = exact.to_float(exact.bernstein_exact(mono, blo, bhi))
+            if np.max(np.abs(kids[c] - want)) > 1e-12 * max(1, np.abs(want).max()):
+                return False
+        return True
+    check("round_split", round_split)
+
+    def round_ends():
+        inst = make_instance(0, 3)
+        o = ref.RefSolver(inst, L=L)
+        f = ref.RefSolver(inst, L=L, fused=True)
+        for _ in range(10):
+            o.step()
+            o.step()
+            f.step()
+            ro, rf = o.result(), f.result()
+            if ro["p_up"] != rf["p_up"] or ro["p_lo"] != rf["p_lo"] or \
+                    not np.array_equal(ro["depth"], rf["depth"]) or \
+                    not np.array_equal(o.list()[0], f.list()[0]):
+                return False
+        return True
+    check("round_ends", round_ends)
+
+    def round_memory():
+        f = ref.RefSolver(make_instance(0, 5).with_options(max_boxes=64), L=L, fused=True)
+        out = f.solve()
+        r = f.result()
+        return out == ref.MEMORY_LIMIT and 4 * r["list_len"] > 64 and 2 * r["list_len"] <= 64
+    check("round_memory", round_memory)
     return failed
 
 

@@ -1,4 +1,4 @@
-"""The multi-waypoint plan workload (Sec. V: the cost is a product over
+"""The multi-waypoint plan workload (Sec. VI: the cost is a product over
 waypoints of the squared distance of the endpoint map, multi-modal): the
 generator's structure, the oracle against brute force on a grid, and the GPU
 path against the oracle."""
