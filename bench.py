@@ -268,6 +268,7 @@ def copy_calibration(mib: int, reps: int):
 MODE_FLAGS = {
     "r0": ("retire_satisfied", 0),   # every box carries every constraint (Alg. Subdivision)
     "r1": ("retire_satisfied", 1),   # constraints certified satisfied on a box are dropped
+    "f1": ("fused_round", 1),        # each pass splits both axes: S_a P S_b^T, one cut per round
 }
 
 
@@ -323,7 +324,7 @@ def main():
                     help="only run device copies of this many MiB (counter calibration) and exit")
     ap.add_argument("--single-reps", type=int, default=20,
                     help="solves of one plan alone per headline precision for the single-plan latency (0: skip)")
-    ap.add_argument("--modes", default="fp64:r0,fp32:r0,fp64:r1,fp32:r1",
+    ap.add_argument("--modes", default="fp64:r0,fp32:r0,fp64:r0:f1,fp32:r0:f1,fp64:r1,fp32:r1",
                     help="comma-separated modes precision[:flag...]; flags: " + ", ".join(MODE_FLAGS) +
                          ". The headline is the best mode that transforms every constraint (r0)")
     args = ap.parse_args()

@@ -42,9 +42,11 @@ extern "C" {
 /* arithmetic of the per-step subdivision */
 enum {
     PCBA_FP64_PLAIN = 0,  /* FP64 patches, unwidened bounds (the paper's semantics) */
-    PCBA_FP32 = 1         /* FP32 patches; every bound widened by a rigorous
-                             rounding-error bound carried per patch; FP64 root,
-                             periodic FP64 re-derivation, FP64 certification */
+    PCBA_FP32 = 1         /* FP32 patches split on the matrix cores (MFMA) as
+                             products with the subdivision matrices of Sec. II-E;
+                             every bound widened by a rigorous rounding-error
+                             bound carried per patch; FP64 root, periodic FP64
+                             re-derivation, FP64 certification */
 };
 
 /* outcomes (pcba_result_t.outcome) */
@@ -52,7 +54,7 @@ enum {
     PCBA_RUNNING = -1,
     PCBA_OPTIMAL = 0,       /* stopping criteria met (tolerance definition, Sec. III-C) */
     PCBA_INFEASIBLE = 1,    /* every box eliminated as infeasible */
-    PCBA_MEMORY_LIMIT = 2,  /* memory test: 2*length(L) > M */
+    PCBA_MEMORY_LIMIT = 2,  /* memory test: 2*length(L) > M (2^l*length(L) with fused_round) */
     PCBA_MAX_ITER = 3,      /* iteration count reached N */
     PCBA_TIMEOUT = 4        /* options.time_limit_s elapsed */
 };
@@ -89,6 +91,19 @@ typedef struct {
                                 are unchanged: in FP64 plain mode the results are
                                 identical to 0, in FP32 mode they remain rigorous.
                                 0: every box carries every patch, as in Alg. PCBA */
+    int32_t fused_round;     /* 0 (default): each pass of the main loop splits one direction,
+                                as Alg. PCBA does.  1: each pass is a whole round: every box
+                                is split along all l axes at once (for l = 2, the children
+                                S_a P S_b^T, a, b in {L, R}, of the subdivision matrices of
+                                Sec. II-E), then bounded and cut off once.  Children are
+                                convex combinations of their parent's coefficients, so a
+                                quarter of an infeasible or suboptimal half is itself
+                                infeasible or suboptimal: the round ends keep the estimate
+                                and list of the one-direction passes, except where those
+                                would have stopped or hit the memory test mid-round.  The
+                                memory test then asks 2^l length(L) <= M; `steps` counts
+                                rounds.  Requires l <= 2 and retire_satisfied = 0
+                                (PCBA_E_ARG otherwise). */
     double time_limit_s;     /* 0 = none */
 } pcba_options;
 
@@ -102,7 +117,7 @@ typedef struct {
     int32_t x_depth[PCBA_MAX_DIM];   /* id of x*: depth per axis ... */
     uint32_t x_index[PCBA_MAX_DIM];  /* ... and index per axis */
     int32_t rounds;             /* n: completed passes over all directions, from 1 */
-    int32_t steps;              /* directional subdivisions performed */
+    int32_t steps;              /* passes performed: directional subdivisions (rounds with fused_round) */
     int64_t list_len;           /* length of the list L now */
     int64_t peak_len;           /* max length of L at a memory test */
     int32_t depth[PCBA_MAX_DIM];/* depth vector of the boxes in L */
@@ -120,8 +135,8 @@ typedef struct {
 typedef struct pcba_problem pcba_problem;
 
 /* Fills *opt with defaults: eps 1e-3, delta 1e-4, eps_eq 1e-4, M 2^20, N 28,
- * FP64 plain, re-derivation every 16 steps, retiring on, stale filter off, no
- * time limit. */
+ * FP64 plain, re-derivation every 16 steps, retiring on, stale filter off,
+ * one direction per pass, no time limit. */
 void pcba_default_options(pcba_options* opt);
 
 /* Builds problem (P) and its root item: every polynomial is zero-padded to the
@@ -167,6 +182,22 @@ int pcba_read_list(const pcba_problem* prob, uint32_t* ids, double* patches, int
 /* PCBA_FP32 only: per-item, per-polynomial error bounds (host, len*(1+alpha+beta)). */
 int pcba_read_errors(const pcba_problem* prob, double* err, int64_t cap);
 int64_t pcba_patch_words(const pcba_problem* prob);
+
+/* The step before the solver in RTD (Sec. II-C): each sensed obstacle point x_i
+ * becomes one inequality of the planning problem, w(x_i, q) + eps_q <= 0, where
+ * w(x, q) (x: a point in the plane, q: the l = 2 plan parameters) is >= 0 on the
+ * forward reachable set, and eps_q > 0 makes the open safe set closed.
+ *  - w_xdeg[2], w_qdeg[2]: w's multi-degree in x and in q (0..PCBA_MAX_DEGREE).
+ *  - w_coef (host): the coefficient of x1^a x2^b q1^c q2^d at offset
+ *    ((a*(w_xdeg[1]+1) + b)*(w_qdeg[0]+1) + c)*(w_qdeg[1]+1) + d.
+ *  - pts (host): n_pts points, x1 then x2 for each.
+ *  - out (host, caller-owned): n_pts polynomials in q of multi-degree w_qdeg, each
+ *    (w_qdeg[0]+1)*(w_qdeg[1]+1) doubles in the layout of pcba_create_problem's
+ *    coefficients: pass out as ineq_coef with w_qdeg as every row of ineq_deg.
+ * FP64 on the host; PCBA_E_ARG for NULL pointers, n_pts < 0, degrees out of
+ * range, non-finite eps_q or points. */
+int pcba_rtd_constraints(const int32_t* w_xdeg, const int32_t* w_qdeg, const double* w_coef, int32_t n_pts,
+                         const double* pts, double eps_q, double* out);
 
 /* FP64 root patches (host, words doubles) as computed on the device. */
 int pcba_read_root(const pcba_problem* prob, double* patches);

@@ -17,15 +17,16 @@ hipError_t launch_plan(const DevInst* d_insts, int n, long long* plan, StepInfo*
 // ev0/ev1 (or null): events stamped at the subdivision kernel's start and end.
 // fuse (n <= PLAN_FUSE_MAX): the kernel forms the step's plan itself, in place
 // of a k_plan launch before it, and writes it to plan / info.  tem / tpm: the
-// largest tile (coefficients, patches) of the problems launched.
+// largest tile (coefficients, patches) of the problems launched; nr: children
+// regions per tile, 2, or NCMAX when some problem splits whole rounds.
 hipError_t launch_sub(const DevInst* d_insts, int n, long long* plan, StepInfo* info, bool fuse,
-                      bool fp32, int maxm, int grid, int tem, int tpm, hipStream_t s, hipEvent_t ev0,
+                      bool fp32, int maxm, int grid, int tem, int tpm, int nr, hipStream_t s, hipEvent_t ev0,
                       hipEvent_t ev1);
 // dynamic LDS bytes of k_sub for those tiles
-size_t sub_lds_bytes(int tem, int tpm, bool fp32);
+size_t sub_lds_bytes(int tem, int tpm, bool fp32, int nr);
 hipError_t launch_rederive(const DevInst* d_insts, int n, const long long* plan, const StepInfo* info,
                            int grid, int tgrid, size_t lds, hipStream_t s);
-// max_children: an upper bound on 2K over the problems at this step
+// max_children: an upper bound on the children (2K, or 2^l K in a round) at this step
 hipError_t launch_cut(const DevInst* d_insts, int n, int64_t max_children, hipStream_t s);
 hipError_t launch_gather(const DevInst* d_insts, int n, InstState* out, hipStream_t s);
 // polynomials per certification workgroup that fit LDS (0: none)

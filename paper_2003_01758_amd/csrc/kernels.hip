@@ -180,7 +180,8 @@ __device__ __forceinline__ long long step_units(const DevInst& I, const PlanStat
 
 // One problem's share of a step's plan: its units per class (v) and the
 // snapshot of its state that the step's kernels use (si).  The memory test of
-// Alg. PCBA runs at the start of the iteration: 2 length(L) > M ends the
+// Alg. PCBA runs at the start of the iteration: 2 length(L) > M (in a round
+// 2^l length(L), the children it makes) ends the
 // solve; more than the device list holds pauses the problem until the host
 // grows the list.  With `commit` the outcome and the peak list length are
 // stored in the state; a caller without it reaches the same decision from the
@@ -191,14 +192,15 @@ __device__ __forceinline__ void plan_one(const DevInst& I, bool commit, long lon
     const gmem_t<InstState> st = as_global(I.st);
     v[0] = v[1] = v[2] = v[3] = 0;
     const int K = ps.K;
+    const long long nc = I.fused ? (1 << I.l) : 2;   // children per parent
     if (ps.status == ST_RUNNING) {
         if (commit && (int64_t)K > ps.peak) st->peak = K;
-        if (2LL * K > (int64_t)I.M) {
+        if (nc * K > (int64_t)I.M) {
             if (commit) {
                 st->status = ST_MEMLIMIT;
                 signal_host(I);
             }
-        } else if (2LL * K > (int64_t)I.cap || (I.retire && 2 * ps.a_live > I.hcap)) {
+        } else if (nc * K > (int64_t)I.cap || (I.retire && 2 * ps.a_live > I.hcap)) {
             if (commit) {
                 st->status = ST_GROW;
                 signal_host(I);
@@ -206,7 +208,7 @@ __device__ __forceinline__ void plan_one(const DevInst& I, bool commit, long lon
         } else {
             const int c = unit_class(I, ps);
             v[c] = c == 2 ? step_units(I, ps) : step_tiles(I, ps);
-            if (c == 2) v[3] = (long long)K * 2 * I.rows;
+            if (c == 2) v[3] = (long long)K * nc * I.rows;
         }
     }
     si.K = K;
@@ -345,6 +347,54 @@ __device__ __forceinline__ void transform_fibre_m(int m, double* x, int base, in
     }
 }
 
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+// `items` fibres of length m, fibre `it` at addr(it) with the given stride,
+// each replaced in place by T x (T: m x m, row-major in LDS, FP64), on the
+// matrix cores: each wave takes blocks of 16 fibres and runs ceil(m/4) steps
+// of the 16x16x4 FP64 MFMA.  Lane (c, q) (c = lane % 16, q = lane / 16)
+// supplies row c, column 4s + q of T and row 4s + q of fibre c, and receives
+// rows q, q + 4, q + 8, q + 12 of the transformed fibre c.  Rows and columns
+// beyond m are zero, so each output is a sum of the m products of its row, in
+// some order: at most m roundings on any term's path (gamma_m, whatever the
+// order).  A wave reads a block's fibres before it writes them and no other
+// wave touches them.
+template <typename Addr>
+__device__ __forceinline__ void mfma_fibres_f64(int items, int m, int stride, const double* T, Addr addr)
+{
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const int col = lane & 15, kq = lane >> 4;
+    const int ks = (m + 3) >> 2;
+    double a[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        const int i = 4 * s + kq;
+        a[s] = (col < m && i < m) ? T[col * m + i] : 0.0;
+    }
+    const int nblk = (items + 15) >> 4;
+    for (int blk = w; blk < nblk; blk += nw) {
+        const int it = blk * 16 + col;
+        const bool v = it < items;
+        double* x = v ? addr(it) : nullptr;
+        double b[4];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const int i = 4 * s + kq;
+            b[s] = (s < ks && v && i < m) ? x[i * stride] : 0.0;
+        }
+        f64x4 d = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+            if (s < ks)   // uniform over the wave
+                d = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s], b[s], d, 0, 0, 0);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int k = 4 * q + kq;
+            if (v && k < m) x[k * stride] = d[q];
+        }
+    }
+}
+
 // One axis of a run of polynomials staged in LDS slots (polynomial q of the
 // run at slot + q * slot_stride, a second chain at + chain_off when nchain is
 // 2): every (chain, polynomial, fibre) of the run is one work item of the
@@ -358,6 +408,7 @@ __device__ __forceinline__ void transform_fibre_m(int m, double* x, int base, in
 struct MatOffs {
     int first[KINDS], second[KINDS];
 };
+template <bool MFMA>
 __device__ __forceinline__ void run_axis(double* slot, int slot_stride, int chain_off, int nchain, int pb,
                                          int pe, int c0, int c1, const AxisGeo (*geo)[MAXL], int r,
                                          const double* mats, const MatOffs& mo)
@@ -381,6 +432,18 @@ __device__ __forceinline__ void run_axis(double* slot, int slot_stride, int chai
         const bool two = o1 >= 0;
         const int per = g.F * nchain;
         const int items = (q1 - q0) * per;
+        if (MFMA) {
+            // every (polynomial, chain, fibre) of the kind with one matrix; the
+            // second matrix, if any, in a second pass
+            auto addr = [&](int it) {
+                const int q = it / per, rem = it - q * per;
+                const int ch = rem / g.F, f = rem - ch * g.F;
+                return slot + (q0 - pb + q) * slot_stride + ch * chain_off + fibre_base(g, f);
+            };
+            mfma_fibres_f64(items, g.m, g.stride, T0, addr);
+            if (two) mfma_fibres_f64(items, g.m, g.stride, T1, addr);
+            continue;
+        }
         for (int it = threadIdx.x; it < items; it += blockDim.x) {
             const int q = it / per, rem = it - q * per;
             const int ch = rem / g.F, f = rem - ch * g.F;
@@ -514,7 +577,7 @@ __global__ __launch_bounds__(256) void k_root(const DevInst* __restrict__ insts,
             mo.first[t] = s_mo[t][r];
             mo.second[t] = s_mo[t][r] + s_geo[t][r].m * s_geo[t][r].m;
         }
-        run_axis(slot, max_S, 0, 1, pb, pe, c0, c1, s_geo, r, mats, mo);
+        run_axis<false>(slot, max_S, 0, 1, pb, pe, c0, c1, s_geo, r, mats, mo);
         __syncthreads();
     }
     for (int p0 = pb; p0 < pe; p0 += nw) {
@@ -791,6 +854,120 @@ __device__ __forceinline__ void tile_split(int np, int S, const FibreGeom& g, T*
     }
 }
 
+// C(n, k) in FP32, exact for n <= 15 (every partial product is an integer
+// below 2^17 and every division is exact)
+__device__ __forceinline__ float binom_f(int n, int k)
+{
+    if (k < 0 || k > n) return 0.0f;
+    float c = 1.0f;
+    for (int i = 1; i <= k; ++i) c = c * (float)(n - k + i) / (float)i;
+    return c;
+}
+
+// Entries of the midpoint subdivision matrices of Sec. II-E for fibres of
+// length m (degree n = m - 1), row k (child coefficient) and column i (parent
+// coefficient): the left half's coefficient k is sum_{i <= k} C(k,i) 2^-k b_i,
+// the right half's sum_{i >= k} C(n-k, i-k) 2^-(n-k) b_i.  The entries are
+// dyadic with numerators below 2^13, so exact in FP32; rows are non-negative
+// and sum to one.
+__device__ __forceinline__ float split_left(int m, int k, int i)
+{
+    return (k < m && i <= k) ? ldexpf(binom_f(k, i), -k) : 0.0f;
+}
+__device__ __forceinline__ float split_right(int m, int k, int i)
+{
+    const int n = m - 1;
+    return (k < m && i >= k && i < m) ? ldexpf(binom_f(n - k, i - k), -(n - k)) : 0.0f;
+}
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// FP32 tiles: the split as a fixed-matrix contraction on the matrix cores.
+// The fibres of the tile along direction r are the columns of X (m x TF); the
+// children are S_L X and S_R X.  Each wave takes blocks of 16 fibres and runs
+// ceil(m/4) steps of the 16x16x4 FP32 MFMA per child: lane (c, q) (c = lane %
+// 16, q = lane / 16) supplies row c, column 4s + q of S and row 4s + q of
+// fibre c, and receives child coefficients 4q..4q+3 of fibre c.  Rows and
+// columns beyond m are zero, so every output sums exactly the m products of
+// its row.  Results go back as tile_split leaves them: the left child in
+// place in a, the right child in b, per-patch min/max of both children and
+// max |parent| folded into key.  A wave reads a block's fibres before it
+// writes them and no other wave touches them, so the in-place write is safe.
+// Rounding: each output is a sum of m products with non-negative weights
+// summing to one, evaluated in some order with at most m roundings on any
+// term's path, so |c~ - c| <= gamma_m max |b| (with u = 2^-23, covering the
+// unit's internal rounding) plus m 2^-126 for flushed subnormals: the bound
+// the caller carries for the split.
+__device__ __forceinline__ void tile_split_mfma(int np, int S, const FibreGeom& g, float* a, float* b,
+                                                unsigned* key)
+{
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const int col = lane & 15, kq = lane >> 4;
+    const int m = g.m, ks = (m + 3) >> 2;
+    float aL[4], aR[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        aL[s] = split_left(m, col, 4 * s + kq);
+        aR[s] = split_right(m, col, 4 * s + kq);
+    }
+    const int TF = np * g.F;
+    const int nblk = (TF + 15) >> 4;
+    for (int blk = w; blk < nblk; blk += nw) {
+        const int f = blk * 16 + col;
+        const bool fv = f < TF;
+        int p = 0, base = 0;
+        if (fv) {
+            p = f / g.F;
+            base = p * S + fibre_base(g, f - p * g.F);
+        }
+        float x[4];
+        float amax = 0.0f;
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const int i = 4 * s + kq;
+            x[s] = (s < ks && fv && i < m) ? a[base + i * g.stride] : 0.0f;
+            amax = fmaxf(amax, fabsf(x[s]));
+        }
+        f32x4 dL = {0.0f, 0.0f, 0.0f, 0.0f}, dR = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            if (s < ks) {   // uniform over the wave
+                dL = __builtin_amdgcn_mfma_f32_16x16x4f32(aL[s], x[s], dL, 0, 0, 0);
+                dR = __builtin_amdgcn_mfma_f32_16x16x4f32(aR[s], x[s], dR, 0, 0, 0);
+            }
+        }
+        float mnL = INFINITY, mxL = -INFINITY, mnR = INFINITY, mxR = -INFINITY;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int k = 4 * kq + q;
+            if (fv && k < m) {
+                a[base + k * g.stride] = dL[q];
+                b[base + k * g.stride] = dR[q];
+                mnL = fminf(mnL, dL[q]);
+                mxL = fmaxf(mxL, dL[q]);
+                mnR = fminf(mnR, dR[q]);
+                mxR = fmaxf(mxR, dR[q]);
+            }
+        }
+        // the four lanes of a fibre (lane, lane ^ 16, lane ^ 32, lane ^ 48)
+#pragma unroll
+        for (int o = 16; o < 64; o <<= 1) {
+            mnL = fminf(mnL, __shfl_xor(mnL, o, 64));
+            mxL = fmaxf(mxL, __shfl_xor(mxL, o, 64));
+            mnR = fminf(mnR, __shfl_xor(mnR, o, 64));
+            mxR = fmaxf(mxR, __shfl_xor(mxR, o, 64));
+            amax = fmaxf(amax, __shfl_xor(amax, o, 64));
+        }
+        if (fv && kq == 0) {
+            atomicMin(&key[5 * p + 0], fkey(mnL));
+            atomicMax(&key[5 * p + 1], fkey(mxL));
+            atomicMin(&key[5 * p + 2], fkey(mnR));
+            atomicMax(&key[5 * p + 3], fkey(mxR));
+            atomicMax(&key[5 * p + 4], fkey(amax));
+        }
+    }
+}
+
 __device__ __forceinline__ long long uniform64(long long x)
 {
     const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)(x & 0xffffffffll));
@@ -867,11 +1044,13 @@ __device__ __forceinline__ void child_bounds(T mn, T mx, double e, double base, 
 // One tile of k_sub (all fields uniform over the workgroup).
 struct PackUnit {
     int bi, kind, np, S, TE, cur, r, gath;
+    int nc;           // children per parent: 2, or 2^l = 4 when the step is a round
     long long P0;     // first patch of the tile in the problem's sequence of this kind
     float invS;
     double pprev;
     uint32_t stamp;
-    FibreGeom g;
+    FibreGeom g;      // fibres of the split (a round: of axis 0)
+    FibreGeom g2;     // a round: fibres of axis 1
 };
 
 // Resolves unit u: the problem (hint only moves forward, since a block's
@@ -924,7 +1103,14 @@ __device__ __forceinline__ void resolve_packed(const DevInst* __restrict__ insts
     c.invS = 1.0f / (float)c.S;
     c.TE = c.np * c.S;
     c.gath = I.retire && c.kind == 1;
-    c.g = fibre_geom(I.dims[c.kind], I.l, c.r, c.S);
+    c.nc = I.fused ? (1 << I.l) : 2;
+    if (c.nc == 4) {
+        c.g = fibre_geom(I.dims[c.kind], I.l, 0, c.S);
+        c.g2 = fibre_geom(I.dims[c.kind], I.l, 1, c.S);
+    } else {
+        c.g = fibre_geom(I.dims[c.kind], I.l, I.fused ? 0 : c.r, c.S);
+        c.g2 = c.g;
+    }
 }
 
 // Patch p of a tile: its parent j, the parent's slot, its index in its kind,
@@ -1011,7 +1197,7 @@ __device__ __forceinline__ int3 block_scan3(int3 x, int3& excl, int* sc)
 template <typename T, int MM, int LB, bool FUSE>
 __global__ __launch_bounds__(SUB_THREADS) void k_sub(const DevInst* __restrict__ insts, int n_inst,
                                                     long long* __restrict__ plan,
-                                                    StepInfo* __restrict__ info, int tem, int tpm)
+                                                    StepInfo* __restrict__ info, int tem, int tpm, int nr)
 {
     typedef typename KeyOf<T>::type K;
     extern __shared__ __align__(16) unsigned char smem[];
@@ -1082,26 +1268,30 @@ __global__ __launch_bounds__(SUB_THREADS) void k_sub(const DevInst* __restrict__
         q8 += (bytes + 15) & ~(size_t)15;
         return r;
     };
-    T* La = (T*)carve((size_t)tem * sizeof(T));
-    T* Lb = (T*)carve((size_t)tem * sizeof(T));
-    K* Lkey = (K*)carve((size_t)5 * tpm * sizeof(K));
+    // the tile and its children: nr regions (2, or 4 when a problem of the
+    // launch splits whole rounds), packed at the tile's own size TE: region q
+    // at La + q TE
+    T* La = (T*)carve((size_t)nr * tem * sizeof(T));
+    // per patch: 5 keys of the split (min, max of both halves, max |parent|);
+    // a round's second split adds 5 per half
+    K* Lkey = (K*)carve((size_t)5 * tpm * (nr > 2 ? 3 : 1) * sizeof(K));
     // the two patch tables (current and next tile) are chosen by selects, not
     // by an indexed per-thread array, so that their accesses stay LDS ones
     long long* Lsrc0 = (long long*)carve((size_t)tpm * 8);
     long long* Lsrc1 = (long long*)carve((size_t)tpm * 8);
-    T* Lshift = (T*)carve((size_t)2 * tpm * sizeof(T));
+    T* Lshift = (T*)carve((size_t)nr * tpm * sizeof(T));
     int4* Linf0 = (int4*)carve((size_t)tpm * 16);
     int4* Linf1 = (int4*)carve((size_t)tpm * 16);
     int* Lwm = (int*)carve((size_t)tpm * 4);          // per patch: children to write (bit c)
     int* Lpre = (int*)carve((size_t)(2 * tpm + 2) * 4);  // per patch: scan of kept (child 0, child 1)
     int* Ldst = (int*)carve((size_t)2 * tpm * 4);     // per patch and child: heap patch or -1
-    uint32_t* Lsfl = (uint32_t*)carve((size_t)2 * tpm * 4);  // per segment and child: flags
+    uint32_t* Lsfl = (uint32_t*)carve((size_t)nr * tpm * 4);  // per segment and child: flags
     int* Lpos = (int*)carve((size_t)2 * tpm * 4);     // per segment and child: list position
     int* Lseg = (int*)carve((size_t)(tpm + 1) * 4);   // per segment: first patch
 
     const int tid = threadIdx.x;
     int hint = 0;
-    PackUnit c, nc;
+    PackUnit c, cn;   // this tile and the next
     T v[LB];
     float ce = 0.0f, ne = 0.0f;     // FP32: this thread's patch's carried error (current, next tile)
     double cb = 0.0, nb = 0.0;      // and its FP64 base
@@ -1129,8 +1319,10 @@ __global__ __launch_bounds__(SUB_THREADS) void k_sub(const DevInst* __restrict__
 
     for (;;) {
         const DevInst& I = insts[c.bi];
-        const int kind = c.kind, np = c.np, S = c.S, TE = c.TE, cur = c.cur, r = c.r, l = I.l;
+        const int kind = c.kind, np = c.np, S = c.S, TE = c.TE, cur = c.cur, r = c.r, l = I.l, nc = c.nc;
         const int4* inf = bufi ? Linf1 : Linf0;
+        T* Lb = La + TE;          // the right half of the (first) split
+        K* Lkey2 = Lkey + 5 * np;   // a round: keys of the second split, 5 per (half, patch)
         // current tile: registers -> LDS; keys and segment flags reset
 #pragma unroll
         for (int q = 0; q < LB; ++q) {
@@ -1138,13 +1330,17 @@ __global__ __launch_bounds__(SUB_THREADS) void k_sub(const DevInst* __restrict__
             if (e < TE) La[e] = v[q];
         }
         if (tid < np) {
-            Lkey[5 * tid + 0] = ~(K)0;
-            Lkey[5 * tid + 1] = 0;
-            Lkey[5 * tid + 2] = ~(K)0;
-            Lkey[5 * tid + 3] = 0;
-            Lkey[5 * tid + 4] = 0;
-            Lsfl[2 * tid] = 0;
-            Lsfl[2 * tid + 1] = 0;
+            for (int h = 0; h < (nc == 4 ? 3 : 1); ++h) {
+                // h = 0: the patch's first split; h = 1, 2: the second split of
+                // its halves (keys at Lkey2 + 5 (half * np + patch))
+                K* kk = Lkey + 5 * (h * np + tid);
+                kk[0] = ~(K)0;
+                kk[1] = 0;
+                kk[2] = ~(K)0;
+                kk[3] = 0;
+                kk[4] = 0;
+            }
+            for (int ch = 0; ch < nr; ++ch) Lsfl[nr * tid + ch] = 0;
         }
         // next tile: resolve it and start loading its patch table
         const long long un = u + gridDim.x;
@@ -1152,87 +1348,114 @@ __global__ __launch_bounds__(SUB_THREADS) void k_sub(const DevInst* __restrict__
         int4 ninf = make_int4(0, 0, 0, 0);
         long long nsrc = 0;
         if (more) {
-            resolve_packed(insts, n_inst, pre, sinfo, un, hint, nc);
-            if (tid < nc.np) patch_info(insts[nc.bi], nc, tid, ninf, nsrc);
+            resolve_packed(insts, n_inst, pre, sinfo, un, hint, cn);
+            if (tid < cn.np) patch_info(insts[cn.bi], cn, tid, ninf, nsrc);
         }
         lds_barrier();
-        tile_split<T, MM>(np, S, c.g, La, Lb, Lkey);
+        // the split: FP32 tiles on the matrix cores, FP64 plain tiles by de
+        // Casteljau as the oracle does.  A round splits along axis 0 (halves in
+        // regions 0 and 1), then both halves along axis 1 (the right quarters to
+        // regions 2 and 3): region b0 + 2 b1 holds the child with bit b0 on axis 0
+        // and b1 on axis 1, the same sequence of operations as the oracle's.
+        if constexpr (sizeof(T) == 4)
+            tile_split_mfma(np, S, c.g, La, Lb, Lkey);
+        else
+            tile_split<T, MM>(np, S, c.g, La, Lb, Lkey);
+        if (nc == 4) {
+            lds_barrier();
+            if constexpr (sizeof(T) == 4)
+                tile_split_mfma(2 * np, S, c.g2, La, La + 2 * TE, Lkey2);
+            else
+                tile_split<T, MM>(2 * np, S, c.g2, La, La + 2 * TE, Lkey2);
+        }
         // the next patch table to LDS (its loads had the split to arrive)
-        if (more && tid < nc.np) {
+        if (more && tid < cn.np) {
             (bufi ? Linf0 : Linf1)[tid] = ninf;
             (bufi ? Lsrc0 : Lsrc1)[tid] = nsrc;
         }
         lds_barrier();
         // next tile's coefficients (and FP32 error bounds and bases) in flight
         if (more) {
-            const DevInst& In = insts[nc.bi];
-            issue_packed<T, LB>(In, nc, bufi ? Lsrc0 : Lsrc1, v);
-            if (fp32 && tid < nc.np) {
-                const int poly = nc.kind == 0 ? 0 : In.count[0] + (nc.kind == 2 ? In.count[1] : 0) + ninf.z;
+            const DevInst& In = insts[cn.bi];
+            issue_packed<T, LB>(In, cn, bufi ? Lsrc0 : Lsrc1, v);
+            if (fp32 && tid < cn.np) {
+                const int poly = cn.kind == 0 ? 0 : In.count[0] + (cn.kind == 2 ? In.count[1] : 0) + ninf.z;
                 const int64_t pi = (int64_t)ninf.y * In.n_polys + poly;
-                ne = as_global(In.err[nc.cur])[pi];
-                nb = as_global(In.base[nc.cur])[pi];
+                ne = as_global(In.err[cn.cur])[pi];
+                nb = as_global(In.base[cn.cur])[pi];
             }
         }
 
-        // per patch (thread p): bounds of both children (widened in FP32 mode),
+        // per patch (thread p): bounds of every child (widened in FP32 mode),
         // records (cost) or flags (constraints)
         const bool act = tid < np;
         const int p = tid;
         int j = 0, slot = 0, id = 0, poly = 0;
-        uint32_t f2[2] = {0, 0};
-        double lo[2] = {0.0, 0.0}, hi[2] = {0.0, 0.0};
+        uint32_t f2[NCMAX] = {0, 0, 0, 0};
+        double lo[NCMAX] = {0.0, 0.0, 0.0, 0.0}, hi[NCMAX] = {0.0, 0.0, 0.0, 0.0};
         if (act) {
             const int4 ip = inf[p];
             j = ip.x;
             slot = ip.y;
             id = ip.z;
             poly = kind == 0 ? 0 : I.count[0] + (kind == 2 ? I.count[1] : 0) + id;
-            double e = 0.0, base = 0.0;
-            if (fp32) {
-                // the stored values are offsets from the patch's FP64 base, which
-                // subdivision keeps (rows sum to one); the split's error grows with
-                // the offsets.  Each child is then re-centred: its base moves by
-                // its midrange offset mc and its offsets become v - mc, so that they
-                // shrink with the box; the shift adds the rounding of v - mc (below
-                // 2^-24 (max - min)) and of the new FP64 base.
-                base = cb;
-                e = (double)round_up_f((double)ce + gamma32(c.g.m) * (double)funkey(Lkey[5 * p + 4]) +
-                                       (double)c.g.m * 0x1p-126);
-                for (int ch = 0; ch < 2; ++ch) {
-                    const float mn = (float)funkey(Lkey[5 * p + 2 * ch]);
-                    const float mx = (float)funkey(Lkey[5 * p + 2 * ch + 1]);
-                    const float mc = 0.5f * mn + 0.5f * mx;
+            // FP32: the split's rounding bound over the parent's offsets (for a
+            // round, the first split's; the second adds its own per half)
+            const double e1 = fp32 ? (double)ce + gamma32(c.g.m) * (double)funkey(Lkey[5 * p + 4]) +
+                                         (double)c.g.m * 0x1p-126
+                                   : 0.0;
+            for (int ch = 0; ch < nc; ++ch) {
+                // the keys of child ch: one split, half ch; a round, half b0 of the
+                // first split and then half b1 of the second
+                const int b0 = nc == 4 ? (ch >> 1) : ch, b1 = ch & 1;
+                const K* kk = nc == 4 ? Lkey2 + 5 * (b0 * np + p) + 2 * b1 : Lkey + 5 * p + 2 * b0;
+                const T mn = funkey(kk[0]), mx = funkey(kk[1]);
+                double e = 0.0, base = 0.0;
+                if (fp32) {
+                    // the stored values are offsets from the patch's FP64 base,
+                    // which subdivision keeps (rows sum to one); the split's error
+                    // grows with the offsets.  Each child is then re-centred: its
+                    // base moves by its midrange offset mc and its offsets become
+                    // v - mc, so that they shrink with the box; the shift adds the
+                    // rounding of v - mc (below 2^-24 (max - min)) and of the new
+                    // FP64 base.
+                    base = cb;
+                    double ee = e1;
+                    if (nc == 4)
+                        ee += gamma32(c.g2.m) * (double)funkey(Lkey2[5 * (b0 * np + p) + 4]) +
+                              (double)c.g2.m * 0x1p-126;
+                    e = (double)round_up_f(ee);
+                    const float mc = 0.5f * (float)mn + 0.5f * (float)mx;
                     const double nbs = base + (double)mc;
-                    const int64_t ci = (int64_t)(2 * j + ch) * I.n_polys + poly;
+                    const int64_t ci = (int64_t)(nc * j + ch) * I.n_polys + poly;
                     as_global(I.err[cur ^ 1])[ci] = round_up_f(e + ((double)mx - (double)mn) * 0x1p-23 +
                                                                fabs(nbs) * 0x1p-52 + 0x1p-126);
                     as_global(I.base[cur ^ 1])[ci] = nbs;
                     Lshift[ch * tpm + p] = (T)mc;
                 }
+                child_bounds<T>(mn, mx, e, base, lo[ch], hi[ch]);
             }
-            for (int ch = 0; ch < 2; ++ch)
-                child_bounds<T>(funkey(Lkey[5 * p + 2 * ch]), funkey(Lkey[5 * p + 2 * ch + 1]), e, base, lo[ch],
-                                hi[ch]);
             if (kind == 0) {
                 // cost records, child ids, then the stamp that publishes the records
-                as_global(I.minP)[2 * j] = lo[0];
-                as_global(I.maxP)[2 * j] = hi[0];
-                as_global(I.minP)[2 * j + 1] = lo[1];
-                as_global(I.maxP)[2 * j + 1] = hi[1];
                 const gmem_t<const uint32_t> pid = as_global((const uint32_t*)I.ids[cur]) + (int64_t)slot * l;
-                const gmem_t<uint32_t> cid = as_global(I.ids[cur ^ 1]) + (int64_t)(2 * j) * l;
-                for (int k = 0; k < l; ++k) {
-                    const uint32_t vv = pid[k];
-                    cid[k] = (k == r) ? 2u * vv : vv;
-                    cid[l + k] = (k == r) ? 2u * vv + 1u : vv;
+                const gmem_t<uint32_t> cid = as_global(I.ids[cur ^ 1]) + (int64_t)(nc * j) * l;
+                for (int ch = 0; ch < nc; ++ch) {
+                    as_global(I.minP)[nc * j + ch] = lo[ch];
+                    as_global(I.maxP)[nc * j + ch] = hi[ch];
+                    for (int k = 0; k < l; ++k) {
+                        const uint32_t vv = pid[k];
+                        // a round halves every axis (bit l-1-k of ch is axis k's half)
+                        const bool split = I.fused || k == r;
+                        const uint32_t half = I.fused ? (uint32_t)((ch >> (l - 1 - k)) & 1) : (uint32_t)ch;
+                        cid[ch * l + k] = split ? 2u * vv + half : vv;
+                    }
                 }
-                if (I.stale) {
-                    __hip_atomic_store(&I.stamp[2 * j], c.stamp, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-                    __hip_atomic_store(&I.stamp[2 * j + 1], c.stamp, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-                }
+                if (I.stale)
+                    for (int ch = 0; ch < nc; ++ch)
+                        __hip_atomic_store(&I.stamp[nc * j + ch], c.stamp, __ATOMIC_RELEASE,
+                                           __HIP_MEMORY_SCOPE_AGENT);
             } else {
-                for (int ch = 0; ch < 2; ++ch) {
+                for (int ch = 0; ch < nc; ++ch) {
                     uint32_t f = 0;
                     if (kind == 1) {
                         if (lo[ch] > 0.0) f |= F_INFEAS;
@@ -1262,8 +1485,8 @@ __global__ __launch_bounds__(SUB_THREADS) void k_sub(const DevInst* __restrict__
             seg = ex.x + start - 1;
             if (act) {
                 if (start) Lseg[seg] = p;
-                if (f2[0]) atomicOr(&Lsfl[2 * seg], f2[0]);
-                if (f2[1]) atomicOr(&Lsfl[2 * seg + 1], f2[1]);
+                for (int ch = 0; ch < nc; ++ch)
+                    if (f2[ch]) atomicOr(&Lsfl[nr * seg + ch], f2[ch]);
                 Lpre[2 * p] = ex.y;
                 Lpre[2 * p + 1] = ex.z;
             }
@@ -1280,9 +1503,9 @@ __global__ __launch_bounds__(SUB_THREADS) void k_sub(const DevInst* __restrict__
             if (tid < s_nseg) {
                 const int a0 = Lseg[tid], a1 = Lseg[tid + 1];
                 const int js = inf[a0].x;
-                for (int ch = 0; ch < 2; ++ch) {
-                    const uint32_t f = Lsfl[2 * tid + ch];
-                    if (f) atomicOr(&I.flags[2 * js + ch], f);
+                for (int ch = 0; ch < nc; ++ch) {
+                    const uint32_t f = Lsfl[nr * tid + ch];
+                    if (f) atomicOr(&I.flags[nc * js + ch], f);
                     if (c.gath) {
                         const int cnt = Lpre[2 * a1 + ch] - Lpre[2 * a0 + ch];
                         Lpos[2 * tid + ch] = cnt ? atomicAdd(&I.na[cur ^ 1][2 * js + ch], cnt) : 0;
@@ -1300,8 +1523,8 @@ __global__ __launch_bounds__(SUB_THREADS) void k_sub(const DevInst* __restrict__
             // cost bound above the previous solution estimate)
             if (act) {
                 int wm = 0;
-                for (int ch = 0; ch < 2; ++ch) {
-                    const bool w = kind == 0 ? !(I.stale && lo[ch] > c.pprev) : !(Lsfl[2 * seg + ch] & F_INFEAS);
+                for (int ch = 0; ch < nc; ++ch) {
+                    const bool w = kind == 0 ? !(I.stale && lo[ch] > c.pprev) : !(Lsfl[nr * seg + ch] & F_INFEAS);
                     if (w) wm |= 1 << ch;
                 }
                 Lwm[p] = wm;
@@ -1309,35 +1532,34 @@ __global__ __launch_bounds__(SUB_THREADS) void k_sub(const DevInst* __restrict__
             lds_barrier();
             const gmem_t<T> dbuf = as_global((T*)I.buf[cur ^ 1]);
             constexpr int SB = 8;
-            for (int e0 = tid; e0 < TE; e0 += SB * SUB_THREADS) {
-                T va[SB], vb[SB];
-                int pp[SB];
+            // child ch of a parent is region ch of the split, or for a round
+            // region b0 + 2 b1 (its halves on axes 0 and 1); it goes to slot nc j + ch
+            for (int ch = 0; ch < nc; ++ch) {
+                const T* src = La + (nc == 4 ? (ch >> 1) + 2 * (ch & 1) : ch) * TE;
+                for (int e0 = tid; e0 < TE; e0 += SB * SUB_THREADS) {
+                    T va[SB];
+                    int pp[SB];
 #pragma unroll
-                for (int q = 0; q < SB; ++q) {
-                    const int e = e0 + q * SUB_THREADS;
-                    pp[q] = -1;
-                    if (e < TE) {
-                        const int pq = patch_of(e, c.invS);
-                        pp[q] = pq;
-                        va[q] = La[e];
-                        vb[q] = Lb[e];
-                        if (fp32) {
-                            va[q] -= Lshift[pq];
-                            vb[q] -= Lshift[tpm + pq];
+                    for (int q = 0; q < SB; ++q) {
+                        const int e = e0 + q * SUB_THREADS;
+                        pp[q] = -1;
+                        if (e < TE) {
+                            const int pq = patch_of(e, c.invS);
+                            pp[q] = pq;
+                            va[q] = src[e];
+                            if (fp32) va[q] -= Lshift[ch * tpm + pq];
                         }
                     }
-                }
 #pragma unroll
-                for (int q = 0; q < SB; ++q) {
-                    const int e = e0 + q * SUB_THREADS;
-                    if (pp[q] >= 0) {
-                        const int pq = pp[q];
-                        const int4 ip = inf[pq];
-                        const int w2 = Lwm[pq];
-                        const int64_t o = (int64_t)(2 * ip.x) * I.stride + I.soff[kind] + (int64_t)ip.z * S +
-                                          (e - pq * S);
-                        if (w2 & 1) dbuf[o] = va[q];
-                        if (w2 & 2) dbuf[o + I.stride] = vb[q];
+                    for (int q = 0; q < SB; ++q) {
+                        const int e = e0 + q * SUB_THREADS;
+                        if (pp[q] >= 0) {
+                            const int pq = pp[q];
+                            const int4 ip = inf[pq];
+                            if ((Lwm[pq] >> ch) & 1)
+                                dbuf[(int64_t)(nc * ip.x + ch) * I.stride + I.soff[kind] + (int64_t)ip.z * S +
+                                     (e - pq * S)] = va[q];
+                        }
                     }
                 }
             }
@@ -1377,7 +1599,7 @@ __global__ __launch_bounds__(SUB_THREADS) void k_sub(const DevInst* __restrict__
         }
         lds_barrier();
         if (!more) break;
-        c = nc;
+        c = cn;
         u = un;
         ce = ne;
         cb = nb;
@@ -1388,8 +1610,9 @@ __global__ __launch_bounds__(SUB_THREADS) void k_sub(const DevInst* __restrict__
 // ------------------------------------------------------------------ k_rederive
 
 // Applies tmat (one m x m matrix per axis) to np patches in LDS (FP64), axis
-// by axis, in place: each thread takes whole fibres, reads one into registers
-// and writes the transformed fibre back (every output sums over i in order).
+// by axis, in place, as FP64 matrix-core products (mfma_fibres_f64): every
+// fibre of the chunk along axis r is a column of one product with the axis's
+// transform.
 __device__ void apply_tmats(double* x, const double* tm, const int* tmoff, const AxisGeo* geo, int l,
                             int S, int np)
 {
@@ -1400,12 +1623,10 @@ __device__ void apply_tmats(double* x, const double* tm, const int* tmoff, const
         g.stride = ag.stride;
         g.F = ag.F;
         const double* Tm = tm + tmoff[r];
-        const int TF = np * g.F;
-        for (int f = threadIdx.x; f < TF; f += blockDim.x) {
+        mfma_fibres_f64(np * g.F, g.m, g.stride, Tm, [&](int f) {
             const int p = f / g.F;
-            const int base = p * S + fibre_base(g, f - p * g.F);
-            transform_fibre_m(g.m, x, base, g.stride, Tm);
-        }
+            return x + p * S + fibre_base(g, f - p * g.F);
+        });
         __syncthreads();
     }
 }
@@ -1427,8 +1648,9 @@ __global__ __launch_bounds__(256) void k_tmat(const DevInst* __restrict__ insts,
         const DevInst& I = insts[bi];
         const InstState* st = I.st;
         const long long v = u - pre[bi];
-        const int j = (int)(v / (2 * I.rows));
-        int rem = (int)(v - (long long)j * 2 * I.rows);
+        const int nc = I.fused ? (1 << I.l) : 2;
+        const int j = (int)(v / (nc * I.rows));
+        int rem = (int)(v - (long long)j * nc * I.rows);
         const int c = rem / I.rows;
         rem -= c * I.rows;
         // locate (kind, axis, row) of this thread
@@ -1444,8 +1666,11 @@ __global__ __launch_bounds__(256) void k_tmat(const DevInst* __restrict__ insts,
         const int m = I.dims[kind][k], n = m - 1, row = rem;
         const int r = st->r, cur = st->cur;
         const uint32_t pid = I.ids[cur][(int64_t)I.live[j] * I.l + k];
-        const int d = st->depth[k] + (k == r ? 1 : 0);
-        const uint32_t idx = (k == r) ? 2u * pid + (uint32_t)c : pid;
+        // child c halves axis r (a round: every axis, bit l-1-k of c on axis k)
+        const bool split = I.fused || k == r;
+        const int d = st->depth[k] + (split ? 1 : 0);
+        const uint32_t half = I.fused ? (uint32_t)((c >> (I.l - 1 - k)) & 1) : (uint32_t)c;
+        const uint32_t idx = split ? 2u * pid + half : pid;
         const double a = ldexp((double)idx, -d), b = ldexp((double)idx + 1.0, -d);
         double Ba[MAXM], Bb[MAXM];
 #pragma unroll
@@ -1460,7 +1685,7 @@ __global__ __launch_bounds__(256) void k_tmat(const DevInst* __restrict__ insts,
             if (q <= n - row) Ba[0] = (1.0 - a) * Ba[0];
             if (q <= row) Bb[0] = (1.0 - b) * Bb[0];
         }
-        double* out = I.tmat + ((int64_t)j * 2 + c) * I.tmw + off + row * m;
+        double* out = I.tmat + ((int64_t)j * nc + c) * I.tmw + off + row * m;
 #pragma unroll
         for (int jj = 0; jj < MAXM; ++jj) {
             if (jj > n) break;
@@ -1482,7 +1707,7 @@ __global__ __launch_bounds__(SUB_THREADS) void k_rederive(const DevInst* __restr
                                                          const StepInfo* __restrict__ info)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ uint32_t s_flag[2];
+    __shared__ uint32_t s_flag[NCMAX];
     __shared__ int s_tmoff[MAXL];
     __shared__ AxisGeo s_geo[MAXL];
     __shared__ double s_base[REDERIVE_CHUNK];   // per patch of a chunk: FP64 base,
@@ -1497,6 +1722,7 @@ __global__ __launch_bounds__(SUB_THREADS) void k_rederive(const DevInst* __restr
         int j, t, mslot, mna;
         unit_of(I, u - pre[bi], si.K, j, t, mslot, mna);
         const int cur = si.cur, r = si.r, l = I.l;
+        const int nc = I.fused ? (1 << l) : 2;
         const int pslot = mslot >= 0 ? mslot : __builtin_amdgcn_readfirstlane(I.live[j]);
         const int kind = (t < I.tile_start[1]) ? 0 : ((t < I.tile_start[2]) ? 1 : 2);
         const int p0 = (t - I.tile_start[kind]) * I.tile_polys[kind];
@@ -1514,7 +1740,7 @@ __global__ __launch_bounds__(SUB_THREADS) void k_rederive(const DevInst* __restr
         for (int k = 0; k < l; ++k) tmsz += I.dims[kind][k] * I.dims[kind][k];
         double* x = (double*)smem;
         double* tm = x + min(np, cp) * S;
-        if (threadIdx.x < 2) s_flag[threadIdx.x] = 0;
+        if (threadIdx.x < NCMAX) s_flag[threadIdx.x] = 0;
         if (threadIdx.x == 0) {
             int o = 0;
             for (int k = 0; k < l; ++k) { s_tmoff[k] = o; o += I.dims[kind][k] * I.dims[kind][k]; }
@@ -1522,15 +1748,15 @@ __global__ __launch_bounds__(SUB_THREADS) void k_rederive(const DevInst* __restr
         }
         double g64 = 0.0;
         for (int k = 0; k < l; ++k) g64 += gamma64(6 * I.dims[kind][k] + 6);
-        for (int cc = 0; cc < 2 * ((np + cp - 1) / cp); ++cc) {
-            const int c = cc & 1;
-            const int q0 = (cc >> 1) * cp;
+        for (int cc = 0; cc < nc * ((np + cp - 1) / cp); ++cc) {
+            const int c = cc % nc;
+            const int q0 = (cc / nc) * cp;
             const int nq = min(cp, np - q0);
             const int TE = nq * S;
             // the chunk's patches in the root (root layout) and in a slot
             const int64_t roff = I.off[kind] + (gath ? 0 : (int64_t)(p0 + q0) * S);
             const int64_t soff = I.soff[kind] + (int64_t)(p0 + q0) * S;
-            const double* tsrc = I.tmat + ((int64_t)j * 2 + c) * I.tmw + I.tmk[kind];
+            const double* tsrc = I.tmat + ((int64_t)j * nc + c) * I.tmw + I.tmk[kind];
             copy_to_lds<double>(tm, tsrc, tmsz);
             if (!gath) {
                 copy_to_lds<double>(x, I.racc + roff, TE);
@@ -1542,7 +1768,7 @@ __global__ __launch_bounds__(SUB_THREADS) void k_rederive(const DevInst* __restr
             }
             __syncthreads();
             apply_tmats(x, tm, s_tmoff, s_geo, l, S, nq);
-            float* child = (float*)I.buf[cur ^ 1] + (int64_t)(2 * j + c) * I.stride;
+            float* child = (float*)I.buf[cur ^ 1] + (int64_t)(nc * j + c) * I.stride;
             float* hc = (float*)I.heap[cur ^ 1];
             uint32_t fl = 0;
             const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -1585,11 +1811,11 @@ __global__ __launch_bounds__(SUB_THREADS) void k_rederive(const DevInst* __restr
                     // retiring mode: an inequality certified satisfied is not carried
                     s_keep[p] = !(gath && hi <= 0.0);
                     s_base[p] = base;
-                    I.err[cur ^ 1][(int64_t)(2 * j + c) * I.n_polys + poly] = (float)e;
-                    I.base[cur ^ 1][(int64_t)(2 * j + c) * I.n_polys + poly] = base;
+                    I.err[cur ^ 1][(int64_t)(nc * j + c) * I.n_polys + poly] = (float)e;
+                    I.base[cur ^ 1][(int64_t)(nc * j + c) * I.n_polys + poly] = base;
                     if (kind == 0) {
-                        I.minP[2 * j + c] = lo;
-                        I.maxP[2 * j + c] = hi;
+                        I.minP[nc * j + c] = lo;
+                        I.maxP[nc * j + c] = hi;
                     } else if (kind == 1) {
                         if (lo > 0.0) fl |= F_INFEAS;
                         if (!(hi <= 0.0)) fl |= F_NOTFEAS;
@@ -1642,16 +1868,18 @@ __global__ __launch_bounds__(SUB_THREADS) void k_rederive(const DevInst* __restr
             __syncthreads();
         }
         if (threadIdx.x == 0) {
-            if (s_flag[0]) atomicOr(&I.flags[2 * j], s_flag[0]);
-            if (s_flag[1]) atomicOr(&I.flags[2 * j + 1], s_flag[1]);
+            for (int c = 0; c < nc; ++c)
+                if (s_flag[c]) atomicOr(&I.flags[nc * j + c], s_flag[c]);
             if (kind == 0) {
                 const uint32_t* pid = I.ids[cur] + (int64_t)pslot * l;
-                uint32_t* cid = I.ids[cur ^ 1] + (int64_t)(2 * j) * l;
-                for (int k = 0; k < l; ++k) {
-                    const uint32_t v = pid[k];
-                    cid[k] = (k == r) ? 2u * v : v;
-                    cid[l + k] = (k == r) ? 2u * v + 1u : v;
-                }
+                uint32_t* cid = I.ids[cur ^ 1] + (int64_t)(nc * j) * l;
+                for (int c = 0; c < nc; ++c)
+                    for (int k = 0; k < l; ++k) {
+                        const uint32_t v = pid[k];
+                        const bool split = I.fused || k == r;
+                        const uint32_t half = I.fused ? (uint32_t)((c >> (l - 1 - k)) & 1) : (uint32_t)c;
+                        cid[c * l + k] = split ? 2u * v + half : v;
+                    }
             }
         }
         __syncthreads();
@@ -1674,7 +1902,8 @@ __global__ __launch_bounds__(CUT_THREADS) void k_cut(const DevInst* __restrict__
     const DevInst& I = insts[blockIdx.x];
     InstState* st = I.st;
     if (st->status != ST_RUNNING) return;
-    const int K = st->K, C = 2 * K, r = st->r, cur = st->cur, l = I.l;
+    const int nc = I.fused ? (1 << I.l) : 2;   // children per parent (a round splits every axis)
+    const int K = st->K, C = nc * K, r = st->r, cur = st->cur, l = I.l;
     const int TP1 = I.tile_polys[1];
     const double pprev = st->p_up;
     const bool fin = pprev < INFINITY;
@@ -1684,9 +1913,10 @@ __global__ __launch_bounds__(CUT_THREADS) void k_cut(const DevInst* __restrict__
     // children's width
     const int steps0 = st->steps, n0 = st->n;
     const long long alive0 = st->a_live;
-    const int depth_k = tid < l ? st->depth[tid] + (tid == r ? 1 : 0) : 0;
+    const int depth_k = tid < l ? st->depth[tid] + ((I.fused || tid == r) ? 1 : 0) : 0;
     double width = 0.0;
-    for (int k = 0; k < l; ++k) width = fmax(width, ldexp(I.width0[k], -(st->depth[k] + (k == r ? 1 : 0))));
+    for (int k = 0; k < l; ++k)
+        width = fmax(width, ldexp(I.width0[k], -(st->depth[k] + ((I.fused || k == r) ? 1 : 0))));
 
     // the child records, read once: the first CUT_CACHE * blockDim children are
     // kept in registers for the three passes below, any further ones are read
@@ -1898,7 +2128,7 @@ __global__ __launch_bounds__(CUT_THREADS) void k_cut(const DevInst* __restrict__
 
     // clear the flags of the next step's children, and in retiring mode their
     // carried counts (they go to the buffer of this step's parents)
-    for (int c = tid; c < 2 * Kn && c < I.cap; c += blockDim.x) {
+    for (int c = tid; c < nc * Kn && c < I.cap; c += blockDim.x) {
         as_global(I.flags)[c] = 0;
         if (I.retire) as_global(I.na[cur])[c] = 0;
     }
@@ -1906,7 +2136,7 @@ __global__ __launch_bounds__(CUT_THREADS) void k_cut(const DevInst* __restrict__
     // per axis (thread k): its depth, and x*'s box if the estimate moved
     const int nxt = cur ^ 1;
     if (tid < l) {
-        if (tid == r) st->depth[tid] = depth_k;
+        if (I.fused || tid == r) st->depth[tid] = depth_k;
         if (update) {
             st->x_index[tid] = I.ids[nxt][(int64_t)arg * l + tid];
             st->x_depth[tid] = depth_k;
@@ -1942,7 +2172,8 @@ __global__ __launch_bounds__(CUT_THREADS) void k_cut(const DevInst* __restrict__
             st->status = ST_OPTIMAL;
             signal_host(I);
         } else {
-            const int rn = (r + 1) % l;
+            // a round leaves the direction at axis 0 and counts one iteration
+            const int rn = I.fused ? 0 : (r + 1) % l;
             st->r = rn;
             const int nn = n0 + (rn == 0 ? 1 : 0);
             st->n = nn;
@@ -2079,7 +2310,7 @@ __global__ __launch_bounds__(256) void k_certify(const DevInst* __restrict__ ins
             mo.first[t] = (t * l + r) * mm2;
             mo.second[t] = -1;
         }
-        run_axis(slot, 2 * max_S, max_S, 2, pb, pe, c0, c1, s_geo, r, tm, mo);
+        run_axis<true>(slot, 2 * max_S, max_S, 2, pb, pe, c0, c1, s_geo, r, tm, mo);
         __syncthreads();
     }
     for (int p0 = pb; p0 < pe; p0 += nw) {
@@ -2312,24 +2543,26 @@ hipError_t launch_plan(const DevInst* d_insts, int n, long long* plan, StepInfo*
 
 // Dynamic LDS bytes of k_sub for tiles of at most tem coefficients and tpm
 // patches (the carve-up at the kernel's start, 16-byte aligned pieces).
-size_t sub_lds_bytes(int tem, int tpm, bool fp32)
+size_t sub_lds_bytes(int tem, int tpm, bool fp32, int nr)
 {
     const size_t el = fp32 ? 4 : 8;
     auto r16 = [](size_t b) { return (b + 15) & ~(size_t)15; };
-    return 2 * r16((size_t)tem * el) + r16((size_t)5 * tpm * el) + 2 * r16((size_t)tpm * 8) +
-           r16((size_t)2 * tpm * el) + 2 * r16((size_t)tpm * 16) + r16((size_t)tpm * 4) +
-           r16((size_t)(2 * tpm + 2) * 4) + 3 * r16((size_t)2 * tpm * 4) + r16((size_t)(tpm + 1) * 4);
+    return r16((size_t)nr * tem * el) + r16((size_t)5 * tpm * (nr > 2 ? 3 : 1) * el) + 2 * r16((size_t)tpm * 8) +
+           r16((size_t)nr * tpm * el) + 2 * r16((size_t)tpm * 16) + r16((size_t)tpm * 4) +
+           r16((size_t)(2 * tpm + 2) * 4) + r16((size_t)2 * tpm * 4) + r16((size_t)nr * tpm * 4) +
+           r16((size_t)2 * tpm * 4) + r16((size_t)(tpm + 1) * 4);
 }
 
 // With ev0/ev1 the launch stamps them at the kernel's own start and end.
 template <typename T, int MM, bool FUSE>
 static hipError_t launch_sub_t(const DevInst* d_insts, int n, long long* plan, StepInfo* info, int grid,
-                               int tem, int tpm, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1)
+                               int tem, int tpm, int nr, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1)
 {
     // registers per thread for a tile in flight: the largest tile / 256 lanes
     constexpr int LB = (sizeof(T) == 8 ? MAX_TILE64 : MAX_TILE32) / SUB_THREADS;
-    if (tem > LB * SUB_THREADS || tpm < 1 || tpm > SUB_THREADS) return hipErrorInvalidValue;
-    const size_t lds = sub_lds_bytes(tem, tpm, sizeof(T) == 4);
+    if (tem > LB * SUB_THREADS || tpm < 1 || tpm > SUB_THREADS || (nr != 2 && nr != NCMAX))
+        return hipErrorInvalidValue;
+    const size_t lds = sub_lds_bytes(tem, tpm, sizeof(T) == 4, nr);
     // no more workgroups than fit on the device at once: the rest would only
     // queue, while resident ones walk the units with the next tile in flight
     const int cus = device_props(current_device()).cus;
@@ -2337,23 +2570,23 @@ static hipError_t launch_sub_t(const DevInst* d_insts, int n, long long* plan, S
     if (cus > 0 && per_cu > 0) grid = std::min(grid, cus * per_cu);
     if (ev0)
         hipExtLaunchKernelGGL((k_sub<T, MM, LB, FUSE>), dim3(grid), dim3(SUB_THREADS), lds, s, ev0, ev1, 0,
-                              d_insts, n, plan, info, tem, tpm);
+                              d_insts, n, plan, info, tem, tpm, nr);
     else
         hipLaunchKernelGGL((k_sub<T, MM, LB, FUSE>), dim3(grid), dim3(SUB_THREADS), lds, s, d_insts, n, plan,
-                           info, tem, tpm);
+                           info, tem, tpm, nr);
     return hipGetLastError();
 }
 
 template <typename T, int MM>
 static hipError_t launch_sub_f(const DevInst* d_insts, int n, long long* plan, StepInfo* info, bool fuse,
-                               int grid, int tem, int tpm, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1)
+                               int grid, int tem, int tpm, int nr, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1)
 {
-    if (fuse) return launch_sub_t<T, MM, true>(d_insts, n, plan, info, grid, tem, tpm, s, ev0, ev1);
-    return launch_sub_t<T, MM, false>(d_insts, n, plan, info, grid, tem, tpm, s, ev0, ev1);
+    if (fuse) return launch_sub_t<T, MM, true>(d_insts, n, plan, info, grid, tem, tpm, nr, s, ev0, ev1);
+    return launch_sub_t<T, MM, false>(d_insts, n, plan, info, grid, tem, tpm, nr, s, ev0, ev1);
 }
 
 hipError_t launch_sub(const DevInst* d_insts, int n, long long* plan, StepInfo* info, bool fuse,
-                      bool fp32, int maxm, int grid, int tem, int tpm, hipStream_t s, hipEvent_t ev0,
+                      bool fp32, int maxm, int grid, int tem, int tpm, int nr, hipStream_t s, hipEvent_t ev0,
                       hipEvent_t ev1)
 {
     if (fuse && n > PLAN_FUSE_MAX) return hipErrorInvalidValue;
@@ -2362,11 +2595,12 @@ hipError_t launch_sub(const DevInst* d_insts, int n, long long* plan, StepInfo* 
         grid = 1;   // the plan is still formed and written
     }
     if (fp32) {
-        if (maxm <= 8) return launch_sub_f<float, 8>(d_insts, n, plan, info, fuse, grid, tem, tpm, s, ev0, ev1);
-        return launch_sub_f<float, 16>(d_insts, n, plan, info, fuse, grid, tem, tpm, s, ev0, ev1);
+        if (maxm <= 8)
+            return launch_sub_f<float, 8>(d_insts, n, plan, info, fuse, grid, tem, tpm, nr, s, ev0, ev1);
+        return launch_sub_f<float, 16>(d_insts, n, plan, info, fuse, grid, tem, tpm, nr, s, ev0, ev1);
     }
-    if (maxm <= 8) return launch_sub_f<double, 8>(d_insts, n, plan, info, fuse, grid, tem, tpm, s, ev0, ev1);
-    return launch_sub_f<double, 16>(d_insts, n, plan, info, fuse, grid, tem, tpm, s, ev0, ev1);
+    if (maxm <= 8) return launch_sub_f<double, 8>(d_insts, n, plan, info, fuse, grid, tem, tpm, nr, s, ev0, ev1);
+    return launch_sub_f<double, 16>(d_insts, n, plan, info, fuse, grid, tem, tpm, nr, s, ev0, ev1);
 }
 
 hipError_t launch_rederive(const DevInst* d_insts, int n, const long long* plan, const StepInfo* info,

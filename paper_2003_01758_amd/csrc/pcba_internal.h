@@ -5,9 +5,11 @@
 // parents are the K items named by `live` in buffer `cur`; the children of
 // parent j go to slots 2j (left) and 2j+1 (right) of buffer cur^1, the order
 // the subdivision of Alg. Subdivision produces when each item is replaced by
-// its two halves.  The cut-off test then writes the slots of the surviving
-// children, in order, into `live`: elimination is a stream compaction of slot
-// indices, and no patch is moved.
+// its two halves (in a round, which splits every axis, its 2^l children go to
+// slots 2^l j + c, c's bits the halves per axis, axis 0 most significant).
+// The cut-off test then writes the slots of the surviving children, in order,
+// into `live`: elimination is a stream compaction of slot indices, and no
+// patch is moved.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -27,6 +29,7 @@ constexpr int REDERIVE_CHUNK = 256;  // patches per re-derivation chunk
 constexpr int MAX_BATCH = 2048;   // problems per launch
 constexpr int MAX_TILE64 = 3584;  // largest tile (coefficients) of an FP64 unit: 14 per lane
 constexpr int MAX_TILE32 = 7168;  // largest tile of an FP32 unit: 28 per lane
+constexpr int NCMAX = 4;          // children per parent: 2, or 2^l = 4 in a round (l <= 2)
 
 // per-child feasibility flags (OR-ed by every tile of the child)
 enum : uint32_t {
@@ -109,7 +112,8 @@ struct DevInst {
     int32_t rederive;              // FP32: re-derive from the FP64 root every this many steps
     int32_t retire;                // retire inequalities certified satisfied on a box
     int32_t rows;                  // transform rows per child: sum over kinds and axes of m
-    int32_t pad0;
+    int32_t fused;                 // 1: every step is a whole round (all l axes split at
+                                   // once, 2^l children per parent); 0: one direction
     int64_t hcap;                  // patches each heap holds
     InstState* st;
     int* hostflag;                 // engine's pinned host word: set when the problem stops running

@@ -138,6 +138,7 @@ struct pcba_problem {
     int n_polys = 0;
     pcba_options opt{};
     bool fp32 = false;
+    int nc = 2;                 // children per parent: 2, or 2^l when each step is a round
     size_t elem = 8;
     int tile_polys[KINDS] = {};
     int ptp[KINDS] = {};       // patches per k_sub tile
@@ -364,6 +365,7 @@ static DevInst make_dev(const pcba_problem* P)
     I.tmat = P->d_tmat;
     I.tmw = P->tmw;
     I.rows = P->rows;
+    I.fused = P->opt.fused_round ? 1 : 0;
     for (int t = 0; t < KINDS; ++t) I.tmk[t] = P->tmk[t];
     I.root = P->root_written ? nullptr : P->d_root;
     I.root_err = P->d_root_err;
@@ -410,7 +412,7 @@ static int64_t hcap0(const pcba_problem* P)
 static int64_t cap0_of(const pcba_problem* P)
 {
     const int64_t by_bytes = ((int64_t)16 << 20) / std::max<int64_t>(1, 2 * item_bytes(P));
-    return std::max<int64_t>(2, std::min<int64_t>(P->M_eff, std::max<int64_t>(CAP0, std::min<int64_t>(1024, by_bytes))));
+    return std::max<int64_t>(P->nc, std::min<int64_t>(P->M_eff, std::max<int64_t>(CAP0, std::min<int64_t>(1024, by_bytes))));
 }
 
 static void free_list(pcba_problem* P)
@@ -739,6 +741,7 @@ void pcba_default_options(pcba_options* o)
     o->rederive_every = 16;
     o->stale_filter = 0;
     o->retire_satisfied = 1;
+    o->fused_round = 0;
     o->time_limit_s = 0.0;
 }
 
@@ -768,6 +771,10 @@ int pcba_create_problem(int32_t l, const double* lo, const double* hi, const int
     if (o.rederive_every < 0) return fail(PCBA_E_ARG, "rederive_every must be >= 0");
     if (o.retire_satisfied != 0 && o.retire_satisfied != 1)
         return fail(PCBA_E_ARG, "retire_satisfied must be 0 or 1");
+    if (o.fused_round != 0 && o.fused_round != 1) return fail(PCBA_E_ARG, "fused_round must be 0 or 1");
+    if (o.fused_round && l > 2) return fail(PCBA_E_ARG, "fused_round needs l <= 2");
+    if (o.fused_round && o.retire_satisfied && n_ineq > 0)
+        return fail(PCBA_E_ARG, "fused_round needs retire_satisfied = 0");
     for (int k = 0; k < l; ++k)
         if (!std::isfinite(lo[k]) || !std::isfinite(hi[k]) || !(hi[k] > lo[k]))
             return fail(PCBA_E_ARG, "box bounds must be finite with lo < hi");
@@ -777,6 +784,7 @@ int pcba_create_problem(int32_t l, const double* lo, const double* hi, const int
     for (int k = 0; k < l; ++k) { P->lo[k] = lo[k]; P->hi[k] = hi[k]; }
     P->opt = o;
     P->fp32 = o.precision == PCBA_FP32;
+    P->nc = o.fused_round ? (1 << l) : 2;
     P->retire = o.retire_satisfied == 1 && n_ineq > 0;
     P->elem = P->fp32 ? 4 : 8;
     P->count[0] = 1;
@@ -836,9 +844,10 @@ int pcba_create_problem(int32_t l, const double* lo, const double* hi, const int
     P->tile_start[KINDS] = T;
     P->T = T;
     // k_sub tiles: runs of ~TILE_ELEMS coefficients of one kind across parents,
-    // at most one patch per lane
+    // at most one patch per lane (a round keeps 2^l children of the tile in LDS:
+    // its tiles are 2 / 2^l as large)
     for (int t = 0; t < KINDS; ++t) {
-        const int target = P->fp32 ? 2 * TILE_ELEMS : TILE_ELEMS;
+        const int target = (P->fp32 ? 2 * TILE_ELEMS : TILE_ELEMS) * 2 / P->nc;
         P->ptp[t] = P->count[t] ? std::max(1, std::min(SUB_THREADS, target / std::max(1, P->S[t]))) : 1;
     }
     // sub-interval transforms per child (FP32 re-derivation): m^2 words and m rows per kind and axis
@@ -1200,13 +1209,14 @@ static int engine_steps(pcba_engine* E, int n_steps)
     }
     const int n = (int)E->active.size();
     bool any64 = false, any32 = false, anyrd = false;
-    int maxm64 = 1, maxm32 = 1;
+    int maxm64 = 1, maxm32 = 1, nr64 = 2, nr32 = 2;
     size_t ldsrd = 0;
     int tem64 = 1, tpm64 = 1, tem32 = 1, tpm32 = 1;
     for (auto* P : E->active) {
         if (P->fp32) {
             any32 = true;
             maxm32 = std::max(maxm32, P->maxm);
+            nr32 = std::max(nr32, P->nc);
             sub_tile(P, &tem32, &tpm32);
             if (P->opt.rederive_every > 0) {
                 anyrd = true;
@@ -1215,6 +1225,7 @@ static int engine_steps(pcba_engine* E, int n_steps)
         } else {
             any64 = true;
             maxm64 = std::max(maxm64, P->maxm);
+            nr64 = std::max(nr64, P->nc);
             sub_tile(P, &tem64, &tpm64);
         }
     }
@@ -1232,19 +1243,20 @@ static int engine_steps(pcba_engine* E, int n_steps)
                 if (__atomic_load_n(E->b.h_flag, __ATOMIC_ACQUIRE)) break;
             }
         }
-        // upper bound of this step's units: K at most doubles per step, and a
-        // problem never holds more than cap/2 parents
+        // upper bound of this step's units: K at most multiplies by the
+        // children per parent each step, and a problem never holds more than
+        // cap / nc parents
         int64_t ub64 = 0, ub32 = 0, ubrd = 0, ubrows = 0, maxc = 0;
         for (auto* P : E->active) {
             if (P->h_st.status != ST_RUNNING) continue;
-            const int64_t k = std::min<int64_t>(P->cap / 2, (int64_t)P->h_st.K << std::min(s, 30));
-            maxc = std::max(maxc, 2 * k);
+            const int64_t k = std::min<int64_t>(P->cap / P->nc, (int64_t)P->h_st.K << std::min(s * (P->nc / 2), 30));
+            maxc = std::max(maxc, P->nc * k);
             const int64_t u = k * P->T;
             if (!P->fp32) ub64 += u;
             else {
                 const int st = P->host_steps + s;
                 const bool due = P->opt.rederive_every > 0 && ((st + 1) % P->opt.rederive_every) == 0;
-                if (due) { ubrd += u; ubrows += k * 2 * P->rows; } else ub32 += u;
+                if (due) { ubrd += u; ubrows += k * P->nc * P->rows; } else ub32 += u;
             }
         }
         // the plan of the step: formed inside the first subdivision launch for
@@ -1261,14 +1273,14 @@ static int engine_steps(pcba_engine* E, int n_steps)
             hipEvent_t e0, e1;
             HIP_TRY(prof_pair(0, &e0, &e1));
             HIP_TRY(launch_sub(E->b.d_insts, n, E->b.d_plan, E->b.d_info, !planned, false, maxm64,
-                               (int)std::min<int64_t>(GRID_MAX, ub64), tem64, tpm64, E->stream, e0, e1));
+                               (int)std::min<int64_t>(GRID_MAX, ub64), tem64, tpm64, nr64, E->stream, e0, e1));
             planned = true;
         }
         if (l32) {
             hipEvent_t e0, e1;
             HIP_TRY(prof_pair(1, &e0, &e1));
             HIP_TRY(launch_sub(E->b.d_insts, n, E->b.d_plan, E->b.d_info, !planned, true, maxm32,
-                               (int)std::min<int64_t>(GRID_MAX, ub32), tem32, tpm32, E->stream, e0, e1));
+                               (int)std::min<int64_t>(GRID_MAX, ub32), tem32, tpm32, nr32, E->stream, e0, e1));
             planned = true;
         }
         if (anyrd && ubrd > 0) {
@@ -1301,7 +1313,7 @@ static int engine_steps(pcba_engine* E, int n_steps)
             // half again the current capacity (bounded by M); in retiring mode the
             // same for the heap, whose children take at most twice the carried
             // patches of the parents
-            const int64_t need = 2 * (int64_t)P->h_st.K;
+            const int64_t need = (int64_t)P->nc * P->h_st.K;
             int64_t want = P->cap, hwant = P->hcap;
             if (need > P->cap)
                 want = std::min<int64_t>(P->M_eff, std::max<int64_t>(need + need / 4, P->cap + P->cap / 2));
@@ -1548,6 +1560,38 @@ int pcba_read_errors(const pcba_problem* P, double* err, int64_t cap)
     if (!P || !err) return fail(PCBA_E_ARG, "NULL argument");
     if (!P->fp32) return fail(PCBA_E_STATE, "error bounds exist only in PCBA_FP32 mode");
     return read_list_impl(P, nullptr, nullptr, err, cap);
+}
+
+int pcba_rtd_constraints(const int32_t* w_xdeg, const int32_t* w_qdeg, const double* w_coef, int32_t n_pts,
+                         const double* pts, double eps_q, double* out)
+{
+    if (!w_xdeg || !w_qdeg || !w_coef || n_pts < 0 || (n_pts > 0 && (!pts || !out)))
+        return fail(PCBA_E_ARG, "NULL argument or n_pts < 0");
+    for (int k = 0; k < 2; ++k)
+        if (w_xdeg[k] < 0 || w_qdeg[k] < 0 || w_xdeg[k] > PCBA_MAX_DEGREE || w_qdeg[k] > PCBA_MAX_DEGREE)
+            return fail(PCBA_E_ARG, "degree outside 0..PCBA_MAX_DEGREE");
+    if (!std::isfinite(eps_q)) return fail(PCBA_E_ARG, "eps_q must be finite");
+    const int na = w_xdeg[0] + 1, nb = w_xdeg[1] + 1;
+    const int64_t nq = (int64_t)(w_qdeg[0] + 1) * (w_qdeg[1] + 1);
+    for (int32_t i = 0; i < n_pts; ++i) {
+        const double x1 = pts[2 * i], x2 = pts[2 * i + 1];
+        if (!std::isfinite(x1) || !std::isfinite(x2)) return fail(PCBA_E_ARG, "non-finite obstacle point");
+        double* g = out + (int64_t)i * nq;
+        for (int64_t e = 0; e < nq; ++e) g[e] = 0.0;
+        // w(x_i, q): the coefficient of q1^c q2^d is sum_{a,b} w[a,b,c,d] x1^a x2^b
+        double pa = 1.0;
+        for (int a = 0; a < na; ++a) {
+            double pb = pa;
+            for (int b = 0; b < nb; ++b) {
+                const double* wab = w_coef + ((int64_t)a * nb + b) * nq;
+                for (int64_t e = 0; e < nq; ++e) g[e] += wab[e] * pb;
+                pb *= x2;
+            }
+            pa *= x1;
+        }
+        g[0] += eps_q;
+    }
+    return PCBA_OK;
 }
 
 int pcba_read_root(const pcba_problem* P, double* patches)

@@ -21,6 +21,17 @@ Workloads (seed of instance k of workload c: PCG64(1_000_003*c + k)):
                 log-uniform in [50,1000], otherwise as workload 1.
   4  "serve":   l=2, workload-1 shapes, constraint count log-uniform in
                 [100,2000].
+  5  "waypoints": l=2, the multi-waypoint product cost (12,12); 100 obstacle
+                constraints (10,10) as in workload 1.
+  6  "rtdpop":  a planning problem built the way RTD builds it (Sec. II-C and
+                Sec. VI): plans q = (speed, yaw rate) in Q = [0,1] x [-1,1];
+                2 to 10 box obstacles of 30 cm ahead of the robot, seen as
+                lidar points x_i on their outlines (48 to 240 points); one
+                constraint w(x_i, q) + eps_q <= 0 per point, eps_q = 1e-4, from
+                a synthetic FRS-like polynomial w (see frs_polynomial); the
+                cost is the product over two waypoints of the squared distance
+                of the plan's endpoint from each.  Nothing is planted: some
+                plans are infeasible.
 """
 from __future__ import annotations
 
@@ -232,8 +243,121 @@ def _obstacle_constraints(rng, l: int, deg: int, count: int, q0) -> list:
     return [np.ascontiguousarray(c) for c in coef]
 
 
+# ---- the RTD planning problem (Sec. II-C, Sec. VI) --------------------------------------
+#
+# A plan q = (q1, q2) in Q = [0,1] x [-1,1] drives the robot from the origin,
+# heading along +x, at speed V_MAX q1 with yaw rate W_MAX q2 for T_PLAN
+# seconds (a unicycle).  The FRS of Sec. II-C holds every (x, q) with x on the
+# path of plan q, grown by the robot's radius and tracking error RHO.  RTD
+# computes offline a polynomial w(x, q) that is >= 0 on the FRS (by sums of
+# squares); here a stand-in is fitted instead: the least-squares polynomial
+# of multi-degree (4, 4) in x and (10, 10) in q to the tube function
+# s(x, q) = RHO^2 - min_t |x - path_q(t)|^2 on a Chebyshev grid, raised by a
+# constant until it is >= 0 at every grid sample where s >= 0.  Online, each
+# sensed obstacle point x_i gives the constraint w(x_i, q) + EPS_Q <= 0.
+
+V_MAX, W_MAX, T_PLAN, RHO, EPS_Q = 1.0, 1.0, 1.5, 0.3, 1e-4
+FRS_XDEG, FRS_QDEG = 4, 10
+_FRS_CACHE = {}
+
+
+def _unicycle_path(q1, q2, t):
+    """Position at time t on the path of plan (q1, q2), arrays broadcast."""
+    v, w = V_MAX * q1, W_MAX * q2
+    small = np.abs(w) < 1e-9
+    ws = np.where(small, 1.0, w)
+    px = np.where(small, v * t, v * np.sin(w * t) / ws)
+    py = np.where(small, 0.0, v * (1.0 - np.cos(w * t)) / ws)
+    return px, py
+
+
+def _cheb_nodes(n, a, b):
+    k = np.arange(n)
+    return 0.5 * (a + b) + 0.5 * (b - a) * np.cos((2 * k + 1) * np.pi / (2 * n))
+
+
+def frs_polynomial() -> np.ndarray:
+    """Coefficients W[a, b, c, d] of the FRS-like w(x, q) = sum W x1^a x2^b q1^c q2^d
+    (shape (5, 5, 11, 11)); deterministic (no random draws), computed once per
+    process."""
+    if "w" in _FRS_CACHE:
+        return _FRS_CACHE["w"]
+    nx, nq, nt = 24, 28, 61
+    X1, X2 = _cheb_nodes(nx, -0.5, 2.0), _cheb_nodes(nx, -1.6, 1.6)
+    Q1, Q2 = _cheb_nodes(nq, 0.0, 1.0), _cheb_nodes(nq, -1.0, 1.0)
+    q1g, q2g, tg = np.meshgrid(Q1, Q2, np.linspace(0.0, T_PLAN, nt), indexing="ij")
+    px, py = _unicycle_path(q1g, q2g, tg)
+    S = np.empty((nx, nx, nq, nq))
+    for a in range(nx):
+        dx2 = (X1[a] - px) ** 2
+        for b in range(nx):
+            S[a, b] = RHO ** 2 - np.min(dx2 + (X2[b] - py) ** 2, axis=-1)
+    axes = ((X1, FRS_XDEG), (X2, FRS_XDEG), (Q1, FRS_QDEG), (Q2, FRS_QDEG))
+    V = [npp.polyvander(v, d) for v, d in axes]
+    P = [np.linalg.pinv(m) for m in V]
+    # least squares on a tensor grid: the pseudo-inverse of a Kronecker
+    # product is the Kronecker product of the pseudo-inverses
+    W = np.einsum("ia,jb,kc,ld,abcd->ijkl", P[0], P[1], P[2], P[3], S, optimize=True)
+    fit = np.einsum("ai,bj,ck,dl,ijkl->abcd", V[0], V[1], V[2], V[3], W, optimize=True)
+    W[0, 0, 0, 0] += max(0.0, float(np.max(-fit[S >= 0.0])))
+    _FRS_CACHE["w"] = W
+    return W
+
+
+def rtd_constraints(W: np.ndarray, pts: np.ndarray, eps_q: float = EPS_Q) -> list:
+    """g_i(q) = w(x_i, q) + eps_q for each obstacle point x_i (rows of pts):
+    coefficient tensors in q, multi-degree (10, 10)."""
+    pts = np.asarray(pts, dtype=np.float64).reshape(-1, 2)
+    V1 = npp.polyvander(pts[:, 0], W.shape[0] - 1)
+    V2 = npp.polyvander(pts[:, 1], W.shape[1] - 1)
+    G = np.einsum("na,nb,abcd->ncd", V1, V2, W)
+    G[:, 0, 0] += eps_q
+    return [np.ascontiguousarray(g) for g in G]
+
+
+def _box_outline(center, angle, half=0.15, step=0.05) -> np.ndarray:
+    """Points every `step` metres along the outline of a square of side 2 half."""
+    n = int(round(2 * half / step))
+    s = np.linspace(-half, half, n + 1)[:-1]
+    pts = np.concatenate([np.stack([s, np.full_like(s, -half)], 1), np.stack([np.full_like(s, half), s], 1),
+                          np.stack([-s, np.full_like(s, half)], 1), np.stack([np.full_like(s, -half), -s], 1)])
+    c, sn = math.cos(angle), math.sin(angle)
+    return pts @ np.array([[c, -sn], [sn, c]]).T + np.asarray(center)
+
+
+def endpoint_map() -> tuple:
+    """The endpoint of plan q after T_PLAN as polynomials in q (multi-degree (1, 3)
+    each): the unicycle's endpoint expanded to third order in the yaw rate."""
+    a, b = V_MAX * T_PLAN, W_MAX * T_PLAN
+    ex, ey = np.zeros((2, 4)), np.zeros((2, 4))
+    ex[1, 0], ex[1, 2] = a, -a * b * b / 6.0
+    ey[1, 1], ey[1, 3] = a * b / 2.0, -a * b ** 3 / 24.0
+    return ex, ey
+
+
+def rtd_pop(rng) -> tuple:
+    """One planning iteration: obstacle points, the two waypoints, the cost."""
+    nbox = int(rng.integers(2, 11))
+    pts = []
+    for _ in range(nbox):
+        center = (rng.uniform(0.3, 3.0), rng.uniform(-1.2, 1.2))
+        pts.append(_box_outline(center, rng.uniform(0.0, 0.5 * math.pi)))
+    pts = np.concatenate(pts)
+    # waypoints 1.5 m ahead, on the left and on the right of the hallway
+    wps = [np.array([1.5, 0.5 + 0.1 * rng.standard_normal()]),
+           np.array([1.5, -0.5 + 0.1 * rng.standard_normal()])]
+    ex, ey = endpoint_map()
+    cost = np.ones((1, 1))
+    for xn in wps:
+        dxp, dyp = ex.copy(), ey.copy()
+        dxp[0, 0] -= xn[0]
+        dyp[0, 0] -= xn[1]
+        cost = poly_mul(cost, poly_mul(dxp, dxp) + poly_mul(dyp, dyp))
+    return pts, wps, cost
+
+
 def make_instance(config: int, index: int = 0, **overrides) -> Instance:
-    """Instance `index` of workload `config` (0..5), seeded PCG64(1_000_003*c + k)."""
+    """Instance `index` of workload `config` (0..6), seeded PCG64(1_000_003*c + k)."""
     rng = np.random.Generator(np.random.PCG64(SEED_STRIDE * config + index))
     if config == 0:
         l = 2
@@ -295,6 +419,11 @@ def make_instance(config: int, index: int = 0, **overrides) -> Instance:
         ineq = _obstacle_constraints(rng, l, 10, 100, q0)
         inst = Instance("waypoints", l, -np.ones(l), np.ones(l), cost, ineq, [],
                         max_boxes=1 << 20, q0=q0)
+    elif config == 6:
+        pts, _, cost = rtd_pop(rng)
+        ineq = rtd_constraints(frs_polynomial(), pts)
+        inst = Instance("rtdpop", 2, np.array([0.0, -1.0]), np.array([1.0, 1.0]), cost, ineq, [],
+                        max_boxes=1 << 20)
     else:
         raise ValueError(f"unknown workload {config}")
     if overrides:

@@ -28,7 +28,8 @@ class Options(C.Structure):
     _fields_ = [("eps", C.c_double), ("delta", C.c_double), ("eps_eq", C.c_double),
                 ("max_boxes", C.c_int64), ("max_iters", C.c_int32), ("precision", C.c_int32),
                 ("rederive_every", C.c_int32), ("stale_filter", C.c_int32),
-                ("retire_satisfied", C.c_int32), ("time_limit_s", C.c_double)]
+                ("retire_satisfied", C.c_int32), ("fused_round", C.c_int32),
+                ("time_limit_s", C.c_double)]
 
 
 class Result(C.Structure):
@@ -83,6 +84,8 @@ def lib():
         L.pcba_read_list.restype = C.c_int
         L.pcba_read_errors.argtypes = [vp, vp, i64]
         L.pcba_read_errors.restype = C.c_int
+        L.pcba_rtd_constraints.argtypes = [vp, vp, vp, i32, vp, dp, vp]
+        L.pcba_rtd_constraints.restype = C.c_int
         L.pcba_read_root.argtypes = [vp, vp]
         L.pcba_read_root.restype = C.c_int
         L.pcba_patch_words.argtypes = [vp]
@@ -150,6 +153,19 @@ def default_options(**kw) -> Options:
     return o
 
 
+def rtd_constraints(w, pts, eps_q: float) -> np.ndarray:
+    """pcba_rtd_constraints: w of shape (xdeg0+1, xdeg1+1, qdeg0+1, qdeg1+1),
+    pts (n, 2); returns (n, qdeg0+1, qdeg1+1) coefficients of w(x_i, q) + eps_q."""
+    w = np.ascontiguousarray(w, dtype=np.float64)
+    pts = np.ascontiguousarray(pts, dtype=np.float64).reshape(-1, 2)
+    xdeg = np.array([w.shape[0] - 1, w.shape[1] - 1], dtype=np.int32)
+    qdeg = np.array([w.shape[2] - 1, w.shape[3] - 1], dtype=np.int32)
+    out = np.empty((len(pts), w.shape[2], w.shape[3]))
+    _check(lib().pcba_rtd_constraints(xdeg.ctypes.data, qdeg.ctypes.data, w.ctypes.data, len(pts),
+                                      pts.ctypes.data, float(eps_q), out.ctypes.data))
+    return out
+
+
 def _arr(a, dtype):
     a = np.ascontiguousarray(a, dtype=dtype)
     return a
@@ -159,7 +175,7 @@ class Problem:
     """Problem (P) on the device.  `inst` is an instances.Instance-like object;
     keyword options override its tolerances (eps, delta, eps_eq, max_boxes,
     max_iters) and set precision ('fp64'|'fp32'), rederive_every, stale_filter,
-    retire_satisfied, time_limit_s."""
+    retire_satisfied, fused_round, time_limit_s."""
 
     def __init__(self, inst, **kw):
         L = lib()

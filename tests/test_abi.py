@@ -69,6 +69,23 @@ def test_default_options_and_argument_validation_without_device():
     rc = L.pcba_create_problem(2, lo.ctypes.data, hi.ctypes.data, deg.ctypes.data, coef.ctypes.data,
                                0, None, None, 0, None, None, ctypes.byref(bad), ctypes.byref(h))
     assert rc == pcba.E_ARG and b"retire_satisfied" in L.pcba_last_error()
+    # a round (fused_round = 1) splits every axis: l <= 2, and no retiring
+    assert pcba.default_options().fused_round == 0
+    bad = pcba.default_options(fused_round=1)   # retire_satisfied stays 1
+    g1 = np.ones(4)
+    rc = L.pcba_create_problem(2, lo.ctypes.data, hi.ctypes.data, deg.ctypes.data, coef.ctypes.data,
+                               1, deg.ctypes.data, g1.ctypes.data, 0, None, None, ctypes.byref(bad),
+                               ctypes.byref(h))
+    assert rc == pcba.E_ARG and b"fused_round" in L.pcba_last_error()
+    bad = pcba.default_options(fused_round=1, retire_satisfied=0)
+    lo3, hi3, deg3 = np.zeros(3), np.ones(3), np.array([1, 1, 1], dtype=np.int32)
+    rc = L.pcba_create_problem(3, lo3.ctypes.data, hi3.ctypes.data, deg3.ctypes.data, np.ones(8).ctypes.data,
+                               0, None, None, 0, None, None, ctypes.byref(bad), ctypes.byref(h))
+    assert rc == pcba.E_ARG and b"l <= 2" in L.pcba_last_error()
+    bad = pcba.default_options(fused_round=2, retire_satisfied=0)
+    rc = L.pcba_create_problem(2, lo.ctypes.data, hi.ctypes.data, deg.ctypes.data, coef.ctypes.data,
+                               0, None, None, 0, None, None, ctypes.byref(bad), ctypes.byref(h))
+    assert rc == pcba.E_ARG
     deg16 = np.array([16, 1], dtype=np.int32)
     rc = L.pcba_create_problem(2, lo.ctypes.data, hi.ctypes.data, deg16.ctypes.data,
                                np.ones(34).ctypes.data, 0, None, None, 0, None, None, None,
