@@ -183,6 +183,24 @@ int pcba_read_list(const pcba_problem* prob, uint32_t* ids, double* patches, int
 int pcba_read_errors(const pcba_problem* prob, double* err, int64_t cap);
 int64_t pcba_patch_words(const pcba_problem* prob);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the ids and
+ * patches of pcba_read_list, with the same layout and meaning, read through a
+ * static device staging array of PCBA_STATIC_SCRATCH_BYTES per device (held by
+ * the library until the process ends) instead of the device buffers that
+ * pcba_read_list allocates per call.  The call makes no device allocation.
+ *  - A list whose staging needs more than the array (len*words*8 bytes, rounded
+ *    up to 256, plus len*l*4 bytes) is rejected with PCBA_E_ARG; nothing is read.
+ *  - Every call on a device shares that device's array: calls that overlap on
+ *    one device (other threads, other streams) race; the caller serializes them.
+ *  - stream: a hipStream_t as void* on which the staging kernel and copies run
+ *    (NULL = the library's stream of the calling thread, created on its first
+ *    use); the call synchronizes it before it returns.
+ *  - ids or patches may be NULL; cap as for pcba_read_list. */
+#define PCBA_STATIC_SCRATCH_BYTES (64ll << 20)
+int pcba_read_list_noalloc(const pcba_problem* prob, uint32_t* ids, double* patches, int64_t cap,
+                           void* stream);
+
 /* The step before the solver in RTD (Sec. II-C): each sensed obstacle point x_i
  * becomes one inequality of the planning problem, w(x_i, q) + eps_q <= 0, where
  * w(x, q) (x: a point in the plane, q: the l = 2 plan parameters) is >= 0 on the

@@ -220,6 +220,34 @@ struct pcba_engine {
 
 // ------------------------------------------------------------------ helpers
 
+// Device staging of pcba_read_list_noalloc, for callers that cannot allocate:
+// one array per device for the life of the process.  Host code never passes
+// `scratch` itself to the device (in host code it names a host-side stand-in);
+// static_scratch looks up, once per device with that device current, the
+// array's device address and hands that out.
+static __device__ __align__(256) unsigned char scratch[PCBA_STATIC_SCRATCH_BYTES];
+
+static int static_scratch(unsigned char** out)
+{
+    constexpr int kMaxDev = 64;
+    static std::mutex mu;
+    static unsigned char* ptr[kMaxDev] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail(PCBA_E_DEVICE, std::string("hipGetDevice: ") + hipGetErrorString(e));
+    if (dev < 0 || dev >= kMaxDev) return fail(PCBA_E_DEVICE, "device index beyond the static scratch table");
+    std::lock_guard<std::mutex> lk(mu);
+    if (!ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(PCBA_E_DEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        ptr[dev] = (unsigned char*)p;
+    }
+    *out = ptr[dev];
+    return PCBA_OK;
+}
+
 // The library's stream of the calling thread on the current device, created on
 // first use and kept for the life of the process (default priority,
 // non-blocking).
@@ -1560,6 +1588,39 @@ int pcba_read_errors(const pcba_problem* P, double* err, int64_t cap)
     if (!P || !err) return fail(PCBA_E_ARG, "NULL argument");
     if (!P->fp32) return fail(PCBA_E_STATE, "error bounds exist only in PCBA_FP32 mode");
     return read_list_impl(P, nullptr, nullptr, err, cap);
+}
+
+int pcba_read_list_noalloc(const pcba_problem* P, uint32_t* ids, double* patches, int64_t cap, void* stream)
+{
+    if (!P) return fail(PCBA_E_ARG, "NULL problem");
+    const int64_t K = P->h_st.K;
+    if (P->list_released) return fail(PCBA_E_STATE, "the list was released to make room for other problems");
+    if (cap < K) return fail(PCBA_E_ARG, "capacity smaller than the list");
+    // staging: the packed patches, then (256-byte aligned) the ids
+    const int64_t pat_bytes = K * P->W * (int64_t)sizeof(double);
+    const int64_t ids_off = (pat_bytes + 255) / 256 * 256;
+    const int64_t need = ids_off + K * P->l * (int64_t)sizeof(uint32_t);
+    if (need > PCBA_STATIC_SCRATCH_BYTES)
+        return fail(PCBA_E_ARG, "the list needs " + std::to_string(need) +
+                                    " bytes of staging, above the static scratch of " +
+                                    std::to_string((long long)PCBA_STATIC_SCRATCH_BYTES) +
+                                    " bytes (pcba_read_list has no such limit)");
+    if (K == 0) return PCBA_OK;
+    unsigned char* base = nullptr;
+    int rc = static_scratch(&base);
+    if (rc != PCBA_OK) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    if (!s) HIP_TRY(library_stream(&s));
+    double* d_out = (double*)base;
+    uint32_t* d_ids = (uint32_t*)(base + ids_off);
+    // an earlier call's staging may still be read by its copies
+    HIP_TRY(hipStreamSynchronize(s));
+    HIP_TRY(launch_pack(make_dev(P), (int)K, d_out, d_ids, nullptr, P->W, s));
+    if (patches)
+        HIP_TRY(hipMemcpyAsync(patches, d_out, (size_t)pat_bytes, hipMemcpyDeviceToHost, s));
+    if (ids) HIP_TRY(hipMemcpyAsync(ids, d_ids, (size_t)K * P->l * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return PCBA_OK;
 }
 
 int pcba_rtd_constraints(const int32_t* w_xdeg, const int32_t* w_qdeg, const double* w_coef, int32_t n_pts,

@@ -21,6 +21,7 @@ OUTCOME_NAMES = {RUNNING: "running", OPTIMAL: "optimal", INFEASIBLE: "infeasible
                  MEMORY_LIMIT: "memory_limit", MAX_ITER: "max_iter", TIMEOUT: "timeout"}
 E_ARG, E_NOMEM, E_DEVICE, E_STATE = -1, -2, -3, -4
 MAX_TRACE = 512
+STATIC_SCRATCH_BYTES = 64 << 20   # PCBA_STATIC_SCRATCH_BYTES
 KERNELS = ("sub_fp64", "sub_fp32", "rederive_fp32", "cut", "plan")
 
 
@@ -84,6 +85,8 @@ def lib():
         L.pcba_read_list.restype = C.c_int
         L.pcba_read_errors.argtypes = [vp, vp, i64]
         L.pcba_read_errors.restype = C.c_int
+        L.pcba_read_list_noalloc.argtypes = [vp, vp, vp, i64, vp]
+        L.pcba_read_list_noalloc.restype = C.c_int
         L.pcba_rtd_constraints.argtypes = [vp, vp, vp, i32, vp, dp, vp]
         L.pcba_rtd_constraints.restype = C.c_int
         L.pcba_read_root.argtypes = [vp, vp]
@@ -236,6 +239,17 @@ class Problem:
         pat = np.empty((n, self.words), dtype=np.float64)
         if n:
             _check(lib().pcba_read_list(self.h, ids.ctypes.data, pat.ctypes.data, n))
+        return ids, pat
+
+    def list_noalloc(self, stream=None):
+        """list() through pcba_read_list_noalloc: no device allocation, staging
+        in the library's static per-device array."""
+        n = C.c_int64()
+        _check(lib().pcba_list_size(self.h, C.byref(n)))
+        n = n.value
+        ids = np.empty((n, self.l), dtype=np.uint32)
+        pat = np.empty((n, self.words), dtype=np.float64)
+        _check(lib().pcba_read_list_noalloc(self.h, ids.ctypes.data, pat.ctypes.data, n, _stream_ptr(stream)))
         return ids, pat
 
     def errors(self) -> np.ndarray:
