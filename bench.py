@@ -269,6 +269,7 @@ MODE_FLAGS = {
     "r0": ("retire_satisfied", 0),   # every box carries every constraint (Alg. Subdivision)
     "r1": ("retire_satisfied", 1),   # constraints certified satisfied on a box are dropped
     "f1": ("fused_round", 1),        # each pass splits both axes: S_a P S_b^T, one cut per round
+    "s1": ("stale_filter", 1),       # children already above the previous estimate are not written
 }
 
 
@@ -322,6 +323,9 @@ def main():
     ap.add_argument("--stale", type=int, default=None, help="1/0: stale-estimate write filter")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="only run device copies of this many MiB (counter calibration) and exit")
+    ap.add_argument("--tune", type=int, default=1,
+                    help="1: pick each mode's launch shape (tile size, workgroups per CU, FP32 "
+                         "re-derivation period) with the autotuner before its warm-up; 0: defaults")
     ap.add_argument("--single-reps", type=int, default=20,
                     help="solves of one plan alone per headline precision for the single-plan latency (0: skip)")
     ap.add_argument("--modes", default="fp64:r0,fp32:r0,fp64:r0:f1,fp32:r0:f1,fp64:r1,fp32:r1",
@@ -352,6 +356,10 @@ def main():
         o.update(opts)
         if prec == "fp32" and args.rederive is not None:
             o["rederive_every"] = args.rederive
+        if args.tune:
+            from paper_2003_01758_amd import tune
+            o = tune.tuned_options(insts, prec, o, reps=3, log=log)
+            log(f"[bench] {name}: tuned options {o}")
         probs = warm(pcba, insts, prec, args.warmup, **o)
         r = run_mode(pcba, probs, insts, prec, args.steps)
         r["precision"], r["options"] = prec, o

@@ -105,6 +105,24 @@ typedef struct {
                                 rounds.  Requires l <= 2 and retire_satisfied = 0
                                 (PCBA_E_ARG otherwise). */
     double time_limit_s;     /* 0 = none */
+    /* Launch shape of the subdivision kernel (speed only: FP64 results do not
+     * depend on it, FP32 bounds stay rigorous).  0 = the library's default. */
+    int32_t tile_coefs;      /* coefficients per tile (per child region): 0, or 256..3584
+                                (FP64) / 256..7168 (PCBA_FP32), and with fused_round at most
+                                2/2^l of that; a patch larger than this gets a tile of its own */
+    int32_t wg_per_cu;       /* workgroups per compute unit of the launch: 0 = as many as
+                                fit, else at most this many */
+    /* Subdivision variants of Sec. III-D and Sec. II-E. */
+    int32_t direction_rule;  /* 0 (default): directions in the order 1..l (Sec. III-D);
+                                1: maximum width, the axis along which the boxes are widest
+                                (the widest box at the list's depth vector; ties to the lowest
+                                axis).  All boxes of a step share the direction. */
+    double subdiv_lambda;    /* subdivision parameter in (0,1), default 1/2: a box [a,b] along
+                                the split axis becomes [a, a + lambda (b-a)] and the rest.  Away
+                                from 1/2 boxes are no longer congruent: the stopping test uses
+                                the widest box, max over axes of (hi - lo) max(lambda,
+                                1-lambda)^depth, and with PCBA_FP32 rederive_every must be 0.
+                                Not with fused_round. */
 } pcba_options;
 
 typedef struct {

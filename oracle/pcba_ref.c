@@ -84,6 +84,8 @@ struct pcba_ref {
     int x_depth[PCBA_REF_MAX_DIM];
     long long peak;
     int fused;                          /* 1: every pass splits along all l axes */
+    int rule;                           /* direction rule: 0 cyclic, 1 maximum width */
+    double lam;                         /* subdivision parameter (1/2: midpoint) */
 };
 
 /* ---- small helpers ---------------------------------------------------------------- */
@@ -204,6 +206,42 @@ int pcba_ref_split(int l, const int* deg, int r, const double* parent,
 }
 
 /*
+ * Split at parameter lambda along axis r (the box [a,b] along r becomes
+ * [a, a + lambda (b-a)] and [a + lambda (b-a), b]) by de Casteljau's
+ * recurrence with that parameter:
+ *   c^(0)_i = b_i,  c^(m)_i = (1 - lambda) c^(m-1)_i + lambda c^(m-1)_{i+1},
+ *   left_k = c^(k)_0,  right_k = c^(n-k)_k.
+ * lambda = 1/2 is pcba_ref_split, whose halving form it reproduces exactly.
+ */
+int pcba_ref_split_at(int l, const int* deg, int r, double lambda, const double* parent,
+                      double* left, double* right)
+{
+    if (!(lambda > 0.0 && lambda < 1.0)) return -1;
+    if (lambda == 0.5) return pcba_ref_split(l, deg, r, parent, left, right);
+    if (l < 1 || l > PCBA_REF_MAX_DIM || r < 0 || r >= l || !deg || !parent || !left || !right)
+        return -1;
+    long long n = deg[r], stride = 1, outer = 1;
+    for (int k = r + 1; k < l; ++k) stride *= deg[k] + 1;
+    for (int k = 0; k < r; ++k) outer *= deg[k] + 1;
+    double c[64];
+    if (n + 1 > 64) return -1;
+    const double mu = 1.0 - lambda;
+    for (long long o = 0; o < outer; ++o)
+        for (long long s = 0; s < stride; ++s) {
+            long long base = o * (n + 1) * stride + s;
+            for (long long i = 0; i <= n; ++i) c[i] = parent[base + i * stride];
+            left[base] = c[0];
+            right[base + n * stride] = c[n];
+            for (long long m = 1; m <= n; ++m) {
+                for (long long i = 0; i + m <= n; ++i) c[i] = mu * c[i] + lambda * c[i + 1];
+                left[base + m * stride] = c[0];
+                right[base + (n - m) * stride] = c[n - m];
+            }
+        }
+    return 0;
+}
+
+/*
  * Round split: bisect along axis 0, then each half along axis 1, and so on.
  * After the split along axis k the children are ordered with the new bit
  * least significant, so the final order has axis 0's bit most significant.
@@ -240,6 +278,56 @@ static long long kind_offset(const pcba_ref* h, int kind, int idx)
     long long off = 0;
     for (int t = 0; t < kind; ++t) off += h->count[t] * h->size[t];
     return off + (long long)idx * h->size[kind];
+}
+
+/* Width along axis k of the widest box at depth d: the splits at lambda keep
+ * the larger share max(lambda, 1 - lambda) (exactly 2^-d at the midpoint). */
+static double axis_width(const pcba_ref* h, int k, int d)
+{
+    const double w = h->hi[k] - h->lo[k];
+    if (h->lam == 0.5) return ldexp(w, -d);
+    const double mu = h->lam > 0.5 ? h->lam : 1.0 - h->lam;
+    double x = w;
+    for (int t = 0; t < d; ++t) x *= mu;
+    return x;
+}
+
+/* The direction of the next split: the next axis in the order 1..l
+ * (Sec. III-D), or under the maximum-width rule the axis along which the
+ * boxes are widest (ties: the lowest axis). */
+static int next_direction(const pcba_ref* h, const int* depth, int r_prev, int first)
+{
+    if (h->rule == 0) return first ? 0 : (r_prev + 1) % h->l;
+    int best = 0;
+    double bw = axis_width(h, 0, depth[0]);
+    for (int k = 1; k < h->l; ++k) {
+        const double wk = axis_width(h, k, depth[k]);
+        if (wk > bw) { bw = wk; best = k; }
+    }
+    return best;
+}
+
+/* Interval along axis k of the box with depth d and index i: the splits
+ * followed from [0,1] (the unit box the patches are expressed over), the
+ * index's bits most significant first (0: the part [a, a + lambda (b-a)],
+ * 1: the rest), then mapped to D. */
+static void box_interval(const pcba_ref* h, int k, int d, unsigned i, double* a_out, double* b_out)
+{
+    const double w = h->hi[k] - h->lo[k];
+    double a, b;
+    if (h->lam == 0.5) {
+        a = ldexp((double)i, -d);
+        b = ldexp((double)i + 1.0, -d);
+    } else {
+        a = 0.0;
+        b = 1.0;
+        for (int t = d - 1; t >= 0; --t) {
+            const double m = a + h->lam * (b - a);
+            if ((i >> t) & 1u) a = m; else b = m;
+        }
+    }
+    *a_out = h->lo[k] + w * a;
+    *b_out = h->lo[k] + w * b;
 }
 
 /* zero-pad a monomial tensor of multi-degree d to multi-degree D (d <= D) */
@@ -326,6 +414,8 @@ pcba_ref* pcba_ref_create(int l, const double* lo, const double* hi,
     }
     memcpy(h->pat, h->root, sizeof(double) * (size_t)h->W);
     h->K = 1;                     /* L = {root item} */
+    h->rule = 0;
+    h->lam = 0.5;
     h->r = 0;
     h->n = 1;
     h->status = PCBA_REF_RUNNING;
@@ -427,7 +517,7 @@ int pcba_ref_step(pcba_ref* h)
             for (int t = 0; t < KINDS; ++t)
                 for (int i = 0; i < h->count[t]; ++i) {
                     long long off = kind_offset(h, t, i);
-                    pcba_ref_split(l, h->deg[t], r, parent + off, left + off, right + off);
+                    pcba_ref_split_at(l, h->deg[t], r, h->lam, parent + off, left + off, right + off);
                 }
             for (int q = 0; q < l; ++q) {
                 cids[(2 * k) * l + q] = h->ids[k * l + q];
@@ -510,7 +600,7 @@ int pcba_ref_step(pcba_ref* h)
     /* stopping criteria: tolerances met by the feasible item attaining p_up */
     double width = 0.0;
     for (int q = 0; q < l; ++q) {
-        double wq = ldexp(h->hi[q] - h->lo[q], -h->depth[q]);
+        double wq = axis_width(h, q, h->depth[q]);
         if (wq > width) width = wq;
     }
     if (h->p_up < INFINITY && h->p_up - h->p_lo <= h->eps && width <= h->delta) {
@@ -519,8 +609,8 @@ int pcba_ref_step(pcba_ref* h)
     }
 
     /* prepare the next iteration (a round-mode pass is a whole round) */
-    h->r = h->fused ? 0 : (r + 1) % l;
-    if (h->r == 0) h->n += 1;
+    h->r = h->fused ? 0 : next_direction(h, h->depth, r, 0);
+    if (h->fused || h->steps % l == 0) h->n += 1;
     if (h->n == h->N) { h->status = PCBA_REF_MAX_ITER; return h->status; }
     return PCBA_REF_RUNNING;
 }
@@ -528,7 +618,19 @@ int pcba_ref_step(pcba_ref* h)
 int pcba_ref_set_fused(pcba_ref* h, int on)
 {
     if (!h || h->steps > 0 || h->status != PCBA_REF_RUNNING) return -1;
+    if (on && (h->rule != 0 || h->lam != 0.5)) return -1;
     h->fused = on ? 1 : 0;
+    return 0;
+}
+
+int pcba_ref_set_split(pcba_ref* h, int rule, double lambda)
+{
+    if (!h || h->steps > 0 || h->status != PCBA_REF_RUNNING) return -1;
+    if ((rule != 0 && rule != 1) || !(lambda > 0.0 && lambda < 1.0)) return -1;
+    if (h->fused && (rule != 0 || lambda != 0.5)) return -1;
+    h->rule = rule;
+    h->lam = lambda;
+    h->r = next_direction(h, h->depth, 0, 1);
     return 0;
 }
 
@@ -552,8 +654,8 @@ void pcba_ref_result_get(const pcba_ref* h, pcba_ref_result* out)
             double w = h->hi[q] - h->lo[q];
             out->x_depth[q] = h->x_depth[q];
             out->x_index[q] = h->x_index[q];
-            out->x_lo[q] = h->lo[q] + w * ldexp((double)h->x_index[q], -h->x_depth[q]);
-            out->x_hi[q] = h->lo[q] + w * ldexp((double)h->x_index[q] + 1.0, -h->x_depth[q]);
+            (void)w;
+            box_interval(h, q, h->x_depth[q], h->x_index[q], &out->x_lo[q], &out->x_hi[q]);
         }
     }
     out->rounds = h->n;
@@ -585,16 +687,16 @@ int pcba_ref_derive(const pcba_ref* h, const int* depth, const unsigned* index,
         if (depth[q] < 0 || depth[q] > 32) return -1;
         total += depth[q];
     }
-    /* the loop's split sequence reaches d only if d_0 >= d_1 >= ... >= d_{l-1} >= d_0 - 1 */
-    for (int q = 1; q < l; ++q)
-        if (depth[q] > depth[q - 1] || depth[q] < depth[0] - 1) return -1;
     double* cur = (double*)malloc(sizeof(double) * (size_t)h->W);
     double* other = (double*)malloc(sizeof(double) * (size_t)h->W);
     if (!cur || !other) { free(cur); free(other); return -1; }
     memcpy(cur, h->root, sizeof(double) * (size_t)h->W);
     int done[PCBA_REF_MAX_DIM] = {0};
+    int r = next_direction(h, done, 0, 1);
     for (int s = 0; s < total; ++s) {
-        int r = s % l;
+        if (s > 0) r = next_direction(h, done, r, 0);
+        /* the loop's sequence of directions must reach the depth vector */
+        if (done[r] >= depth[r]) { free(cur); free(other); return -1; }
         unsigned bit = (index[r] >> (depth[r] - 1 - done[r])) & 1u;
         for (int t = 0; t < KINDS; ++t)
             for (int i = 0; i < h->count[t]; ++i) {
@@ -603,9 +705,9 @@ int pcba_ref_derive(const pcba_ref* h, const int* depth, const unsigned* index,
                 double* dump = (double*)malloc(sizeof(double) * (size_t)h->size[t]);
                 if (!dump) { free(cur); free(other); return -1; }
                 if (bit == 0)
-                    pcba_ref_split(l, h->deg[t], r, cur + off, other + off, dump);
+                    pcba_ref_split_at(l, h->deg[t], r, h->lam, cur + off, other + off, dump);
                 else
-                    pcba_ref_split(l, h->deg[t], r, cur + off, dump, other + off);
+                    pcba_ref_split_at(l, h->deg[t], r, h->lam, cur + off, dump, other + off);
                 free(dump);
             }
         double* sw = cur; cur = other; other = sw;

@@ -70,6 +70,13 @@ int pcba_ref_to_bernstein(int l, const int* deg, const double* lo, const double*
 int pcba_ref_split(int l, const int* deg, int r, const double* parent,
                    double* left, double* right);
 
+/* Split along axis r at parameter lambda in (0,1): the box's extent [a,b] along
+ * r becomes [a, a + lambda (b-a)] (left) and [a + lambda (b-a), b] (right)
+ * (Sec. II-E allows any parameter in [0,1]; 1/2 is pcba_ref_split).
+ * Returns 0 or -1. */
+int pcba_ref_split_at(int l, const int* deg, int r, double lambda, const double* parent,
+                      double* left, double* right);
+
 /* Round split: the patch bisected along every axis in turn, axis 0 first
  * (each of Sec. II-E's constant-matrix products along one axis, applied l
  * times), giving the 2^l children of the sub-boxes in the order of their id
@@ -104,6 +111,17 @@ int pcba_ref_step(pcba_ref* h);
  * every pass.  Returns 0, or -1 once the problem has stepped. */
 int pcba_ref_set_fused(pcba_ref* h, int on);
 
+/* Direction rule and subdivision parameter, chosen before the first pass:
+ * rule 0 (default) splits along the axes in the order 1..l (Sec. III-D);
+ * rule 1 splits along the axis of maximum width (the widest box at the list's
+ * depth vector, ties to the lowest axis; all boxes share the direction).
+ * lambda in (0,1) (default 1/2) splits each box at a + lambda (b - a); the
+ * stopping test then uses the widest box's width, max over axes of
+ * (hi - lo) max(lambda, 1-lambda)^depth.  The iteration count n advances
+ * every l passes.  Not with round mode.  Returns 0, or -1 on a bad argument
+ * or once the problem has stepped. */
+int pcba_ref_set_split(pcba_ref* h, int rule, double lambda);
+
 /* Steps until an outcome is reached; returns it. */
 int pcba_ref_solve(pcba_ref* h);
 
@@ -120,9 +138,10 @@ void pcba_ref_kind_degree(const pcba_ref* h, int kind, int* deg);
 void pcba_ref_list(const pcba_ref* h, unsigned* ids, double* patches);
 
 /* Patches of the box (depth, index) derived from the root by the same sequence
- * of splits the main loop applies (directions cycle 0..l-1 from the root; each
- * step keeps the child named by the next bit of the index, most significant
- * first).  depth must be a depth vector the loop reaches.  Returns 0 or -1. */
+ * of splits the main loop applies (the directions of the rule in force, at its
+ * parameter; each step keeps the child named by the next bit of the index,
+ * most significant first).  depth must be a depth vector the loop reaches.
+ * Returns 0 or -1. */
 int pcba_ref_derive(const pcba_ref* h, const int* depth, const unsigned* index,
                     double* patches);
 

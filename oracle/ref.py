@@ -54,6 +54,10 @@ def load(path):
         L.pcba_ref_to_bernstein.restype = C.c_int
         L.pcba_ref_split.argtypes = [C.c_int, ip, C.c_int, dp, dp, dp]
         L.pcba_ref_split.restype = C.c_int
+        L.pcba_ref_split_at.argtypes = [C.c_int, ip, C.c_int, C.c_double, dp, dp, dp]
+        L.pcba_ref_split_at.restype = C.c_int
+        L.pcba_ref_set_split.argtypes = [C.c_void_p, C.c_int, C.c_double]
+        L.pcba_ref_set_split.restype = C.c_int
         L.pcba_ref_split_round.argtypes = [C.c_int, ip, dp, dp]
         L.pcba_ref_split_round.restype = C.c_int
         L.pcba_ref_set_fused.argtypes = [C.c_void_p, C.c_int]
@@ -107,6 +111,19 @@ def split(patch: np.ndarray, r: int, L=None):
     return left, right
 
 
+def split_at(patch: np.ndarray, r: int, lam: float, L=None):
+    """Children of a split along axis r at parameter lam (left: [a, a + lam (b-a)])."""
+    patch = np.ascontiguousarray(patch, dtype=np.float64)
+    deg = np.array([s - 1 for s in patch.shape], dtype=np.int32)
+    left = np.empty_like(patch)
+    right = np.empty_like(patch)
+    rc = (L or lib()).pcba_ref_split_at(patch.ndim, deg, r, float(lam), patch.reshape(-1), left.reshape(-1),
+                                        right.reshape(-1))
+    if rc != 0:
+        raise ValueError("pcba_ref_split_at rejected its arguments")
+    return left, right
+
+
 def split_round(patch: np.ndarray, L=None) -> np.ndarray:
     """The 2^l children of a patch bisected along every axis, axis 0 first;
     child c (axis 0's bit most significant) at out[c]."""
@@ -128,7 +145,7 @@ class RefSolver:
     object (l, lo, hi, cost_deg, cost_flat, ineq_deg, ineq_flat, eq_deg, eq_flat,
     eps, delta, eps_eq, max_boxes, max_iters)."""
 
-    def __init__(self, inst, L=None, fused=False, **override):
+    def __init__(self, inst, L=None, fused=False, rule=0, lam=0.5, **override):
         L = L or lib()
         self.L = L
         g = lambda k: override.get(k, getattr(inst, k))
@@ -149,6 +166,8 @@ class RefSolver:
             raise ValueError("pcba_ref_create rejected the problem")
         self.h = h
         self.words = int(L.pcba_ref_patch_words(h))
+        if (rule != 0 or lam != 0.5) and L.pcba_ref_set_split(h, int(rule), float(lam)) != 0:
+            raise ValueError("pcba_ref_set_split rejected the rule or parameter")
         if fused and L.pcba_ref_set_fused(h, 1) != 0:
             raise ValueError("pcba_ref_set_fused failed")
 

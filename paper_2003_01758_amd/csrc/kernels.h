@@ -18,10 +18,11 @@ hipError_t launch_plan(const DevInst* d_insts, int n, long long* plan, StepInfo*
 // fuse (n <= PLAN_FUSE_MAX): the kernel forms the step's plan itself, in place
 // of a k_plan launch before it, and writes it to plan / info.  tem / tpm: the
 // largest tile (coefficients, patches) of the problems launched; nr: children
-// regions per tile, 2, or NCMAX when some problem splits whole rounds.
+// regions per tile, 2, or NCMAX when some problem splits whole rounds; wg_cap:
+// workgroups per compute unit at most (0: as many as fit).
 hipError_t launch_sub(const DevInst* d_insts, int n, long long* plan, StepInfo* info, bool fuse,
-                      bool fp32, int maxm, int grid, int tem, int tpm, int nr, hipStream_t s, hipEvent_t ev0,
-                      hipEvent_t ev1);
+                      bool fp32, int maxm, int grid, int tem, int tpm, int nr, int wg_cap, hipStream_t s,
+                      hipEvent_t ev0, hipEvent_t ev1);
 // dynamic LDS bytes of k_sub for those tiles
 size_t sub_lds_bytes(int tem, int tpm, bool fp32, int nr);
 hipError_t launch_rederive(const DevInst* d_insts, int n, const long long* plan, const StepInfo* info,

@@ -722,7 +722,10 @@ __global__ void k_reset(const DevInst* __restrict__ insts, int n)
     InstState* st = I.st;
     st->status = ST_RUNNING;
     st->K = 1;
-    st->r = 0;
+    {
+        const int d0[MAXL] = {};
+        st->r = I.rule == 1 ? widest_axis(I.width0, I.lam, d0, I.l) : 0;
+    }
     st->n = 1;
     st->steps = 0;
     st->cur = 0;
@@ -797,6 +800,36 @@ __device__ __forceinline__ void split_fibre(T* __restrict__ a, T* __restrict__ b
     }
 }
 
+// The same fibre split at parameter lam (the box [a,b] becomes [a, a + lam (b-a)]
+// and the rest): c_i <- (1 - lam) c_i + lam c_{i+1}, products and sum in the
+// order the oracle takes them.
+template <typename T, int M>
+__device__ __forceinline__ void split_fibre_at(T* __restrict__ a, T* __restrict__ b, int base, int stride, T lam,
+                                               T& mnL, T& mxL, T& mnR, T& mxR, T& amax)
+{
+    const T mu = (T)1 - lam;
+    T c[M];
+#pragma unroll
+    for (int i = 0; i < M; ++i) {
+        c[i] = a[base + i * stride];
+        amax = fmax(amax, fabs(c[i]));
+    }
+    mnL = mxL = c[0];
+    mnR = mxR = c[M - 1];
+    b[base + (M - 1) * stride] = c[M - 1];
+#pragma unroll
+    for (int lev = 1; lev < M; ++lev) {
+#pragma unroll
+        for (int i = 0; i + lev < M; ++i) c[i] = mu * c[i] + lam * c[i + 1];
+        a[base + lev * stride] = c[0];
+        b[base + (M - 1 - lev) * stride] = c[M - 1 - lev];
+        mnL = fmin(mnL, c[0]);
+        mxL = fmax(mxL, c[0]);
+        mnR = fmin(mnR, c[M - 1 - lev]);
+        mxR = fmax(mxR, c[M - 1 - lev]);
+    }
+}
+
 // Barrier for LDS data only: waits for this wave's LDS operations, not for its
 // global stores, which stay in flight across the barrier.
 __device__ __forceinline__ void lds_barrier()
@@ -829,16 +862,24 @@ __device__ __forceinline__ void copy_to_lds(T* __restrict__ dst, const T* __rest
 // lds_barrier().
 template <typename T, int MM>
 __device__ __forceinline__ void tile_split(int np, int S, const FibreGeom& g, T* a, T* b,
-                                           typename KeyOf<T>::type* key)
+                                           typename KeyOf<T>::type* key, double lam)
 {
+    const bool mid = lam == 0.5;
     const int TF = np * g.F;
     for (int f = threadIdx.x; f < TF; f += blockDim.x) {
         const int p = f / g.F;
         const int base = p * S + fibre_base(g, f - p * g.F);
         T mnL, mxL, mnR, mxR, amax = (T)0;
         switch (g.m) {
-#define PCBA_SPLIT_CASE(MV) \
-        case MV: if (MV <= MM) split_fibre<T, MV>(a, b, base, g.stride, mnL, mxL, mnR, mxR, amax); break;
+#define PCBA_SPLIT_CASE(MV)                                                                          \
+        case MV:                                                                                     \
+            if (MV <= MM) {                                                                          \
+                if (mid)                                                                             \
+                    split_fibre<T, MV>(a, b, base, g.stride, mnL, mxL, mnR, mxR, amax);              \
+                else                                                                                 \
+                    split_fibre_at<T, MV>(a, b, base, g.stride, (T)lam, mnL, mxL, mnR, mxR, amax);   \
+            }                                                                                        \
+            break;
             PCBA_SPLIT_CASE(1) PCBA_SPLIT_CASE(2) PCBA_SPLIT_CASE(3) PCBA_SPLIT_CASE(4)
             PCBA_SPLIT_CASE(5) PCBA_SPLIT_CASE(6) PCBA_SPLIT_CASE(7) PCBA_SPLIT_CASE(8)
             PCBA_SPLIT_CASE(9) PCBA_SPLIT_CASE(10) PCBA_SPLIT_CASE(11) PCBA_SPLIT_CASE(12)
@@ -879,85 +920,112 @@ __device__ __forceinline__ float split_right(int m, int k, int i)
     const int n = m - 1;
     return (k < m && i >= k && i < m) ? ldexpf(binom_f(n - k, i - k), -(n - k)) : 0.0f;
 }
+// At a subdivision parameter lam: left row k holds C(k,i) lam^i (1-lam)^(k-i),
+// right row k holds C(n-k, i-k) lam^(i-k) (1-lam)^(n-i); formed in FP64 and
+// rounded to FP32 (relative error below 2^-24 per entry).
+__device__ __forceinline__ double pow_i(double x, int e)
+{
+    double r = 1.0;
+    for (int t = 0; t < e; ++t) r *= x;
+    return r;
+}
+__device__ __forceinline__ float split_left_at(int m, int k, int i, double lam)
+{
+    return (k < m && i <= k) ? (float)((double)binom_f(k, i) * pow_i(lam, i) * pow_i(1.0 - lam, k - i)) : 0.0f;
+}
+__device__ __forceinline__ float split_right_at(int m, int k, int i, double lam)
+{
+    const int n = m - 1;
+    return (k < m && i >= k && i < m)
+               ? (float)((double)binom_f(n - k, i - k) * pow_i(lam, i - k) * pow_i(1.0 - lam, n - i))
+               : 0.0f;
+}
 
-typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 // FP32 tiles: the split as a fixed-matrix contraction on the matrix cores.
 // The fibres of the tile along direction r are the columns of X (m x TF); the
-// children are S_L X and S_R X.  Each wave takes blocks of 16 fibres and runs
-// ceil(m/4) steps of the 16x16x4 FP32 MFMA per child: lane (c, q) (c = lane %
-// 16, q = lane / 16) supplies row c, column 4s + q of S and row 4s + q of
-// fibre c, and receives child coefficients 4q..4q+3 of fibre c.  Rows and
-// columns beyond m are zero, so every output sums exactly the m products of
-// its row.  Results go back as tile_split leaves them: the left child in
-// place in a, the right child in b, per-patch min/max of both children and
-// max |parent| folded into key.  A wave reads a block's fibres before it
-// writes them and no other wave touches them, so the in-place write is safe.
+// children are S_L X and S_R X, computed together as one product with the
+// stacked matrix [S_L; S_R] (rows 0..15 the left child's coefficients, rows
+// 16..31 the right child's).  Each wave takes blocks of 32 fibres and runs
+// ceil(m/2) steps of the 32x32x2 FP32 MFMA: lane (c, q) (c = lane % 32,
+// q = lane / 32) supplies row c, column 2s + q of the stacked matrix and row
+// 2s + q of fibre c, and receives rows 8h + 4q .. 8h + 4q + 3 (h = 0..3) of
+// the product for fibre c, so the two lanes of a fibre hold all of its
+// children's coefficients between them.  Rows and columns beyond m are zero,
+// so every output sums exactly the m products of its row.  Results go back as
+// tile_split leaves them: the left child in place in a, the right child in b,
+// per-patch min/max of both children and max |parent| folded into key.  A wave
+// reads a block's fibres before it writes them and no other wave touches
+// them, so the in-place write is safe.
 // Rounding: each output is a sum of m products with non-negative weights
 // summing to one, evaluated in some order with at most m roundings on any
 // term's path, so |c~ - c| <= gamma_m max |b| (with u = 2^-23, covering the
 // unit's internal rounding) plus m 2^-126 for flushed subnormals: the bound
 // the caller carries for the split.
 __device__ __forceinline__ void tile_split_mfma(int np, int S, const FibreGeom& g, float* a, float* b,
-                                                unsigned* key)
+                                                unsigned* key, double lam)
 {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    const int col = lane & 15, kq = lane >> 4;
-    const int m = g.m, ks = (m + 3) >> 2;
-    float aL[4], aR[4];
+    const int col = lane & 31, kq = lane >> 5;
+    const int m = g.m, ks = (m + 1) >> 1;
+    // this lane's entries of the stacked matrix: row col, columns 2s + kq
+    float aS[8];
 #pragma unroll
-    for (int s = 0; s < 4; ++s) {
-        aL[s] = split_left(m, col, 4 * s + kq);
-        aR[s] = split_right(m, col, 4 * s + kq);
+    for (int s = 0; s < 8; ++s) {
+        const int i = 2 * s + kq;
+        const int row = col & 15;
+        const bool right = col >= 16;
+        aS[s] = lam == 0.5 ? (right ? split_right(m, row, i) : split_left(m, row, i))
+                           : (right ? split_right_at(m, row, i, lam) : split_left_at(m, row, i, lam));
     }
     const int TF = np * g.F;
-    const int nblk = (TF + 15) >> 4;
+    const int nblk = (TF + 31) >> 5;
+    const float invF = 1.0f / (float)g.F;
     for (int blk = w; blk < nblk; blk += nw) {
-        const int f = blk * 16 + col;
+        const int f = blk * 32 + col;
         const bool fv = f < TF;
         int p = 0, base = 0;
         if (fv) {
-            p = f / g.F;
+            p = (int)(((float)f + 0.5f) * invF);   // f / F (exact: f < 2^22)
             base = p * S + fibre_base(g, f - p * g.F);
         }
-        float x[4];
+        float x[8];
         float amax = 0.0f;
 #pragma unroll
-        for (int s = 0; s < 4; ++s) {
-            const int i = 4 * s + kq;
+        for (int s = 0; s < 8; ++s) {
+            const int i = 2 * s + kq;
             x[s] = (s < ks && fv && i < m) ? a[base + i * g.stride] : 0.0f;
             amax = fmaxf(amax, fabsf(x[s]));
         }
-        f32x4 dL = {0.0f, 0.0f, 0.0f, 0.0f}, dR = {0.0f, 0.0f, 0.0f, 0.0f};
+        f32x16 d = {};
 #pragma unroll
-        for (int s = 0; s < 4; ++s) {
-            if (s < ks) {   // uniform over the wave
-                dL = __builtin_amdgcn_mfma_f32_16x16x4f32(aL[s], x[s], dL, 0, 0, 0);
-                dR = __builtin_amdgcn_mfma_f32_16x16x4f32(aR[s], x[s], dR, 0, 0, 0);
-            }
-        }
+        for (int s = 0; s < 8; ++s)
+            if (s < ks)   // uniform over the wave
+                d = __builtin_amdgcn_mfma_f32_32x32x2f32(aS[s], x[s], d, 0, 0, 0);
         float mnL = INFINITY, mxL = -INFINITY, mnR = INFINITY, mxR = -INFINITY;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int k = 4 * kq + q;
+        for (int q = 0; q < 16; ++q) {
+            const int row = 8 * (q >> 2) + 4 * kq + (q & 3);
+            const int k = row & 15;
             if (fv && k < m) {
-                a[base + k * g.stride] = dL[q];
-                b[base + k * g.stride] = dR[q];
-                mnL = fminf(mnL, dL[q]);
-                mxL = fmaxf(mxL, dL[q]);
-                mnR = fminf(mnR, dR[q]);
-                mxR = fmaxf(mxR, dR[q]);
+                if (row < 16) {
+                    a[base + k * g.stride] = d[q];
+                    mnL = fminf(mnL, d[q]);
+                    mxL = fmaxf(mxL, d[q]);
+                } else {
+                    b[base + k * g.stride] = d[q];
+                    mnR = fminf(mnR, d[q]);
+                    mxR = fmaxf(mxR, d[q]);
+                }
             }
         }
-        // the four lanes of a fibre (lane, lane ^ 16, lane ^ 32, lane ^ 48)
-#pragma unroll
-        for (int o = 16; o < 64; o <<= 1) {
-            mnL = fminf(mnL, __shfl_xor(mnL, o, 64));
-            mxL = fmaxf(mxL, __shfl_xor(mxL, o, 64));
-            mnR = fminf(mnR, __shfl_xor(mnR, o, 64));
-            mxR = fmaxf(mxR, __shfl_xor(mxR, o, 64));
-            amax = fmaxf(amax, __shfl_xor(amax, o, 64));
-        }
+        // the two lanes of a fibre (lane and lane ^ 32)
+        mnL = fminf(mnL, __shfl_xor(mnL, 32, 64));
+        mxL = fmaxf(mxL, __shfl_xor(mxL, 32, 64));
+        mnR = fminf(mnR, __shfl_xor(mnR, 32, 64));
+        mxR = fmaxf(mxR, __shfl_xor(mxR, 32, 64));
+        amax = fmaxf(amax, __shfl_xor(amax, 32, 64));
         if (fv && kq == 0) {
             atomicMin(&key[5 * p + 0], fkey(mnL));
             atomicMax(&key[5 * p + 1], fkey(mxL));
@@ -1044,6 +1112,7 @@ __device__ __forceinline__ void child_bounds(T mn, T mx, double e, double base, 
 // One tile of k_sub (all fields uniform over the workgroup).
 struct PackUnit {
     int bi, kind, np, S, TE, cur, r, gath;
+    int contig;       // the tile's patches are consecutive patches of one parent
     int nc;           // children per parent: 2, or 2^l = 4 when the step is a round
     long long P0;     // first patch of the tile in the problem's sequence of this kind
     float invS;
@@ -1103,6 +1172,12 @@ __device__ __forceinline__ void resolve_packed(const DevInst* __restrict__ insts
     c.invS = 1.0f / (float)c.S;
     c.TE = c.np * c.S;
     c.gath = I.retire && c.kind == 1;
+    {
+        // without the heap, a parent's patches of a kind are consecutive in
+        // its slot: a tile within one parent is one run of coefficients
+        const long long cnt = c.kind == 0 ? 1 : I.count[c.kind];
+        c.contig = !c.gath && c.P0 / cnt == (c.P0 + c.np - 1) / cnt;
+    }
     c.nc = I.fused ? (1 << I.l) : 2;
     if (c.nc == 4) {
         c.g = fibre_geom(I.dims[c.kind], I.l, 0, c.S);
@@ -1146,11 +1221,17 @@ __device__ __forceinline__ void issue_packed(const DevInst& I, const PackUnit& c
     const unsigned bhi = __builtin_amdgcn_readfirstlane((unsigned)(bu >> 32));
     const gmem_t<const T> base = as_global((const T*)(((unsigned long long)bhi << 32) | blo));
     long long o[LB];
+    if (c.contig) {
+        const long long s0 = uniform64(src[0]);
 #pragma unroll
-    for (int q = 0; q < LB; ++q) {
-        const int e = min((int)threadIdx.x + q * SUB_THREADS, max(c.TE - 1, 0));
-        const int p = patch_of(e, c.invS);
-        o[q] = src[p] + (e - p * c.S);
+        for (int q = 0; q < LB; ++q) o[q] = s0 + min((int)threadIdx.x + q * SUB_THREADS, max(c.TE - 1, 0));
+    } else {
+#pragma unroll
+        for (int q = 0; q < LB; ++q) {
+            const int e = min((int)threadIdx.x + q * SUB_THREADS, max(c.TE - 1, 0));
+            const int p = patch_of(e, c.invS);
+            o[q] = src[p] + (e - p * c.S);
+        }
     }
 #pragma unroll
     for (int q = 0; q < LB; ++q)
@@ -1194,8 +1275,11 @@ __device__ __forceinline__ int3 block_scan3(int3 x, int3& excl, int* sc)
 // from k_plan's output but formed by every workgroup in LDS from the problems'
 // states (one thread per problem); workgroup 0 alone commits the memory test's
 // outcome and writes the plan and snapshots for the step's later kernels.
+// Two workgroups of four waves per compute unit (two waves per SIMD): the
+// register budget is then 256 per lane, which the FP32 form, with its matrix
+// accumulators, would otherwise exceed by a few and fall to one wave per SIMD.
 template <typename T, int MM, int LB, bool FUSE>
-__global__ __launch_bounds__(SUB_THREADS) void k_sub(const DevInst* __restrict__ insts, int n_inst,
+__global__ __launch_bounds__(SUB_THREADS, 2) void k_sub(const DevInst* __restrict__ insts, int n_inst,
                                                     long long* __restrict__ plan,
                                                     StepInfo* __restrict__ info, int tem, int tpm, int nr)
 {
@@ -1279,48 +1363,70 @@ __global__ __launch_bounds__(SUB_THREADS) void k_sub(const DevInst* __restrict__
     // by an indexed per-thread array, so that their accesses stay LDS ones
     long long* Lsrc0 = (long long*)carve((size_t)tpm * 8);
     long long* Lsrc1 = (long long*)carve((size_t)tpm * 8);
+    long long* Lsrc2 = (long long*)carve((size_t)tpm * 8);
     T* Lshift = (T*)carve((size_t)nr * tpm * sizeof(T));
     int4* Linf0 = (int4*)carve((size_t)tpm * 16);
     int4* Linf1 = (int4*)carve((size_t)tpm * 16);
+    int4* Linf2 = (int4*)carve((size_t)tpm * 16);
     int* Lwm = (int*)carve((size_t)tpm * 4);          // per patch: children to write (bit c)
     int* Lpre = (int*)carve((size_t)(2 * tpm + 2) * 4);  // per patch: scan of kept (child 0, child 1)
     int* Ldst = (int*)carve((size_t)2 * tpm * 4);     // per patch and child: heap patch or -1
     uint32_t* Lsfl = (uint32_t*)carve((size_t)nr * tpm * 4);  // per segment and child: flags
     int* Lpos = (int*)carve((size_t)2 * tpm * 4);     // per segment and child: list position
     int* Lseg = (int*)carve((size_t)(tpm + 1) * 4);   // per segment: first patch
+    int64_t* Ldsto = (int64_t*)carve((size_t)tpm * 8);  // per patch: destination less its tile offset
 
     const int tid = threadIdx.x;
     int hint = 0;
-    PackUnit c, cn;   // this tile and the next
+    PackUnit c, cn, c2;   // this tile, the next, the one after
     T v[LB];
     float ce = 0.0f, ne = 0.0f;     // FP32: this thread's patch's carried error (current, next tile)
     double cb = 0.0, nb = 0.0;      // and its FP64 base
-    int bufi = 0;
+    // Three patch tables in LDS, in turn: this tile's (tb), the next one's
+    // (its coefficients are loaded while this tile is processed) and the one
+    // after (its table is loaded during this tile).  Chosen by selects, not by
+    // an indexed per-thread array, so that their accesses stay LDS ones.
+    int tb = 0;
+    auto inf_of = [&](int b) { return b == 0 ? Linf0 : (b == 1 ? Linf1 : Linf2); };
+    auto src_of = [&](int b) { return b == 0 ? Lsrc0 : (b == 1 ? Lsrc1 : Lsrc2); };
+    auto fp32_patch = [&](const PackUnit& pu, const int4 pinf, float& e, double& b) {
+        const DevInst& In = insts[pu.bi];
+        const int poly = pu.kind == 0 ? 0 : In.count[0] + (pu.kind == 2 ? In.count[1] : 0) + pinf.z;
+        const int64_t pi = (int64_t)pinf.y * In.n_polys + poly;
+        e = as_global(In.err[pu.cur])[pi];
+        b = as_global(In.base[pu.cur])[pi];
+    };
 
-    // the first tile: patch table, then its coefficients in flight
+    // the first tile's table, the second's, then the first tile's coefficients in flight
     resolve_packed(insts, n_inst, pre, sinfo, u, hint, c);
     if (tid < c.np) {
-        int4 inf;
-        long long src;
-        patch_info(insts[c.bi], c, tid, inf, src);
-        Linf0[tid] = inf;
-        Lsrc0[tid] = src;
+        int4 pinf;
+        long long psrc;
+        patch_info(insts[c.bi], c, tid, pinf, psrc);
+        Linf0[tid] = pinf;
+        Lsrc0[tid] = psrc;
+    }
+    long long u1 = u + gridDim.x;
+    bool more1 = u1 < total;
+    if (more1) {
+        resolve_packed(insts, n_inst, pre, sinfo, u1, hint, cn);
+        if (tid < cn.np) {
+            int4 pinf;
+            long long psrc;
+            patch_info(insts[cn.bi], cn, tid, pinf, psrc);
+            Linf1[tid] = pinf;
+            Lsrc1[tid] = psrc;
+        }
     }
     __syncthreads();
     issue_packed<T, LB>(insts[c.bi], c, Lsrc0, v);
-    if (fp32 && tid < c.np) {
-        const DevInst& I0 = insts[c.bi];
-        const int4 inf = Linf0[tid];
-        const int poly = c.kind == 0 ? 0 : I0.count[0] + (c.kind == 2 ? I0.count[1] : 0) + inf.z;
-        const int64_t pi = (int64_t)inf.y * I0.n_polys + poly;
-        ce = as_global(I0.err[c.cur])[pi];
-        cb = as_global(I0.base[c.cur])[pi];
-    }
+    if (fp32 && tid < c.np) fp32_patch(c, Linf0[tid], ce, cb);
 
     for (;;) {
         const DevInst& I = insts[c.bi];
         const int kind = c.kind, np = c.np, S = c.S, TE = c.TE, cur = c.cur, r = c.r, l = I.l, nc = c.nc;
-        const int4* inf = bufi ? Linf1 : Linf0;
+        const int4* inf = inf_of(tb);
+        const int tn = tb == 2 ? 0 : tb + 1, t2 = tn == 2 ? 0 : tn + 1;
         T* Lb = La + TE;          // the right half of the (first) split
         K* Lkey2 = Lkey + 5 * np;   // a round: keys of the second split, 5 per (half, patch)
         // current tile: registers -> LDS; keys and segment flags reset
@@ -1342,14 +1448,20 @@ __global__ __launch_bounds__(SUB_THREADS) void k_sub(const DevInst* __restrict__
             }
             for (int ch = 0; ch < nr; ++ch) Lsfl[nr * tid + ch] = 0;
         }
-        // next tile: resolve it and start loading its patch table
-        const long long un = u + gridDim.x;
-        const bool more = un < total;
+        // the next tile's coefficients (and FP32 error bounds and bases) in
+        // flight for the whole of this tile
+        if (more1) {
+            issue_packed<T, LB>(insts[cn.bi], cn, src_of(tn), v);
+            if (fp32 && tid < cn.np) fp32_patch(cn, inf_of(tn)[tid], ne, nb);
+        }
+        // the tile after: resolve it and start loading its patch table
+        const long long u2 = u1 + gridDim.x;
+        const bool more2 = more1 && u2 < total;
         int4 ninf = make_int4(0, 0, 0, 0);
         long long nsrc = 0;
-        if (more) {
-            resolve_packed(insts, n_inst, pre, sinfo, un, hint, cn);
-            if (tid < cn.np) patch_info(insts[cn.bi], cn, tid, ninf, nsrc);
+        if (more2) {
+            resolve_packed(insts, n_inst, pre, sinfo, u2, hint, c2);
+            if (tid < c2.np) patch_info(insts[c2.bi], c2, tid, ninf, nsrc);
         }
         lds_barrier();
         // the split: FP32 tiles on the matrix cores, FP64 plain tiles by de
@@ -1358,33 +1470,22 @@ __global__ __launch_bounds__(SUB_THREADS) void k_sub(const DevInst* __restrict__
         // regions 2 and 3): region b0 + 2 b1 holds the child with bit b0 on axis 0
         // and b1 on axis 1, the same sequence of operations as the oracle's.
         if constexpr (sizeof(T) == 4)
-            tile_split_mfma(np, S, c.g, La, Lb, Lkey);
+            tile_split_mfma(np, S, c.g, La, Lb, Lkey, I.lam);
         else
-            tile_split<T, MM>(np, S, c.g, La, Lb, Lkey);
+            tile_split<T, MM>(np, S, c.g, La, Lb, Lkey, I.lam);
         if (nc == 4) {
             lds_barrier();
             if constexpr (sizeof(T) == 4)
-                tile_split_mfma(2 * np, S, c.g2, La, La + 2 * TE, Lkey2);
+                tile_split_mfma(2 * np, S, c.g2, La, La + 2 * TE, Lkey2, I.lam);
             else
-                tile_split<T, MM>(2 * np, S, c.g2, La, La + 2 * TE, Lkey2);
+                tile_split<T, MM>(2 * np, S, c.g2, La, La + 2 * TE, Lkey2, I.lam);
         }
-        // the next patch table to LDS (its loads had the split to arrive)
-        if (more && tid < cn.np) {
-            (bufi ? Linf0 : Linf1)[tid] = ninf;
-            (bufi ? Lsrc0 : Lsrc1)[tid] = nsrc;
+        // the table of the tile after next to LDS (its loads had the split to arrive)
+        if (more2 && tid < c2.np) {
+            inf_of(t2)[tid] = ninf;
+            src_of(t2)[tid] = nsrc;
         }
         lds_barrier();
-        // next tile's coefficients (and FP32 error bounds and bases) in flight
-        if (more) {
-            const DevInst& In = insts[cn.bi];
-            issue_packed<T, LB>(In, cn, bufi ? Lsrc0 : Lsrc1, v);
-            if (fp32 && tid < cn.np) {
-                const int poly = cn.kind == 0 ? 0 : In.count[0] + (cn.kind == 2 ? In.count[1] : 0) + ninf.z;
-                const int64_t pi = (int64_t)ninf.y * In.n_polys + poly;
-                ne = as_global(In.err[cn.cur])[pi];
-                nb = as_global(In.base[cn.cur])[pi];
-            }
-        }
 
         // per patch (thread p): bounds of every child (widened in FP32 mode),
         // records (cost) or flags (constraints)
@@ -1401,7 +1502,10 @@ __global__ __launch_bounds__(SUB_THREADS) void k_sub(const DevInst* __restrict__
             poly = kind == 0 ? 0 : I.count[0] + (kind == 2 ? I.count[1] : 0) + id;
             // FP32: the split's rounding bound over the parent's offsets (for a
             // round, the first split's; the second adds its own per half)
-            const double e1 = fp32 ? (double)ce + gamma32(c.g.m) * (double)funkey(Lkey[5 * p + 4]) +
+            // (away from the midpoint the matrix entries are rounded to FP32 too:
+            // |S~ - S| <= 2^-24 S adds less than two more roundings per term)
+            const int mx_extra = I.lam == 0.5 ? 0 : 2;
+            const double e1 = fp32 ? (double)ce + gamma32(c.g.m + mx_extra) * (double)funkey(Lkey[5 * p + 4]) +
                                          (double)c.g.m * 0x1p-126
                                    : 0.0;
             for (int ch = 0; ch < nc; ++ch) {
@@ -1533,35 +1637,63 @@ __global__ __launch_bounds__(SUB_THREADS) void k_sub(const DevInst* __restrict__
             const gmem_t<T> dbuf = as_global((T*)I.buf[cur ^ 1]);
             constexpr int SB = 8;
             // child ch of a parent is region ch of the split, or for a round
-            // region b0 + 2 b1 (its halves on axes 0 and 1); it goes to slot nc j + ch
+            // region b0 + 2 b1 (its halves on axes 0 and 1); it goes to slot nc j + ch.
+            // A run of patches of one parent (a segment) is contiguous in LDS and
+            // in the child's slot.  A tile of one segment (the usual constraint
+            // tile without retiring) is copied as one run per child; otherwise
+            // each patch's destination, less its position in the tile, is
+            // tabulated once (-1: not written) and each element adds its offset.
+            const bool one_seg = kind != 0 && s_nseg == 1;
             for (int ch = 0; ch < nc; ++ch) {
                 const T* src = La + (nc == 4 ? (ch >> 1) + 2 * (ch & 1) : ch) * TE;
+                if (one_seg) {
+                    if (!((Lwm[0] >> ch) & 1)) continue;   // uniform: the whole tile's child
+                    const int4 ip = inf[0];
+                    const int64_t d0 = (int64_t)(nc * ip.x + ch) * I.stride + I.soff[kind] + (int64_t)ip.z * S;
+                    for (int e0 = tid; e0 < TE; e0 += SB * SUB_THREADS) {
+                        T va[SB];
+#pragma unroll
+                        for (int q = 0; q < SB; ++q) {
+                            const int e = e0 + q * SUB_THREADS;
+                            if (e < TE) {
+                                va[q] = src[e];
+                                if (fp32) va[q] -= Lshift[ch * tpm + patch_of(e, c.invS)];
+                            }
+                        }
+#pragma unroll
+                        for (int q = 0; q < SB; ++q) {
+                            const int e = e0 + q * SUB_THREADS;
+                            if (e < TE) dbuf[d0 + e] = va[q];
+                        }
+                    }
+                    continue;
+                }
+                if (act) {
+                    const int4 ip = inf[p];
+                    Ldsto[p] = ((Lwm[p] >> ch) & 1) ? (int64_t)(nc * ip.x + ch) * I.stride + I.soff[kind] +
+                                                          (int64_t)ip.z * S - (int64_t)p * S
+                                                    : (int64_t)-1;
+                }
+                lds_barrier();
                 for (int e0 = tid; e0 < TE; e0 += SB * SUB_THREADS) {
                     T va[SB];
-                    int pp[SB];
+                    int64_t dd[SB];
 #pragma unroll
                     for (int q = 0; q < SB; ++q) {
                         const int e = e0 + q * SUB_THREADS;
-                        pp[q] = -1;
+                        dd[q] = -1;
                         if (e < TE) {
                             const int pq = patch_of(e, c.invS);
-                            pp[q] = pq;
+                            dd[q] = Ldsto[pq];
                             va[q] = src[e];
                             if (fp32) va[q] -= Lshift[ch * tpm + pq];
                         }
                     }
 #pragma unroll
-                    for (int q = 0; q < SB; ++q) {
-                        const int e = e0 + q * SUB_THREADS;
-                        if (pp[q] >= 0) {
-                            const int pq = pp[q];
-                            const int4 ip = inf[pq];
-                            if ((Lwm[pq] >> ch) & 1)
-                                dbuf[(int64_t)(nc * ip.x + ch) * I.stride + I.soff[kind] + (int64_t)ip.z * S +
-                                     (e - pq * S)] = va[q];
-                        }
-                    }
+                    for (int q = 0; q < SB; ++q)
+                        if (dd[q] >= 0) dbuf[dd[q] + e0 + q * SUB_THREADS] = va[q];
                 }
+                lds_barrier();
             }
         } else {
             // retiring mode: every kept (patch, child) gets its heap patch and
@@ -1598,12 +1730,15 @@ __global__ __launch_bounds__(SUB_THREADS) void k_sub(const DevInst* __restrict__
             }
         }
         lds_barrier();
-        if (!more) break;
+        if (!more1) break;
         c = cn;
-        u = un;
+        cn = c2;
+        u = u1;
+        u1 = u2;
+        more1 = more2;
         ce = ne;
         cb = nb;
-        bufi ^= 1;
+        tb = tn;
     }
 }
 
@@ -1914,9 +2049,13 @@ __global__ __launch_bounds__(CUT_THREADS) void k_cut(const DevInst* __restrict__
     const int steps0 = st->steps, n0 = st->n;
     const long long alive0 = st->a_live;
     const int depth_k = tid < l ? st->depth[tid] + ((I.fused || tid == r) ? 1 : 0) : 0;
+    // the children's depth vector, and the widest child's width
+    int dnew[MAXL];
     double width = 0.0;
-    for (int k = 0; k < l; ++k)
-        width = fmax(width, ldexp(I.width0[k], -(st->depth[k] + ((I.fused || k == r) ? 1 : 0))));
+    for (int k = 0; k < l; ++k) {
+        dnew[k] = st->depth[k] + ((I.fused || k == r) ? 1 : 0);
+        width = fmax(width, axis_width(I.width0[k], I.lam, dnew[k]));
+    }
 
     // the child records, read once: the first CUT_CACHE * blockDim children are
     // kept in registers for the three passes below, any further ones are read
@@ -2172,10 +2311,12 @@ __global__ __launch_bounds__(CUT_THREADS) void k_cut(const DevInst* __restrict__
             st->status = ST_OPTIMAL;
             signal_host(I);
         } else {
-            // a round leaves the direction at axis 0 and counts one iteration
-            const int rn = I.fused ? 0 : (r + 1) % l;
+            // the next direction: axis 0 again after a round, the next axis in the
+            // order 1..l, or the widest axis; the iteration count advances every
+            // l directional steps (every round)
+            const int rn = I.fused ? 0 : (I.rule == 1 ? widest_axis(I.width0, I.lam, dnew, l) : (r + 1) % l);
             st->r = rn;
-            const int nn = n0 + (rn == 0 ? 1 : 0);
+            const int nn = n0 + ((I.fused || (steps0 + 1) % l == 0) ? 1 : 0);
             st->n = nn;
             if (nn == I.N) {
                 st->status = ST_MAXITER;
@@ -2196,9 +2337,12 @@ __global__ __launch_bounds__(CUT_THREADS) void k_cut(const DevInst* __restrict__
 // flight at once) while it builds the transforms of every kind and axis; then
 // each wave takes one polynomial per round and each lane whole fibres, the
 // signed chain and the |.| chain side by side.  The basis values come from
-// b^q_s(t) = C(q,s) t^s (1-t)^(q-s): 1 - t is exact (t is dyadic), so each
-// carries at most q+1 roundings, within the gamma_{2q} that the bound on T
-// assumes.
+// b^q_s(t) = C(q,s) t^s (1-t)^(q-s): at the midpoint parameter 1 - t is exact
+// (t is dyadic), so each carries at most q+1 roundings; with another
+// subdivision parameter 1 - t carries one rounding more and each value at most
+// 2q: within the gamma_{2q} that the bound on T assumes.  The box certified is
+// the one whose interval the host reports (the same FP64 recurrence from the
+// index bits).
 // LDS (doubles): transforms, KINDS * l blocks of mm^2 (mm: the problem's longest
 // fibre); basis tables, 2 KINDS l mm^2; then 2 ppb slots of max_S.
 __global__ __launch_bounds__(256) void k_certify(const DevInst* __restrict__ insts, int n,
@@ -2277,7 +2421,9 @@ __global__ __launch_bounds__(256) void k_certify(const DevInst* __restrict__ ins
         const int m = I.dims[kind][k];
         const int q = q2 / m, s2 = q2 - q * m;
         if (q >= m || s2 > q) continue;
-        const double t = ldexp((double)st->x_index[k] + (double)side, -st->x_depth[k]);
+        double ta, tb;
+        unit_interval(I.lam, st->x_depth[k], st->x_index[k], ta, tb);
+        const double t = side ? tb : ta;
         const double u = 1.0 - t;
         double v = 1.0;
         for (int i = 0; i < s2; ++i) v *= t;
@@ -2547,16 +2693,16 @@ size_t sub_lds_bytes(int tem, int tpm, bool fp32, int nr)
 {
     const size_t el = fp32 ? 4 : 8;
     auto r16 = [](size_t b) { return (b + 15) & ~(size_t)15; };
-    return r16((size_t)nr * tem * el) + r16((size_t)5 * tpm * (nr > 2 ? 3 : 1) * el) + 2 * r16((size_t)tpm * 8) +
-           r16((size_t)nr * tpm * el) + 2 * r16((size_t)tpm * 16) + r16((size_t)tpm * 4) +
+    return r16((size_t)nr * tem * el) + r16((size_t)5 * tpm * (nr > 2 ? 3 : 1) * el) + 3 * r16((size_t)tpm * 8) +
+           r16((size_t)nr * tpm * el) + 3 * r16((size_t)tpm * 16) + r16((size_t)tpm * 4) +
            r16((size_t)(2 * tpm + 2) * 4) + r16((size_t)2 * tpm * 4) + r16((size_t)nr * tpm * 4) +
-           r16((size_t)2 * tpm * 4) + r16((size_t)(tpm + 1) * 4);
+           r16((size_t)2 * tpm * 4) + r16((size_t)(tpm + 1) * 4) + r16((size_t)tpm * 8);
 }
 
 // With ev0/ev1 the launch stamps them at the kernel's own start and end.
 template <typename T, int MM, bool FUSE>
 static hipError_t launch_sub_t(const DevInst* d_insts, int n, long long* plan, StepInfo* info, int grid,
-                               int tem, int tpm, int nr, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1)
+                               int tem, int tpm, int nr, int wg_cap, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1)
 {
     // registers per thread for a tile in flight: the largest tile / 256 lanes
     constexpr int LB = (sizeof(T) == 8 ? MAX_TILE64 : MAX_TILE32) / SUB_THREADS;
@@ -2566,7 +2712,8 @@ static hipError_t launch_sub_t(const DevInst* d_insts, int n, long long* plan, S
     // no more workgroups than fit on the device at once: the rest would only
     // queue, while resident ones walk the units with the next tile in flight
     const int cus = device_props(current_device()).cus;
-    const int per_cu = occupancy_per_cu((const void*)k_sub<T, MM, LB, FUSE>, SUB_THREADS, lds);
+    int per_cu = occupancy_per_cu((const void*)k_sub<T, MM, LB, FUSE>, SUB_THREADS, lds);
+    if (wg_cap > 0 && per_cu > 0) per_cu = std::min(per_cu, wg_cap);
     if (cus > 0 && per_cu > 0) grid = std::min(grid, cus * per_cu);
     if (ev0)
         hipExtLaunchKernelGGL((k_sub<T, MM, LB, FUSE>), dim3(grid), dim3(SUB_THREADS), lds, s, ev0, ev1, 0,
@@ -2579,15 +2726,16 @@ static hipError_t launch_sub_t(const DevInst* d_insts, int n, long long* plan, S
 
 template <typename T, int MM>
 static hipError_t launch_sub_f(const DevInst* d_insts, int n, long long* plan, StepInfo* info, bool fuse,
-                               int grid, int tem, int tpm, int nr, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1)
+                               int grid, int tem, int tpm, int nr, int wg_cap, hipStream_t s, hipEvent_t ev0,
+                               hipEvent_t ev1)
 {
-    if (fuse) return launch_sub_t<T, MM, true>(d_insts, n, plan, info, grid, tem, tpm, nr, s, ev0, ev1);
-    return launch_sub_t<T, MM, false>(d_insts, n, plan, info, grid, tem, tpm, nr, s, ev0, ev1);
+    if (fuse) return launch_sub_t<T, MM, true>(d_insts, n, plan, info, grid, tem, tpm, nr, wg_cap, s, ev0, ev1);
+    return launch_sub_t<T, MM, false>(d_insts, n, plan, info, grid, tem, tpm, nr, wg_cap, s, ev0, ev1);
 }
 
 hipError_t launch_sub(const DevInst* d_insts, int n, long long* plan, StepInfo* info, bool fuse,
-                      bool fp32, int maxm, int grid, int tem, int tpm, int nr, hipStream_t s, hipEvent_t ev0,
-                      hipEvent_t ev1)
+                      bool fp32, int maxm, int grid, int tem, int tpm, int nr, int wg_cap, hipStream_t s,
+                      hipEvent_t ev0, hipEvent_t ev1)
 {
     if (fuse && n > PLAN_FUSE_MAX) return hipErrorInvalidValue;
     if (grid <= 0) {
@@ -2596,11 +2744,11 @@ hipError_t launch_sub(const DevInst* d_insts, int n, long long* plan, StepInfo* 
     }
     if (fp32) {
         if (maxm <= 8)
-            return launch_sub_f<float, 8>(d_insts, n, plan, info, fuse, grid, tem, tpm, nr, s, ev0, ev1);
-        return launch_sub_f<float, 16>(d_insts, n, plan, info, fuse, grid, tem, tpm, nr, s, ev0, ev1);
+            return launch_sub_f<float, 8>(d_insts, n, plan, info, fuse, grid, tem, tpm, nr, wg_cap, s, ev0, ev1);
+        return launch_sub_f<float, 16>(d_insts, n, plan, info, fuse, grid, tem, tpm, nr, wg_cap, s, ev0, ev1);
     }
-    if (maxm <= 8) return launch_sub_f<double, 8>(d_insts, n, plan, info, fuse, grid, tem, tpm, nr, s, ev0, ev1);
-    return launch_sub_f<double, 16>(d_insts, n, plan, info, fuse, grid, tem, tpm, nr, s, ev0, ev1);
+    if (maxm <= 8) return launch_sub_f<double, 8>(d_insts, n, plan, info, fuse, grid, tem, tpm, nr, wg_cap, s, ev0, ev1);
+    return launch_sub_f<double, 16>(d_insts, n, plan, info, fuse, grid, tem, tpm, nr, wg_cap, s, ev0, ev1);
 }
 
 hipError_t launch_rederive(const DevInst* d_insts, int n, const long long* plan, const StepInfo* info,

@@ -127,6 +127,9 @@ struct DevInst {
     int32_t dims[KINDS][MAXL];     // fibre length (degree + 1) per axis and kind
     double eps, delta, eps_eq;
     double width0[MAXL];           // hi - lo of D
+    double lam;                    // subdivision parameter (1/2: midpoint)
+    int32_t rule;                  // direction rule: 0 the order 1..l, 1 maximum width
+    int32_t pad_rule;
     void* buf[2];                  // item buffers (double or float), cap * stride each
     uint32_t* ids[2];              // cap * l box indices
     float* err[2];                 // FP32 mode: cap * n_polys error bounds
@@ -169,9 +172,59 @@ struct DevInst {
     const int* matoff;             // KINDS * MAXL offsets into mats
     // padding to a multiple of 128 bytes: in a device array (256-byte aligned)
     // every problem's plan fields (the first 112 bytes) then share one cache line
-    char pad_end[112];
+    char pad_end[96];
 };
 static_assert(sizeof(DevInst) % 128 == 0, "DevInst: keep the size a multiple of 128 bytes");
+
+// ---- box geometry of the subdivision variants (Sec. III-D, Sec. II-E) -----------------
+
+// Width along one axis of the widest box at depth d: splits at lam keep at
+// most the share max(lam, 1 - lam) (exactly w 2^-d at the midpoint).
+__host__ __device__ inline double axis_width(double w, double lam, int d)
+{
+    if (lam == 0.5) return ldexp(w, -d);
+    const double mu = lam > 0.5 ? lam : 1.0 - lam;
+    double x = w;
+    for (int t = 0; t < d; ++t) x *= mu;
+    return x;
+}
+
+// The direction of the next split under the maximum-width rule: the axis
+// along which the widest box is widest, ties to the lowest axis.
+__host__ __device__ inline int widest_axis(const double* width0, double lam, const int* depth, int l)
+{
+    int best = 0;
+    double bw = axis_width(width0[0], lam, depth[0]);
+    for (int k = 1; k < l; ++k) {
+        const double wk = axis_width(width0[k], lam, depth[k]);
+        if (wk > bw) {
+            bw = wk;
+            best = k;
+        }
+    }
+    return best;
+}
+
+// The part [a, b] of [0, 1] that the box with index i at depth d covers along
+// an axis: the splits followed from [0, 1], the index's bits most significant
+// first (0: [a, a + lam (b - a)], 1: the rest).
+__host__ __device__ inline void unit_interval(double lam, int d, uint32_t i, double& a, double& b)
+{
+    if (lam == 0.5) {
+        a = ldexp((double)i, -d);
+        b = ldexp((double)i + 1.0, -d);
+        return;
+    }
+    a = 0.0;
+    b = 1.0;
+    for (int t = d - 1; t >= 0; --t) {
+        const double m = a + lam * (b - a);
+        if ((i >> t) & 1u)
+            a = m;
+        else
+            b = m;
+    }
+}
 
 // ordered integer keys: key(a) < key(b) iff a < b (non-NaN), so min/max of
 // floating values can use integer atomics

@@ -394,6 +394,8 @@ static DevInst make_dev(const pcba_problem* P)
     I.tmw = P->tmw;
     I.rows = P->rows;
     I.fused = P->opt.fused_round ? 1 : 0;
+    I.rule = P->opt.direction_rule;
+    I.lam = P->opt.subdiv_lambda;
     for (int t = 0; t < KINDS; ++t) I.tmk[t] = P->tmk[t];
     I.root = P->root_written ? nullptr : P->d_root;
     I.root_err = P->d_root_err;
@@ -739,6 +741,12 @@ static int reset_batch(pcba_problem* const* probs, int n, hipStream_t s)
         st0.status = ST_RUNNING;
         st0.K = 1;
         st0.n = 1;
+        if (P->opt.direction_rule == 1) {
+            double w0[MAXL];
+            int d0[MAXL] = {};
+            for (int k = 0; k < P->l; ++k) w0[k] = P->hi[k] - P->lo[k];
+            st0.r = widest_axis(w0, P->opt.subdiv_lambda, d0, P->l);
+        }
         st0.p_up = INFINITY;
         st0.p_lo = INFINITY;
         st0.p_cert = INFINITY;
@@ -771,6 +779,10 @@ void pcba_default_options(pcba_options* o)
     o->retire_satisfied = 1;
     o->fused_round = 0;
     o->time_limit_s = 0.0;
+    o->tile_coefs = 0;
+    o->wg_per_cu = 0;
+    o->direction_rule = 0;
+    o->subdiv_lambda = 0.5;
 }
 
 int pcba_create_problem(int32_t l, const double* lo, const double* hi, const int32_t* cost_deg,
@@ -800,6 +812,23 @@ int pcba_create_problem(int32_t l, const double* lo, const double* hi, const int
     if (o.retire_satisfied != 0 && o.retire_satisfied != 1)
         return fail(PCBA_E_ARG, "retire_satisfied must be 0 or 1");
     if (o.fused_round != 0 && o.fused_round != 1) return fail(PCBA_E_ARG, "fused_round must be 0 or 1");
+    {
+        const int tmax = o.precision == PCBA_FP32 ? MAX_TILE32 : MAX_TILE64;
+        if (o.tile_coefs != 0 && (o.tile_coefs < 256 || o.tile_coefs > tmax))
+            return fail(PCBA_E_ARG, "tile_coefs must be 0 or within 256.." + std::to_string(tmax));
+        // a round keeps 2^l child regions of a tile in LDS: the regions together
+        // stay within the two of a one-direction step
+        if (o.fused_round && o.tile_coefs * (1 << l) > 2 * tmax)
+            return fail(PCBA_E_ARG, "tile_coefs too large for fused_round (2^l regions in LDS)");
+    }
+    if (o.wg_per_cu < 0) return fail(PCBA_E_ARG, "wg_per_cu must be >= 0");
+    if (o.direction_rule != 0 && o.direction_rule != 1) return fail(PCBA_E_ARG, "direction_rule must be 0 or 1");
+    if (!(o.subdiv_lambda > 0.0 && o.subdiv_lambda < 1.0))
+        return fail(PCBA_E_ARG, "subdiv_lambda must lie in (0,1)");
+    if (o.fused_round && (o.direction_rule != 0 || o.subdiv_lambda != 0.5))
+        return fail(PCBA_E_ARG, "fused_round needs direction_rule = 0 and subdiv_lambda = 1/2");
+    if (o.precision == PCBA_FP32 && o.subdiv_lambda != 0.5 && o.rederive_every != 0)
+        return fail(PCBA_E_ARG, "PCBA_FP32 with subdiv_lambda != 1/2 needs rederive_every = 0");
     if (o.fused_round && l > 2) return fail(PCBA_E_ARG, "fused_round needs l <= 2");
     if (o.fused_round && o.retire_satisfied && n_ineq > 0)
         return fail(PCBA_E_ARG, "fused_round needs retire_satisfied = 0");
@@ -875,7 +904,7 @@ int pcba_create_problem(int32_t l, const double* lo, const double* hi, const int
     // at most one patch per lane (a round keeps 2^l children of the tile in LDS:
     // its tiles are 2 / 2^l as large)
     for (int t = 0; t < KINDS; ++t) {
-        const int target = (P->fp32 ? 2 * TILE_ELEMS : TILE_ELEMS) * 2 / P->nc;
+        const int target = o.tile_coefs > 0 ? o.tile_coefs : (P->fp32 ? 2 * TILE_ELEMS : TILE_ELEMS) * 2 / P->nc;
         P->ptp[t] = P->count[t] ? std::max(1, std::min(SUB_THREADS, target / std::max(1, P->S[t]))) : 1;
     }
     // sub-interval transforms per child (FP32 re-derivation): m^2 words and m rows per kind and axis
@@ -1237,7 +1266,7 @@ static int engine_steps(pcba_engine* E, int n_steps)
     }
     const int n = (int)E->active.size();
     bool any64 = false, any32 = false, anyrd = false;
-    int maxm64 = 1, maxm32 = 1, nr64 = 2, nr32 = 2;
+    int maxm64 = 1, maxm32 = 1, nr64 = 2, nr32 = 2, wg64 = 0, wg32 = 0;
     size_t ldsrd = 0;
     int tem64 = 1, tpm64 = 1, tem32 = 1, tpm32 = 1;
     for (auto* P : E->active) {
@@ -1245,6 +1274,7 @@ static int engine_steps(pcba_engine* E, int n_steps)
             any32 = true;
             maxm32 = std::max(maxm32, P->maxm);
             nr32 = std::max(nr32, P->nc);
+            wg32 = std::max(wg32, P->opt.wg_per_cu);
             sub_tile(P, &tem32, &tpm32);
             if (P->opt.rederive_every > 0) {
                 anyrd = true;
@@ -1254,6 +1284,7 @@ static int engine_steps(pcba_engine* E, int n_steps)
             any64 = true;
             maxm64 = std::max(maxm64, P->maxm);
             nr64 = std::max(nr64, P->nc);
+            wg64 = std::max(wg64, P->opt.wg_per_cu);
             sub_tile(P, &tem64, &tpm64);
         }
     }
@@ -1301,14 +1332,14 @@ static int engine_steps(pcba_engine* E, int n_steps)
             hipEvent_t e0, e1;
             HIP_TRY(prof_pair(0, &e0, &e1));
             HIP_TRY(launch_sub(E->b.d_insts, n, E->b.d_plan, E->b.d_info, !planned, false, maxm64,
-                               (int)std::min<int64_t>(GRID_MAX, ub64), tem64, tpm64, nr64, E->stream, e0, e1));
+                               (int)std::min<int64_t>(GRID_MAX, ub64), tem64, tpm64, nr64, wg64, E->stream, e0, e1));
             planned = true;
         }
         if (l32) {
             hipEvent_t e0, e1;
             HIP_TRY(prof_pair(1, &e0, &e1));
             HIP_TRY(launch_sub(E->b.d_insts, n, E->b.d_plan, E->b.d_info, !planned, true, maxm32,
-                               (int)std::min<int64_t>(GRID_MAX, ub32), tem32, tpm32, nr32, E->stream, e0, e1));
+                               (int)std::min<int64_t>(GRID_MAX, ub32), tem32, tpm32, nr32, wg32, E->stream, e0, e1));
             planned = true;
         }
         if (anyrd && ubrd > 0) {
@@ -1510,8 +1541,10 @@ int pcba_result(const pcba_problem* P, pcba_result_t* out)
             const double w = P->hi[k] - P->lo[k];
             out->x_depth[k] = st.x_depth[k];
             out->x_index[k] = st.x_index[k];
-            out->x_lo[k] = P->lo[k] + w * ldexp((double)st.x_index[k], -st.x_depth[k]);
-            out->x_hi[k] = P->lo[k] + w * ldexp((double)st.x_index[k] + 1.0, -st.x_depth[k]);
+            double ta, tb;
+            unit_interval(P->opt.subdiv_lambda, st.x_depth[k], st.x_index[k], ta, tb);
+            out->x_lo[k] = P->lo[k] + w * ta;
+            out->x_hi[k] = P->lo[k] + w * tb;
         }
     }
     out->rounds = st.n;

@@ -30,7 +30,8 @@ class Options(C.Structure):
                 ("max_boxes", C.c_int64), ("max_iters", C.c_int32), ("precision", C.c_int32),
                 ("rederive_every", C.c_int32), ("stale_filter", C.c_int32),
                 ("retire_satisfied", C.c_int32), ("fused_round", C.c_int32),
-                ("time_limit_s", C.c_double)]
+                ("time_limit_s", C.c_double), ("tile_coefs", C.c_int32), ("wg_per_cu", C.c_int32),
+                ("direction_rule", C.c_int32), ("subdiv_lambda", C.c_double)]
 
 
 class Result(C.Structure):
@@ -178,7 +179,8 @@ class Problem:
     """Problem (P) on the device.  `inst` is an instances.Instance-like object;
     keyword options override its tolerances (eps, delta, eps_eq, max_boxes,
     max_iters) and set precision ('fp64'|'fp32'), rederive_every, stale_filter,
-    retire_satisfied, fused_round, time_limit_s."""
+    retire_satisfied, fused_round, time_limit_s, tile_coefs, wg_per_cu,
+    direction_rule, subdiv_lambda."""
 
     def __init__(self, inst, **kw):
         L = lib()

@@ -40,7 +40,8 @@ def test_default_options_and_argument_validation_without_device():
     assert o.eps == 1e-3 and o.delta == 1e-4 and o.max_iters == 28 and o.max_boxes == 1 << 20
     # the C side fills every field: a layout mismatch would misplace these
     assert o.rederive_every == 16 and o.stale_filter == 0 and o.retire_satisfied == 1
-    assert o.time_limit_s == 0.0 and ctypes.sizeof(o) == 64
+    assert o.time_limit_s == 0.0 and o.tile_coefs == 0 and o.wg_per_cu == 0 and ctypes.sizeof(o) == 88
+    assert o.direction_rule == 0 and o.subdiv_lambda == 0.5
     # argument errors are detected before any device call
     L = pcba.lib()
     h = ctypes.c_void_p()
@@ -82,6 +83,19 @@ def test_default_options_and_argument_validation_without_device():
     rc = L.pcba_create_problem(3, lo3.ctypes.data, hi3.ctypes.data, deg3.ctypes.data, np.ones(8).ctypes.data,
                                0, None, None, 0, None, None, ctypes.byref(bad), ctypes.byref(h))
     assert rc == pcba.E_ARG and b"l <= 2" in L.pcba_last_error()
+    # launch-shape knobs: tile size in range, workgroup count not negative
+    for kw in (dict(tile_coefs=100), dict(tile_coefs=4096), dict(wg_per_cu=-1),
+               dict(tile_coefs=2048, fused_round=1, retire_satisfied=0),
+               # subdivision variants: rule 0 or 1, lambda inside (0,1), not with
+               # rounds, and FP32 away from the midpoint without re-derivation
+               dict(direction_rule=2), dict(subdiv_lambda=0.0), dict(subdiv_lambda=1.0),
+               dict(fused_round=1, retire_satisfied=0, direction_rule=1),
+               dict(fused_round=1, retire_satisfied=0, subdiv_lambda=0.25),
+               dict(precision=1, subdiv_lambda=0.25)):
+        bad = pcba.default_options(**kw)
+        rc = L.pcba_create_problem(2, lo.ctypes.data, hi.ctypes.data, deg.ctypes.data, coef.ctypes.data,
+                                   0, None, None, 0, None, None, ctypes.byref(bad), ctypes.byref(h))
+        assert rc == pcba.E_ARG, kw
     bad = pcba.default_options(fused_round=2, retire_satisfied=0)
     rc = L.pcba_create_problem(2, lo.ctypes.data, hi.ctypes.data, deg.ctypes.data, coef.ctypes.data,
                                0, None, None, 0, None, None, ctypes.byref(bad), ctypes.byref(h))

@@ -25,8 +25,10 @@ SRC = os.path.join(ROOT, "oracle", "pcba_ref.c")
 
 MUTATIONS = {
     "split_weight": ("c[i] = (c[i] + c[i + 1]) * 0.5;", "c[i] = (c[i] + c[i + 1]) * 0.4999;"),
-    "split_right_index": ("right[base + (n - m) * stride] = c[n - m];",
-                          "right[base + (n - m) * stride] = c[0];"),
+    "split_right_index": ("c[i] = (c[i] + c[i + 1]) * 0.5;\n                left[base + m * stride] = c[0];\n"
+                          "                right[base + (n - m) * stride] = c[n - m];",
+                          "c[i] = (c[i] + c[i + 1]) * 0.5;\n                left[base + m * stride] = c[0];\n"
+                          "                right[base + (n - m) * stride] = c[0];"),
     "conversion_binomial": ("U[k * m + i] = binom(k, i) / binom(n, i);",
                             "U[k * m + i] = binom(k, i) / binom(n, k);"),
     "premap_sign": ("for (int t = 0; t < j - i; ++t) lp *= lo[r];",
@@ -39,13 +41,17 @@ MUTATIONS = {
     "feasible_uses_min": ("if (!(mx <= 0.0)) b.feasible = 0;", "if (!(mn <= 0.0)) b.feasible = 0;"),
     "keep_uses_max": ("keep[c] = (char)(!bd[c].infeasible && bd[c].minP <= h->p_up);",
                       "keep[c] = (char)(!bd[c].infeasible && bd[c].maxP <= h->p_up);"),
-    "direction_stuck": ("h->r = h->fused ? 0 : (r + 1) % l;", "h->r = h->fused ? 0 : r;"),
+    "direction_stuck": ("if (h->rule == 0) return first ? 0 : (r_prev + 1) % h->l;",
+                        "if (h->rule == 0) return first ? 0 : r_prev;"),
     "right_child_id": ("cids[(2 * k + 1) * l + r] = 2u * h->ids[k * l + r] + 1u;",
                        "cids[(2 * k + 1) * l + r] = 2u * h->ids[k * l + r];"),
     "eq_band_upper": ("if (!(-h->eps_eq <= mn && mn <= 0.0 && 0.0 <= mx && mx <= h->eps_eq))",
                       "if (!(-h->eps_eq <= mn && mn <= 0.0 && 0.0 <= mx))"),
-    "width_off_by_one": ("double wq = ldexp(h->hi[q] - h->lo[q], -h->depth[q]);",
-                         "double wq = ldexp(h->hi[q] - h->lo[q], -h->depth[q] - 2);"),
+    "width_off_by_one": ("if (h->lam == 0.5) return ldexp(w, -d);",
+                         "if (h->lam == 0.5) return ldexp(w, -d - 2);"),
+    "split_lambda_swapped": ("c[i] = mu * c[i] + lambda * c[i + 1];", "c[i] = lambda * c[i] + mu * c[i + 1];"),
+    "lambda_box_bits": ("if ((i >> t) & 1u) a = m; else b = m;", "if ((i >> t) & 1u) b = m; else a = m;"),
+    "maxwidth_narrowest": ("if (wk > bw) { bw = wk; best = k; }", "if (wk < bw) { bw = wk; best = k; }"),
     "round_id_bit_order": ("cids[(nc * k + c) * l + q] = 2u * h->ids[k * l + q] + (unsigned)((c >> (l - 1 - q)) & 1);",
                            "cids[(nc * k + c) * l + q] = 2u * h->ids[k * l + q] + (unsigned)((c >> q) & 1);"),
     "round_depth_one_axis": ("for (int q = 0; q < l; ++q) h->depth[q] += 1;", "h->depth[0] += 1;"),
@@ -255,6 +261,58 @@ def battery(L):
         r = f.result()
         return out == ref.MEMORY_LIMIT and 4 * r["list_len"] > 64 and 2 * r["list_len"] <= 64
     check("round_memory", round_memory)
+
+    # subdivision at a parameter lambda: both parts against exact Bernstein
+    # coefficients over [a, a + lambda (b-a)] and [a + lambda (b-a), b]
+    def split_lambda():
+        rng = np.random.default_rng(12)
+        mono = rng.integers(-5, 6, size=(5, 4))
+        lo, hi = [-1.0, 0.0], [1.0, 2.0]
+        P = ref.to_bernstein(mono.astype(float), lo, hi, L=L)
+        for r, lam in ((0, 0.25), (1, 0.375), (0, 0.75)):
+            left, right = ref.split_at(P, r, lam, L=L)
+            cut = lo[r] + lam * (hi[r] - lo[r])
+            hl = list(hi); hl[r] = cut
+            lr = list(lo); lr[r] = cut
+            wl = exact.to_float(exact.bernstein_exact(mono, lo, hl))
+            wr = exact.to_float(exact.bernstein_exact(mono, lr, hi))
+            if np.max(np.abs(left - wl)) > 1e-12 * max(1, np.abs(wl).max()):
+                return False
+            if np.max(np.abs(right - wr)) > 1e-12 * max(1, np.abs(wr).max()):
+                return False
+        return True
+    check("split_lambda", split_lambda)
+
+    # a solve at lambda = 3/8: the returned box contains the planted minimiser's
+    # value within the bracket, and its reported interval is the box of its id
+    def lambda_solve():
+        p = next(q for q in pp.load()["objectives"] if q["name"] == "DP2")
+        inst = pp.planted_constraint_instance(p, 10, seed=3)
+        s = ref.RefSolver(inst, L=L, lam=0.375, eps=1e-4, delta=1e-3, eps_eq=1e-6, max_boxes=1 << 16,
+                          max_iters=28)
+        out = s.solve()
+        r = s.result()
+        c = 0.5 * (r["x_lo"] + r["x_hi"])
+        widest = max((inst.hi[k] - inst.lo[k]) * 0.625 ** r["depth"][k] for k in range(2))
+        return out == ref.OPTIMAL and r["p_lo"] <= 1e-9 and r["p_up"] <= 1e-4 + 1e-9 and \
+            all(poly_eval(g, c) <= 0 for g in inst.ineq) and widest <= 1e-3 and \
+            r["p_lo"] - 1e-12 <= poly_eval(inst.cost, c) <= r["p_up"] + 1e-12
+    check("lambda_solve", lambda_solve)
+
+    # maximum-width rule on a box four times wider along x1: the direction
+    # follows the widths of the boxes
+    def maxwidth_order():
+        cost = np.zeros((3, 3)); cost[2, 0] = 1.0; cost[0, 2] = 1.0
+        inst = Instance("w", 2, np.array([-2.0, -0.5]), np.array([2.0, 0.5]), cost, [], [],
+                        eps=1e-6, delta=1e-3, eps_eq=1e-6, max_boxes=1 << 16)
+        s = ref.RefSolver(inst, L=L, rule=1)
+        seq = [s.result()["next_dir"]]
+        for _ in range(8):
+            s.step()
+            seq.append(s.result()["next_dir"])
+        # widths (4,1) -> (2,1) -> (1,1), a tie to x1 -> (1/2,1) -> then alternating
+        return seq[:6] == [0, 0, 0, 1, 0, 1]
+    check("maxwidth_order", maxwidth_order)
     return failed
 
 
