@@ -11,8 +11,9 @@ certification, then every plan's result record copied into one host array.
 Inputs are resident in device memory when the timed region starts
 (pcba_reset recomputes the root patches from the resident monomials).
 
-Prints one JSON line: certified solves/s of the better of the FP32 path
-(rigorously widened bounds, FP64 certification) and the plain FP64 path, with
+Prints one JSON line: certified solves/s of the best of the FP32 path
+(rigorously widened bounds, FP64 certification; the split by de Casteljau on
+the vector ALUs or as products on the matrix cores) and the plain FP64 path, with
 p50/p99 per-plan latency, both paths' figures, the roofline of the dominant
 kernel (HIP events around its launches over a second, instrumented pass of the
 same steps), and the FP64 CPU oracle timed on a bounded sample.
@@ -270,6 +271,7 @@ MODE_FLAGS = {
     "r1": ("retire_satisfied", 1),   # constraints certified satisfied on a box are dropped
     "f1": ("fused_round", 1),        # each pass splits both axes: S_a P S_b^T, one cut per round
     "s1": ("stale_filter", 1),       # children already above the previous estimate are not written
+    "mm": ("split_engine", 1),       # FP32 split on the matrix cores (default: de Casteljau on the VALUs)
 }
 
 
@@ -324,11 +326,15 @@ def main():
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="only run device copies of this many MiB (counter calibration) and exit")
     ap.add_argument("--tune", type=int, default=1,
-                    help="1: pick each mode's launch shape (tile size, workgroups per CU, FP32 "
-                         "re-derivation period) with the autotuner before its warm-up; 0: defaults")
+                    help="each mode's launch shape (tile size, workgroups per CU, FP32 re-derivation "
+                         "period): 1 the tuned shape kept with the package, tuned now where it has "
+                         "none; 2 tuned now; 0 the library's defaults")
+    ap.add_argument("--tune-cache", default=None,
+                    help="JSON file of tuned shapes to read and to write tuning results to "
+                         "(default: the package's, read only)")
     ap.add_argument("--single-reps", type=int, default=20,
                     help="solves of one plan alone per headline precision for the single-plan latency (0: skip)")
-    ap.add_argument("--modes", default="fp64:r0,fp32:r0,fp64:r0:f1,fp32:r0:f1,fp64:r1,fp32:r1",
+    ap.add_argument("--modes", default="fp64:r0,fp32:r0,fp32:r0:mm,fp64:r0:f1,fp32:r0:f1,fp64:r1,fp32:r1,fp32:r1:mm",
                     help="comma-separated modes precision[:flag...]; flags: " + ", ".join(MODE_FLAGS) +
                          ". The headline is the best mode that transforms every constraint (r0)")
     args = ap.parse_args()
@@ -358,7 +364,9 @@ def main():
             o["rederive_every"] = args.rederive
         if args.tune:
             from paper_2003_01758_amd import tune
-            o = tune.tuned_options(insts, prec, o, reps=3, log=log)
+            cache = tune.Cache(args.tune_cache or tune.DEFAULT_CACHE)
+            o = tune.tuned_options(insts, prec, o, cache=cache, reps=3, log=log, retune=args.tune == 2,
+                                   write=args.tune_cache is not None)
             log(f"[bench] {name}: tuned options {o}")
         probs = warm(pcba, insts, prec, args.warmup, **o)
         r = run_mode(pcba, probs, insts, prec, args.steps)
@@ -430,6 +438,10 @@ def main():
         "certified": f"{best['certified']}/{best['total']}",
         "modes": {n: summary(n) for n in results},
         "max_abs_p_between_modes": dp,
+        # the metric's comparison on the hot path (every constraint transformed):
+        # FP32 split on the matrix cores and on the vector ALUs against FP64 plain
+        "fp32_vs_fp64_r0": {n: {"solves_per_s": round(results[n]["solves_per_s"], 3),
+                                "p99_ms": round(results[n]["p99_ms"], 4)} for n in hot},
         "single_plan": single,
         "roofline": roofline_of(head, best),
     }

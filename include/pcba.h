@@ -42,11 +42,20 @@ extern "C" {
 /* arithmetic of the per-step subdivision */
 enum {
     PCBA_FP64_PLAIN = 0,  /* FP64 patches, unwidened bounds (the paper's semantics) */
-    PCBA_FP32 = 1         /* FP32 patches split on the matrix cores (MFMA) as
-                             products with the subdivision matrices of Sec. II-E;
-                             every bound widened by a rigorous rounding-error
-                             bound carried per patch; FP64 root, periodic FP64
-                             re-derivation, FP64 certification */
+    PCBA_FP32 = 1         /* FP32 patches (offsets from a per-patch FP64 base),
+                             split by the engine split_engine names; every bound
+                             widened by a rigorous rounding-error bound carried
+                             per patch; FP64 root, periodic FP64 re-derivation,
+                             FP64 certification */
+};
+
+/* how PCBA_FP32 splits a patch (pcba_options.split_engine) */
+enum {
+    PCBA_SPLIT_VALU = 0,  /* de Casteljau at the subdivision parameter on the vector
+                             ALUs, one fibre per lane (Sec. II-E) */
+    PCBA_SPLIT_MFMA = 1   /* on the matrix cores: both children of a block of fibres
+                             as one product with the stacked subdivision matrices
+                             [S_L; S_R] of Sec. II-E (FP32 MFMA) */
 };
 
 /* outcomes (pcba_result_t.outcome) */
@@ -117,6 +126,9 @@ typedef struct {
                                 1: maximum width, the axis along which the boxes are widest
                                 (the widest box at the list's depth vector; ties to the lowest
                                 axis).  All boxes of a step share the direction. */
+    int32_t split_engine;    /* PCBA_FP32 only: PCBA_SPLIT_VALU (default) or PCBA_SPLIT_MFMA.
+                                Both carry a rigorous bound for their own rounding; the
+                                results differ only within it */
     double subdiv_lambda;    /* subdivision parameter in (0,1), default 1/2: a box [a,b] along
                                 the split axis becomes [a, a + lambda (b-a)] and the rest.  Away
                                 from 1/2 boxes are no longer congruent: the stopping test uses

@@ -1464,19 +1464,22 @@ __global__ __launch_bounds__(SUB_THREADS, 2) void k_sub(const DevInst* __restric
             if (tid < c2.np) patch_info(insts[c2.bi], c2, tid, ninf, nsrc);
         }
         lds_barrier();
-        // the split: FP32 tiles on the matrix cores, FP64 plain tiles by de
-        // Casteljau as the oracle does.  A round splits along axis 0 (halves in
+        // the split: FP64 plain tiles by de Casteljau as the oracle does, FP32
+        // tiles by de Casteljau too or (the problem's choice, uniform over the
+        // workgroup) on the matrix cores.  A round splits along axis 0 (halves in
         // regions 0 and 1), then both halves along axis 1 (the right quarters to
         // regions 2 and 3): region b0 + 2 b1 holds the child with bit b0 on axis 0
         // and b1 on axis 1, the same sequence of operations as the oracle's.
-        if constexpr (sizeof(T) == 4)
-            tile_split_mfma(np, S, c.g, La, Lb, Lkey, I.lam);
+        bool on_mfma = false;
+        if constexpr (sizeof(T) == 4) on_mfma = I.mfma != 0;
+        if (on_mfma)
+            tile_split_mfma(np, S, c.g, (float*)La, (float*)Lb, (unsigned*)Lkey, I.lam);
         else
             tile_split<T, MM>(np, S, c.g, La, Lb, Lkey, I.lam);
         if (nc == 4) {
             lds_barrier();
-            if constexpr (sizeof(T) == 4)
-                tile_split_mfma(2 * np, S, c.g2, La, La + 2 * TE, Lkey2, I.lam);
+            if (on_mfma)
+                tile_split_mfma(2 * np, S, c.g2, (float*)La, (float*)(La + 2 * TE), (unsigned*)Lkey2, I.lam);
             else
                 tile_split<T, MM>(2 * np, S, c.g2, La, La + 2 * TE, Lkey2, I.lam);
         }
@@ -1502,11 +1505,22 @@ __global__ __launch_bounds__(SUB_THREADS, 2) void k_sub(const DevInst* __restric
             poly = kind == 0 ? 0 : I.count[0] + (kind == 2 ? I.count[1] : 0) + id;
             // FP32: the split's rounding bound over the parent's offsets (for a
             // round, the first split's; the second adds its own per half)
-            // (away from the midpoint the matrix entries are rounded to FP32 too:
-            // |S~ - S| <= 2^-24 S adds less than two more roundings per term)
-            const int mx_extra = I.lam == 0.5 ? 0 : 2;
+            // gamma_k here takes u = 2^-23, twice the unit roundoff.  At the
+            // midpoint both engines stay within gamma_m: the products round at
+            // most m times on any term's path, de Casteljau rounds one sum per
+            // level (m - 1 roundings of 2^-24, the halving exact).  Away from
+            // it the matrix entries are rounded to FP32 (|S~ - S| <= 2^-24 S:
+            // less than two more roundings per term).  De Casteljau rounds two
+            // products and a sum per level, two roundings of 2^-24 on a term's
+            // path (m - 1 of u), and when fl(lam) or fl(1 - fl(lam)) is not
+            // exact the two weights are off by at most 2^-23 together, at most
+            // u max|c| more per level.  Should subnormal results be flushed,
+            // each rounded operation on a term's path adds below 2^-126 (at
+            // most two per level at the midpoint, three away from it).
+            const bool w_exact = (double)(float)I.lam == I.lam && (double)(1.0f - (float)I.lam) == 1.0 - I.lam;
+            const int mx_extra = I.lam == 0.5 ? 0 : (I.mfma ? 2 : (w_exact ? 0 : c.g.m));
             const double e1 = fp32 ? (double)ce + gamma32(c.g.m + mx_extra) * (double)funkey(Lkey[5 * p + 4]) +
-                                         (double)c.g.m * 0x1p-126
+                                         (double)(3 * c.g.m) * 0x1p-126
                                    : 0.0;
             for (int ch = 0; ch < nc; ++ch) {
                 // the keys of child ch: one split, half ch; a round, half b0 of the
@@ -1527,7 +1541,7 @@ __global__ __launch_bounds__(SUB_THREADS, 2) void k_sub(const DevInst* __restric
                     double ee = e1;
                     if (nc == 4)
                         ee += gamma32(c.g2.m) * (double)funkey(Lkey2[5 * (b0 * np + p) + 4]) +
-                              (double)c.g2.m * 0x1p-126;
+                              (double)(2 * c.g2.m) * 0x1p-126;
                     e = (double)round_up_f(ee);
                     const float mc = 0.5f * (float)mn + 0.5f * (float)mx;
                     const double nbs = base + (double)mc;

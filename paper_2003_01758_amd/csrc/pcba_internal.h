@@ -129,7 +129,7 @@ struct DevInst {
     double width0[MAXL];           // hi - lo of D
     double lam;                    // subdivision parameter (1/2: midpoint)
     int32_t rule;                  // direction rule: 0 the order 1..l, 1 maximum width
-    int32_t pad_rule;
+    int32_t mfma;                  // FP32: split on the matrix cores (else de Casteljau on the VALUs)
     void* buf[2];                  // item buffers (double or float), cap * stride each
     uint32_t* ids[2];              // cap * l box indices
     float* err[2];                 // FP32 mode: cap * n_polys error bounds

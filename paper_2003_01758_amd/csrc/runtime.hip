@@ -395,6 +395,7 @@ static DevInst make_dev(const pcba_problem* P)
     I.rows = P->rows;
     I.fused = P->opt.fused_round ? 1 : 0;
     I.rule = P->opt.direction_rule;
+    I.mfma = (P->opt.precision == PCBA_FP32 && P->opt.split_engine == PCBA_SPLIT_MFMA) ? 1 : 0;
     I.lam = P->opt.subdiv_lambda;
     for (int t = 0; t < KINDS; ++t) I.tmk[t] = P->tmk[t];
     I.root = P->root_written ? nullptr : P->d_root;
@@ -782,6 +783,7 @@ void pcba_default_options(pcba_options* o)
     o->tile_coefs = 0;
     o->wg_per_cu = 0;
     o->direction_rule = 0;
+    o->split_engine = PCBA_SPLIT_VALU;
     o->subdiv_lambda = 0.5;
 }
 
@@ -823,6 +825,8 @@ int pcba_create_problem(int32_t l, const double* lo, const double* hi, const int
     }
     if (o.wg_per_cu < 0) return fail(PCBA_E_ARG, "wg_per_cu must be >= 0");
     if (o.direction_rule != 0 && o.direction_rule != 1) return fail(PCBA_E_ARG, "direction_rule must be 0 or 1");
+    if (o.split_engine != PCBA_SPLIT_VALU && o.split_engine != PCBA_SPLIT_MFMA)
+        return fail(PCBA_E_ARG, "split_engine must be PCBA_SPLIT_VALU or PCBA_SPLIT_MFMA");
     if (!(o.subdiv_lambda > 0.0 && o.subdiv_lambda < 1.0))
         return fail(PCBA_E_ARG, "subdiv_lambda must lie in (0,1)");
     if (o.fused_round && (o.direction_rule != 0 || o.subdiv_lambda != 0.5))

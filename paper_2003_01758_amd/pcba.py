@@ -16,6 +16,7 @@ LIB_PATH = os.path.join(HERE, "libpcba.so")
 
 MAX_DIM = 8
 FP64_PLAIN, FP32 = 0, 1
+SPLIT_VALU, SPLIT_MFMA = 0, 1
 RUNNING, OPTIMAL, INFEASIBLE, MEMORY_LIMIT, MAX_ITER, TIMEOUT = -1, 0, 1, 2, 3, 4
 OUTCOME_NAMES = {RUNNING: "running", OPTIMAL: "optimal", INFEASIBLE: "infeasible",
                  MEMORY_LIMIT: "memory_limit", MAX_ITER: "max_iter", TIMEOUT: "timeout"}
@@ -31,7 +32,8 @@ class Options(C.Structure):
                 ("rederive_every", C.c_int32), ("stale_filter", C.c_int32),
                 ("retire_satisfied", C.c_int32), ("fused_round", C.c_int32),
                 ("time_limit_s", C.c_double), ("tile_coefs", C.c_int32), ("wg_per_cu", C.c_int32),
-                ("direction_rule", C.c_int32), ("subdiv_lambda", C.c_double)]
+                ("direction_rule", C.c_int32), ("split_engine", C.c_int32),
+                ("subdiv_lambda", C.c_double)]
 
 
 class Result(C.Structure):
@@ -153,6 +155,8 @@ def default_options(**kw) -> Options:
     for k, v in kw.items():
         if k == "precision" and isinstance(v, str):
             v = {"fp64": FP64_PLAIN, "fp32": FP32}[v]
+        if k == "split_engine" and isinstance(v, str):
+            v = {"valu": SPLIT_VALU, "mfma": SPLIT_MFMA}[v]
         setattr(o, k, v)
     return o
 
@@ -180,7 +184,7 @@ class Problem:
     keyword options override its tolerances (eps, delta, eps_eq, max_boxes,
     max_iters) and set precision ('fp64'|'fp32'), rederive_every, stale_filter,
     retire_satisfied, fused_round, time_limit_s, tile_coefs, wg_per_cu,
-    direction_rule, subdiv_lambda."""
+    direction_rule, split_engine ('valu'|'mfma'), subdiv_lambda."""
 
     def __init__(self, inst, **kw):
         L = lib()

@@ -40,7 +40,9 @@ def class_key(inst, precision: str, opts: dict) -> str:
     bucket = 0 if inst.n_ineq == 0 else int(round(math.log2(inst.n_ineq)))
     return json.dumps({"l": int(inst.l), "sizes": degs, "ineq_log2": bucket, "eq": int(inst.n_eq),
                        "precision": precision, "retire": int(opts.get("retire_satisfied", 1)),
-                       "round": int(opts.get("fused_round", 0))}, sort_keys=True)
+                       "round": int(opts.get("fused_round", 0)),
+                       "mfma": int(opts.get("split_engine", 0)) if precision == "fp32" else 0},
+                      sort_keys=True)
 
 
 def candidates(precision: str, opts: dict, l: int):
@@ -104,6 +106,10 @@ def tune(insts, precision: str, opts: dict, reps: int = 3, log=None) -> dict:
     return best
 
 
+# tuned shapes kept with the package, written from measured runs
+DEFAULT_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned_shapes.json")
+
+
 class Cache:
     """Tuned shapes by class, in a JSON file."""
 
@@ -117,8 +123,10 @@ class Cache:
     def get(self, key: str):
         return self.data.get(key)
 
-    def put(self, key: str, rec: dict):
+    def put(self, key: str, rec: dict, write: bool = True):
         self.data[key] = rec
+        if not write:
+            return
         d = os.path.dirname(self.path)
         if d:
             os.makedirs(d, exist_ok=True)
@@ -126,15 +134,19 @@ class Cache:
             json.dump(self.data, f, indent=1, sort_keys=True)
 
 
-def tuned_options(insts, precision: str, opts: dict, cache: Cache | None = None, reps: int = 3, log=None) -> dict:
-    """opts plus the tuned shape of the class of insts[0] (tuned on insts when
-    the cache has no entry)."""
+def tuned_options(insts, precision: str, opts: dict, cache: Cache | None = None, reps: int = 3, log=None,
+                  retune: bool = False, write: bool = True) -> dict:
+    """opts plus the tuned shape of the class of insts[0]: the cache's entry,
+    or (none, or retune) one tuned on insts and put in the cache (written to
+    its file if `write`)."""
     key = class_key(insts[0], precision, opts)
-    rec = cache.get(key) if cache else None
+    rec = None if (retune or cache is None) else cache.get(key)
     if rec is None:
         rec = tune(insts, precision, opts, reps=reps, log=log)
         if cache:
-            cache.put(key, rec)
+            cache.put(key, rec, write=write)
+    elif log:
+        log(f"[tune] {precision}: shape from the cache: {rec['shape']}")
     out = dict(opts)
     out.update(rec["shape"])
     return out

@@ -129,11 +129,12 @@ def test_fp64_full_rtd_solve_matches_oracle(gpu, k):
     assert max(poly_eval(q, c) for q in inst.ineq) <= 1e-6
 
 
+@pytest.mark.parametrize("engine", ["valu", "mfma"])
 @pytest.mark.parametrize("name", ["small0", "small1", "rtd40", "batch_l3", "P4", "circle_eq"])
-def test_fp32_solve_matches_oracle_within_eps(gpu, name):
+def test_fp32_solve_matches_oracle_within_eps(gpu, name, engine):
     inst = CASES[name]()
-    print(f"[fp32 solve] {name}", flush=True)
-    rg = gpu.Problem(inst, precision="fp32").solve()
+    print(f"[fp32 solve] {name} {engine}", flush=True)
+    rg = gpu.Problem(inst, precision="fp32", split_engine=engine).solve()
     o = ref.RefSolver(inst)
     o.solve()
     ro = o.result()
@@ -150,13 +151,14 @@ def test_fp32_solve_matches_oracle_within_eps(gpu, name):
         assert abs(poly_eval(q, c)) <= inst.eps_eq + 1e-6
 
 
+@pytest.mark.parametrize("engine", ["valu", "mfma"])
 @pytest.mark.parametrize("name,rederive", [("rtd40", 8), ("rtd40", 0), ("small1", 3), ("batch_l3", 5)])
-def test_fp32_error_bound_is_sound(gpu, name, rederive):
+def test_fp32_error_bound_is_sound(gpu, name, rederive, engine):
     # every FP32 coefficient stays within its patch's carried bound of the FP64
     # patch the oracle derives for the same box id
     inst = CASES[name]()
-    print(f"[fp32 bound] {name} rederive={rederive}", flush=True)
-    g = gpu.Problem(inst, precision="fp32", rederive_every=rederive)
+    print(f"[fp32 bound] {name} rederive={rederive} {engine}", flush=True)
+    g = gpu.Problem(inst, precision="fp32", rederive_every=rederive, split_engine=engine)
     o = ref.RefSolver(inst)
     sizes = [int(np.prod(inst.cost.shape))]
     kdeg = [o.kind_degree(1), o.kind_degree(2)]
@@ -199,10 +201,12 @@ def test_batch_results_equal_alone(gpu):
 
 
 def test_fp32_batch_results_equal_alone(gpu):
-    names = ["small0", "rtd40", "batch_l3"]
+    # the batch mixes both split engines: each problem's tiles take its own
+    names = ["small0", "rtd40", "batch_l3", "small0", "rtd40", "batch_l3"]
+    engines = ["valu"] * 3 + ["mfma"] * 3
     insts = [CASES[n]() for n in names]
-    alone = [gpu.Problem(i, precision="fp32").solve() for i in insts]
-    mixed = gpu.solve_batch([gpu.Problem(i, precision="fp32") for i in insts])
+    alone = [gpu.Problem(i, precision="fp32", split_engine=e).solve() for i, e in zip(insts, engines)]
+    mixed = gpu.solve_batch([gpu.Problem(i, precision="fp32", split_engine=e) for i, e in zip(insts, engines)])
     for n, a, b in zip(names, alone, mixed):
         for key in ("outcome", "p_up", "p_lo", "steps", "certified"):
             assert a[key] == b[key], (n, key)

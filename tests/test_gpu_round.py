@@ -98,11 +98,12 @@ def test_fp64_round_full_rtd_solve_matches_oracle(gpu, k):
     assert max(poly_eval(q, c) for q in inst.ineq) <= 1e-6
 
 
+@pytest.mark.parametrize("engine", ["valu", "mfma"])
 @pytest.mark.parametrize("name", ["small0", "small1", "rtd40", "P2", "waypoints30"])
-def test_fp32_round_solve_matches_oracle_within_eps(gpu, name):
+def test_fp32_round_solve_matches_oracle_within_eps(gpu, name, engine):
     inst = CASES[name]()
-    print(f"[round fp32 solve] {name}", flush=True)
-    rg = gpu.Problem(inst, precision="fp32", retire_satisfied=0, fused_round=1).solve()
+    print(f"[round fp32 solve] {name} {engine}", flush=True)
+    rg = gpu.Problem(inst, precision="fp32", retire_satisfied=0, fused_round=1, split_engine=engine).solve()
     o = ref.RefSolver(inst, fused=True)
     o.solve()
     ro = o.result()
@@ -115,14 +116,16 @@ def test_fp32_round_solve_matches_oracle_within_eps(gpu, name):
         assert poly_eval(q, c) <= 1e-6
 
 
+@pytest.mark.parametrize("engine", ["valu", "mfma"])
 @pytest.mark.parametrize("name,rederive", [("rtd40", 4), ("rtd40", 0), ("small1", 3)])
-def test_fp32_round_error_bound_is_sound(gpu, name, rederive):
-    # every FP32 coefficient after a round (two products on the matrix cores)
-    # stays within its patch's carried bound of the oracle's FP64 patch of the
-    # same box
+def test_fp32_round_error_bound_is_sound(gpu, name, rederive, engine):
+    # every FP32 coefficient after a round (two splits, by de Casteljau or as
+    # products on the matrix cores) stays within its patch's carried bound of
+    # the oracle's FP64 patch of the same box
     inst = CASES[name]()
-    print(f"[round fp32 bound] {name} rederive={rederive}", flush=True)
-    g = gpu.Problem(inst, precision="fp32", retire_satisfied=0, fused_round=1, rederive_every=rederive)
+    print(f"[round fp32 bound] {name} rederive={rederive} {engine}", flush=True)
+    g = gpu.Problem(inst, precision="fp32", retire_satisfied=0, fused_round=1, rederive_every=rederive,
+                    split_engine=engine)
     o = ref.RefSolver(inst)
     sizes = [int(np.prod(inst.cost.shape))]
     kdeg = [o.kind_degree(1), o.kind_degree(2)]

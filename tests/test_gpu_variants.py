@@ -4,9 +4,10 @@ the oracle run with the same rule and parameter.
 
 FP64 plain mode performs the oracle's operations in the oracle's order
 (de Casteljau at the parameter, products and sum as the oracle writes them),
-so step traces are compared step by step; FP32 splits on the matrix cores with
-the parameter's matrices rounded to FP32 and a bound widened for that, and is
-compared on final results."""
+so step traces are compared step by step; FP32 splits by de Casteljau with
+rounded weights or on the matrix cores with the parameter's matrices rounded
+to FP32, a bound widened for either, and is compared on final results and on
+the soundness of its carried bounds."""
 import numpy as np
 import pytest
 
@@ -97,11 +98,12 @@ FP32_CASES = [("small1", rule, lam) for rule, lam in VARIANTS] + \
               ("rtdpop9", 0, 0.375), ("rtdpop9", 1, 0.375)]
 
 
+@pytest.mark.parametrize("engine", ["valu", "mfma"])
 @pytest.mark.parametrize("name,rule,lam", FP32_CASES)
-def test_fp32_within_eps_and_certified(gpu, name, rule, lam):
+def test_fp32_within_eps_and_certified(gpu, name, rule, lam, engine):
     inst = CASES[name]()
-    print(f"[variant fp32] {name} rule={rule} lam={lam}", flush=True)
-    kw = dict(direction_rule=rule, subdiv_lambda=lam)
+    print(f"[variant fp32] {name} rule={rule} lam={lam} {engine}", flush=True)
+    kw = dict(direction_rule=rule, subdiv_lambda=lam, split_engine=engine)
     if lam != 0.5:
         kw["rederive_every"] = 0
     r = gpu.Problem(inst, precision="fp32", **kw).solve()
@@ -113,6 +115,45 @@ def test_fp32_within_eps_and_certified(gpu, name, rule, lam):
     assert r["certified"]
     c = 0.5 * (r["x_lo"] + r["x_hi"])
     assert max(poly_eval(g, c) for g in inst.ineq) <= 1e-6
+
+
+@pytest.mark.parametrize("engine", ["valu", "mfma"])
+@pytest.mark.parametrize("name,rule,lam", [("small1", 0, 0.375), ("small1", 1, 0.625), ("rtd40", 0, 0.375),
+                                           ("rtd40", 1, 0.625)])
+def test_fp32_error_bound_is_sound_away_from_the_midpoint(gpu, name, rule, lam, engine):
+    # every FP32 coefficient stays within its patch's carried bound of the FP64
+    # patch the oracle derives for the same box under the same rule and lambda
+    # (de Casteljau with rounded weights, or the rounded matrices)
+    inst = CASES[name]()
+    print(f"[variant fp32 bound] {name} rule={rule} lam={lam} {engine}", flush=True)
+    g = gpu.Problem(inst, precision="fp32", direction_rule=rule, subdiv_lambda=lam, rederive_every=0,
+                    split_engine=engine)
+    o = ref.RefSolver(inst, rule=rule, lam=lam)
+    sizes = [int(np.prod(inst.cost.shape))]
+    kdeg = [o.kind_degree(1), o.kind_degree(2)]
+    sizes += [int(np.prod(kdeg[0] + 1))] * inst.n_ineq + [int(np.prod(kdeg[1] + 1))] * inst.n_eq
+    offs = np.concatenate([[0], np.cumsum(sizes)])
+    rng = np.random.default_rng(3)
+    checked = 0
+    for step in range(40):
+        r = g.step(1)
+        ids, pat = g.list()
+        err = g.errors()
+        for row in rng.choice(len(ids), size=min(6, len(ids)), replace=False) if len(ids) else []:
+            want = o.derive(r["depth"], ids[row])
+            for p in range(len(sizes)):
+                got = pat[row, offs[p]:offs[p + 1]]
+                w = want[offs[p]:offs[p + 1]]
+                if np.isnan(got).all():
+                    # retired on an ancestor whose widened bound was <= 0
+                    assert w.max() <= 1e-12 * max(1.0, np.abs(w).max()), (step, row, p)
+                    continue
+                d = np.abs(got - w).max()
+                assert d <= err[row, p], (step, row, p, d, err[row, p])
+                checked += 1
+        if r["outcome"] != gpu.RUNNING:
+            break
+    assert checked > 0
 
 
 def test_maximum_width_rule_follows_the_box(gpu):
