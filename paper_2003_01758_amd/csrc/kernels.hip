@@ -866,9 +866,13 @@ __device__ __forceinline__ void tile_split(int np, int S, const FibreGeom& g, T*
 {
     const bool mid = lam == 0.5;
     const int TF = np * g.F;
+    // quotients by reciprocals, exact for dividends below 2^22 (see patch_of)
+    const float invF = 1.0f / (float)g.F, invT = 1.0f / (float)g.stride;
     for (int f = threadIdx.x; f < TF; f += blockDim.x) {
-        const int p = f / g.F;
-        const int base = p * S + fibre_base(g, f - p * g.F);
+        const int p = (int)(((float)f + 0.5f) * invF);
+        const int q = f - p * g.F;
+        const int outer = (int)(((float)q + 0.5f) * invT);
+        const int base = p * S + outer * g.m * g.stride + (q - outer * g.stride);
         T mnL, mxL, mnR, mxR, amax = (T)0;
         switch (g.m) {
 #define PCBA_SPLIT_CASE(MV)                                                                          \
@@ -1593,7 +1597,25 @@ __global__ __launch_bounds__(SUB_THREADS, 2) void k_sub(const DevInst* __restric
         // sub-boxes, and the child drops it), in one workgroup scan
         int seg = 0, k0 = 0, k1 = 0;
         int3 ex = make_int3(0, 0, 0), tot = make_int3(0, 0, 0);
-        if (kind != 0) {
+        if (kind != 0 && c.contig) {
+            // a tile inside one parent is one segment: no scan.  The children's
+            // flags are ORed per wave by ballots, then across the waves in LDS
+            for (int ch = 0; ch < nc; ++ch) {
+                const uint32_t f = (__ballot(act && (f2[ch] & F_INFEAS)) ? F_INFEAS : 0u) |
+                                   (__ballot(act && (f2[ch] & F_NOTFEAS)) ? F_NOTFEAS : 0u);
+                if (f && (tid & 63) == 0) atomicOr(&Lsfl[ch], f);
+            }
+            if (tid == 0) {
+                Lseg[0] = 0;
+                Lseg[1] = np;
+                s_nseg = 1;
+            }
+            lds_barrier();
+            if (tid < nc) {
+                const uint32_t f = Lsfl[tid];
+                if (f) atomicOr(&I.flags[nc * inf[0].x + tid], f);
+            }
+        } else if (kind != 0) {
             const int start = act && (p == 0 || inf[p - 1].x != j);
             if (c.gath && act) {
                 k0 = hi[0] > 0.0;
