@@ -157,7 +157,8 @@ typedef struct {
                                    FP64 error bound */
     double p_cert;              /* rigorous FP64 upper bound of p over x* */
     double cert_err;            /* the FP64 error bound used for the certificate */
-    double err_max;             /* PCBA_FP32: largest per-patch error bound in the list */
+    double err_max;             /* PCBA_FP32: largest error bound given to a patch by a
+                                   subdivision since the last reset (0 in FP64 plain mode) */
     double seconds;             /* wall time of the last solve call */
     int64_t capacity;           /* items the device list can hold now */
 } pcba_result_t;

@@ -634,7 +634,7 @@ __global__ __launch_bounds__(256) void k_root(const DevInst* __restrict__ insts,
             }
             // the accurate root's bound, the rounding of the offsets (the FP64
             // difference and the conversion, 2^-23 of the largest), underflow
-            I.err[0][poly] = round_up_f(I.root_err[poly] + hr * 0x1p-23 + 0x1p-126);
+            I.err[0][poly] = make_float2(round_up_f(I.root_err[poly] + hr * 0x1p-23 + 0x1p-126), 0.0f);
             I.base[0][poly] = pbase;
         }
     }
@@ -776,16 +776,18 @@ __global__ void k_reset(const DevInst* __restrict__ insts, int n)
 // buffer a (every fibre belongs to one thread), the right child goes to b.
 template <typename T, int M>
 __device__ __forceinline__ void split_fibre(T* __restrict__ a, T* __restrict__ b, int base,
-                                            int stride, T& mnL, T& mxL, T& mnR, T& mxR, T& amax)
+                                            int stride, T s0, T& mnL, T& mxL, T& mnR, T& mxR, T& amax)
 {
     T c[M];
 #pragma unroll
     for (int i = 0; i < M; ++i) {
         c[i] = a[base + i * stride];
+        if constexpr (sizeof(T) == 4) c[i] -= s0;   // FP32: less the pending shift
         amax = fmax(amax, fabs(c[i]));
     }
     mnL = mxL = c[0];
     mnR = mxR = c[M - 1];
+    if constexpr (sizeof(T) == 4) a[base] = c[0];   // the left child's first coefficient, shifted
     b[base + (M - 1) * stride] = c[M - 1];
 #pragma unroll
     for (int lev = 1; lev < M; ++lev) {
@@ -804,18 +806,20 @@ __device__ __forceinline__ void split_fibre(T* __restrict__ a, T* __restrict__ b
 // and the rest): c_i <- (1 - lam) c_i + lam c_{i+1}, products and sum in the
 // order the oracle takes them.
 template <typename T, int M>
-__device__ __forceinline__ void split_fibre_at(T* __restrict__ a, T* __restrict__ b, int base, int stride, T lam,
-                                               T& mnL, T& mxL, T& mnR, T& mxR, T& amax)
+__device__ __forceinline__ void split_fibre_at(T* __restrict__ a, T* __restrict__ b, int base, int stride, T s0,
+                                               T lam, T& mnL, T& mxL, T& mnR, T& mxR, T& amax)
 {
     const T mu = (T)1 - lam;
     T c[M];
 #pragma unroll
     for (int i = 0; i < M; ++i) {
         c[i] = a[base + i * stride];
+        if constexpr (sizeof(T) == 4) c[i] -= s0;   // FP32: less the pending shift
         amax = fmax(amax, fabs(c[i]));
     }
     mnL = mxL = c[0];
     mnR = mxR = c[M - 1];
+    if constexpr (sizeof(T) == 4) a[base] = c[0];   // the left child's first coefficient, shifted
     b[base + (M - 1) * stride] = c[M - 1];
 #pragma unroll
     for (int lev = 1; lev < M; ++lev) {
@@ -858,11 +862,11 @@ __device__ __forceinline__ void copy_to_lds(T* __restrict__ dst, const T* __rest
 
 // Splits the staged tile (np patches of S coefficients at a) along the fibres
 // of geometry g: left child in place in a, right child in b, per-patch min/max
-// of both children and max |parent| folded into key.  Callers follow with
-// lds_barrier().
+// of both children and max |parent| folded into key.  With sh (FP32), patch p
+// is split as its values less sh[p].  Callers follow with lds_barrier().
 template <typename T, int MM>
 __device__ __forceinline__ void tile_split(int np, int S, const FibreGeom& g, T* a, T* b,
-                                           typename KeyOf<T>::type* key, double lam)
+                                           typename KeyOf<T>::type* key, double lam, const T* sh)
 {
     const bool mid = lam == 0.5;
     const int TF = np * g.F;
@@ -874,14 +878,15 @@ __device__ __forceinline__ void tile_split(int np, int S, const FibreGeom& g, T*
         const int outer = (int)(((float)q + 0.5f) * invT);
         const int base = p * S + outer * g.m * g.stride + (q - outer * g.stride);
         T mnL, mxL, mnR, mxR, amax = (T)0;
+        const T s0 = sh ? sh[p] : (T)0;
         switch (g.m) {
 #define PCBA_SPLIT_CASE(MV)                                                                          \
         case MV:                                                                                     \
             if (MV <= MM) {                                                                          \
                 if (mid)                                                                             \
-                    split_fibre<T, MV>(a, b, base, g.stride, mnL, mxL, mnR, mxR, amax);              \
+                    split_fibre<T, MV>(a, b, base, g.stride, s0, mnL, mxL, mnR, mxR, amax);          \
                 else                                                                                 \
-                    split_fibre_at<T, MV>(a, b, base, g.stride, (T)lam, mnL, mxL, mnR, mxR, amax);   \
+                    split_fibre_at<T, MV>(a, b, base, g.stride, s0, (T)lam, mnL, mxL, mnR, mxR, amax); \
             }                                                                                        \
             break;
             PCBA_SPLIT_CASE(1) PCBA_SPLIT_CASE(2) PCBA_SPLIT_CASE(3) PCBA_SPLIT_CASE(4)
@@ -958,7 +963,8 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 // the product for fibre c, so the two lanes of a fibre hold all of its
 // children's coefficients between them.  Rows and columns beyond m are zero,
 // so every output sums exactly the m products of its row.  Results go back as
-// tile_split leaves them: the left child in place in a, the right child in b,
+// tile_split leaves them (with sh, patch p's values less sh[p] are split): the
+// left child in place in a, the right child in b,
 // per-patch min/max of both children and max |parent| folded into key.  A wave
 // reads a block's fibres before it writes them and no other wave touches
 // them, so the in-place write is safe.
@@ -968,7 +974,7 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 // unit's internal rounding) plus m 2^-126 for flushed subnormals: the bound
 // the caller carries for the split.
 __device__ __forceinline__ void tile_split_mfma(int np, int S, const FibreGeom& g, float* a, float* b,
-                                                unsigned* key, double lam)
+                                                unsigned* key, double lam, const float* sh)
 {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
     const int col = lane & 31, kq = lane >> 5;
@@ -996,10 +1002,11 @@ __device__ __forceinline__ void tile_split_mfma(int np, int S, const FibreGeom& 
         }
         float x[8];
         float amax = 0.0f;
+        const float s0 = (fv && sh) ? sh[p] : 0.0f;   // the patch's pending shift
 #pragma unroll
         for (int s = 0; s < 8; ++s) {
             const int i = 2 * s + kq;
-            x[s] = (s < ks && fv && i < m) ? a[base + i * g.stride] : 0.0f;
+            x[s] = (s < ks && fv && i < m) ? a[base + i * g.stride] - s0 : 0.0f;
             amax = fmaxf(amax, fabsf(x[s]));
         }
         f32x16 d = {};
@@ -1126,6 +1133,13 @@ struct PackUnit {
     FibreGeom g2;     // a round: fibres of axis 1
 };
 
+// a / b for a >= 0 and 0 < b < 2^31: a 32-bit division when a fits (the usual
+// case), the 64-bit one otherwise
+__device__ __forceinline__ long long div_nn(long long a, int b)
+{
+    return a < 0x100000000ll ? (long long)((unsigned)a / (unsigned)b) : a / b;
+}
+
 // Resolves unit u: the problem (hint only moves forward, since a block's
 // units increase), the kind and the tile's first patch.  Per problem the
 // units are ceil(K / ptp0) cost tiles, ceil(K beta / ptp2) equality tiles,
@@ -1149,14 +1163,14 @@ __device__ __forceinline__ void resolve_packed(const DevInst* __restrict__ insts
     long long v = u - pre[hint];
     const long long K = si.K;
     long long total;
-    const long long U0 = (K + I.ptp[0] - 1) / I.ptp[0];
+    const long long U0 = div_nn(K + I.ptp[0] - 1, I.ptp[0]);
     if (v < U0) {
         c.kind = 0;
         total = K;
     } else {
         v -= U0;
         const long long n2 = K * I.count[2];
-        const long long U2 = (n2 + I.ptp[2] - 1) / I.ptp[2];
+        const long long U2 = div_nn(n2 + I.ptp[2] - 1, I.ptp[2]);
         if (v < U2) {
             c.kind = 2;
             total = n2;
@@ -1179,8 +1193,8 @@ __device__ __forceinline__ void resolve_packed(const DevInst* __restrict__ insts
     {
         // without the heap, a parent's patches of a kind are consecutive in
         // its slot: a tile within one parent is one run of coefficients
-        const long long cnt = c.kind == 0 ? 1 : I.count[c.kind];
-        c.contig = !c.gath && c.P0 / cnt == (c.P0 + c.np - 1) / cnt;
+        const int cnt = c.kind == 0 ? 1 : I.count[c.kind];
+        c.contig = !c.gath && div_nn(c.P0, cnt) == div_nn(c.P0 + c.np - 1, cnt);
     }
     c.nc = I.fused ? (1 << I.l) : 2;
     if (c.nc == 4) {
@@ -1206,7 +1220,7 @@ __device__ __forceinline__ void patch_info(const DevInst& I, const PackUnit& c, 
         return;
     }
     const int cnt = c.kind == 0 ? 1 : I.count[c.kind];
-    const int j = (int)(P / cnt), id = (int)(P - (long long)j * cnt);
+    const int j = (int)div_nn(P, cnt), id = (int)(P - (long long)j * cnt);
     const int slot = as_global(I.live)[j];
     inf = make_int4(j, slot, id, 0);
     src = (long long)slot * I.stride + I.soff[c.kind] + (long long)id * c.S;
@@ -1346,8 +1360,13 @@ __global__ __launch_bounds__(SUB_THREADS, 2) void k_sub(const DevInst* __restric
         sinfo = s_info;
     }
     const long long total = pre[n_inst];
-    long long u = blockIdx.x;
-    if (u >= total) return;
+    // each workgroup takes a run of consecutive units, so that its successive
+    // tiles mostly belong to one problem (its descriptor stays in the scalar
+    // cache) and to one parent (consecutive coefficients)
+    const long long chunk = (total + gridDim.x - 1) / gridDim.x;
+    long long u = (long long)blockIdx.x * chunk;
+    const long long uend = min(total, u + chunk);
+    if (u >= uend) return;
 
     // LDS carve-up (16-byte aligned pieces)
     unsigned char* q8 = smem;
@@ -1368,7 +1387,7 @@ __global__ __launch_bounds__(SUB_THREADS, 2) void k_sub(const DevInst* __restric
     long long* Lsrc0 = (long long*)carve((size_t)tpm * 8);
     long long* Lsrc1 = (long long*)carve((size_t)tpm * 8);
     long long* Lsrc2 = (long long*)carve((size_t)tpm * 8);
-    T* Lshift = (T*)carve((size_t)nr * tpm * sizeof(T));
+    T* Lpend = (T*)carve((size_t)tpm * sizeof(T));      // FP32: per patch, its pending shift
     int4* Linf0 = (int4*)carve((size_t)tpm * 16);
     int4* Linf1 = (int4*)carve((size_t)tpm * 16);
     int4* Linf2 = (int4*)carve((size_t)tpm * 16);
@@ -1384,8 +1403,10 @@ __global__ __launch_bounds__(SUB_THREADS, 2) void k_sub(const DevInst* __restric
     int hint = 0;
     PackUnit c, cn, c2;   // this tile, the next, the one after
     T v[LB];
-    float ce = 0.0f, ne = 0.0f;     // FP32: this thread's patch's carried error (current, next tile)
-    double cb = 0.0, nb = 0.0;      // and its FP64 base
+    // FP32: this thread's patch's carried error and pending shift (current, next
+    // tile) and its FP64 base
+    float2 ce = make_float2(0.0f, 0.0f), ne = make_float2(0.0f, 0.0f);
+    double cb = 0.0, nb = 0.0;
     // Three patch tables in LDS, in turn: this tile's (tb), the next one's
     // (its coefficients are loaded while this tile is processed) and the one
     // after (its table is loaded during this tile).  Chosen by selects, not by
@@ -1393,11 +1414,12 @@ __global__ __launch_bounds__(SUB_THREADS, 2) void k_sub(const DevInst* __restric
     int tb = 0;
     auto inf_of = [&](int b) { return b == 0 ? Linf0 : (b == 1 ? Linf1 : Linf2); };
     auto src_of = [&](int b) { return b == 0 ? Lsrc0 : (b == 1 ? Lsrc1 : Lsrc2); };
-    auto fp32_patch = [&](const PackUnit& pu, const int4 pinf, float& e, double& b) {
+    auto fp32_patch = [&](const PackUnit& pu, const int4 pinf, float2& e, double& b) {
         const DevInst& In = insts[pu.bi];
         const int poly = pu.kind == 0 ? 0 : In.count[0] + (pu.kind == 2 ? In.count[1] : 0) + pinf.z;
         const int64_t pi = (int64_t)pinf.y * In.n_polys + poly;
-        e = as_global(In.err[pu.cur])[pi];
+        const gmem_t<const float> ep = as_global((const float*)In.err[pu.cur]);
+        e = make_float2(ep[2 * pi], ep[2 * pi + 1]);
         b = as_global(In.base[pu.cur])[pi];
     };
 
@@ -1410,8 +1432,8 @@ __global__ __launch_bounds__(SUB_THREADS, 2) void k_sub(const DevInst* __restric
         Linf0[tid] = pinf;
         Lsrc0[tid] = psrc;
     }
-    long long u1 = u + gridDim.x;
-    bool more1 = u1 < total;
+    long long u1 = u + 1;
+    bool more1 = u1 < uend;
     if (more1) {
         resolve_packed(insts, n_inst, pre, sinfo, u1, hint, cn);
         if (tid < cn.np) {
@@ -1451,6 +1473,7 @@ __global__ __launch_bounds__(SUB_THREADS, 2) void k_sub(const DevInst* __restric
                 kk[4] = 0;
             }
             for (int ch = 0; ch < nr; ++ch) Lsfl[nr * tid + ch] = 0;
+            if (fp32) Lpend[tid] = (T)ce.y;
         }
         // the next tile's coefficients (and FP32 error bounds and bases) in
         // flight for the whole of this tile
@@ -1459,8 +1482,8 @@ __global__ __launch_bounds__(SUB_THREADS, 2) void k_sub(const DevInst* __restric
             if (fp32 && tid < cn.np) fp32_patch(cn, inf_of(tn)[tid], ne, nb);
         }
         // the tile after: resolve it and start loading its patch table
-        const long long u2 = u1 + gridDim.x;
-        const bool more2 = more1 && u2 < total;
+        const long long u2 = u1 + 1;
+        const bool more2 = more1 && u2 < uend;
         int4 ninf = make_int4(0, 0, 0, 0);
         long long nsrc = 0;
         if (more2) {
@@ -1476,16 +1499,18 @@ __global__ __launch_bounds__(SUB_THREADS, 2) void k_sub(const DevInst* __restric
         // and b1 on axis 1, the same sequence of operations as the oracle's.
         bool on_mfma = false;
         if constexpr (sizeof(T) == 4) on_mfma = I.mfma != 0;
+        // (FP32: the first split takes each patch's values less its pending shift)
         if (on_mfma)
-            tile_split_mfma(np, S, c.g, (float*)La, (float*)Lb, (unsigned*)Lkey, I.lam);
+            tile_split_mfma(np, S, c.g, (float*)La, (float*)Lb, (unsigned*)Lkey, I.lam, (const float*)Lpend);
         else
-            tile_split<T, MM>(np, S, c.g, La, Lb, Lkey, I.lam);
+            tile_split<T, MM>(np, S, c.g, La, Lb, Lkey, I.lam, fp32 ? Lpend : nullptr);
         if (nc == 4) {
             lds_barrier();
             if (on_mfma)
-                tile_split_mfma(2 * np, S, c.g2, (float*)La, (float*)(La + 2 * TE), (unsigned*)Lkey2, I.lam);
+                tile_split_mfma(2 * np, S, c.g2, (float*)La, (float*)(La + 2 * TE), (unsigned*)Lkey2, I.lam,
+                                nullptr);
             else
-                tile_split<T, MM>(2 * np, S, c.g2, La, La + 2 * TE, Lkey2, I.lam);
+                tile_split<T, MM>(2 * np, S, c.g2, La, La + 2 * TE, Lkey2, I.lam, nullptr);
         }
         // the table of the tile after next to LDS (its loads had the split to arrive)
         if (more2 && tid < c2.np) {
@@ -1501,6 +1526,7 @@ __global__ __launch_bounds__(SUB_THREADS, 2) void k_sub(const DevInst* __restric
         int j = 0, slot = 0, id = 0, poly = 0;
         uint32_t f2[NCMAX] = {0, 0, 0, 0};
         double lo[NCMAX] = {0.0, 0.0, 0.0, 0.0}, hi[NCMAX] = {0.0, 0.0, 0.0, 0.0};
+        double emx = 0.0;   // FP32: the largest error bound given to a child here
         if (act) {
             const int4 ip = inf[p];
             j = ip.x;
@@ -1523,8 +1549,15 @@ __global__ __launch_bounds__(SUB_THREADS, 2) void k_sub(const DevInst* __restric
             // most two per level at the midpoint, three away from it).
             const bool w_exact = (double)(float)I.lam == I.lam && (double)(1.0f - (float)I.lam) == 1.0 - I.lam;
             const int mx_extra = I.lam == 0.5 ? 0 : (I.mfma ? 2 : (w_exact ? 0 : c.g.m));
-            const double e1 = fp32 ? (double)ce + gamma32(c.g.m + mx_extra) * (double)funkey(Lkey[5 * p + 4]) +
-                                         (double)(3 * c.g.m) * 0x1p-126
+            // The split took the parent's values less its pending shift s, so
+            // the children are offsets from the base plus s (in FP64, rounded:
+            // 2^-52 of it); the subtraction rounds below 2^-23 of the largest
+            // shifted value (max |parent| of the split's keys), or flushes.
+            const double amax = fp32 ? (double)funkey(Lkey[5 * p + 4]) : 0.0;
+            const bool shifted = fp32 && ce.y != 0.0f;
+            const double nbs = shifted ? cb + (double)ce.y : cb;
+            const double e1 = fp32 ? (double)ce.x + gamma32(c.g.m + mx_extra) * amax + (double)(3 * c.g.m) * 0x1p-126 +
+                                         (shifted ? amax * 0x1p-23 + 0x1p-126 + fabs(nbs) * 0x1p-52 : 0.0)
                                    : 0.0;
             for (int ch = 0; ch < nc; ++ch) {
                 // the keys of child ch: one split, half ch; a round, half b0 of the
@@ -1534,26 +1567,25 @@ __global__ __launch_bounds__(SUB_THREADS, 2) void k_sub(const DevInst* __restric
                 const T mn = funkey(kk[0]), mx = funkey(kk[1]);
                 double e = 0.0, base = 0.0;
                 if (fp32) {
-                    // the stored values are offsets from the patch's FP64 base,
-                    // which subdivision keeps (rows sum to one); the split's error
-                    // grows with the offsets.  Each child is then re-centred: its
-                    // base moves by its midrange offset mc and its offsets become
-                    // v - mc, so that they shrink with the box; the shift adds the
-                    // rounding of v - mc (below 2^-24 (max - min)) and of the new
-                    // FP64 base.
-                    base = cb;
+                    // the stored values are offsets from an FP64 base, which
+                    // subdivision keeps (rows sum to one); the split's error grows
+                    // with the offsets.  Each child is re-centred lazily: its
+                    // midrange offset mc is stored as its pending shift, and its
+                    // own split will subtract it first, so that the offsets it
+                    // splits shrink with the box.
+                    base = nbs;
                     double ee = e1;
                     if (nc == 4)
                         ee += gamma32(c.g2.m) * (double)funkey(Lkey2[5 * (b0 * np + p) + 4]) +
                               (double)(2 * c.g2.m) * 0x1p-126;
                     e = (double)round_up_f(ee);
                     const float mc = 0.5f * (float)mn + 0.5f * (float)mx;
-                    const double nbs = base + (double)mc;
                     const int64_t ci = (int64_t)(nc * j + ch) * I.n_polys + poly;
-                    as_global(I.err[cur ^ 1])[ci] = round_up_f(e + ((double)mx - (double)mn) * 0x1p-23 +
-                                                               fabs(nbs) * 0x1p-52 + 0x1p-126);
+                    const gmem_t<float> eo = as_global((float*)I.err[cur ^ 1]);
+                    eo[2 * ci] = (float)e;
+                    eo[2 * ci + 1] = mc;
                     as_global(I.base[cur ^ 1])[ci] = nbs;
-                    Lshift[ch * tpm + p] = (T)mc;
+                    emx = fmax(emx, e);
                 }
                 child_bounds<T>(mn, mx, e, base, lo[ch], hi[ch]);
             }
@@ -1590,6 +1622,13 @@ __global__ __launch_bounds__(SUB_THREADS, 2) void k_sub(const DevInst* __restric
                     f2[ch] = f;
                 }
             }
+        }
+        if (fp32) {
+            // the largest bound of the solve so far (non-negative doubles order
+            // as their bit patterns)
+            for (int o = 32; o > 0; o >>= 1) emx = fmax(emx, __shfl_xor(emx, o, 64));
+            if ((tid & 63) == 0 && emx > 0.0)
+                atomicMax((unsigned long long*)&I.st->err_max, (unsigned long long)__double_as_longlong(emx));
         }
         // constraint tiles: segments (runs of patches of one parent) and, in
         // retiring mode, which children keep each patch (an inequality
@@ -1693,7 +1732,6 @@ __global__ __launch_bounds__(SUB_THREADS, 2) void k_sub(const DevInst* __restric
                             const int e = e0 + q * SUB_THREADS;
                             if (e < TE) {
                                 va[q] = src[e];
-                                if (fp32) va[q] -= Lshift[ch * tpm + patch_of(e, c.invS)];
                             }
                         }
 #pragma unroll
@@ -1722,7 +1760,6 @@ __global__ __launch_bounds__(SUB_THREADS, 2) void k_sub(const DevInst* __restric
                             const int pq = patch_of(e, c.invS);
                             dd[q] = Ldsto[pq];
                             va[q] = src[e];
-                            if (fp32) va[q] -= Lshift[ch * tpm + pq];
                         }
                     }
 #pragma unroll
@@ -1760,9 +1797,8 @@ __global__ __launch_bounds__(SUB_THREADS, 2) void k_sub(const DevInst* __restric
                 const int pq = patch_of(e, c.invS);
                 const int dl = Ldst[pq], dr = Ldst[tpm + pq];
                 const int rr = e - pq * S;
-                const T sl = fp32 ? Lshift[pq] : (T)0, sr = fp32 ? Lshift[tpm + pq] : (T)0;
-                if (dl >= 0) hc[(int64_t)dl * S + rr] = La[e] - sl;
-                if (dr >= 0) hc[(int64_t)dr * S + rr] = Lb[e] - sr;
+                if (dl >= 0) hc[(int64_t)dl * S + rr] = La[e];
+                if (dr >= 0) hc[(int64_t)dr * S + rr] = Lb[e];
             }
         }
         lds_barrier();
@@ -1982,7 +2018,7 @@ __global__ __launch_bounds__(SUB_THREADS) void k_rederive(const DevInst* __restr
                     // retiring mode: an inequality certified satisfied is not carried
                     s_keep[p] = !(gath && hi <= 0.0);
                     s_base[p] = base;
-                    I.err[cur ^ 1][(int64_t)(nc * j + c) * I.n_polys + poly] = (float)e;
+                    I.err[cur ^ 1][(int64_t)(nc * j + c) * I.n_polys + poly] = make_float2((float)e, 0.0f);
                     I.base[cur ^ 1][(int64_t)(nc * j + c) * I.n_polys + poly] = base;
                     if (kind == 0) {
                         I.minP[nc * j + c] = lo;
@@ -2610,7 +2646,7 @@ __global__ void k_pack(DevInst I, double* __restrict__ out, uint32_t* __restrict
         ids_out[(int64_t)j * I.l + threadIdx.x] = I.ids[st->cur][(int64_t)slot * I.l + threadIdx.x];
     if (I.fp32 && err_out)
         for (int p = threadIdx.x; p < I.n_polys; p += blockDim.x)
-            err_out[(int64_t)j * I.n_polys + p] = (double)I.err[st->cur][(int64_t)slot * I.n_polys + p];
+            err_out[(int64_t)j * I.n_polys + p] = (double)I.err[st->cur][(int64_t)slot * I.n_polys + p].x;
 }
 
 __global__ void k_gather(const DevInst* __restrict__ insts, int n, InstState* __restrict__ out)
@@ -2730,7 +2766,7 @@ size_t sub_lds_bytes(int tem, int tpm, bool fp32, int nr)
     const size_t el = fp32 ? 4 : 8;
     auto r16 = [](size_t b) { return (b + 15) & ~(size_t)15; };
     return r16((size_t)nr * tem * el) + r16((size_t)5 * tpm * (nr > 2 ? 3 : 1) * el) + 3 * r16((size_t)tpm * 8) +
-           r16((size_t)nr * tpm * el) + 3 * r16((size_t)tpm * 16) + r16((size_t)tpm * 4) +
+           r16((size_t)tpm * el) + 3 * r16((size_t)tpm * 16) + r16((size_t)tpm * 4) +
            r16((size_t)(2 * tpm + 2) * 4) + r16((size_t)2 * tpm * 4) + r16((size_t)nr * tpm * 4) +
            r16((size_t)2 * tpm * 4) + r16((size_t)(tpm + 1) * 4) + r16((size_t)tpm * 8);
 }

@@ -132,7 +132,9 @@ struct DevInst {
     int32_t mfma;                  // FP32: split on the matrix cores (else de Casteljau on the VALUs)
     void* buf[2];                  // item buffers (double or float), cap * stride each
     uint32_t* ids[2];              // cap * l box indices
-    float* err[2];                 // FP32 mode: cap * n_polys error bounds
+    float2* err[2];                // FP32 mode: cap * n_polys pairs (error bound, pending
+                                   // shift s): the next split works on the stored values
+                                   // less s, relative to the base plus s
     double* base[2];               // FP32 mode: cap * n_polys FP64 bases; a patch's
                                    // coefficients are base + its stored FP32 values
     int32_t* live;                 // cap: slots of the live items, in list order

@@ -157,7 +157,7 @@ struct pcba_problem {
     double* d_cert = nullptr;
     void* d_buf[2] = {nullptr, nullptr};
     uint32_t* d_ids[2] = {nullptr, nullptr};
-    float* d_err[2] = {nullptr, nullptr};
+    float2* d_err[2] = {nullptr, nullptr};   // FP32 mode: per-patch (error bound, pending shift)
     double* d_base[2] = {nullptr, nullptr};   // FP32 mode: per-patch FP64 bases
     int32_t* d_live = nullptr;
     double* d_minP = nullptr;
@@ -493,7 +493,7 @@ static int alloc_list(pcba_problem* P, int64_t ncap, int64_t nhcap, hipStream_t 
         return fail(PCBA_E_NOMEM, "an inequality heap would exceed 2^31 patches");
     void* nb[2] = {nullptr, nullptr};
     uint32_t* ni[2] = {nullptr, nullptr};
-    float* ne[2] = {nullptr, nullptr};
+    float2* ne[2] = {nullptr, nullptr};
     double* nbs[2] = {nullptr, nullptr};
     int32_t* nlive = nullptr;
     double *nmin = nullptr, *nmax = nullptr;
@@ -533,7 +533,7 @@ static int alloc_list(pcba_problem* P, int64_t ncap, int64_t nhcap, hipStream_t 
         ok = pool_alloc(&nb[b], (size_t)ncap * P->stride * P->elem) == hipSuccess &&
              pool_alloc((void**)&ni[b], (size_t)ncap * P->l * sizeof(uint32_t)) == hipSuccess;
         if (ok && P->fp32)
-            ok = pool_alloc((void**)&ne[b], (size_t)ncap * P->n_polys * sizeof(float)) == hipSuccess &&
+            ok = pool_alloc((void**)&ne[b], (size_t)ncap * P->n_polys * sizeof(float2)) == hipSuccess &&
                  pool_alloc((void**)&nbs[b], (size_t)ncap * P->n_polys * sizeof(double)) == hipSuccess;
         if (ok && P->retire)
             ok = pool_alloc((void**)&nact[b], (size_t)ncap * P->count[1] * sizeof(int2)) == hipSuccess &&
@@ -569,7 +569,7 @@ static int alloc_list(pcba_problem* P, int64_t ncap, int64_t nhcap, hipStream_t 
             e = hipMemcpyAsync(ni[cur], P->d_ids[cur], (size_t)used * P->l * sizeof(uint32_t),
                                hipMemcpyDeviceToDevice, s);
         if (e == hipSuccess && P->fp32)
-            e = hipMemcpyAsync(ne[cur], P->d_err[cur], (size_t)used * P->n_polys * sizeof(float),
+            e = hipMemcpyAsync(ne[cur], P->d_err[cur], (size_t)used * P->n_polys * sizeof(float2),
                                hipMemcpyDeviceToDevice, s);
         if (e == hipSuccess && P->fp32)
             e = hipMemcpyAsync(nbs[cur], P->d_base[cur], (size_t)used * P->n_polys * sizeof(double),

@@ -165,7 +165,7 @@ def test_fp32_error_bound_is_sound(gpu, name, rederive, engine):
     sizes += [int(np.prod(kdeg[0] + 1))] * inst.n_ineq + [int(np.prod(kdeg[1] + 1))] * inst.n_eq
     offs = np.concatenate([[0], np.cumsum(sizes)])
     rng = np.random.default_rng(1)
-    worst = 0.0
+    worst = seen = 0.0
     for step in range(60):
         r = g.step(1)
         ids, pat = g.list()
@@ -181,8 +181,12 @@ def test_fp32_error_bound_is_sound(gpu, name, rederive, engine):
                     continue
                 d = np.abs(got - w).max()
                 assert d <= err[row, p], (step, row, p, d, err[row, p])
+                seen = max(seen, float(err[row, p]))
                 if err[row, p] > 0:
                     worst = max(worst, d / err[row, p])
+        if rederive == 0 and seen > 0:
+            # every bound checked came from a subdivision: err_max covers it
+            assert r["err_max"] >= seen, step
         if r["outcome"] != gpu.RUNNING:
             break
     print(f"largest error / bound seen: {worst:.3g}")
