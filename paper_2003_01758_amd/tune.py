@@ -27,7 +27,7 @@ from . import pcba
 # per compute unit
 TILES = {"fp64": (1408, 2048, 2816, 3584), "fp32": (2816, 4096, 5632, 7168)}
 WGS = (0, 1)
-REDERIVE = (8, 16, 32)   # directional steps between FP64 re-derivations (halved for rounds)
+REDERIVE = (8, 16, 32, 0)   # directional steps between FP64 re-derivations (halved for rounds; 0 never)
 
 
 def class_key(inst, precision: str, opts: dict) -> str:
@@ -54,19 +54,29 @@ def candidates(precision: str, opts: dict, l: int):
     return [{"tile_coefs": t, "wg_per_cu": w} for t in tiles for w in WGS]
 
 
-def _time_batch(insts, precision, opts, reps, limit_s=0.0):
-    """Median seconds of `reps` batched solves after one untimed solve; with
-    limit_s, every problem carries that time limit, so a shape that makes the
-    solve far slower than the default ends early (its problems stop with
-    TIMEOUT) instead of running on."""
+def _certified(res, precision):
+    ok = (res["outcome"] == pcba.OPTIMAL) & (res["certified"] != 0)
+    if precision == "fp32":
+        ok = ok | (res["outcome"] == pcba.INFEASIBLE)
+    return int(np.count_nonzero(ok))
+
+
+def _time_batch(insts, precision, opts, reps, limit_s=0.0, need=0):
+    """Median seconds of `reps` batched solves after one untimed solve, and the
+    problems certified; with limit_s, every problem carries that time limit, so
+    a shape that makes the solve far slower than the default ends early (its
+    problems stop with TIMEOUT) instead of running on.  A candidate that
+    certifies fewer than `need` problems (a re-derivation period whose FP32
+    bounds outgrow eps before delta is reached) is not a candidate either."""
     if limit_s > 0:
         opts = dict(opts, time_limit_s=limit_s)
     probs = [pcba.Problem(i, precision=precision, **opts) for i in insts]
     batch = pcba.Batch(probs)
     pcba.reset_batch(batch)
-    pcba.solve_batch(batch, as_array=True)     # first solve: list growth, caches
-    times = []
-    for _ in range(reps):
+    res = pcba.solve_batch(batch, as_array=True)     # first solve: list growth, caches
+    cert = _certified(res, precision)
+    times = [math.inf] if cert < need else []
+    for _ in range(reps if cert >= need else 0):
         t0 = time.perf_counter()
         pcba.reset_batch(batch)
         res = pcba.solve_batch(batch, as_array=True)
@@ -76,19 +86,20 @@ def _time_batch(insts, precision, opts, reps, limit_s=0.0):
             break
     for p in probs:
         p.close()
-    return float(np.median(times))
+    return float(np.median(times)), cert
 
 
 def tune(insts, precision: str, opts: dict, reps: int = 3, log=None) -> dict:
     """The fastest candidate shape for the batch `insts` (the options in opts
-    fixed); returns the shape with its median batch time and the default's."""
-    base = _time_batch(insts, precision, opts, reps)
+    fixed); returns the shape with its median batch time and the default's.
+    Candidates must certify as many problems as the default does."""
+    base, need = _time_batch(insts, precision, opts, reps)
     best = {"shape": {}, "seconds": base}
 
     def trial(cand):
         o = dict(opts)
         o.update(cand)
-        t = _time_batch(insts, precision, o, reps, limit_s=4.0 * base + 0.05)
+        t, _ = _time_batch(insts, precision, o, reps, limit_s=4.0 * base + 0.05, need=need)
         if log:
             log(f"[tune] {precision} {cand}: {t * 1e3:.2f} ms")
         if t < best["seconds"]:
@@ -101,7 +112,7 @@ def tune(insts, precision: str, opts: dict, reps: int = 3, log=None) -> dict:
         shape = dict(best["shape"])
         per = 2 if opts.get("fused_round", 0) else 1    # a round is two directional steps
         for r in REDERIVE:
-            trial(dict(shape, rederive_every=max(1, r // per)))
+            trial(dict(shape, rederive_every=max(1, r // per) if r else 0))
     best["default_seconds"] = base
     return best
 
