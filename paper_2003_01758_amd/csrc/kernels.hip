@@ -1527,11 +1527,28 @@ __global__ __launch_bounds__(SUB_THREADS, 2) void k_sub(const DevInst* __restric
         uint32_t f2[NCMAX] = {0, 0, 0, 0};
         double lo[NCMAX] = {0.0, 0.0, 0.0, 0.0}, hi[NCMAX] = {0.0, 0.0, 0.0, 0.0};
         double emx = 0.0;   // FP32: the largest error bound given to a child here
+        // stale filter, constraint tiles: children already known dead are not
+        // written (bit ch): infeasible by another tile of this step, or with a
+        // cost lower bound recorded this step above the previous estimate (the
+        // new one can only be lower, so the cut drops them).  The loads go out
+        // here and are used after the bounds.
+        uint32_t known_dead = 0;
         if (act) {
             const int4 ip = inf[p];
             j = ip.x;
             slot = ip.y;
             id = ip.z;
+            if (I.stale && kind != 0 && !c.gath) {
+                for (int ch = 0; ch < nc; ++ch) {
+                    const int64_t ci = (int64_t)nc * j + ch;
+                    const uint32_t fl = __hip_atomic_load(&I.flags[ci], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    const unsigned long long rec = __hip_atomic_load(&I.stamp[ci], __ATOMIC_RELAXED,
+                                                                     __HIP_MEMORY_SCOPE_AGENT);
+                    const bool above = (uint32_t)(rec >> 32) == c.stamp &&
+                                       (double)__uint_as_float((uint32_t)rec) > c.pprev;
+                    if ((fl & F_INFEAS) || above) known_dead |= 1u << ch;
+                }
+            }
             poly = kind == 0 ? 0 : I.count[0] + (kind == 2 ? I.count[1] : 0) + id;
             // FP32: the split's rounding bound over the parent's offsets (for a
             // round, the first split's; the second adds its own per half)
@@ -1590,7 +1607,8 @@ __global__ __launch_bounds__(SUB_THREADS, 2) void k_sub(const DevInst* __restric
                 child_bounds<T>(mn, mx, e, base, lo[ch], hi[ch]);
             }
             if (kind == 0) {
-                // cost records, child ids, then the stamp that publishes the records
+                // cost records, child ids, and with the stale filter the record
+                // that constraint tiles of this step read
                 const gmem_t<const uint32_t> pid = as_global((const uint32_t*)I.ids[cur]) + (int64_t)slot * l;
                 const gmem_t<uint32_t> cid = as_global(I.ids[cur ^ 1]) + (int64_t)(nc * j) * l;
                 for (int ch = 0; ch < nc; ++ch) {
@@ -1605,9 +1623,14 @@ __global__ __launch_bounds__(SUB_THREADS, 2) void k_sub(const DevInst* __restric
                     }
                 }
                 if (I.stale)
-                    for (int ch = 0; ch < nc; ++ch)
-                        __hip_atomic_store(&I.stamp[nc * j + ch], c.stamp, __ATOMIC_RELEASE,
-                                           __HIP_MEMORY_SCOPE_AGENT);
+                    for (int ch = 0; ch < nc; ++ch) {
+                        // the stamp and a float at or below the cost lower bound, in
+                        // one store, so that a reader needs no fence
+                        float fl = (float)lo[ch];
+                        if ((double)fl > lo[ch]) fl = nextafterf(fl, -INFINITY);
+                        const unsigned long long rec = ((unsigned long long)c.stamp << 32) | __float_as_uint(fl);
+                        __hip_atomic_store(&I.stamp[nc * j + ch], rec, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    }
             } else {
                 for (int ch = 0; ch < nc; ++ch) {
                     uint32_t f = 0;
@@ -1703,7 +1726,8 @@ __global__ __launch_bounds__(SUB_THREADS, 2) void k_sub(const DevInst* __restric
             if (act) {
                 int wm = 0;
                 for (int ch = 0; ch < nc; ++ch) {
-                    const bool w = kind == 0 ? !(I.stale && lo[ch] > c.pprev) : !(Lsfl[nr * seg + ch] & F_INFEAS);
+                    const bool w = kind == 0 ? !(I.stale && lo[ch] > c.pprev)
+                                             : !(Lsfl[nr * seg + ch] & F_INFEAS) && !((known_dead >> ch) & 1u);
                     if (w) wm |= 1 << ch;
                 }
                 Lwm[p] = wm;

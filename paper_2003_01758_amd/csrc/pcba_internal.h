@@ -141,7 +141,9 @@ struct DevInst {
     double* minP;                  // child records, cap each
     double* maxP;
     uint32_t* flags;
-    uint32_t* stamp;               // cap: step stamp of minP/maxP, set after they are written
+    unsigned long long* stamp;     // cap: the step's stamp (high word) and the bits of an FP32
+                                   // value at or below the child's cost lower bound (low
+                                   // word), written together in one store (stale filter)
     // retiring mode: a box carries only the inequalities not yet certified
     // satisfied on it.  act[b][slot*count[1] + q], q < na[b][slot], are their
     // (index, heap patch) pairs, in any order; the patch itself is S[1]

@@ -163,7 +163,7 @@ struct pcba_problem {
     double* d_minP = nullptr;
     double* d_maxP = nullptr;
     uint32_t* d_flags = nullptr;
-    uint32_t* d_stamp = nullptr;
+    unsigned long long* d_stamp = nullptr;
     int2* d_act[2] = {nullptr, nullptr};   // retiring mode: carried inequalities per slot
     int32_t* d_na[2] = {nullptr, nullptr};
     void* d_heap[2] = {nullptr, nullptr};  // retiring mode: the carried inequality patches
@@ -414,7 +414,9 @@ static DevInst make_dev(const pcba_problem* P)
 
 static int64_t item_bytes(const pcba_problem* P)
 {
-    return P->stride * (int64_t)P->elem + (int64_t)P->l * 4 + (P->fp32 ? P->n_polys * 12 : 0) + 4 + 8 + 8 + 4 +
+    // slot, box ids, FP32 (error bound, shift) and base per patch, live index,
+    // minP, maxP, flags, stale-filter record
+    return P->stride * (int64_t)P->elem + (int64_t)P->l * 4 + (P->fp32 ? P->n_polys * 16 : 0) + 4 + 8 + 8 + 4 + 8 +
            (P->retire ? (int64_t)P->count[1] * 8 + 4 + 8 : 0);
 }
 
@@ -498,7 +500,7 @@ static int alloc_list(pcba_problem* P, int64_t ncap, int64_t nhcap, hipStream_t 
     int32_t* nlive = nullptr;
     double *nmin = nullptr, *nmax = nullptr;
     uint32_t* nfl = nullptr;
-    uint32_t* nst = nullptr;
+    unsigned long long* nst = nullptr;
     double* ntm = nullptr;
     int2* nact[2] = {nullptr, nullptr};
     int32_t* nna[2] = {nullptr, nullptr};
@@ -548,7 +550,7 @@ static int alloc_list(pcba_problem* P, int64_t ncap, int64_t nhcap, hipStream_t 
          pool_alloc((void**)&nmin, (size_t)ncap * sizeof(double)) == hipSuccess &&
          pool_alloc((void**)&nmax, (size_t)ncap * sizeof(double)) == hipSuccess &&
          pool_alloc((void**)&nfl, (size_t)ncap * sizeof(uint32_t)) == hipSuccess &&
-         pool_alloc((void**)&nst, (size_t)ncap * sizeof(uint32_t)) == hipSuccess;
+         pool_alloc((void**)&nst, (size_t)ncap * sizeof(unsigned long long)) == hipSuccess;
     if (ok && need_tm)
         ok = pool_alloc((void**)&ntm, (size_t)(ncap / 2 + 1) * 2 * P->tmw * sizeof(double)) == hipSuccess;
     if (!ok) {
@@ -557,7 +559,7 @@ static int alloc_list(pcba_problem* P, int64_t ncap, int64_t nhcap, hipStream_t 
         return fail(PCBA_E_NOMEM, "device list allocation failed");
     }
     hipError_t e = hipMemsetAsync(nfl, 0, (size_t)ncap * sizeof(uint32_t), s);
-    if (e == hipSuccess) e = hipMemsetAsync(nst, 0, (size_t)ncap * sizeof(uint32_t), s);
+    if (e == hipSuccess) e = hipMemsetAsync(nst, 0, (size_t)ncap * sizeof(unsigned long long), s);
     for (int b = 0; b < 2 && e == hipSuccess && P->retire; ++b)
         e = hipMemsetAsync(nna[b], 0, (size_t)ncap * sizeof(int32_t), s);
     if (e == hipSuccess && P->cap > 0) {

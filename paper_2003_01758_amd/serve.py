@@ -10,6 +10,7 @@ receding-horizon planner (a new plan every 0.5 s, a solver budget of 0.4 s,
 Sec. VI) motivates the per-plan deadline.
 
 Usage: python -m paper_2003_01758_amd.serve --rate 200 --duration 60
+       python -m paper_2003_01758_amd.serve --sweep 500,1000,2000,4000 --duration 10
 """
 from __future__ import annotations
 
@@ -109,6 +110,29 @@ def summarize(records, duration):
                 wall_s=span, offered_s=duration)
 
 
+def sweep(args, log):
+    """Saturation: the highest Poisson arrival rate whose p99 latency (arrival
+    to certified result) stays within the deadline with every plan certified."""
+    pool = [make_instance(4, args.seed * 100000 + k) for k in range(args.pool)]
+    best, rows = None, []
+    for rate in [float(x) for x in args.sweep.split(",")]:
+        arrivals = poisson_arrivals(rate, args.duration, args.seed)
+        requests = [pool[k % len(pool)] for k in range(len(arrivals))]
+        srv = Server(int(args.budget_gib * 2**30), precision=args.precision,
+                     steps_per_round=args.steps_per_round)
+        out = summarize(srv.serve(requests, arrivals), args.duration)
+        out.update(rate=rate)
+        rows.append(out)
+        log(f"[sweep] rate {rate:.0f}/s: p50/p99 {out['p50_ms']:.2f}/{out['p99_ms']:.2f} ms, "
+            f"miss rate {out['deadline_miss_rate']:.4f}, {out['certified']}/{out['plans']} certified")
+        print(json.dumps(out), flush=True)
+        if out["p99_ms"] > 1e3 * srv.deadline or out["certified"] < out["plans"]:
+            break
+        best = rate
+    print(json.dumps({"sweep": rows, "precision": args.precision, "max_rate_within_deadline": best,
+                      "deadline_s": 0.5, "duration_s": args.duration}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--rate", type=float, default=200.0)
@@ -119,8 +143,15 @@ def main():
     ap.add_argument("--steps-per-round", type=int, default=2)
     ap.add_argument("--pool", type=int, default=256,
                     help="distinct plans generated; arrivals cycle through them")
+    ap.add_argument("--sweep", default=None,
+                    help="comma-separated arrival rates, each served for --duration seconds in "
+                         "turn, up to the first whose p99 latency misses the deadline; reports "
+                         "the highest rate served within it")
     args = ap.parse_args()
     log = lambda *a: print(*a, file=sys.stderr, flush=True)
+    if args.sweep:
+        sweep(args, log)
+        return
     arrivals = poisson_arrivals(args.rate, args.duration, args.seed)
     npool = min(args.pool, len(arrivals))
     log(f"[serve] {len(arrivals)} arrivals over {args.duration:.0f} s; generating {npool} distinct plans")
