@@ -135,6 +135,14 @@ typedef struct {
                                 the widest box, max over axes of (hi - lo) max(lambda,
                                 1-lambda)^depth, and with PCBA_FP32 rederive_every must be 0.
                                 Not with fused_round. */
+    int32_t persistent_steps;/* 0 (default): one launch per kernel per step.  1: when every
+                                problem of a batch asks for it, the batch is of one precision (at
+                                most 256 problems, lists of at most 4,096 boxes) and no FP32
+                                re-derivation falls due, several whole steps (subdivision, cut)
+                                run in one cooperative launch with grid barriers between the
+                                phases.  Results are the same either way; on MI355X the barriers'
+                                device-scope release and acquire (eight XCDs, each with its own
+                                L2) cost more than the launches they save. */
 } pcba_options;
 
 typedef struct {

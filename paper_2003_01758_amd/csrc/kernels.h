@@ -23,6 +23,14 @@ hipError_t launch_plan(const DevInst* d_insts, int n, long long* plan, StepInfo*
 hipError_t launch_sub(const DevInst* d_insts, int n, long long* plan, StepInfo* info, bool fuse,
                       bool fp32, int maxm, int grid, int tem, int tpm, int nr, int wg_cap, hipStream_t s,
                       hipEvent_t ev0, hipEvent_t ev1);
+// Up to n_steps whole steps (subdivision, cut) of a batch of one precision in
+// one cooperative launch with grid barriers between the phases (n <=
+// PLAN_FUSE_MAX, no FP32 re-derivation due within them).  bar: two device
+// words (cleared here); herr: a host word the kernel sets to 1 if a barrier
+// wait timed out.
+hipError_t launch_steps(const DevInst* d_insts, int n, long long* plan, StepInfo* info, bool fp32, int maxm,
+                        int tem, int tpm, int nr, int wg_cap, int n_steps, unsigned* bar, int* herr,
+                        hipStream_t s);
 // dynamic LDS bytes of k_sub for those tiles
 size_t sub_lds_bytes(int tem, int tpm, bool fp32, int nr);
 hipError_t launch_rederive(const DevInst* d_insts, int n, const long long* plan, const StepInfo* info,

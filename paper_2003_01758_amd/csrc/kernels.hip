@@ -1293,13 +1293,11 @@ __device__ __forceinline__ int3 block_scan3(int3 x, int3& excl, int* sc)
 // from k_plan's output but formed by every workgroup in LDS from the problems'
 // states (one thread per problem); workgroup 0 alone commits the memory test's
 // outcome and writes the plan and snapshots for the step's later kernels.
-// Two workgroups of four waves per compute unit (two waves per SIMD): the
-// register budget is then 256 per lane, which the FP32 form, with its matrix
-// accumulators, would otherwise exceed by a few and fall to one wave per SIMD.
+// Returns whether the step has units of this launch's class at all.
 template <typename T, int MM, int LB, bool FUSE>
-__global__ __launch_bounds__(SUB_THREADS, 2) void k_sub(const DevInst* __restrict__ insts, int n_inst,
-                                                    long long* __restrict__ plan,
-                                                    StepInfo* __restrict__ info, int tem, int tpm, int nr)
+__device__ __forceinline__ bool sub_run(const DevInst* __restrict__ insts, int n_inst,
+                                        long long* __restrict__ plan, StepInfo* __restrict__ info, int tem,
+                                        int tpm, int nr)
 {
     typedef typename KeyOf<T>::type K;
     extern __shared__ __align__(16) unsigned char smem[];
@@ -1366,7 +1364,7 @@ __global__ __launch_bounds__(SUB_THREADS, 2) void k_sub(const DevInst* __restric
     const long long chunk = (total + gridDim.x - 1) / gridDim.x;
     long long u = (long long)blockIdx.x * chunk;
     const long long uend = min(total, u + chunk);
-    if (u >= uend) return;
+    if (u >= uend) return total > 0;
 
     // LDS carve-up (16-byte aligned pieces)
     unsigned char* q8 = smem;
@@ -1836,6 +1834,18 @@ __global__ __launch_bounds__(SUB_THREADS, 2) void k_sub(const DevInst* __restric
         cb = nb;
         tb = tn;
     }
+    return true;
+}
+
+// Two workgroups of four waves per compute unit (two waves per SIMD): the
+// register budget is then 256 per lane, which the FP32 form, with its matrix
+// accumulators, would otherwise exceed by a few and fall to one wave per SIMD.
+template <typename T, int MM, int LB, bool FUSE>
+__global__ __launch_bounds__(SUB_THREADS, 2) void k_sub(const DevInst* __restrict__ insts, int n_inst,
+                                                    long long* __restrict__ plan,
+                                                    StepInfo* __restrict__ info, int tem, int tpm, int nr)
+{
+    sub_run<T, MM, LB, FUSE>(insts, n_inst, plan, info, tem, tpm, nr);
 }
 
 // ------------------------------------------------------------------ k_rederive
@@ -2119,18 +2129,21 @@ __global__ __launch_bounds__(SUB_THREADS) void k_rederive(const DevInst* __restr
 
 // ------------------------------------------------------------------ k_cut
 
-__global__ __launch_bounds__(CUT_THREADS) void k_cut(const DevInst* __restrict__ insts, int n_inst)
+// The cut of problem b by the calling workgroup (a multiple of 64 lanes, at
+// most NT).
+template <int NT>
+__device__ __forceinline__ void cut_run(const DevInst* __restrict__ insts, int b)
 {
-    __shared__ double shd[CUT_THREADS / 64];
-    __shared__ int shi[CUT_THREADS / 64];
-    __shared__ int wsum[CUT_THREADS / 64 + 1];
-    __shared__ long long wun[CUT_THREADS / 64 + 1];
-    __shared__ long long wap[CUT_THREADS / 64 + 1];
-    __shared__ int s_kc[CUT_THREADS];   // retiring mode: a chunk's kept children's slots
-    __shared__ int s_ka[CUT_THREADS];   // and the offsets of their carried patches
-    __shared__ long long wact[CUT_THREADS / 64];
-    __shared__ double s_plo[CUT_THREADS / 64];
-    const DevInst& I = insts[blockIdx.x];
+    __shared__ double shd[NT / 64];
+    __shared__ int shi[NT / 64];
+    __shared__ int wsum[NT / 64 + 1];
+    __shared__ long long wun[NT / 64 + 1];
+    __shared__ long long wap[NT / 64 + 1];
+    __shared__ int s_kc[NT];   // retiring mode: a chunk's kept children's slots
+    __shared__ int s_ka[NT];   // and the offsets of their carried patches
+    __shared__ long long wact[NT / 64];
+    __shared__ double s_plo[NT / 64];
+    const DevInst& I = insts[b];
     InstState* st = I.st;
     if (st->status != ST_RUNNING) return;
     const int nc = I.fused ? (1 << I.l) : 2;   // children per parent (a round splits every axis)
@@ -2419,6 +2432,75 @@ __global__ __launch_bounds__(CUT_THREADS) void k_cut(const DevInst* __restrict__
                 signal_host(I);
             }
         }
+    }
+}
+
+__global__ __launch_bounds__(CUT_THREADS) void k_cut(const DevInst* __restrict__ insts, int n_inst)
+{
+    (void)n_inst;
+    cut_run<CUT_THREADS>(insts, blockIdx.x);
+}
+
+// ------------------------------------------------------------------ k_steps
+
+// Waits until every workgroup of the grid has arrived at barrier number gen
+// (bar[0] counts arrivals; the grid is co-resident, launched cooperatively).
+// Every wait is bounded: after STEP_WAIT_TICKS of the 100 MHz clock the
+// workgroup sets bar[1], reports it in the host word herr and returns false,
+// and every workgroup returns false once bar[1] is set, so the kernel always
+// ends.
+constexpr unsigned long long STEP_WAIT_TICKS = 1000000000ull;   // 10 s
+__device__ __forceinline__ bool grid_barrier(unsigned* bar, unsigned gen, int* herr)
+{
+    __shared__ int s_ok;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();   // this workgroup's writes before its arrival
+        atomicAdd(&bar[0], 1u);
+        const unsigned target = gen * gridDim.x;
+        const unsigned long long t0 = wall_clock64();
+        int ok = 1;
+        while (__hip_atomic_load(&bar[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            if (__hip_atomic_load(&bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ||
+                wall_clock64() - t0 > STEP_WAIT_TICKS) {
+                ok = 0;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(4);
+        }
+        if (!ok) {
+            atomicExch(&bar[1], 1u);
+            __hip_atomic_store(herr, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        }
+        __threadfence();   // the other workgroups' writes after it
+        s_ok = ok;
+    }
+    __syncthreads();
+    return s_ok != 0;
+}
+
+// Up to n_steps steps of a batch of one precision in one cooperative launch:
+// per step the subdivision (plan formed in LDS, as k_sub with FUSE), a grid
+// barrier, the cut (workgroup b takes problems b, b + grid, ...), a grid
+// barrier.  The sequence of operations per step is that of the k_sub and
+// k_cut launches.  Stops early once the plan of a step has no units (no
+// problem of the batch is running).
+template <typename T, int MM, int LB>
+__global__ __launch_bounds__(SUB_THREADS, 2) void k_steps(const DevInst* __restrict__ insts, int n_inst,
+                                                      long long* __restrict__ plan,
+                                                      StepInfo* __restrict__ info, int tem, int tpm, int nr,
+                                                      int n_steps, unsigned* __restrict__ bar, int* herr)
+{
+    unsigned gen = 0;
+    for (int s = 0; s < n_steps; ++s) {
+        const bool work = sub_run<T, MM, LB, true>(insts, n_inst, plan, info, tem, tpm, nr);
+        if (!grid_barrier(bar, ++gen, herr)) return;
+        if (!work) return;   // the same plan in every workgroup: all leave together
+        for (int b = blockIdx.x; b < n_inst; b += gridDim.x) {
+            cut_run<SUB_THREADS>(insts, b);
+            __syncthreads();
+        }
+        if (!grid_barrier(bar, ++gen, herr)) return;
     }
 }
 
@@ -2845,6 +2927,45 @@ hipError_t launch_sub(const DevInst* d_insts, int n, long long* plan, StepInfo* 
     }
     if (maxm <= 8) return launch_sub_f<double, 8>(d_insts, n, plan, info, fuse, grid, tem, tpm, nr, wg_cap, s, ev0, ev1);
     return launch_sub_f<double, 16>(d_insts, n, plan, info, fuse, grid, tem, tpm, nr, wg_cap, s, ev0, ev1);
+}
+
+template <typename T, int MM>
+static hipError_t launch_steps_t(const DevInst* d_insts, int n, long long* plan, StepInfo* info, int tem, int tpm,
+                                 int nr, int wg_cap, int n_steps, unsigned* bar, int* herr, hipStream_t s)
+{
+    constexpr int LB = (sizeof(T) == 8 ? MAX_TILE64 : MAX_TILE32) / SUB_THREADS;
+    if (tem > LB * SUB_THREADS || tpm < 1 || tpm > SUB_THREADS || (nr != 2 && nr != NCMAX))
+        return hipErrorInvalidValue;
+    const size_t lds = sub_lds_bytes(tem, tpm, sizeof(T) == 4, nr);
+    const void* kern = (const void*)k_steps<T, MM, LB>;
+    const int cus = device_props(current_device()).cus;
+    int per_cu = occupancy_per_cu(kern, SUB_THREADS, lds);
+    if (wg_cap > 0 && per_cu > 0) per_cu = std::min(per_cu, wg_cap);
+    if (cus <= 0 || per_cu <= 0) return hipErrorInvalidConfiguration;
+    // the barrier's counters start at zero (a fill kernel, as for the flags)
+    hipError_t e = hipMemsetAsync(bar, 0, 2 * sizeof(unsigned), s);
+    if (e != hipSuccess) return e;
+    int grid = cus * per_cu;
+    void* args[] = {(void*)&d_insts, (void*)&n, (void*)&plan, (void*)&info, (void*)&tem,
+                    (void*)&tpm, (void*)&nr, (void*)&n_steps, (void*)&bar, (void*)&herr};
+    // co-residency of the whole grid is what the grid barrier relies on: the
+    // cooperative launch fails rather than start a grid that does not fit
+    return hipLaunchCooperativeKernel(kern, dim3(grid), dim3(SUB_THREADS), args, (unsigned)lds, s);
+}
+
+hipError_t launch_steps(const DevInst* d_insts, int n, long long* plan, StepInfo* info, bool fp32, int maxm,
+                        int tem, int tpm, int nr, int wg_cap, int n_steps, unsigned* bar, int* herr,
+                        hipStream_t s)
+{
+    if (n > PLAN_FUSE_MAX || n_steps <= 0) return hipErrorInvalidValue;
+    if (fp32) {
+        if (maxm <= 8)
+            return launch_steps_t<float, 8>(d_insts, n, plan, info, tem, tpm, nr, wg_cap, n_steps, bar, herr, s);
+        return launch_steps_t<float, 16>(d_insts, n, plan, info, tem, tpm, nr, wg_cap, n_steps, bar, herr, s);
+    }
+    if (maxm <= 8)
+        return launch_steps_t<double, 8>(d_insts, n, plan, info, tem, tpm, nr, wg_cap, n_steps, bar, herr, s);
+    return launch_steps_t<double, 16>(d_insts, n, plan, info, tem, tpm, nr, wg_cap, n_steps, bar, herr, s);
 }
 
 hipError_t launch_rederive(const DevInst* d_insts, int n, const long long* plan, const StepInfo* info,

@@ -205,6 +205,9 @@ struct EngineBufs {
     DevInst* h_insts = nullptr;    // pinned staging of the descriptors (outlives the async copy)
     int* h_flag = nullptr;         // pinned word the kernels set when a problem stops running
     int* d_flag = nullptr;         // its device address
+    int* h_berr = nullptr;         // pinned word set by a timed-out grid barrier wait (k_steps)
+    int* d_berr = nullptr;         // its device address
+    unsigned* d_bar = nullptr;     // k_steps: the grid barrier's arrival count and abort word
     hipEvent_t ev[2] = {nullptr, nullptr};   // ends of the last two chunks of steps
 };
 
@@ -284,6 +287,8 @@ static void bufs_free(EngineBufs& b)
     if (b.h_states) (void)hipHostFree(b.h_states);
     if (b.h_insts) (void)hipHostFree(b.h_insts);
     if (b.h_flag) (void)hipHostFree(b.h_flag);
+    if (b.h_berr) (void)hipHostFree(b.h_berr);
+    if (b.d_bar) (void)hipFree(b.d_bar);
     for (int k = 0; k < 2; ++k)
         if (b.ev[k]) (void)hipEventDestroy(b.ev[k]);
     b = EngineBufs();
@@ -332,6 +337,9 @@ static hipError_t bufs_get(int cap, EngineBufs* out)
     if (e == hipSuccess) e = hipHostMalloc((void**)&b.h_insts, c * sizeof(DevInst), hipHostMallocDefault);
     if (e == hipSuccess) e = hipHostMalloc((void**)&b.h_flag, sizeof(int), hipHostMallocDefault);
     if (e == hipSuccess) e = hipHostGetDevicePointer((void**)&b.d_flag, b.h_flag, 0);
+    if (e == hipSuccess) e = hipHostMalloc((void**)&b.h_berr, sizeof(int), hipHostMallocDefault);
+    if (e == hipSuccess) e = hipHostGetDevicePointer((void**)&b.d_berr, b.h_berr, 0);
+    if (e == hipSuccess) e = hipMalloc((void**)&b.d_bar, 2 * sizeof(unsigned));
     for (int k = 0; k < 2 && e == hipSuccess; ++k) e = hipEventCreateWithFlags(&b.ev[k], hipEventDisableTiming);
     if (e != hipSuccess) {
         bufs_free(b);
@@ -787,6 +795,7 @@ void pcba_default_options(pcba_options* o)
     o->direction_rule = 0;
     o->split_engine = PCBA_SPLIT_VALU;
     o->subdiv_lambda = 0.5;
+    o->persistent_steps = 0;
 }
 
 int pcba_create_problem(int32_t l, const double* lo, const double* hi, const int32_t* cost_deg,
@@ -827,6 +836,8 @@ int pcba_create_problem(int32_t l, const double* lo, const double* hi, const int
     }
     if (o.wg_per_cu < 0) return fail(PCBA_E_ARG, "wg_per_cu must be >= 0");
     if (o.direction_rule != 0 && o.direction_rule != 1) return fail(PCBA_E_ARG, "direction_rule must be 0 or 1");
+    if (o.persistent_steps != 0 && o.persistent_steps != 1)
+        return fail(PCBA_E_ARG, "persistent_steps must be 0 or 1");
     if (o.split_engine != PCBA_SPLIT_VALU && o.split_engine != PCBA_SPLIT_MFMA)
         return fail(PCBA_E_ARG, "split_engine must be PCBA_SPLIT_VALU or PCBA_SPLIT_MFMA");
     if (!(o.subdiv_lambda > 0.0 && o.subdiv_lambda < 1.0))
@@ -1299,6 +1310,27 @@ static int engine_steps(pcba_engine* E, int n_steps)
     // busy) and stops early when a kernel has flagged a problem that finished
     // or paused for growth.
     __atomic_store_n(E->b.h_flag, 0, __ATOMIC_RELEASE);
+    // Whole steps in one cooperative launch (k_steps) when the batch allows it:
+    // one precision, at most PLAN_FUSE_MAX problems, every problem asking for it,
+    // short lists (its cut runs on the subdivision's 256 lanes), kernel timing
+    // off (the timed launches are per kernel), and for the steps in which no
+    // FP32 re-derivation falls due.
+    bool persist = !g_prof.on && n <= PLAN_FUSE_MAX && any64 != any32;
+    for (auto* P : E->active)
+        if (!P->opt.persistent_steps || P->cap > 4096) persist = false;
+    if (persist) {
+        int coop = 0;
+        persist = hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, E->b.dev) == hipSuccess && coop;
+    }
+    auto rd_due = [&](int s) {
+        for (auto* P : E->active) {
+            if (!P->fp32 || P->opt.rederive_every <= 0 || P->h_st.status != ST_RUNNING) continue;
+            if ((P->host_steps + s + 1) % P->opt.rederive_every == 0) return true;
+        }
+        return false;
+    };
+    bool used_steps = false;
+    if (persist) *E->b.h_berr = 0;
     for (int s = 0; s < n_steps; ++s) {
         if (s > 0 && s % CHECK_STEPS == 0) {
             const int k = (s / CHECK_STEPS) & 1;
@@ -1306,6 +1338,21 @@ static int engine_steps(pcba_engine* E, int n_steps)
             if (s >= 2 * CHECK_STEPS) {
                 HIP_TRY(hipEventSynchronize(E->b.ev[k ^ 1]));
                 if (__atomic_load_n(E->b.h_flag, __ATOMIC_ACQUIRE)) break;
+            }
+        }
+        if (persist) {
+            // the rest of this check interval, up to a step with a re-derivation
+            const int lim = std::min(CHECK_STEPS - s % CHECK_STEPS, n_steps - s);
+            int kk = 0;
+            while (kk < lim && !rd_due(s + kk)) ++kk;
+            if (kk > 0) {
+                const bool f32 = any32;
+                HIP_TRY(launch_steps(E->b.d_insts, n, E->b.d_plan, E->b.d_info, f32, f32 ? maxm32 : maxm64,
+                                     f32 ? tem32 : tem64, f32 ? tpm32 : tpm64, f32 ? nr32 : nr64,
+                                     f32 ? wg32 : wg64, kk, E->b.d_bar, E->b.d_berr, E->stream));
+                used_steps = true;
+                s += kk - 1;
+                continue;
             }
         }
         // upper bound of this step's units: K at most multiplies by the
@@ -1361,6 +1408,8 @@ static int engine_steps(pcba_engine* E, int n_steps)
     HIP_TRY(launch_gather(E->b.d_insts, n, E->b.d_states, E->stream));   // into host memory
     HIP_TRY(hipStreamSynchronize(E->stream));
     prof_collect();
+    if (used_steps && __atomic_load_n(E->b.h_berr, __ATOMIC_ACQUIRE))
+        return fail(PCBA_E_DEVICE, "a grid barrier of the step kernel timed out");
 
     // growth, time limits, finished problems
     const double t = now_s();

@@ -33,7 +33,7 @@ class Options(C.Structure):
                 ("retire_satisfied", C.c_int32), ("fused_round", C.c_int32),
                 ("time_limit_s", C.c_double), ("tile_coefs", C.c_int32), ("wg_per_cu", C.c_int32),
                 ("direction_rule", C.c_int32), ("split_engine", C.c_int32),
-                ("subdiv_lambda", C.c_double)]
+                ("subdiv_lambda", C.c_double), ("persistent_steps", C.c_int32)]
 
 
 class Result(C.Structure):
@@ -184,7 +184,7 @@ class Problem:
     keyword options override its tolerances (eps, delta, eps_eq, max_boxes,
     max_iters) and set precision ('fp64'|'fp32'), rederive_every, stale_filter,
     retire_satisfied, fused_round, time_limit_s, tile_coefs, wg_per_cu,
-    direction_rule, split_engine ('valu'|'mfma'), subdiv_lambda."""
+    direction_rule, split_engine ('valu'|'mfma'), subdiv_lambda, persistent_steps."""
 
     def __init__(self, inst, **kw):
         L = lib()

@@ -40,8 +40,9 @@ def test_default_options_and_argument_validation_without_device():
     assert o.eps == 1e-3 and o.delta == 1e-4 and o.max_iters == 28 and o.max_boxes == 1 << 20
     # the C side fills every field: a layout mismatch would misplace these
     assert o.rederive_every == 16 and o.stale_filter == 0 and o.retire_satisfied == 1
-    assert o.time_limit_s == 0.0 and o.tile_coefs == 0 and o.wg_per_cu == 0 and ctypes.sizeof(o) == 88
+    assert o.time_limit_s == 0.0 and o.tile_coefs == 0 and o.wg_per_cu == 0 and ctypes.sizeof(o) == 96
     assert o.direction_rule == 0 and o.subdiv_lambda == 0.5 and o.split_engine == pcba.SPLIT_VALU
+    assert o.persistent_steps == 0
     # argument errors are detected before any device call
     L = pcba.lib()
     h = ctypes.c_void_p()
@@ -89,7 +90,7 @@ def test_default_options_and_argument_validation_without_device():
                # subdivision variants: rule 0 or 1, lambda inside (0,1), not with
                # rounds, and FP32 away from the midpoint without re-derivation; split
                # engine 0 (vector ALUs) or 1 (matrix cores)
-               dict(direction_rule=2), dict(subdiv_lambda=0.0), dict(subdiv_lambda=1.0), dict(split_engine=2),
+               dict(direction_rule=2), dict(subdiv_lambda=0.0), dict(subdiv_lambda=1.0), dict(split_engine=2), dict(persistent_steps=2),
                dict(fused_round=1, retire_satisfied=0, direction_rule=1),
                dict(fused_round=1, retire_satisfied=0, subdiv_lambda=0.25),
                dict(precision=1, subdiv_lambda=0.25)):

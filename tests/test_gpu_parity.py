@@ -300,3 +300,23 @@ def test_fp64_large_list_trace_matches_oracle(gpu, stale):
     for s, row in enumerate(gold):
         assert tr["k_kept"][s] == row["k"], (s, tr["k_kept"][s], row["k"])
         assert tr["p_lo"][s] == row["p_lo"], s
+
+
+@pytest.mark.parametrize("prec,retire,rederive", [("fp64", 0, 16), ("fp64", 1, 16), ("fp32", 0, 0), ("fp32", 1, 16)])
+def test_persistent_steps_equal_launches(gpu, prec, retire, rederive):
+    # several whole steps per cooperative launch (grid barriers between the
+    # subdivision and the cut) against one launch per kernel per step: the
+    # same operations in the same order, so every result is identical
+    insts = [CASES[n]() for n in ("small0", "small1", "rtd40", "P4", "batch_l3", "small7")]
+    print(f"[persistent] {prec} retire={retire} rederive={rederive}", flush=True)
+    out = []
+    for persist in (0, 1):
+        probs = [gpu.Problem(i, precision=prec, retire_satisfied=retire, rederive_every=rederive,
+                             persistent_steps=persist) for i in insts]
+        out.append(gpu.solve_batch(probs))
+        for p in probs:
+            p.close()
+    for k, (a, b) in enumerate(zip(*out)):
+        for key in ("outcome", "p_up", "p_lo", "steps", "peak_len", "certified", "p_cert"):
+            assert a[key] == b[key], (k, key)
+        assert np.array_equal(a["x_index"], b["x_index"]), k
