@@ -324,6 +324,16 @@ void pcba_profile_reset(void);
 /* total milliseconds and launch counts per kernel id (arrays of PCBA_NUM_KERNELS) */
 void pcba_profile_read(double* ms, int64_t* launches);
 
+/* ---- launch policy of the cut-off test and compaction (Alg. CutOffTest, Eliminate) --
+ * A problem's cut runs in one workgroup while the step has at most `children`
+ * children (2K, or 2^l K in a round); above that it is split over workgroups of
+ * `part` children each (four more launches: the parts' minima, the estimate and
+ * each part's kept count, the order-preserving compaction at the parts' offsets,
+ * the state's updates).  Results are the same either way.  Process-wide; default
+ * 32,768 and 4,096; children 0 never splits.  PCBA_E_ARG if children < 0 or
+ * part < 64.  Set it while no engine runs steps. */
+int pcba_set_cut_split(int64_t children, int32_t part);
+
 /* Footprint estimate used for admission: bytes of a list of `boxes` items. */
 int64_t pcba_footprint_bytes(const pcba_problem* prob, int64_t boxes);
 

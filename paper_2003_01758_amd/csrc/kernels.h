@@ -35,8 +35,12 @@ hipError_t launch_steps(const DevInst* d_insts, int n, long long* plan, StepInfo
 size_t sub_lds_bytes(int tem, int tpm, bool fp32, int nr);
 hipError_t launch_rederive(const DevInst* d_insts, int n, const long long* plan, const StepInfo* info,
                            int grid, int tgrid, size_t lds, hipStream_t s);
-// max_children: an upper bound on the children (2K, or 2^l K in a round) at this step
-hipError_t launch_cut(const DevInst* d_insts, int n, int64_t max_children, hipStream_t s);
+// max_children: an upper bound on the children (2K, or 2^l K in a round) at this
+// step.  A problem with more than split (> 0) children is cut across workgroups
+// of `part` children (four more launches, parts: at least
+// n * ceil(max_children / part) records).
+hipError_t launch_cut(const DevInst* d_insts, const StepInfo* info, int n, int64_t max_children,
+                      long long split, int part, CutPart* parts, int64_t parts_cap, hipStream_t s);
 hipError_t launch_gather(const DevInst* d_insts, int n, InstState* out, hipStream_t s);
 // polynomials per certification workgroup that fit LDS (0: none)
 int certify_run_length(int max_S, int tm_words);

@@ -2130,9 +2130,24 @@ __global__ __launch_bounds__(SUB_THREADS) void k_rederive(const DevInst* __restr
 // ------------------------------------------------------------------ k_cut
 
 // The cut of problem b by the calling workgroup (a multiple of 64 lanes, at
-// most NT).
+// most NT).  phase 0: the whole cut by one workgroup, unless the step has more
+// than `split` children (then it returns: the cut is split).  A split cut runs
+// in four launches over G workgroups per problem, workgroup g taking children
+// [g part, (g+1) part) of the step's C (parts[b G + g] holds its
+// figures; the step's K, r, cur, steps and previous estimate come from info,
+// which the state's updates in phase 4 do not touch):
+//   1: the least max B over its feasible children (and the first child
+//      attaining it) and the least min B over its live children;
+//   2: the estimate from all parts' minima, then its kept children, their
+//      inequality units and carried patches;
+//   3: the offsets of its kept children from the parts before it, then the
+//      same order-preserving compaction as phase 0 over its children;
+//   4: the flags of the next step's children cleared over its share, and
+//      (g = 0) the state's updates as phase 0 makes them.
 template <int NT>
-__device__ __forceinline__ void cut_run(const DevInst* __restrict__ insts, int b)
+__device__ __forceinline__ void cut_phase(const DevInst* __restrict__ insts, const StepInfo* __restrict__ info,
+                                          int b, int phase, int g, int G, CutPart* __restrict__ parts,
+                                          long long split, int part)
 {
     __shared__ double shd[NT / 64];
     __shared__ int shi[NT / 64];
@@ -2145,17 +2160,74 @@ __device__ __forceinline__ void cut_run(const DevInst* __restrict__ insts, int b
     __shared__ double s_plo[NT / 64];
     const DevInst& I = insts[b];
     InstState* st = I.st;
-    if (st->status != ST_RUNNING) return;
     const int nc = I.fused ? (1 << I.l) : 2;   // children per parent (a round splits every axis)
-    const int K = st->K, C = nc * K, r = st->r, cur = st->cur, l = I.l;
+    int K, r, cur, steps0;
+    double pprev;
+    if (phase == 0) {
+        if (st->status != ST_RUNNING) return;
+        K = st->K;
+        if ((long long)nc * K > split) return;   // a split cut takes it
+        r = st->r;
+        cur = st->cur;
+        steps0 = st->steps;
+        pprev = st->p_up;
+    } else {
+        const StepInfo si = info[b];
+        K = si.K;
+        r = si.r;
+        cur = si.cur;
+        steps0 = si.steps;
+        pprev = si.p_up;
+    }
+    const int C = nc * K, l = I.l;
+    const int Gb = (int)(((long long)C + part - 1) / part);   // parts of a split cut
+    CutPart* pp = parts + (long long)b * G;
+    if (phase == 1) {
+        // this part of a running problem whose cut is split, or nothing (the
+        // later phases read the mark)
+        const bool mine = st->status == ST_RUNNING && (long long)C > split && g < Gb;
+        __syncthreads();
+        if (threadIdx.x == 0) pp[g].valid = mine ? 1 : 0;
+        if (!mine) return;
+    } else if (phase > 1) {
+        if (!pp[g].valid) return;
+    }
     const int TP1 = I.tile_polys[1];
-    const double pprev = st->p_up;
     const bool fin = pprev < INFINITY;
     const int tid = threadIdx.x;
+    // this workgroup's children
+    const int cbeg = phase == 0 ? 0 : g * part;
+    const int cend = phase == 0 ? C : min(C, cbeg + part);
+    if (phase == 1) {
+        double mm = INFINITY, pl = INFINITY;
+        int ag = INT_MAX;
+        for (int c = cbeg + tid; c < cend; c += blockDim.x) {
+            const double mnp = as_global(I.minP)[c];
+            const uint32_t fl = as_global(I.flags)[c];
+            const bool dead = fin && mnp > pprev;
+            if (dead || (fl & F_INFEAS)) continue;
+            pl = fmin(pl, mnp);
+            if (fl & F_NOTFEAS) continue;
+            const double mx = as_global(I.maxP)[c];
+            if (mx < mm) {
+                mm = mx;
+                ag = c;
+            }
+        }
+        const double mb = block_min1(mm, shd);
+        const int ab = block_min1_i(mm == mb ? ag : INT_MAX, shi);
+        const double pb = block_min1(pl, s_plo);
+        if (tid == 0) {
+            pp[g].m = mb;
+            pp[g].arg = ab;
+            pp[g].plo = pb;
+        }
+        return;
+    }
     // state the final updates need, read before the passes: the step count,
     // carried patches, iteration count, per axis (thread k) its depth, and the
     // children's width
-    const int steps0 = st->steps, n0 = st->n;
+    const int n0 = st->n;
     const long long alive0 = st->a_live;
     const int depth_k = tid < l ? st->depth[tid] + ((I.fused || tid == r) ? 1 : 0) : 0;
     // the children's depth vector, and the widest child's width
@@ -2168,7 +2240,7 @@ __device__ __forceinline__ void cut_run(const DevInst* __restrict__ insts, int b
 
     // the child records, read once: the first CUT_CACHE * blockDim children are
     // kept in registers for the three passes below, any further ones are read
-    // again in each pass
+    // again in each pass (phase 0)
     const bool ret = I.retire != 0;
     const int bd = blockDim.x;
     double cmn[CUT_CACHE], cmx[CUT_CACHE];
@@ -2181,7 +2253,7 @@ __device__ __forceinline__ void cut_run(const DevInst* __restrict__ insts, int b
         cmx[q] = INFINITY;
         cfl[q] = F_INFEAS;
         cna[q] = 0;
-        if (c < C) {
+        if (phase == 0 && c < C) {
             cmn[q] = as_global(I.minP)[c];
             cmx[q] = as_global(I.maxP)[c];
             cfl[q] = as_global(I.flags)[c];
@@ -2189,22 +2261,32 @@ __device__ __forceinline__ void cut_run(const DevInst* __restrict__ insts, int b
         }
     }
 
-    // solution estimate: least max B_p over feasible children
+    // solution estimate: least max B_p over feasible children (phases 2-4: the
+    // least of the parts' minima, the first child attaining it)
     double m = INFINITY;
+    int arg = INT_MAX;
+    if (phase > 1) {
+        for (int q = 0; q < Gb; ++q) {
+            const double pm = pp[q].m;
+            if (pm < m) {
+                m = pm;
+                arg = pp[q].arg;
+            }
+        }
+    }
 #pragma unroll
     for (int q = 0; q < CUT_CACHE; ++q) {
         const bool dead = fin && cmn[q] > pprev;
         if (!dead && !(cfl[q] & (F_INFEAS | F_NOTFEAS))) m = fmin(m, cmx[q]);
     }
-    for (int c = tid + CUT_CACHE * bd; c < C; c += bd) {
+    for (int c = tid + CUT_CACHE * bd; phase == 0 && c < C; c += bd) {
         const double mnp = I.minP[c];
         const bool dead = fin && mnp > pprev;
         if (!dead && !(I.flags[c] & (F_INFEAS | F_NOTFEAS))) m = fmin(m, I.maxP[c]);
     }
-    m = block_min1(m, shd);
+    if (phase == 0) m = block_min1(m, shd);
     const bool update = (m < INFINITY) && (m <= pprev);
-    int arg = INT_MAX;
-    if (update) {
+    if (phase == 0 && update) {
 #pragma unroll
         for (int q = 0; q < CUT_CACHE; ++q) {
             const int c = tid + q * bd;
@@ -2226,12 +2308,59 @@ __device__ __forceinline__ void cut_run(const DevInst* __restrict__ insts, int b
     int base = 0;
     long long ubase = 0, abase = 0, asum = 0;
     const int lane = tid & 63, w = tid >> 6, nw = blockDim.x >> 6;
+    if (phase == 2) {
+        // this part's kept children, their units and carried patches
+        long long kk = 0, uu = 0, aa = 0;
+        for (int c = cbeg + tid; c < cend; c += bd) {
+            const double mnp = as_global(I.minP)[c];
+            const uint32_t fl = as_global(I.flags)[c];
+            const bool dead = fin && mnp > pprev;
+            if (dead || (fl & F_INFEAS) || !(mnp <= p_up)) continue;
+            kk += 1;
+            if (ret) {
+                const int a = as_global(I.na[cur ^ 1])[c];
+                uu += (a + TP1 - 1) / TP1;
+                aa += a;
+            }
+        }
+        for (int o = 32; o > 0; o >>= 1) {
+            kk += __shfl_xor(kk, o, 64);
+            uu += __shfl_xor(uu, o, 64);
+            aa += __shfl_xor(aa, o, 64);
+        }
+        if (lane == 0) {
+            wact[w] = kk;
+            wun[w] = uu;
+            wap[w] = aa;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            long long k2 = 0, u2 = 0, a2 = 0;
+            for (int q = 0; q < nw; ++q) {
+                k2 += wact[q];
+                u2 += wun[q];
+                a2 += wap[q];
+            }
+            pp[g].kept = (int)k2;
+            pp[g].units = u2;
+            pp[g].patches = a2;
+        }
+        return;
+    }
+    if (phase == 3) {
+        // the kept children, units and patches of the parts before this one
+        for (int q = 0; q < g; ++q) {
+            base += pp[q].kept;
+            ubase += pp[q].units;
+            abase += pp[q].patches;
+        }
+    }
     // one chunk of blockDim children starting at c0 (uniform trip count: every
     // thread runs every chunk, so the barriers inside are reached by all)
     auto chunk = [&](int c0, double mnp, uint32_t fl, int a) {
         const int c = c0 + tid;
         bool keep = false;
-        if (c < C) {
+        if (c < cend) {
             const bool dead = fin && mnp > pprev;
             if (!dead && !(fl & F_INFEAS)) {
                 plo = fmin(plo, mnp);
@@ -2339,47 +2468,71 @@ __device__ __forceinline__ void cut_run(const DevInst* __restrict__ insts, int b
         abase += wap[nw];
         __syncthreads();
     };
+    if (phase == 0) {
 #pragma unroll
-    for (int q = 0; q < CUT_CACHE; ++q) {
-        if (q * bd >= C) break;
-        chunk(q * bd, cmn[q], cfl[q], cna[q]);
-    }
-    for (int c0 = CUT_CACHE * bd; c0 < C; c0 += bd) {
-        const int c = c0 + tid;
-        double mnp = INFINITY;
-        uint32_t fl = F_INFEAS;
-        int a = 0;
-        if (c < C) {
-            mnp = as_global(I.minP)[c];
-            fl = as_global(I.flags)[c];
-            if (ret) a = as_global(I.na[cur ^ 1])[c];
+        for (int q = 0; q < CUT_CACHE; ++q) {
+            if (q * bd >= C) break;
+            chunk(q * bd, cmn[q], cfl[q], cna[q]);
         }
-        chunk(c0, mnp, fl, a);
+    }
+    if (phase != 4) {
+        for (int c0 = cbeg + (phase == 0 ? CUT_CACHE * bd : 0); c0 < cend; c0 += bd) {
+            const int c = c0 + tid;
+            double mnp = INFINITY;
+            uint32_t fl = F_INFEAS;
+            int a = 0;
+            if (c < cend) {
+                mnp = as_global(I.minP)[c];
+                fl = as_global(I.flags)[c];
+                if (ret) a = as_global(I.na[cur ^ 1])[c];
+            }
+            chunk(c0, mnp, fl, a);
+        }
+    }
+    if (phase == 3) return;
+    if (phase == 4) {
+        // the totals of all parts
+        for (int q = 0; q < Gb; ++q) {
+            base += pp[q].kept;
+            ubase += pp[q].units;
+            asum += pp[q].patches;
+            plo = fmin(plo, pp[q].plo);
+        }
     }
     // least lower bound and the inequality patches the kept children carry,
     // in one reduction
-    plo = wave_min(plo);
-    for (int o = 32; o > 0; o >>= 1) asum += __shfl_xor(asum, o, 64);
-    if (lane == 0) {
-        s_plo[w] = plo;
-        wact[w] = asum;
-    }
-    __syncthreads();
-    plo = s_plo[0];
-    asum = 0;
-    for (int q = 0; q < nw; ++q) {
-        plo = fmin(plo, s_plo[q]);
-        asum += wact[q];
+    // (phase 4 has the totals in every lane already)
+    if (phase == 0) {
+        plo = wave_min(plo);
+        for (int o = 32; o > 0; o >>= 1) asum += __shfl_xor(asum, o, 64);
+        if (lane == 0) {
+            s_plo[w] = plo;
+            wact[w] = asum;
+        }
+        __syncthreads();
+        plo = s_plo[0];
+        asum = 0;
+        for (int q = 0; q < nw; ++q) {
+            plo = fmin(plo, s_plo[q]);
+            asum += wact[q];
+        }
     }
     const int Kn = base;
     if (!I.retire) asum = (long long)Kn * I.count[1];
 
     // clear the flags of the next step's children, and in retiring mode their
-    // carried counts (they go to the buffer of this step's parents)
-    for (int c = tid; c < nc * Kn && c < I.cap; c += blockDim.x) {
-        as_global(I.flags)[c] = 0;
-        if (I.retire) as_global(I.na[cur])[c] = 0;
+    // carried counts (they go to the buffer of this step's parents); a split
+    // cut clears them in Gb shares
+    {
+        const long long nclr = min((long long)nc * Kn, (long long)I.cap);
+        const long long share = phase == 0 ? nclr : (nclr + Gb - 1) / Gb;
+        const long long c1 = min(nclr, (phase == 0 ? 0 : (long long)g * share) + share);
+        for (long long c = (phase == 0 ? 0 : (long long)g * share) + tid; c < c1; c += blockDim.x) {
+            as_global(I.flags)[c] = 0;
+            if (I.retire) as_global(I.na[cur])[c] = 0;
+        }
     }
+    if (g != 0) return;   // the state's updates: one workgroup
 
     // per axis (thread k): its depth, and x*'s box if the estimate moved
     const int nxt = cur ^ 1;
@@ -2435,10 +2588,29 @@ __device__ __forceinline__ void cut_run(const DevInst* __restrict__ insts, int b
     }
 }
 
-__global__ __launch_bounds__(CUT_THREADS) void k_cut(const DevInst* __restrict__ insts, int n_inst)
+template <int NT>
+__device__ __forceinline__ void cut_run(const DevInst* __restrict__ insts, int b)
+{
+    cut_phase<NT>(insts, nullptr, b, 0, 0, 1, nullptr, LLONG_MAX, 1);
+}
+
+// The cut, one workgroup per problem; with split > 0, problems with more than
+// split children at this step are left to k_cut_split.
+__global__ __launch_bounds__(CUT_THREADS) void k_cut(const DevInst* __restrict__ insts, int n_inst,
+                                                     long long split)
 {
     (void)n_inst;
-    cut_run<CUT_THREADS>(insts, blockIdx.x);
+    cut_phase<CUT_THREADS>(insts, nullptr, blockIdx.x, 0, 0, 1, nullptr, split, 1);
+}
+
+// One phase (1-4) of the split cut: workgroup (b, g) = (blockIdx / G, blockIdx % G).
+__global__ __launch_bounds__(CUT_THREADS) void k_cut_split(const DevInst* __restrict__ insts,
+                                                           const StepInfo* __restrict__ info, int phase, int G,
+                                                           CutPart* __restrict__ parts, long long split,
+                                                           int part)
+{
+    const int b = blockIdx.x / G, g = blockIdx.x - b * G;
+    cut_phase<CUT_THREADS>(insts, info, b, phase, g, G, parts, split, part);
 }
 
 // ------------------------------------------------------------------ k_steps
@@ -2979,14 +3151,26 @@ hipError_t launch_rederive(const DevInst* d_insts, int n, const long long* plan,
     return hipGetLastError();
 }
 
-hipError_t launch_cut(const DevInst* d_insts, int n, int64_t max_children, hipStream_t s)
+hipError_t launch_cut(const DevInst* d_insts, const StepInfo* info, int n, int64_t max_children,
+                      long long split, int part, CutPart* parts, int64_t parts_cap, hipStream_t s)
 {
     // short lists: four waves walk the children in a few passes with cheaper
     // barriers; longer ones take eight waves (fewer passes, the carried-patch
     // copy twice as wide), the longest the full workgroup
     const int threads = max_children <= 1024 ? 256 : (max_children <= 8192 ? 512 : CUT_THREADS);
-    hipLaunchKernelGGL(k_cut, dim3(n), dim3(threads), 0, s, d_insts, n);
-    return hipGetLastError();
+    const bool splitting = split > 0 && max_children > split;
+    if (splitting && part < 1) return hipErrorInvalidValue;
+    const int G = splitting ? (int)((max_children + part - 1) / part) : 1;
+    if (splitting && (int64_t)n * G > parts_cap) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_cut, dim3(n), dim3(threads), 0, s, d_insts, n, splitting ? split : LLONG_MAX);
+    hipError_t e = hipGetLastError();
+    // problems with more children than split: four launches over G workgroups each
+    for (int phase = 1; splitting && phase <= 4 && e == hipSuccess; ++phase) {
+        hipLaunchKernelGGL(k_cut_split, dim3(n * G), dim3(CUT_THREADS), 0, s, d_insts, info, phase, G, parts,
+                           split, part);
+        e = hipGetLastError();
+    }
+    return e;
 }
 
 hipError_t launch_gather(const DevInst* d_insts, int n, InstState* out, hipStream_t s)

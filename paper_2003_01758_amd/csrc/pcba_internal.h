@@ -25,6 +25,20 @@ constexpr int CERT_PPB = 16;    // polynomials per certification workgroup
 constexpr int PLAN_FUSE_MAX = 256;  // batches up to this size form the plan inside k_sub (<= SUB_THREADS)
 constexpr int CUT_THREADS = 1024;
 constexpr int CUT_CACHE = 4;      // children per thread k_cut keeps in registers
+constexpr int CUT_PART_DEFAULT = 4096;           // children per workgroup of a split cut
+constexpr long long CUT_SPLIT_DEFAULT = 32768;   // children above which a problem's cut is split
+
+// Per (problem, part) record of a cut split across workgroups.
+struct CutPart {
+    double m;            // least max B over the part's feasible children
+    double plo;          // least min B over its live children
+    int arg;             // first child attaining m
+    int valid;           // the part belongs to a running problem whose cut is split
+    int kept;            // its kept children
+    int pad;
+    long long units;     // their inequality units (retiring mode)
+    long long patches;   // their carried inequality patches (retiring mode)
+};
 constexpr int REDERIVE_CHUNK = 256;  // patches per re-derivation chunk
 constexpr int MAX_BATCH = 2048;   // problems per launch
 constexpr int MAX_TILE64 = 3584;  // largest tile (coefficients) of an FP64 unit: 14 per lane

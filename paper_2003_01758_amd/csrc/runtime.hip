@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <atomic>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -41,6 +42,10 @@ constexpr int MAX_STEPS_PER_SYNC = 64;
 constexpr int TILE_ELEMS = 2816;   // target coefficients per FP64 tile (per LDS region)
 constexpr int MAX_PATCH = 3584;    // largest patch (coefficients): LDS stays within 64 KB
 constexpr int CAP0 = 64;           // initial list capacity (items per buffer)
+
+// children above which a problem's cut is split across workgroups (0: never)
+std::atomic<long long> g_cut_split{CUT_SPLIT_DEFAULT};
+std::atomic<int> g_cut_part{CUT_PART_DEFAULT};   // children per workgroup of a split cut
 
 double now_s()
 {
@@ -208,6 +213,8 @@ struct EngineBufs {
     int* h_berr = nullptr;         // pinned word set by a timed-out grid barrier wait (k_steps)
     int* d_berr = nullptr;         // its device address
     unsigned* d_bar = nullptr;     // k_steps: the grid barrier's arrival count and abort word
+    CutPart* d_parts = nullptr;    // records of cuts split across workgroups
+    int64_t parts_cap = 0;
     hipEvent_t ev[2] = {nullptr, nullptr};   // ends of the last two chunks of steps
 };
 
@@ -289,6 +296,7 @@ static void bufs_free(EngineBufs& b)
     if (b.h_flag) (void)hipHostFree(b.h_flag);
     if (b.h_berr) (void)hipHostFree(b.h_berr);
     if (b.d_bar) (void)hipFree(b.d_bar);
+    if (b.d_parts) (void)hipFree(b.d_parts);
     for (int k = 0; k < 2; ++k)
         if (b.ev[k]) (void)hipEventDestroy(b.ev[k]);
     b = EngineBufs();
@@ -1402,7 +1410,23 @@ static int engine_steps(pcba_engine* E, int n_steps)
             HIP_TRY(prof_end(2, E->stream));
         }
         HIP_TRY(prof_begin(E->stream));
-        HIP_TRY(launch_cut(E->b.d_insts, n, maxc, E->stream));
+        const long long split = g_cut_split.load(std::memory_order_relaxed);
+        const int part = g_cut_part.load(std::memory_order_relaxed);
+        if (split > 0 && maxc > split) {
+            // room for the split cut's records (grown between steps: the stream
+            // is drained before the old buffer goes)
+            const int64_t need = (int64_t)n * ((maxc + part - 1) / part);
+            if (need > E->b.parts_cap) {
+                HIP_TRY(hipStreamSynchronize(E->stream));
+                if (E->b.d_parts) HIP_TRY(hipFree(E->b.d_parts));
+                E->b.d_parts = nullptr;
+                E->b.parts_cap = 0;
+                HIP_TRY(hipMalloc((void**)&E->b.d_parts, (size_t)need * sizeof(CutPart)));
+                E->b.parts_cap = need;
+            }
+        }
+        HIP_TRY(launch_cut(E->b.d_insts, E->b.d_info, n, maxc, split, part, E->b.d_parts, E->b.parts_cap,
+                           E->stream));
         HIP_TRY(prof_end(3, E->stream));
     }
     HIP_TRY(launch_gather(E->b.d_insts, n, E->b.d_states, E->stream));   // into host memory
@@ -1708,6 +1732,15 @@ int pcba_read_list_noalloc(const pcba_problem* P, uint32_t* ids, double* patches
         HIP_TRY(hipMemcpyAsync(patches, d_out, (size_t)pat_bytes, hipMemcpyDeviceToHost, s));
     if (ids) HIP_TRY(hipMemcpyAsync(ids, d_ids, (size_t)K * P->l * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
+    return PCBA_OK;
+}
+
+int pcba_set_cut_split(int64_t children, int32_t part)
+{
+    if (children < 0) return fail(PCBA_E_ARG, "children must be >= 0");
+    if (part < 64) return fail(PCBA_E_ARG, "part must be >= 64");
+    g_cut_split.store(children, std::memory_order_relaxed);
+    g_cut_part.store(part, std::memory_order_relaxed);
     return PCBA_OK;
 }
 

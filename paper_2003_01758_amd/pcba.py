@@ -66,6 +66,8 @@ def lib():
                               "(there is no CPU fallback)")
         L = C.CDLL(LIB_PATH)
         vp, i32, i64, dp = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+        L.pcba_set_cut_split.argtypes = [C.c_int64, C.c_int32]
+        L.pcba_set_cut_split.restype = C.c_int32
         L.pcba_default_options.argtypes = [C.POINTER(Options)]
         L.pcba_default_options.restype = None
         L.pcba_create_problem.argtypes = [i32, vp, vp, vp, vp, i32, vp, vp, i32, vp, vp,
@@ -159,6 +161,12 @@ def default_options(**kw) -> Options:
             v = {"valu": SPLIT_VALU, "mfma": SPLIT_MFMA}[v]
         setattr(o, k, v)
     return o
+
+
+def set_cut_split(children: int = 32768, part: int = 4096) -> None:
+    """pcba_set_cut_split: children per step above which a problem's cut runs
+    across workgroups of `part` children (children 0: never)."""
+    _check(lib().pcba_set_cut_split(int(children), int(part)))
 
 
 def rtd_constraints(w, pts, eps_q: float) -> np.ndarray:

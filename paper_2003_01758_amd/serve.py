@@ -17,6 +17,7 @@ from __future__ import annotations
 import argparse
 import collections
 import json
+import math
 import sys
 import time
 
@@ -41,9 +42,13 @@ class Server:
     """Continuous batching of plan requests on one GPU."""
 
     def __init__(self, budget_bytes: int, reserve_boxes: int = 256, steps_per_round: int = 2,
-                 precision: str = "fp32", deadline_s: float = 0.5, **options):
+                 precision: str = "fp32", deadline_s: float = 0.5, max_waiting: int = 64, **options):
         self.engine = pcba.Engine(budget_bytes=budget_bytes, reserve_boxes=reserve_boxes)
         self.steps = steps_per_round
+        # problems created (device memory held) but not yet admitted: arrivals
+        # beyond these wait as requests, so an overload grows a host queue, not
+        # device allocations
+        self.max_waiting = max_waiting
         self.precision = precision
         self.deadline = deadline_s
         self.options = options
@@ -63,7 +68,7 @@ class Server:
         while n_done < len(requests):
             now = time.perf_counter() - t0
             # arrivals up to now become problems on the device
-            while pending and pending[0][0] <= now:
+            while pending and pending[0][0] <= now and len(queue) < self.max_waiting:
                 ta, i = pending.popleft()
                 prob = pcba.Problem(requests[i], precision=self.precision,
                                     time_limit_s=self.deadline, **self.options)
@@ -89,7 +94,7 @@ class Server:
                                       deadline_missed=bool(lat > self.deadline or not certified))
                     prob.close()
                     n_done += 1
-            elif pending:
+            elif pending and not queue:
                 # idle until the next arrival
                 time.sleep(max(0.0, min(pending[0][0] - now, 0.001)))
             if log and time.perf_counter() - last_log > 5.0:
@@ -120,7 +125,11 @@ def sweep(args, log):
         requests = [pool[k % len(pool)] for k in range(len(arrivals))]
         srv = Server(int(args.budget_gib * 2**30), precision=args.precision,
                      steps_per_round=args.steps_per_round)
-        out = summarize(srv.serve(requests, arrivals), args.duration)
+        try:
+            out = summarize(srv.serve(requests, arrivals), args.duration)
+        except pcba.PcbaError as e:   # an overload the library refused: the rate is not served
+            out = dict(plans=len(requests), certified=0, p50_ms=math.inf, p99_ms=math.inf,
+                       deadline_miss_rate=1.0, error=str(e))
         out.update(rate=rate)
         rows.append(out)
         log(f"[sweep] rate {rate:.0f}/s: p50/p99 {out['p50_ms']:.2f}/{out['p99_ms']:.2f} ms, "

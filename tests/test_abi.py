@@ -45,6 +45,7 @@ def test_default_options_and_argument_validation_without_device():
     assert o.persistent_steps == 0
     # argument errors are detected before any device call
     L = pcba.lib()
+    assert L.pcba_set_cut_split(-1, 4096) == pcba.E_ARG and L.pcba_set_cut_split(1024, 32) == pcba.E_ARG
     h = ctypes.c_void_p()
     rc = L.pcba_create_problem(0, None, None, None, None, 0, None, None, 0, None, None, None,
                                ctypes.byref(h))

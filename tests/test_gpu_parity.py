@@ -82,11 +82,22 @@ def test_root_patches_match_oracle(gpu, name):
     assert _patch_close(got, want)
 
 
+@pytest.fixture
+def cut_split(gpu, request):
+    # split: every cut over workgroups of 64 children once a step has more
+    # than 64 children (the library's default splits from 32,768 on)
+    if request.param == "split":
+        gpu.set_cut_split(64, 64)
+    yield request.param
+    gpu.set_cut_split()
+
+
+@pytest.mark.parametrize("cut_split", ["one", "split"], indirect=True)
 @pytest.mark.parametrize("retire", [1, 0])
 @pytest.mark.parametrize("name", list(CASES))
-def test_fp64_step_trace_matches_oracle(gpu, name, retire):
+def test_fp64_step_trace_matches_oracle(gpu, name, retire, cut_split):
     inst = CASES[name]()
-    print(f"[fp64 trace] {name} retire={retire}", flush=True)
+    print(f"[fp64 trace] {name} retire={retire} cut={cut_split}", flush=True)
     g = gpu.Problem(inst, retire_satisfied=retire)
     o = ref.RefSolver(inst)
     for step in range(200):
@@ -316,6 +327,29 @@ def test_persistent_steps_equal_launches(gpu, prec, retire, rederive):
         out.append(gpu.solve_batch(probs))
         for p in probs:
             p.close()
+    for k, (a, b) in enumerate(zip(*out)):
+        for key in ("outcome", "p_up", "p_lo", "steps", "peak_len", "certified", "p_cert"):
+            assert a[key] == b[key], (k, key)
+        assert np.array_equal(a["x_index"], b["x_index"]), k
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_split_cut_batch_equals_one_workgroup_cut(gpu, prec):
+    # a batch of problems of different sizes: with the cut split over
+    # workgroups of 64 children (problem b, part g from one grid) every result
+    # equals the one-workgroup cut's
+    insts = [CASES[n]() for n in ("small0", "rtd40", "P4", "batch_l3", "circle_eq", "small7")]
+    print(f"[split cut batch] {prec}", flush=True)
+    out = []
+    for split in (0, 64):
+        gpu.set_cut_split(split, 64)
+        try:
+            probs = [gpu.Problem(i, precision=prec) for i in insts]
+            out.append(gpu.solve_batch(probs))
+            for p in probs:
+                p.close()
+        finally:
+            gpu.set_cut_split()
     for k, (a, b) in enumerate(zip(*out)):
         for key in ("outcome", "p_up", "p_lo", "steps", "peak_len", "certified", "p_cert"):
             assert a[key] == b[key], (k, key)

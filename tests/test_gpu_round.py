@@ -53,10 +53,21 @@ def _patch_close(a, b):
     return float(np.abs(a - b).max(initial=0.0)) <= REL * scale
 
 
+@pytest.fixture
+def cut_split(gpu, request):
+    # split: every cut over workgroups of 64 children once a round has more
+    # than 64 children (four per parent)
+    if request.param == "split":
+        gpu.set_cut_split(64, 64)
+    yield request.param
+    gpu.set_cut_split()
+
+
+@pytest.mark.parametrize("cut_split", ["one", "split"], indirect=True)
 @pytest.mark.parametrize("name", list(CASES))
-def test_fp64_round_trace_matches_oracle(gpu, name):
+def test_fp64_round_trace_matches_oracle(gpu, name, cut_split):
     inst = CASES[name]()
-    print(f"[round fp64 trace] {name}", flush=True)
+    print(f"[round fp64 trace] {name} cut={cut_split}", flush=True)
     g = gpu.Problem(inst, retire_satisfied=0, fused_round=1)
     o = ref.RefSolver(inst, fused=True)
     for step in range(200):
