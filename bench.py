@@ -173,7 +173,7 @@ def measured_traffic(mode_name, kernel):
     size), or None when the kernel source has changed since the counters were
     taken or the mode was not counted."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "k_sub_rtd256_hbm_bytes.md")
+    path = os.path.join(ROOT, "profiles", "k_sub_rtd256_r0_hbm_bytes.md")
     try:
         line = [ln for ln in open(path) if ln.strip().startswith("{")][-1]
         rec = json.loads(line)

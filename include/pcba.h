@@ -137,7 +137,8 @@ typedef struct {
                                 Not with fused_round. */
     int32_t persistent_steps;/* 0 (default): one launch per kernel per step.  1: when every
                                 problem of a batch asks for it, the batch is of one precision (at
-                                most 256 problems, lists of at most 4,096 boxes) and no FP32
+                                most 256 problems, lists of at most 4,096 boxes, FP32 split on
+                                the vector ALUs) and no FP32
                                 re-derivation falls due, several whole steps (subdivision, cut)
                                 run in one cooperative launch with grid barriers between the
                                 phases.  Results are the same either way; on MI355X the barriers'

@@ -20,8 +20,9 @@ hipError_t launch_plan(const DevInst* d_insts, int n, long long* plan, StepInfo*
 // largest tile (coefficients, patches) of the problems launched; nr: children
 // regions per tile, 2, or NCMAX when some problem splits whole rounds; wg_cap:
 // workgroups per compute unit at most (0: as many as fit).
+// mfma: some FP32 problem of the launch splits on the matrix cores.
 hipError_t launch_sub(const DevInst* d_insts, int n, long long* plan, StepInfo* info, bool fuse,
-                      bool fp32, int maxm, int grid, int tem, int tpm, int nr, int wg_cap, hipStream_t s,
+                      bool fp32, bool mfma, int maxm, int grid, int tem, int tpm, int nr, int wg_cap, hipStream_t s,
                       hipEvent_t ev0, hipEvent_t ev1);
 // Up to n_steps whole steps (subdivision, cut) of a batch of one precision in
 // one cooperative launch with grid barriers between the phases (n <=

@@ -1294,7 +1294,9 @@ __device__ __forceinline__ int3 block_scan3(int3 x, int3& excl, int* sc)
 // states (one thread per problem); workgroup 0 alone commits the memory test's
 // outcome and writes the plan and snapshots for the step's later kernels.
 // Returns whether the step has units of this launch's class at all.
-template <typename T, int MM, int LB, bool FUSE>
+// MF: FP32 problems may split on the matrix cores (the matrix-core code is
+// compiled in only then, so that the vector-ALU form keeps its registers).
+template <typename T, int MM, int LB, bool FUSE, bool MF>
 __device__ __forceinline__ bool sub_run(const DevInst* __restrict__ insts, int n_inst,
                                         long long* __restrict__ plan, StepInfo* __restrict__ info, int tem,
                                         int tpm, int nr)
@@ -1496,7 +1498,7 @@ __device__ __forceinline__ bool sub_run(const DevInst* __restrict__ insts, int n
         // regions 2 and 3): region b0 + 2 b1 holds the child with bit b0 on axis 0
         // and b1 on axis 1, the same sequence of operations as the oracle's.
         bool on_mfma = false;
-        if constexpr (sizeof(T) == 4) on_mfma = I.mfma != 0;
+        if constexpr (sizeof(T) == 4 && MF) on_mfma = I.mfma != 0;
         // (FP32: the first split takes each patch's values less its pending shift)
         if (on_mfma)
             tile_split_mfma(np, S, c.g, (float*)La, (float*)Lb, (unsigned*)Lkey, I.lam, (const float*)Lpend);
@@ -1840,12 +1842,12 @@ __device__ __forceinline__ bool sub_run(const DevInst* __restrict__ insts, int n
 // Two workgroups of four waves per compute unit (two waves per SIMD): the
 // register budget is then 256 per lane, which the FP32 form, with its matrix
 // accumulators, would otherwise exceed by a few and fall to one wave per SIMD.
-template <typename T, int MM, int LB, bool FUSE>
+template <typename T, int MM, int LB, bool FUSE, bool MF>
 __global__ __launch_bounds__(SUB_THREADS, 2) void k_sub(const DevInst* __restrict__ insts, int n_inst,
                                                     long long* __restrict__ plan,
                                                     StepInfo* __restrict__ info, int tem, int tpm, int nr)
 {
-    sub_run<T, MM, LB, FUSE>(insts, n_inst, plan, info, tem, tpm, nr);
+    sub_run<T, MM, LB, FUSE, MF>(insts, n_inst, plan, info, tem, tpm, nr);
 }
 
 // ------------------------------------------------------------------ k_rederive
@@ -2665,7 +2667,7 @@ __global__ __launch_bounds__(SUB_THREADS, 2) void k_steps(const DevInst* __restr
 {
     unsigned gen = 0;
     for (int s = 0; s < n_steps; ++s) {
-        const bool work = sub_run<T, MM, LB, true>(insts, n_inst, plan, info, tem, tpm, nr);
+        const bool work = sub_run<T, MM, LB, true, false>(insts, n_inst, plan, info, tem, tpm, nr);
         if (!grid_barrier(bar, ++gen, herr)) return;
         if (!work) return;   // the same plan in every workgroup: all leave together
         for (int b = blockIdx.x; b < n_inst; b += gridDim.x) {
@@ -3050,7 +3052,7 @@ size_t sub_lds_bytes(int tem, int tpm, bool fp32, int nr)
 }
 
 // With ev0/ev1 the launch stamps them at the kernel's own start and end.
-template <typename T, int MM, bool FUSE>
+template <typename T, int MM, bool FUSE, bool MF>
 static hipError_t launch_sub_t(const DevInst* d_insts, int n, long long* plan, StepInfo* info, int grid,
                                int tem, int tpm, int nr, int wg_cap, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1)
 {
@@ -3062,29 +3064,30 @@ static hipError_t launch_sub_t(const DevInst* d_insts, int n, long long* plan, S
     // no more workgroups than fit on the device at once: the rest would only
     // queue, while resident ones walk the units with the next tile in flight
     const int cus = device_props(current_device()).cus;
-    int per_cu = occupancy_per_cu((const void*)k_sub<T, MM, LB, FUSE>, SUB_THREADS, lds);
+    int per_cu = occupancy_per_cu((const void*)k_sub<T, MM, LB, FUSE, MF>, SUB_THREADS, lds);
     if (wg_cap > 0 && per_cu > 0) per_cu = std::min(per_cu, wg_cap);
     if (cus > 0 && per_cu > 0) grid = std::min(grid, cus * per_cu);
     if (ev0)
-        hipExtLaunchKernelGGL((k_sub<T, MM, LB, FUSE>), dim3(grid), dim3(SUB_THREADS), lds, s, ev0, ev1, 0,
+        hipExtLaunchKernelGGL((k_sub<T, MM, LB, FUSE, MF>), dim3(grid), dim3(SUB_THREADS), lds, s, ev0, ev1, 0,
                               d_insts, n, plan, info, tem, tpm, nr);
     else
-        hipLaunchKernelGGL((k_sub<T, MM, LB, FUSE>), dim3(grid), dim3(SUB_THREADS), lds, s, d_insts, n, plan,
+        hipLaunchKernelGGL((k_sub<T, MM, LB, FUSE, MF>), dim3(grid), dim3(SUB_THREADS), lds, s, d_insts, n, plan,
                            info, tem, tpm, nr);
     return hipGetLastError();
 }
 
-template <typename T, int MM>
+template <typename T, int MM, bool MF>
 static hipError_t launch_sub_f(const DevInst* d_insts, int n, long long* plan, StepInfo* info, bool fuse,
                                int grid, int tem, int tpm, int nr, int wg_cap, hipStream_t s, hipEvent_t ev0,
                                hipEvent_t ev1)
 {
-    if (fuse) return launch_sub_t<T, MM, true>(d_insts, n, plan, info, grid, tem, tpm, nr, wg_cap, s, ev0, ev1);
-    return launch_sub_t<T, MM, false>(d_insts, n, plan, info, grid, tem, tpm, nr, wg_cap, s, ev0, ev1);
+    if (fuse)
+        return launch_sub_t<T, MM, true, MF>(d_insts, n, plan, info, grid, tem, tpm, nr, wg_cap, s, ev0, ev1);
+    return launch_sub_t<T, MM, false, MF>(d_insts, n, plan, info, grid, tem, tpm, nr, wg_cap, s, ev0, ev1);
 }
 
 hipError_t launch_sub(const DevInst* d_insts, int n, long long* plan, StepInfo* info, bool fuse,
-                      bool fp32, int maxm, int grid, int tem, int tpm, int nr, int wg_cap, hipStream_t s,
+                      bool fp32, bool mfma, int maxm, int grid, int tem, int tpm, int nr, int wg_cap, hipStream_t s,
                       hipEvent_t ev0, hipEvent_t ev1)
 {
     if (fuse && n > PLAN_FUSE_MAX) return hipErrorInvalidValue;
@@ -3092,13 +3095,19 @@ hipError_t launch_sub(const DevInst* d_insts, int n, long long* plan, StepInfo* 
         if (!fuse) return hipSuccess;
         grid = 1;   // the plan is still formed and written
     }
+    if (fp32 && mfma) {
+        if (maxm <= 8)
+            return launch_sub_f<float, 8, true>(d_insts, n, plan, info, fuse, grid, tem, tpm, nr, wg_cap, s, ev0, ev1);
+        return launch_sub_f<float, 16, true>(d_insts, n, plan, info, fuse, grid, tem, tpm, nr, wg_cap, s, ev0, ev1);
+    }
     if (fp32) {
         if (maxm <= 8)
-            return launch_sub_f<float, 8>(d_insts, n, plan, info, fuse, grid, tem, tpm, nr, wg_cap, s, ev0, ev1);
-        return launch_sub_f<float, 16>(d_insts, n, plan, info, fuse, grid, tem, tpm, nr, wg_cap, s, ev0, ev1);
+            return launch_sub_f<float, 8, false>(d_insts, n, plan, info, fuse, grid, tem, tpm, nr, wg_cap, s, ev0, ev1);
+        return launch_sub_f<float, 16, false>(d_insts, n, plan, info, fuse, grid, tem, tpm, nr, wg_cap, s, ev0, ev1);
     }
-    if (maxm <= 8) return launch_sub_f<double, 8>(d_insts, n, plan, info, fuse, grid, tem, tpm, nr, wg_cap, s, ev0, ev1);
-    return launch_sub_f<double, 16>(d_insts, n, plan, info, fuse, grid, tem, tpm, nr, wg_cap, s, ev0, ev1);
+    if (maxm <= 8)
+        return launch_sub_f<double, 8, false>(d_insts, n, plan, info, fuse, grid, tem, tpm, nr, wg_cap, s, ev0, ev1);
+    return launch_sub_f<double, 16, false>(d_insts, n, plan, info, fuse, grid, tem, tpm, nr, wg_cap, s, ev0, ev1);
 }
 
 template <typename T, int MM>

@@ -1290,13 +1290,14 @@ static int engine_steps(pcba_engine* E, int n_steps)
         if (rc != PCBA_OK) return rc;
     }
     const int n = (int)E->active.size();
-    bool any64 = false, any32 = false, anyrd = false;
+    bool any64 = false, any32 = false, anyrd = false, mf32 = false;
     int maxm64 = 1, maxm32 = 1, nr64 = 2, nr32 = 2, wg64 = 0, wg32 = 0;
     size_t ldsrd = 0;
     int tem64 = 1, tpm64 = 1, tem32 = 1, tpm32 = 1;
     for (auto* P : E->active) {
         if (P->fp32) {
             any32 = true;
+            if (P->opt.split_engine == PCBA_SPLIT_MFMA) mf32 = true;
             maxm32 = std::max(maxm32, P->maxm);
             nr32 = std::max(nr32, P->nc);
             wg32 = std::max(wg32, P->opt.wg_per_cu);
@@ -1323,7 +1324,7 @@ static int engine_steps(pcba_engine* E, int n_steps)
     // short lists (its cut runs on the subdivision's 256 lanes), kernel timing
     // off (the timed launches are per kernel), and for the steps in which no
     // FP32 re-derivation falls due.
-    bool persist = !g_prof.on && n <= PLAN_FUSE_MAX && any64 != any32;
+    bool persist = !g_prof.on && n <= PLAN_FUSE_MAX && any64 != any32 && !mf32;
     for (auto* P : E->active)
         if (!P->opt.persistent_steps || P->cap > 4096) persist = false;
     if (persist) {
@@ -1392,14 +1393,14 @@ static int engine_steps(pcba_engine* E, int n_steps)
         if (l64) {
             hipEvent_t e0, e1;
             HIP_TRY(prof_pair(0, &e0, &e1));
-            HIP_TRY(launch_sub(E->b.d_insts, n, E->b.d_plan, E->b.d_info, !planned, false, maxm64,
+            HIP_TRY(launch_sub(E->b.d_insts, n, E->b.d_plan, E->b.d_info, !planned, false, false, maxm64,
                                (int)std::min<int64_t>(GRID_MAX, ub64), tem64, tpm64, nr64, wg64, E->stream, e0, e1));
             planned = true;
         }
         if (l32) {
             hipEvent_t e0, e1;
             HIP_TRY(prof_pair(1, &e0, &e1));
-            HIP_TRY(launch_sub(E->b.d_insts, n, E->b.d_plan, E->b.d_info, !planned, true, maxm32,
+            HIP_TRY(launch_sub(E->b.d_insts, n, E->b.d_plan, E->b.d_info, !planned, true, mf32, maxm32,
                                (int)std::min<int64_t>(GRID_MAX, ub32), tem32, tpm32, nr32, wg32, E->stream, e0, e1));
             planned = true;
         }
