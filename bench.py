@@ -265,6 +265,38 @@ def copy_calibration(mib: int, reps: int):
     print(json.dumps({"copy_bytes": n, "copies": reps}), flush=True)
 
 
+def cut_scaling(max_steps: int = 80, max_children: int = 600000):
+    """The cut kernel's time per step against the step's children, on the 4-D
+    workload (100 inequalities, 2 equalities, M 2^21, retiring on), with the cut
+    in one workgroup per problem and split across workgroups: one JSON line per
+    step (HIP events around the cut's launches)."""
+    from paper_2003_01758_amd import pcba
+    from paper_2003_01758_amd.instances import make_instance
+    rows = {}
+    for mode, split in (("one", 0), ("split", 32768)):
+        pcba.set_cut_split(split, 4096)
+        g = pcba.Problem(make_instance(2, 0).with_options(max_boxes=1 << 21), retire_satisfied=1)
+        pcba.profile_enable(True)
+        for step in range(max_steps):
+            pcba.profile_reset()
+            r = g.step(1)
+            ms, n = pcba.profile_read()["cut"]
+            kin = int(g.trace()["k_in"][step])
+            rows.setdefault(step, {})[mode] = (2 * kin, ms * 1e3, n)
+            if r["outcome"] != pcba.RUNNING or 2 * kin > max_children:
+                break
+        pcba.profile_enable(False)
+        g.close()
+    pcba.set_cut_split()
+    for step in sorted(rows):
+        d = rows[step]
+        if "one" in d and "split" in d and d["one"][0] == d["split"][0]:
+            c = d["one"][0]
+            print(json.dumps({"step": step, "children": c, "cut_us_one_workgroup": round(d["one"][1], 2),
+                              "cut_us_split": round(d["split"][1], 2),
+                              "ns_per_child_one": round(1e3 * d["one"][1] / max(c, 1), 3),
+                              "ns_per_child_split": round(1e3 * d["split"][1] / max(c, 1), 3)}), flush=True)
+
 
 MODE_FLAGS = {
     "r0": ("retire_satisfied", 0),   # every box carries every constraint (Alg. Subdivision)
@@ -323,6 +355,8 @@ def main():
                     help="oracle worker processes (the host's share of cores)")
     ap.add_argument("--rederive", type=int, default=None, help="FP32 re-derivation period (steps)")
     ap.add_argument("--stale", type=int, default=None, help="1/0: stale-estimate write filter")
+    ap.add_argument("--cut-scaling", action="store_true",
+                    help="only measure the cut kernel against the list length (4-D workload) and exit")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="only run device copies of this many MiB (counter calibration) and exit")
     ap.add_argument("--tune", type=int, default=1,
@@ -340,6 +374,9 @@ def main():
     args = ap.parse_args()
     if args.copy_mib > 0:
         copy_calibration(args.copy_mib, 2)
+        return
+    if args.cut_scaling:
+        cut_scaling()
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU: this build has no multi-GPU path (asked for {args.gpus})",
