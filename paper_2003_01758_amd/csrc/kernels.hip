@@ -1131,6 +1131,10 @@ struct PackUnit {
     uint32_t stamp;
     FibreGeom g;      // fibres of the split (a round: of axis 0)
     FibreGeom g2;     // a round: fibres of axis 1
+    long long u;      // the unit, and the end of its problem's units of this kind
+    long long ukend;
+    long long total;  // patches of this kind in the problem's step
+    int ptp, cnt;     // patches per tile of the kind; patches of the kind per parent
 };
 
 // a / b for a >= 0 and 0 < b < 2^31: a 32-bit division when a fits (the usual
@@ -1180,6 +1184,16 @@ __device__ __forceinline__ void resolve_packed(const DevInst* __restrict__ insts
             total = I.retire ? (long long)si.A : K * I.count[1];
         }
     }
+    // the end of this kind's units (the next unit of the same kind continues
+    // from this one: resolve_next)
+    {
+        const long long U = div_nn(total + I.ptp[c.kind] - 1, I.ptp[c.kind]);
+        c.ukend = uniform64(u - v + U);
+    }
+    c.u = u;
+    c.total = total;
+    c.ptp = I.ptp[c.kind];
+    c.cnt = c.kind == 0 ? 1 : I.count[c.kind];
     c.P0 = uniform64(v * I.ptp[c.kind]);
     c.np = __builtin_amdgcn_readfirstlane((int)min((long long)I.ptp[c.kind], total - c.P0));
     c.cur = si.cur;
@@ -1190,12 +1204,9 @@ __device__ __forceinline__ void resolve_packed(const DevInst* __restrict__ insts
     c.invS = 1.0f / (float)c.S;
     c.TE = c.np * c.S;
     c.gath = I.retire && c.kind == 1;
-    {
-        // without the heap, a parent's patches of a kind are consecutive in
-        // its slot: a tile within one parent is one run of coefficients
-        const int cnt = c.kind == 0 ? 1 : I.count[c.kind];
-        c.contig = !c.gath && div_nn(c.P0, cnt) == div_nn(c.P0 + c.np - 1, cnt);
-    }
+    // without the heap, a parent's patches of a kind are consecutive in its
+    // slot: a tile within one parent is one run of coefficients
+    c.contig = !c.gath && div_nn(c.P0, c.cnt) == div_nn(c.P0 + c.np - 1, c.cnt);
     c.nc = I.fused ? (1 << I.l) : 2;
     if (c.nc == 4) {
         c.g = fibre_geom(I.dims[c.kind], I.l, 0, c.S);
@@ -1204,6 +1215,25 @@ __device__ __forceinline__ void resolve_packed(const DevInst* __restrict__ insts
         c.g = fibre_geom(I.dims[c.kind], I.l, I.fused ? 0 : c.r, c.S);
         c.g2 = c.g;
     }
+}
+
+// Unit u when it follows `prev` (u = prev.u + 1) in the same problem and kind
+// (a workgroup's units are consecutive): the next tile of the same patch
+// sequence, without resolving it again; otherwise resolve_packed.
+__device__ __forceinline__ void resolve_next(const DevInst* __restrict__ insts, int n, const long long* pre,
+                                             const StepInfo* info, long long u, int& hint, const PackUnit& prev,
+                                             PackUnit& c)
+{
+    if (u == prev.u + 1 && u < prev.ukend) {
+        c = prev;
+        c.u = u;
+        c.P0 = uniform64(prev.P0 + prev.ptp);
+        c.np = __builtin_amdgcn_readfirstlane((int)min((long long)prev.ptp, prev.total - c.P0));
+        c.TE = c.np * c.S;
+        c.contig = !c.gath && div_nn(c.P0, c.cnt) == div_nn(c.P0 + c.np - 1, c.cnt);
+        return;
+    }
+    resolve_packed(insts, n, pre, info, u, hint, c);
 }
 
 // Patch p of a tile: its parent j, the parent's slot, its index in its kind,
@@ -1435,7 +1465,7 @@ __device__ __forceinline__ bool sub_run(const DevInst* __restrict__ insts, int n
     long long u1 = u + 1;
     bool more1 = u1 < uend;
     if (more1) {
-        resolve_packed(insts, n_inst, pre, sinfo, u1, hint, cn);
+        resolve_next(insts, n_inst, pre, sinfo, u1, hint, c, cn);
         if (tid < cn.np) {
             int4 pinf;
             long long psrc;
@@ -1487,7 +1517,7 @@ __device__ __forceinline__ bool sub_run(const DevInst* __restrict__ insts, int n
         int4 ninf = make_int4(0, 0, 0, 0);
         long long nsrc = 0;
         if (more2) {
-            resolve_packed(insts, n_inst, pre, sinfo, u2, hint, c2);
+            resolve_next(insts, n_inst, pre, sinfo, u2, hint, cn, c2);
             if (tid < c2.np) patch_info(insts[c2.bi], c2, tid, ninf, nsrc);
         }
         lds_barrier();
