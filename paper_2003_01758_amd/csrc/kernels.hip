@@ -1418,6 +1418,9 @@ __device__ __forceinline__ bool sub_run(const DevInst* __restrict__ insts, int n
     long long* Lsrc1 = (long long*)carve((size_t)tpm * 8);
     long long* Lsrc2 = (long long*)carve((size_t)tpm * 8);
     T* Lpend = (T*)carve((size_t)tpm * sizeof(T));      // FP32: per patch, its pending shift
+    float* Lcerr = (float*)carve((size_t)tpm * 4);      // FP32: per patch, its carried bound
+    double* Lcbase = (double*)carve((size_t)tpm * 8);   // FP32: per patch, its FP64 base
+    int* Ldead = (int*)carve((size_t)tpm * 4);          // per patch: children known dead (stale filter)
     int4* Linf0 = (int4*)carve((size_t)tpm * 16);
     int4* Linf1 = (int4*)carve((size_t)tpm * 16);
     int4* Linf2 = (int4*)carve((size_t)tpm * 16);
@@ -1503,7 +1506,12 @@ __device__ __forceinline__ bool sub_run(const DevInst* __restrict__ insts, int n
                 kk[4] = 0;
             }
             for (int ch = 0; ch < nr; ++ch) Lsfl[nr * tid + ch] = 0;
-            if (fp32) Lpend[tid] = (T)ce.y;
+            if (fp32) {
+                Lpend[tid] = (T)ce.y;
+                Lcerr[tid] = ce.x;
+                Lcbase[tid] = cb;
+            }
+            Ldead[tid] = 0;
         }
         // the next tile's coefficients (and FP32 error bounds and bases) in
         // flight for the whole of this tile
@@ -1550,9 +1558,15 @@ __device__ __forceinline__ bool sub_run(const DevInst* __restrict__ insts, int n
         lds_barrier();
 
         // per patch (thread p): bounds of every child (widened in FP32 mode),
-        // records (cost) or flags (constraints)
-        const bool act = tid < np;
-        const int p = tid;
+        // records (cost) or flags (constraints).  A constraint tile inside one
+        // parent with at most 64 patches takes one wave per child instead
+        // (thread p + 64 ch bounds child ch of patch p), so the children are
+        // bounded in parallel; the patch's FP32 figures then come from LDS.
+        const bool split_b = kind != 0 && c.contig && np <= 64 && nc * 64 <= SUB_THREADS;
+        const int p = split_b ? (tid & 63) : tid;
+        const int chb = split_b ? (tid >> 6) : 0;
+        const bool act = split_b ? (p < np && chb < nc) : tid < np;
+        const int ch0 = split_b ? chb : 0, ch1 = split_b ? chb + 1 : nc;   // the children it bounds
         int j = 0, slot = 0, id = 0, poly = 0;
         uint32_t f2[NCMAX] = {0, 0, 0, 0};
         double lo[NCMAX] = {0.0, 0.0, 0.0, 0.0}, hi[NCMAX] = {0.0, 0.0, 0.0, 0.0};
@@ -1569,7 +1583,7 @@ __device__ __forceinline__ bool sub_run(const DevInst* __restrict__ insts, int n
             slot = ip.y;
             id = ip.z;
             if (I.stale && kind != 0 && !c.gath) {
-                for (int ch = 0; ch < nc; ++ch) {
+                for (int ch = ch0; ch < ch1; ++ch) {
                     const int64_t ci = (int64_t)nc * j + ch;
                     const uint32_t fl = __hip_atomic_load(&I.flags[ci], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     const unsigned long long rec = __hip_atomic_load(&I.stamp[ci], __ATOMIC_RELAXED,
@@ -1601,12 +1615,19 @@ __device__ __forceinline__ bool sub_run(const DevInst* __restrict__ insts, int n
             // 2^-52 of it); the subtraction rounds below 2^-23 of the largest
             // shifted value (max |parent| of the split's keys), or flushes.
             const double amax = fp32 ? (double)funkey(Lkey[5 * p + 4]) : 0.0;
-            const bool shifted = fp32 && ce.y != 0.0f;
-            const double nbs = shifted ? cb + (double)ce.y : cb;
-            const double e1 = fp32 ? (double)ce.x + gamma32(c.g.m + mx_extra) * amax + (double)(3 * c.g.m) * 0x1p-126 +
+            float pe = ce.x, ps = ce.y;
+            double pb = cb;
+            if (fp32 && split_b) {
+                pe = Lcerr[p];
+                ps = (float)Lpend[p];
+                pb = Lcbase[p];
+            }
+            const bool shifted = fp32 && ps != 0.0f;
+            const double nbs = shifted ? pb + (double)ps : pb;
+            const double e1 = fp32 ? (double)pe + gamma32(c.g.m + mx_extra) * amax + (double)(3 * c.g.m) * 0x1p-126 +
                                          (shifted ? amax * 0x1p-23 + 0x1p-126 + fabs(nbs) * 0x1p-52 : 0.0)
                                    : 0.0;
-            for (int ch = 0; ch < nc; ++ch) {
+            for (int ch = ch0; ch < ch1; ++ch) {
                 // the keys of child ch: one split, half ch; a round, half b0 of the
                 // first split and then half b1 of the second
                 const int b0 = nc == 4 ? (ch >> 1) : ch, b1 = ch & 1;
@@ -1662,7 +1683,7 @@ __device__ __forceinline__ bool sub_run(const DevInst* __restrict__ insts, int n
                         __hip_atomic_store(&I.stamp[nc * j + ch], rec, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     }
             } else {
-                for (int ch = 0; ch < nc; ++ch) {
+                for (int ch = ch0; ch < ch1; ++ch) {
                     uint32_t f = 0;
                     if (kind == 1) {
                         if (lo[ch] > 0.0) f |= F_INFEAS;
@@ -1697,6 +1718,8 @@ __device__ __forceinline__ bool sub_run(const DevInst* __restrict__ insts, int n
                                    (__ballot(act && (f2[ch] & F_NOTFEAS)) ? F_NOTFEAS : 0u);
                 if (f && (tid & 63) == 0) atomicOr(&Lsfl[ch], f);
             }
+            // the children known dead, per patch (one wave per child bounds them)
+            if (act && known_dead) atomicOr(&Ldead[p], (int)known_dead);
             if (tid == 0) {
                 Lseg[0] = 0;
                 Lseg[1] = np;
@@ -1753,11 +1776,12 @@ __device__ __forceinline__ bool sub_run(const DevInst* __restrict__ insts, int n
             // children patches to the children's slots, not to a child already
             // condemned (infeasible from this tile, or with the stale filter a
             // cost bound above the previous solution estimate)
-            if (act) {
+            if (act && chb == 0) {
                 int wm = 0;
+                const uint32_t kd = split_b ? (uint32_t)Ldead[p] : known_dead;
                 for (int ch = 0; ch < nc; ++ch) {
                     const bool w = kind == 0 ? !(I.stale && lo[ch] > c.pprev)
-                                             : !(Lsfl[nr * seg + ch] & F_INFEAS) && !((known_dead >> ch) & 1u);
+                                             : !(Lsfl[nr * seg + ch] & F_INFEAS) && !((kd >> ch) & 1u);
                     if (w) wm |= 1 << ch;
                 }
                 Lwm[p] = wm;
@@ -3076,7 +3100,8 @@ size_t sub_lds_bytes(int tem, int tpm, bool fp32, int nr)
     const size_t el = fp32 ? 4 : 8;
     auto r16 = [](size_t b) { return (b + 15) & ~(size_t)15; };
     return r16((size_t)nr * tem * el) + r16((size_t)5 * tpm * (nr > 2 ? 3 : 1) * el) + 3 * r16((size_t)tpm * 8) +
-           r16((size_t)tpm * el) + 3 * r16((size_t)tpm * 16) + r16((size_t)tpm * 4) +
+           r16((size_t)tpm * el) + r16((size_t)tpm * 4) + r16((size_t)tpm * 8) + r16((size_t)tpm * 4) +
+           3 * r16((size_t)tpm * 16) + r16((size_t)tpm * 4) +
            r16((size_t)(2 * tpm + 2) * 4) + r16((size_t)2 * tpm * 4) + r16((size_t)nr * tpm * 4) +
            r16((size_t)2 * tpm * 4) + r16((size_t)(tpm + 1) * 4) + r16((size_t)tpm * 8);
 }
