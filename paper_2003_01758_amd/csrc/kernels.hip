@@ -1803,19 +1803,34 @@ __device__ __forceinline__ bool sub_run(const DevInst* __restrict__ insts, int n
                     if (!((Lwm[0] >> ch) & 1)) continue;   // uniform: the whole tile's child
                     const int4 ip = inf[0];
                     const int64_t d0 = (int64_t)(nc * ip.x + ch) * I.stride + I.soff[kind] + (int64_t)ip.z * S;
-                    for (int e0 = tid; e0 < TE; e0 += SB * SUB_THREADS) {
-                        T va[SB];
+                    // 16-byte stores: the elements before the destination's
+                    // first 16-byte boundary and after its last one singly
+                    // (buffers are 256-byte aligned), whole vectors between
+                    constexpr int VE = 16 / sizeof(T);
+                    using V = T __attribute__((ext_vector_type(VE)));
+                    const int h = min((int)((VE - (int)(d0 & (VE - 1))) & (VE - 1)), TE);
+                    const int nv = (TE - h) / VE, t0 = h + nv * VE, nt = TE - t0;
+                    if (tid < h) dbuf[d0 + tid] = src[tid];
+                    if (tid >= SUB_THREADS - nt) {
+                        const int e = t0 + tid - (SUB_THREADS - nt);
+                        dbuf[d0 + e] = src[e];
+                    }
+                    const gmem_t<V> dv = (gmem_t<V>)(dbuf + d0 + h);
+                    const T* sv = src + h;
+                    constexpr int SV = 4;
+                    for (int i0 = tid; i0 < nv; i0 += SV * SUB_THREADS) {
+                        V va[SV];
 #pragma unroll
-                        for (int q = 0; q < SB; ++q) {
-                            const int e = e0 + q * SUB_THREADS;
-                            if (e < TE) {
-                                va[q] = src[e];
-                            }
+                        for (int q = 0; q < SV; ++q) {
+                            const int i = i0 + q * SUB_THREADS;
+                            if (i < nv)
+#pragma unroll
+                                for (int k = 0; k < VE; ++k) va[q][k] = sv[i * VE + k];
                         }
 #pragma unroll
-                        for (int q = 0; q < SB; ++q) {
-                            const int e = e0 + q * SUB_THREADS;
-                            if (e < TE) dbuf[d0 + e] = va[q];
+                        for (int q = 0; q < SV; ++q) {
+                            const int i = i0 + q * SUB_THREADS;
+                            if (i < nv) dv[i] = va[q];
                         }
                     }
                     continue;
