@@ -2022,9 +2022,6 @@ __global__ __launch_bounds__(SUB_THREADS) void k_rederive(const DevInst* __restr
     __shared__ uint32_t s_flag[NCMAX];
     __shared__ int s_tmoff[MAXL];
     __shared__ AxisGeo s_geo[MAXL];
-    __shared__ double s_base[REDERIVE_CHUNK];   // per patch of a chunk: FP64 base,
-    __shared__ int s_keep[REDERIVE_CHUNK];      // whether the child carries it,
-    __shared__ int s_dst[REDERIVE_CHUNK];       // and its heap patch (retiring mode)
     const long long* pre = plan + 2 * (n_inst + 1);
     const long long total = pre[n_inst];
     for (long long u = blockIdx.x; u < total; u += gridDim.x) {
@@ -2050,8 +2047,20 @@ __global__ __launch_bounds__(SUB_THREADS) void k_rederive(const DevInst* __restr
         const int cp = min(REDERIVE_CHUNK, max(1, MAX_TILE64 / S));
         int tmsz = 0;
         for (int k = 0; k < l; ++k) tmsz += I.dims[kind][k] * I.dims[kind][k];
+        // dynamic LDS: the chunk, the transforms, then per patch of a chunk its
+        // FP64 base, FP64 range (order keys), root bound, FP32 offsets' range,
+        // whether the child carries it, its heap patch (retiring mode) and its
+        // polynomial: 52 bytes
+        const int npc = min(np, cp);
         double* x = (double*)smem;
-        double* tm = x + min(np, cp) * S;
+        double* tm = x + npc * S;
+        double* s_base = tm + tmsz;
+        unsigned long long* s_kd = (unsigned long long*)(s_base + npc);
+        double* s_rb = (double*)(s_kd + 2 * npc);
+        unsigned int* s_kf = (unsigned int*)(s_rb + npc);
+        int* s_keep = (int*)(s_kf + 2 * npc);
+        int* s_dst = s_keep + npc;
+        int* s_poly = s_dst + npc;
         if (threadIdx.x < NCMAX) s_flag[threadIdx.x] = 0;
         if (threadIdx.x == 0) {
             int o = 0;
@@ -2069,6 +2078,19 @@ __global__ __launch_bounds__(SUB_THREADS) void k_rederive(const DevInst* __restr
             const int64_t roff = I.off[kind] + (gath ? 0 : (int64_t)(p0 + q0) * S);
             const int64_t soff = I.soff[kind] + (int64_t)(p0 + q0) * S;
             const double* tsrc = I.tmat + ((int64_t)j * nc + c) * I.tmw + I.tmk[kind];
+            // per patch: its polynomial and root figures, and the range keys reset
+            for (int p = threadIdx.x; p < nq; p += blockDim.x) {
+                const int id = gath ? pact[p0 + q0 + p].x : p0 + q0 + p;
+                const int poly = kind == 0 ? 0 : I.count[0] + (kind == 2 ? I.count[1] : 0) + id;
+                s_poly[p] = poly;
+                // root bound (rows of T sum to one) + transform rounding on
+                // |T||root| <= max|root|
+                s_rb[p] = I.root_err[poly] + g64 * I.root_abs[poly] * 1.01;
+                s_kd[2 * p] = ~0ull;
+                s_kd[2 * p + 1] = 0ull;
+                s_kf[2 * p] = ~0u;
+                s_kf[2 * p + 1] = 0u;
+            }
             copy_to_lds<double>(tm, tsrc, tmsz);
             if (!gath) {
                 copy_to_lds<double>(x, I.racc + roff, TE);
@@ -2084,58 +2106,65 @@ __global__ __launch_bounds__(SUB_THREADS) void k_rederive(const DevInst* __restr
             float* hc = (float*)I.heap[cur ^ 1];
             uint32_t fl = 0;
             const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-            // each patch: its FP64 range and base (the midrange), the FP32
-            // offsets' range, the error bound and the child's bounds (one wave
-            // per patch; lane 0 records them)
-            for (int p = wv; p < nq; p += blockDim.x >> 6) {
-                const int id = gath ? pact[p0 + q0 + p].x : p0 + q0 + p;
-                const int poly = (kind == 0 ? 0 : I.count[0] + (kind == 2 ? I.count[1] : 0) + id);
+            // each patch: its FP64 range and base (the midrange), then the
+            // FP32 offsets' range, each by nseg threads per patch (thread s
+            // takes the patch's elements s, s + nseg, ...) and order keys in
+            // LDS; then one thread per patch forms the error bound and the
+            // child's bounds
+            const int nseg = max(1, min(S, (int)blockDim.x / nq));
+            const int ntask = nq * nseg;
+            for (int k = threadIdx.x; k < ntask; k += blockDim.x) {
+                const int p = k / nseg, sg = k - p * nseg;
                 double vmn = INFINITY, vmx = -INFINITY;
-                for (int e = lane; e < S; e += 64) {
+                for (int e = sg; e < S; e += nseg) {
                     const double v = x[p * S + e];
                     vmn = fmin(vmn, v);
                     vmx = fmax(vmx, v);
                 }
-                for (int o = 32; o > 0; o >>= 1) {
-                    vmn = fmin(vmn, __shfl_xor(vmn, o, 64));
-                    vmx = fmax(vmx, __shfl_xor(vmx, o, 64));
-                }
-                const double base = 0.5 * vmn + 0.5 * vmx;
+                atomicMin(&s_kd[2 * p], fkey(vmn));
+                atomicMax(&s_kd[2 * p + 1], fkey(vmx));
+            }
+            __syncthreads();
+            for (int p = threadIdx.x; p < nq; p += blockDim.x)
+                s_base[p] = 0.5 * funkey(s_kd[2 * p]) + 0.5 * funkey(s_kd[2 * p + 1]);
+            __syncthreads();
+            for (int k = threadIdx.x; k < ntask; k += blockDim.x) {
+                const int p = k / nseg, sg = k - p * nseg;
+                const double b = s_base[p];
                 float mn = INFINITY, mx = -INFINITY;
-                for (int e = lane; e < S; e += 64) {
-                    const float d = (float)(x[p * S + e] - base);
+                for (int e = sg; e < S; e += nseg) {
+                    const float d = (float)(x[p * S + e] - b);
                     mn = fminf(mn, d);
                     mx = fmaxf(mx, d);
                 }
-                for (int o = 32; o > 0; o >>= 1) {
-                    mn = fminf(mn, __shfl_xor(mn, o, 64));
-                    mx = fmaxf(mx, __shfl_xor(mx, o, 64));
-                }
-                if (lane == 0) {
-                    // root bound (rows of T sum to one) + transform rounding on
-                    // |T||root| <= max|root| + rounding of the offsets (the FP64
-                    // difference and the FP32 conversion) + underflow
-                    const double amax = fmax(fabs((double)mn), fabs((double)mx));
-                    const double e = (double)round_up_f(I.root_err[poly] + g64 * I.root_abs[poly] * 1.01 +
-                                                        amax * 0x1p-23 + 0x1p-126);
-                    double lo, hi;
-                    child_bounds<float>(mn, mx, e, base, lo, hi);
-                    // retiring mode: an inequality certified satisfied is not carried
-                    s_keep[p] = !(gath && hi <= 0.0);
-                    s_base[p] = base;
-                    I.err[cur ^ 1][(int64_t)(nc * j + c) * I.n_polys + poly] = make_float2((float)e, 0.0f);
-                    I.base[cur ^ 1][(int64_t)(nc * j + c) * I.n_polys + poly] = base;
-                    if (kind == 0) {
-                        I.minP[nc * j + c] = lo;
-                        I.maxP[nc * j + c] = hi;
-                    } else if (kind == 1) {
-                        if (lo > 0.0) fl |= F_INFEAS;
-                        if (!(hi <= 0.0)) fl |= F_NOTFEAS;
-                    } else {
-                        if (lo > 0.0 || hi < 0.0) fl |= F_INFEAS;
-                        if (!(-I.eps_eq <= lo && lo <= 0.0 && 0.0 <= hi && hi <= I.eps_eq))
-                            fl |= F_NOTFEAS;
-                    }
+                atomicMin(&s_kf[2 * p], fkey(mn));
+                atomicMax(&s_kf[2 * p + 1], fkey(mx));
+            }
+            __syncthreads();
+            for (int p = threadIdx.x; p < nq; p += blockDim.x) {
+                const int poly = s_poly[p];
+                const double base = s_base[p];
+                const float mn = funkey(s_kf[2 * p]), mx = funkey(s_kf[2 * p + 1]);
+                // the root's part + rounding of the offsets (the FP64
+                // difference and the FP32 conversion) + underflow
+                const double amax = fmax(fabs((double)mn), fabs((double)mx));
+                const double e = (double)round_up_f(s_rb[p] + amax * 0x1p-23 + 0x1p-126);
+                double lo, hi;
+                child_bounds<float>(mn, mx, e, base, lo, hi);
+                // retiring mode: an inequality certified satisfied is not carried
+                s_keep[p] = !(gath && hi <= 0.0);
+                I.err[cur ^ 1][(int64_t)(nc * j + c) * I.n_polys + poly] = make_float2((float)e, 0.0f);
+                I.base[cur ^ 1][(int64_t)(nc * j + c) * I.n_polys + poly] = base;
+                if (kind == 0) {
+                    I.minP[nc * j + c] = lo;
+                    I.maxP[nc * j + c] = hi;
+                } else if (kind == 1) {
+                    if (lo > 0.0) fl |= F_INFEAS;
+                    if (!(hi <= 0.0)) fl |= F_NOTFEAS;
+                } else {
+                    if (lo > 0.0 || hi < 0.0) fl |= F_INFEAS;
+                    if (!(-I.eps_eq <= lo && lo <= 0.0 && 0.0 <= hi && hi <= I.eps_eq))
+                        fl |= F_NOTFEAS;
                 }
             }
             __syncthreads();
@@ -2170,8 +2199,9 @@ __global__ __launch_bounds__(SUB_THREADS) void k_rederive(const DevInst* __restr
             }
             __syncthreads();
             // the kept patches' FP32 offsets: to the child's slot, or its heap patch
+            const float invS = 1.0f / (float)S;
             for (int e = threadIdx.x; e < TE; e += blockDim.x) {
-                const int p = e / S;
+                const int p = patch_of(e, invS);
                 if (!s_keep[p]) continue;
                 float* dp = gath ? hc + (int64_t)s_dst[p] * S : child + soff + (int64_t)p * S;
                 dp[e - p * S] = (float)(x[e] - s_base[p]);

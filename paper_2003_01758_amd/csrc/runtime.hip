@@ -1227,13 +1227,15 @@ static void sub_tile(const pcba_problem* P, int* tem, int* tpm)
 }
 static size_t rederive_lds(const pcba_problem* P)
 {
-    int TE = P->S[0];
+    // the largest chunk, transforms and per-patch records (52 bytes) of any kind
+    int TE = P->S[0], npc = 1;
     for (int t = 1; t < KINDS; ++t)
         if (P->count[t]) {
             const int cp = std::min(REDERIVE_CHUNK, std::max(1, MAX_TILE64 / P->S[t]));
             TE = std::max(TE, std::min(P->tile_polys[t], cp) * P->S[t]);
+            npc = std::max(npc, std::min(P->tile_polys[t], cp));
         }
-    return ((size_t)TE + (size_t)P->l * P->maxm * P->maxm) * 8 + 16;
+    return ((size_t)TE + (size_t)P->l * P->maxm * P->maxm) * 8 + (size_t)npc * 52 + 16;
 }
 
 // FP64 certification of every finished problem in one launch, then their states.
