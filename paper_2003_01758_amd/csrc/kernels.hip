@@ -1935,9 +1935,13 @@ __device__ void apply_tmats(double* x, const double* tm, const int* tmoff, const
         g.stride = ag.stride;
         g.F = ag.F;
         const double* Tm = tm + tmoff[r];
+        // quotients by reciprocals, exact for dividends below 2^22 (see patch_of)
+        const float invF = 1.0f / (float)g.F, invT = 1.0f / (float)g.stride;
         mfma_fibres_f64(np * g.F, g.m, g.stride, Tm, [&](int f) {
-            const int p = f / g.F;
-            return x + p * S + fibre_base(g, f - p * g.F);
+            const int p = (int)(((float)f + 0.5f) * invF);
+            const int q = f - p * g.F;
+            const int outer = (int)(((float)q + 0.5f) * invT);
+            return x + p * S + outer * g.m * g.stride + (q - outer * g.stride);
         });
         __syncthreads();
     }
@@ -2093,7 +2097,7 @@ __global__ __launch_bounds__(SUB_THREADS) void k_rederive(const DevInst* __restr
             }
             copy_to_lds<double>(tm, tsrc, tmsz);
             if (!gath) {
-                copy_to_lds<double>(x, I.racc + roff, TE);
+                copy_to_lds<double, MAX_TILE64 / SUB_THREADS>(x, I.racc + roff, TE);   // one round of loads
             } else {
                 for (int e = threadIdx.x; e < TE; e += blockDim.x) {
                     const int p = e / S;
