@@ -1775,18 +1775,24 @@ __device__ __forceinline__ bool sub_run(const DevInst* __restrict__ insts, int n
         if (!c.gath) {
             // children patches to the children's slots, not to a child already
             // condemned (infeasible from this tile, or with the stale filter a
-            // cost bound above the previous solution estimate)
-            if (act && chb == 0) {
-                int wm = 0;
-                const uint32_t kd = split_b ? (uint32_t)Ldead[p] : known_dead;
-                for (int ch = 0; ch < nc; ++ch) {
-                    const bool w = kind == 0 ? !(I.stale && lo[ch] > c.pprev)
-                                             : !(Lsfl[nr * seg + ch] & F_INFEAS) && !((kd >> ch) & 1u);
-                    if (w) wm |= 1 << ch;
+            // cost bound above the previous solution estimate).  A constraint
+            // tile of one segment without the stale filter writes child ch
+            // unless the tile's flags condemn it, which every thread reads
+            const bool one_seg = kind != 0 && s_nseg == 1;
+            const bool by_flags = one_seg && !I.stale;
+            if (!by_flags) {
+                if (act && chb == 0) {
+                    int wm = 0;
+                    const uint32_t kd = split_b ? (uint32_t)Ldead[p] : known_dead;
+                    for (int ch = 0; ch < nc; ++ch) {
+                        const bool w = kind == 0 ? !(I.stale && lo[ch] > c.pprev)
+                                                 : !(Lsfl[nr * seg + ch] & F_INFEAS) && !((kd >> ch) & 1u);
+                        if (w) wm |= 1 << ch;
+                    }
+                    Lwm[p] = wm;
                 }
-                Lwm[p] = wm;
+                lds_barrier();
             }
-            lds_barrier();
             const gmem_t<T> dbuf = as_global((T*)I.buf[cur ^ 1]);
             constexpr int SB = 8;
             // child ch of a parent is region ch of the split, or for a round
@@ -1796,11 +1802,11 @@ __device__ __forceinline__ bool sub_run(const DevInst* __restrict__ insts, int n
             // tile without retiring) is copied as one run per child; otherwise
             // each patch's destination, less its position in the tile, is
             // tabulated once (-1: not written) and each element adds its offset.
-            const bool one_seg = kind != 0 && s_nseg == 1;
             for (int ch = 0; ch < nc; ++ch) {
                 const T* src = La + (nc == 4 ? (ch >> 1) + 2 * (ch & 1) : ch) * TE;
                 if (one_seg) {
-                    if (!((Lwm[0] >> ch) & 1)) continue;   // uniform: the whole tile's child
+                    // uniform: the whole tile's child
+                    if (by_flags ? (Lsfl[ch] & F_INFEAS) != 0u : !((Lwm[0] >> ch) & 1)) continue;
                     const int4 ip = inf[0];
                     const int64_t d0 = (int64_t)(nc * ip.x + ch) * I.stride + I.soff[kind] + (int64_t)ip.z * S;
                     // 16-byte stores: the elements before the destination's
