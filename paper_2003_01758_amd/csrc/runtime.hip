@@ -928,9 +928,15 @@ int pcba_create_problem(int32_t l, const double* lo, const double* hi, const int
     // k_sub tiles: runs of ~TILE_ELEMS coefficients of one kind across parents,
     // at most one patch per lane (a round keeps 2^l children of the tile in LDS:
     // its tiles are 2 / 2^l as large)
+    // The LDS of a tile is sized for the largest tile of any kind and for the
+    // most patches of any kind; with constraints, the cost patches (one per
+    // parent, a small share of the work) go 64 to a tile, so that their count
+    // does not set the per-patch tables of every tile.
     for (int t = 0; t < KINDS; ++t) {
         const int target = o.tile_coefs > 0 ? o.tile_coefs : (P->fp32 ? 2 * TILE_ELEMS : TILE_ELEMS) * 2 / P->nc;
-        P->ptp[t] = P->count[t] ? std::max(1, std::min(SUB_THREADS, target / std::max(1, P->S[t]))) : 1;
+        int cap = SUB_THREADS;
+        if (t == 0 && P->count[1] + P->count[2] > 0) cap = 64;
+        P->ptp[t] = P->count[t] ? std::max(1, std::min(cap, target / std::max(1, P->S[t]))) : 1;
     }
     // sub-interval transforms per child (FP32 re-derivation): m^2 words and m rows per kind and axis
     for (int t = 0; t < KINDS; ++t) {
