@@ -24,9 +24,8 @@ from . import pcba
 
 # candidate shapes: tile sizes around the default (2,816 coefficients per FP64
 # tile, twice that in FP32, half in a round of l = 2), one or two workgroups
-# per compute unit.  (FP32 tiles above about 6,200 coefficients have measured
-# far slower on the rtd workload: 6,144 took 58 ms a batch, 6,400 and up 84-91.)
-TILES = {"fp64": (1408, 2048, 2816, 3584), "fp32": (2816, 4096, 5632, 6144)}
+# per compute unit
+TILES = {"fp64": (1408, 2048, 2816, 3584), "fp32": (2816, 4096, 5632, 7168)}
 WGS = (0, 1)
 REDERIVE = (8, 16, 32, 0)   # directional steps between FP64 re-derivations (halved for rounds; 0 never)
 
