@@ -118,7 +118,9 @@ typedef struct {
      * depend on it, FP32 bounds stay rigorous).  0 = the library's default. */
     int32_t tile_coefs;      /* coefficients per tile (per child region): 0, or 256..3584
                                 (FP64) / 256..7168 (PCBA_FP32), and with fused_round at most
-                                2/2^l of that; a patch larger than this gets a tile of its own */
+                                2/2^l of that; a patch larger than this gets a tile of its own;
+                                at most 256 patches to a tile, and at most 64 cost patches when
+                                the problem has constraints */
     int32_t wg_per_cu;       /* workgroups per compute unit of the launch: 0 = as many as
                                 fit, else at most this many */
     /* Subdivision variants of Sec. III-D and Sec. II-E. */
